@@ -1,0 +1,271 @@
+/*
+ * ddgmres.h -- C ABI of the MI355X (gfx950) data-driven GMRES library.
+ *
+ * Solves the 2D frequency-domain Maxwell equation for E_z (Sec. 2, Eq. 1),
+ *     [curl curl - omega^2 eps(x)/c^2] E = -i omega mu0 J,
+ * discretised on the Yee grid with stretched-coordinate PML backed by
+ * periodic boundaries, A f = b, by GMRES (Eq. 2) whose Krylov space is
+ * augmented with a predicted subspace span(v_1..v_N) (Eqs. 3-5; the
+ * supplement's update rule: QR of A V, projected Arnoldi, block least squares).
+ *
+ * Conventions
+ *   - Units c = mu0 = eps0 = 1, lengths in micrometres, omega = 2 pi / lambda,
+ *     time dependence exp(+i omega t); PML stretch s = 1 - i sigma/omega.
+ *   - Grids are row-major with x fastest: flat index = iy*nx + ix, D = nx*ny.
+ *   - Complex vectors are interleaved (re, im): DD_C64 = 2 x float (8 B),
+ *     DD_C128 = 2 x double (16 B), the memory layout of torch.complex64/128.
+ *   - Pointers are DEVICE pointers unless marked (host).
+ *   - Work is ordered on the given stream; a call returns once its work is
+ *     enqueued unless stated otherwise.  Calls that report results on the
+ *     host (dd_solver_solve, gmres_solve*) synchronise the stream.
+ *   - No C++ exception crosses this boundary.  Every non-OK status leaves a
+ *     message for dd_last_error() (per thread).
+ */
+#ifndef DDGMRES_H
+#define DDGMRES_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DD_OK = 0,
+  DD_NOT_CONVERGED = 1, /* iteration budget spent; x holds the last iterate  */
+  DD_EINVAL = -1,       /* invalid argument (sizes, omega, dx, pml, tol ...)   */
+  DD_ENOMEM = -2,       /* device or host allocation failed                    */
+  DD_EHIP = -3,         /* a HIP runtime call failed                           */
+  DD_ENONFINITE = -4    /* non-finite permittivity or right-hand side          */
+} dd_status;
+
+typedef enum { DD_C64 = 0, DD_C128 = 1 } dd_prec;
+
+/* PML description (host struct).  The profile is sigma(d) = sigma_max (d/n)^m
+ * with sigma_max = -(m+1) ln_R / (2 n dx), d = depth in cells (integer and
+ * half-integer positions, clamped to n).  The paper names PML without
+ * parameters (Sec. 2); grade_m = 3, ln_R = -16 are the defaults used here.
+ * npml_x / npml_y = 0 disables the layer on that axis. */
+typedef struct {
+  int npml_x, npml_y;
+  int grade_m;
+  double ln_R;
+} dd_pml;
+
+typedef struct fdfd_op fdfd_op;
+typedef struct dd_solver dd_solver;
+typedef struct dd_cnn dd_cnn;
+
+/* ------------------------------------------------------------------------
+ * FDFD operator (Sec. 2, Eq. 1 and the paragraph after it)
+ * ------------------------------------------------------------------------ */
+
+/* Create the operator A = -(Dxb Dxf + Dyb Dyf) - omega^2 diag(eps).
+ *   eps   (host) [ny][nx] relative permittivity, copied; may be freed on return.
+ *   nx, ny >= 3; omega > 0; dx > 0; 2*npml < n on each axis.
+ * Errors: DD_EINVAL for bad sizes/parameters, DD_ENONFINITE for non-finite
+ * eps, DD_ENOMEM / DD_EHIP on allocation or copy failure (op left NULL).
+ * The operator owns its device buffers until fdfd_op_destroy. */
+dd_status fdfd_op_create(const float* eps, int nx, int ny, double omega, double dx,
+                         const dd_pml* pml, fdfd_op** op);
+
+/* y = A x for one vector of D elements in precision p (x and y must not
+ * alias).  Enqueued on stream. */
+dd_status fdfd_op_apply(const fdfd_op* op, const void* x, void* y, dd_prec p,
+                        hipStream_t stream);
+
+/* Grid size of an operator (host out-params); returns D or -1 on NULL. */
+int fdfd_op_dims(const fdfd_op* op, int* nx, int* ny);
+
+void fdfd_op_destroy(fdfd_op* op);
+
+/* ------------------------------------------------------------------------
+ * Data-driven GMRES solver (Sec. 2, Eqs. 2-5; supplement Sec. 1)
+ * ------------------------------------------------------------------------
+ * A solver object holds the workspace for a batch of nb problems (one
+ * operator each, sizes may differ) that are iterated in lockstep: every
+ * kernel launch advances all unfinished problems by one step.
+ *
+ * Per cycle (restart length m): r = b - A x in FP64; c0 = C^H r and the
+ * projected start r~ = r - C c0 (C from the thin QR A V = C R); Arnoldi on
+ * P A (P = I - C C^H) with classical Gram-Schmidt run cgs_passes times over
+ * [C, Q]; the Hessenberg matrix, its Givens rotations and the residual
+ * estimate are kept in FP64; when the estimate drops to tol*||b|| (or after
+ * m steps) the block least-squares problem of the supplement is solved
+ * (x_aug = c0 - B y, B = C^H A Q) and x += V R^{-1} x_aug + Q y in FP64.
+ * A new cycle starts from the recomputed FP64 residual; the solve has
+ * converged when ||b - A x|| / ||b|| <= tol.
+ */
+typedef struct {
+  dd_prec inner;        /* precision of matvecs and Gram-Schmidt (DD_C64 default) */
+  int cgs_passes;       /* 1 = classical Gram-Schmidt, 2 = CGS2 (default)          */
+  int restart;          /* m >= 1 (default 100)                                     */
+  int kmax;             /* largest number of augmenting vectors, 0..64 (default 0) */
+  int elems_per_thread; /* field elements per thread: 0 = auto, or 1, 2, 4, 8       */
+  int hist_cap;         /* residual-history entries kept per problem (default 0)   */
+  int check_every;      /* steps between host checks for an early cycle end (4)    */
+} dd_solver_opts;
+
+/* Per-problem result (host struct). */
+typedef struct {
+  int status;          /* DD_OK or DD_NOT_CONVERGED                              */
+  int iters;           /* Arnoldi steps (the paper's "iterations")               */
+  int matvecs;         /* every application of A: setup k + steps + residuals   */
+  int restarts;        /* cycles started                                         */
+  int k_used;          /* augmenting columns kept after rank checks             */
+  int fallback_plain;  /* 1 if a subspace was given but no column was usable     */
+  double rel_res_true; /* ||b - A x|| / ||b|| recomputed in FP64 at the end      */
+  double rel_res_est;  /* last Givens residual estimate / ||b||                  */
+} dd_info;
+
+void dd_solver_opts_default(dd_solver_opts* o);
+
+/* Allocate the workspace for nb problems.  ops (host array of nb operator
+ * handles) are borrowed until destroy or the next dd_solver_bind.
+ * Errors: DD_EINVAL (nb < 1, restart < 1, kmax outside 0..64, bad
+ * elems_per_thread), DD_ENOMEM / DD_EHIP. */
+dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
+                           dd_solver** out);
+
+/* Replace the operators of an existing solver by operators of the same grid
+ * sizes (slot by slot).  Clears any subspace.  DD_EINVAL on a size mismatch. */
+dd_status dd_solver_bind(dd_solver* s, const fdfd_op* const* ops);
+
+/* Augmentation setup (supplement: QR of A V, storage of R^{-1}).
+ * U (host array of nb device pointers, entries may be NULL) points to
+ * [k[p]][D_p] vectors in the solver's inner precision; k (host) per problem,
+ * 0 <= k[p] <= kmax; U == NULL or k == NULL clears all subspaces.
+ * Computes W = A U, then C = W R^{-1} by Cholesky QR applied twice with the
+ * Gram matrices accumulated in FP64; a column whose Cholesky pivot falls
+ * below 1e-6 of the largest is dropped (k_used reports the rest), columns
+ * with non-finite entries are dropped.  The vectors are copied; U may be
+ * reused once the stream has passed this call. */
+dd_status dd_solver_set_subspace(dd_solver* s, const void* const* U, const int* k,
+                                 hipStream_t stream);
+
+/* Solve all nb problems.  b[p]: [D_p] c128 right-hand side; x0 (host array,
+ * may be NULL, entries may be NULL = zero start): [D_p] c128 initial guess;
+ * x[p]: [D_p] c128 output (may alias x0[p]).  tol >= 0, maxit >= 0 (Arnoldi
+ * steps per problem).  info (host, may be NULL) receives nb records.
+ * Synchronises the stream.  Returns DD_OK if every problem converged,
+ * DD_NOT_CONVERGED otherwise (x then holds the last iterate), DD_ENONFINITE
+ * if a right-hand side is not finite, DD_EINVAL / DD_EHIP on errors.
+ * ||b|| = 0 gives x = 0, DD_OK, rel_res_true = 0. */
+dd_status dd_solver_solve(dd_solver* s, const void* const* b, const void* const* x0,
+                          double tol, int maxit, void* const* x, dd_info* info,
+                          hipStream_t stream);
+
+/* Copy problem p's residual history (Givens estimate / ||b|| after each
+ * Arnoldi step of the last solve, up to hist_cap entries) to host out[cap];
+ * *n receives the number of entries written. */
+dd_status dd_solver_history(const dd_solver* s, int p, double* out, int cap, int* n);
+
+/* Test introspection: copy an internal array of problem p to host memory.
+ * what: 0 = C [k][D] (inner precision), 1 = Q [m+1][D] (after a full cycle the
+ * last slot holds the new Arnoldi vector before normalisation, of norm
+ * H[m-1][m]), 2 = H [m][m+1]
+ * (FP64 complex, column-major, as built before rotation), 3 = B = C^H A Q
+ * [m][k] (FP64 complex), 4 = R^{-1} [k][k] (FP64 complex, row-major).
+ * bytes must match the array size exactly; synchronises the device. */
+dd_status dd_solver_debug_copy(const dd_solver* s, int p, int what, void* host_out,
+                               size_t bytes);
+
+/* Device bytes held by the solver workspace. */
+size_t dd_solver_device_bytes(const dd_solver* s);
+
+void dd_solver_destroy(dd_solver* s);
+
+/* One-call convenience wrappers: create a solver, set the subspace, solve,
+ * destroy.  U: [k][D] in the inner precision or NULL; opts may be NULL
+ * (defaults).  Same status rules as dd_solver_solve. */
+dd_status gmres_solve(const fdfd_op* op, const void* b, const void* x0, const void* U, int k,
+                      double tol, int restart, int maxit, const dd_solver_opts* opts, void* x,
+                      dd_info* info, hipStream_t stream);
+dd_status gmres_solve_batched(const fdfd_op* const* ops, int nb, const void* const* b,
+                              const void* const* x0, const void* const* U, const int* k,
+                              double tol, int restart, int maxit, const dd_solver_opts* opts,
+                              void* const* x, dd_info* info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Principal-component basis (Sec. 3, PCA paragraph)
+ * ------------------------------------------------------------------------
+ * Leading left singular vectors of the uncentred snapshot matrix S whose M
+ * columns are solution fields (an "incomplete SVD").  Computed as the FP64
+ * Gram matrix G = S^H S on the device, its eigen-decomposition on the host
+ * (FP64 Jacobi), U = S W diag(1/sigma) on the device, then re-orthonormalised
+ * by Cholesky QR.
+ *   S:  [M][D] c64 snapshots (device), M >= k >= 1.
+ *   U:  [k][D] c64 output basis (device).
+ *   sigma (host, may be NULL): k singular values, descending.
+ * Synchronises the stream. */
+dd_status pca_build(const void* S, int M, int D, int k, void* U, double* sigma,
+                    hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Projection loss of a subspace (Sec. 3, eq:proj_loss), batched evaluation
+ * ------------------------------------------------------------------------
+ * l = 1 - ||Q^H f||^2 / ||f||^2 with Q an orthonormal basis of span(V).
+ * V: [nb][k][D] c64, f: [nb][D] c128 (device); out (host) [nb].
+ * Synchronises the stream. */
+dd_status proj_loss_batched(const void* V, const void* f, int nb, int k, int D, double* out,
+                            hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Convolutional subspace predictor (Sec. 3, CNN paragraph; Methods)
+ * ------------------------------------------------------------------------
+ * Encoder-decoder of eight 3x3 convolutions on a [B][ny][nx] permittivity
+ * image (the architecture figure of the paper is not available; the layer
+ * list is fixed by dd_cnn_layer_info).  Activations are bf16 in NHWC
+ * layout, products accumulate in FP32 on the matrix cores, master weights
+ * and Adam moments are FP32.  The 2k output channels are read as k complex
+ * fields (channel 2j = real part, 2j+1 = imaginary part of v_j).
+ */
+
+/* Create a network for input images of ny x nx (both multiples of 4) and up
+ * to max_batch images per call, k output fields.  Weights are
+ * initialised from seed (He-uniform, host RNG, documented in the source). */
+dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, unsigned long long seed,
+                        dd_cnn** out);
+void dd_cnn_destroy(dd_cnn* net);
+
+/* Number of layers and, per layer (host out-params, may be NULL): input
+ * channels, output channels, stride (1 or 2), upsample-before (0/1), relu (0/1). */
+int dd_cnn_layer_info(const dd_cnn* net, int layer, int* cin, int* cout, int* stride,
+                      int* upsample, int* relu);
+
+/* Number of FP32 parameters (weights + biases) and host copies in / out in the
+ * layout [layer][cout][cin][3][3] then [layer][cout] biases, layer by layer. */
+size_t dd_cnn_num_params(const dd_cnn* net);
+dd_status dd_cnn_get_params(const dd_cnn* net, float* host_out, size_t count);
+dd_status dd_cnn_set_params(dd_cnn* net, const float* host_in, size_t count);
+
+/* Forward pass.  eps: [B][ny][nx] float32 permittivity (device); the input is
+ * normalised as (eps - 2.085) / (12.25 - 2.085).  U: [B][k][ny*nx] c64
+ * output fields (device).  B <= max_batch. */
+dd_status predict_subspace(dd_cnn* net, const float* eps, int B, void* U, hipStream_t stream);
+
+/* One training step on a batch: forward, mean-squared error against target
+ * [B][k][ny*nx] c64 (device, same layout as U), backward, Adam update with
+ * learning rate lr, betas (b1, b2), epsilon 1e-8.  *loss (host, may be NULL)
+ * receives the batch loss (synchronises the stream when non-NULL). */
+dd_status dd_cnn_train_step(dd_cnn* net, const float* eps, const void* target, int B,
+                            float lr, float b1, float b2, float* loss, hipStream_t stream);
+
+/* Gradient of the batch loss w.r.t. all parameters (no update), FP32 host
+ * out[count] in the dd_cnn_get_params layout; for gradient checks. */
+dd_status dd_cnn_grad(dd_cnn* net, const float* eps, const void* target, int B, float* loss,
+                      float* host_grad, size_t count, hipStream_t stream);
+
+/* Copy the bf16 activations of layer l's output (NHWC, as float32) to host;
+ * layer = -1 gives the normalised input.  For tests. */
+dd_status dd_cnn_debug_activation(const dd_cnn* net, int layer, int B, float* host_out,
+                                  size_t count);
+
+/* Last error message of this thread ("" if none). */
+const char* dd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDGMRES_H */

@@ -1,0 +1,271 @@
+"""MI355X (gfx950) data-driven GMRES for 2D FDFD Maxwell problems.
+
+Python binding of libddgmres.so: argument marshalling only.  torch tensors
+provide device memory and the current HIP stream; every arithmetic step of the
+solver, the principal-component basis and the convolutional predictor runs in
+the library's HIP kernels.  The names follow the C ABI in include/ddgmres.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import DD_C64, DD_C128, DDError, check, ptr_array
+
+__all__ = ["FdfdOp", "Solver", "gmres_solve", "gmres_solve_batched", "pca_build",
+           "proj_loss_batched", "Cnn", "DDError", "lib_path"]
+
+
+def lib_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype=None, numel=None, what="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class FdfdOp:
+    """A = -(Dxb Dxf + Dyb Dyf) - omega^2 diag(eps) on an nx x ny Yee grid (Eq. 1)."""
+
+    def __init__(self, eps, omega, dx, npml, grade=3, ln_R=-16.0, npml_y=None):
+        eps = np.ascontiguousarray(np.asarray(eps, dtype=np.float32))
+        if eps.ndim != 2:
+            raise ValueError("eps must be [ny, nx]")
+        self.ny, self.nx = eps.shape
+        self.D = self.nx * self.ny
+        self.omega, self.dx, self.npml = float(omega), float(dx), int(npml)
+        pml = _lib.dd_pml(int(npml), int(npml if npml_y is None else npml_y), int(grade),
+                          float(ln_R))
+        h = C.c_void_p()
+        check(_lib.lib().fdfd_op_create(eps.ctypes.data_as(C.POINTER(C.c_float)), self.nx,
+                                        self.ny, self.omega, self.dx, C.byref(pml),
+                                        C.byref(h)), "fdfd_op_create")
+        self._h = h
+
+    @classmethod
+    def from_instance(cls, inst):
+        return cls(inst.eps, inst.omega, inst.dx, inst.npml)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, x, out=None):
+        torch = _torch()
+        prec = DD_C64 if x.dtype == torch.complex64 else DD_C128
+        if x.dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("x must be complex64 or complex128")
+        if out is None:
+            out = torch.empty_like(x)
+        check(_lib.lib().fdfd_op_apply(self._h, _dev(x, numel=self.D, what="x"),
+                                       _dev(out, x.dtype, self.D, "out"), prec, _stream()),
+              "fdfd_op_apply")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().fdfd_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hist_cap=0,
+          check_every=4):
+    o = _lib.dd_solver_opts()
+    _lib.lib().dd_solver_opts_default(C.byref(o))
+    o.inner = DD_C64 if inner == "c64" else DD_C128
+    o.cgs_passes = int(cgs_passes)
+    o.restart = int(restart)
+    o.kmax = int(kmax)
+    o.elems_per_thread = int(elems_per_thread)
+    o.hist_cap = int(hist_cap)
+    o.check_every = int(check_every)
+    return o
+
+
+class Solver:
+    """Batched data-driven GMRES over a list of operators (lockstep cycles)."""
+
+    def __init__(self, ops, restart=100, kmax=0, inner="c64", cgs_passes=2,
+                 elems_per_thread=0, hist_cap=0, check_every=4):
+        self.ops = list(ops)
+        self.nb = len(self.ops)
+        self.opts = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap,
+                          check_every)
+        self.inner = inner
+        self.restart, self.kmax = int(restart), int(kmax)
+        h = C.c_void_p()
+        check(_lib.lib().dd_solver_create(ptr_array([o.handle for o in self.ops]), self.nb,
+                                          C.byref(self.opts), C.byref(h)), "dd_solver_create")
+        self._h = h
+        self._U = None
+        self.k = [0] * self.nb
+
+    def bind(self, ops):
+        ops = list(ops)
+        check(_lib.lib().dd_solver_bind(self._h, ptr_array([o.handle for o in ops])),
+              "dd_solver_bind")
+        self.ops = ops
+        self.k = [0] * self.nb
+
+    def set_subspace(self, U):
+        """U: list (one per problem) of [k, D] tensors in the inner precision, or None."""
+        torch = _torch()
+        if U is None:
+            check(_lib.lib().dd_solver_set_subspace(self._h, None, None, _stream()),
+                  "dd_solver_set_subspace")
+            self.k = [0] * self.nb
+            return
+        dt = torch.complex64 if self.inner == "c64" else torch.complex128
+        ptrs, ks = [], (C.c_int * self.nb)()
+        for p, u in enumerate(U):
+            if u is None or u.numel() == 0:
+                ptrs.append(None)
+                ks[p] = 0
+                continue
+            if u.dim() != 2 or u.shape[1] != self.ops[p].D:
+                raise ValueError(f"U[{p}] must be [k, D={self.ops[p].D}]")
+            ptrs.append(_dev(u, dt, what=f"U[{p}]").value)
+            ks[p] = u.shape[0]
+        check(_lib.lib().dd_solver_set_subspace(self._h, ptr_array(ptrs), ks, _stream()),
+              "dd_solver_set_subspace")
+        self.k = list(ks)
+
+    def solve(self, b, x0=None, tol=1e-6, maxit=20000, x=None):
+        """b: list of [D] complex128 tensors.  Returns (x list, list of info dicts, status)."""
+        torch = _torch()
+        if x is None:
+            x = [torch.empty_like(bb) for bb in b]
+        bp = ptr_array([_dev(bb, torch.complex128, self.ops[p].D, f"b[{p}]").value
+                        for p, bb in enumerate(b)])
+        xp = ptr_array([_dev(xx, torch.complex128, self.ops[p].D, f"x[{p}]").value
+                        for p, xx in enumerate(x)])
+        x0p = None
+        if x0 is not None:
+            x0p = ptr_array([None if v is None else
+                             _dev(v, torch.complex128, self.ops[p].D, f"x0[{p}]").value
+                             for p, v in enumerate(x0)])
+        info = (_lib.dd_info * self.nb)()
+        st = check(_lib.lib().dd_solver_solve(self._h, bp, x0p, float(tol), int(maxit), xp, info,
+                                              _stream()), "dd_solver_solve")
+        return x, [i.as_dict() for i in info], st
+
+    def history(self, p):
+        cap = self.opts.hist_cap
+        out = np.zeros(max(cap, 1), np.float64)
+        n = C.c_int()
+        check(_lib.lib().dd_solver_history(self._h, p, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                           cap, C.byref(n)), "dd_solver_history")
+        return out[:n.value].copy()
+
+    def debug(self, p, what):
+        """Internal arrays of problem p: 'C', 'Q', 'H', 'B', 'Rinv' (see the C header)."""
+        D = self.ops[p].D
+        k, m = self.k[p], self.restart
+        cdt = np.complex64 if self.inner == "c64" else np.complex128
+        shapes = {"C": (0, (k, D), cdt), "Q": (1, (m + 1, D), cdt),
+                  "H": (2, (m, m + 1), np.complex128), "B": (3, (m, k), np.complex128),
+                  "Rinv": (4, (k, k), np.complex128)}
+        code, shape, dt = shapes[what]
+        out = np.zeros(shape, dt)
+        check(_lib.lib().dd_solver_debug_copy(self._h, p, code, out.ctypes.data_as(C.c_void_p),
+                                              out.nbytes), "dd_solver_debug_copy")
+        return out
+
+    @property
+    def device_bytes(self):
+        return _lib.lib().dd_solver_device_bytes(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().dd_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gmres_solve(op, b, U=None, tol=1e-6, restart=100, maxit=20000, x0=None, inner="c64",
+                cgs_passes=2, x=None):
+    """One problem: returns (x, info dict, status)."""
+    torch = _torch()
+    if x is None:
+        x = torch.empty_like(b)
+    o = _opts(restart, 0, inner, cgs_passes)
+    info = _lib.dd_info()
+    k = 0 if U is None else U.shape[0]
+    dt = torch.complex64 if inner == "c64" else torch.complex128
+    st = check(_lib.lib().gmres_solve(
+        op.handle, _dev(b, torch.complex128, op.D, "b"),
+        None if x0 is None else _dev(x0, torch.complex128, op.D, "x0"),
+        None if U is None else _dev(U, dt, what="U"), k, float(tol), int(restart), int(maxit),
+        C.byref(o), _dev(x, torch.complex128, op.D, "x"), C.byref(info), _stream()),
+        "gmres_solve")
+    return x, info.as_dict(), st
+
+
+def gmres_solve_batched(ops, b, U=None, tol=1e-6, restart=100, maxit=20000, inner="c64",
+                        cgs_passes=2):
+    s = Solver(ops, restart=restart, kmax=max([0] + [u.shape[0] for u in (U or []) if u is not None]),
+               inner=inner, cgs_passes=cgs_passes)
+    try:
+        if U is not None:
+            s.set_subspace(U)
+        return s.solve(b, tol=tol, maxit=maxit)
+    finally:
+        s.close()
+
+
+def pca_build(S, k):
+    """S: [M, D] complex64 snapshots (device).  Returns (U [k, D] complex64, sigma [k])."""
+    torch = _torch()
+    M, D = S.shape
+    U = torch.empty((k, D), dtype=torch.complex64, device=S.device)
+    sig = np.zeros(k, np.float64)
+    check(_lib.lib().pca_build(_dev(S, torch.complex64, what="S"), M, D, k, _dev(U),
+                               sig.ctypes.data_as(C.POINTER(C.c_double)), _stream()), "pca_build")
+    return U, sig
+
+
+def proj_loss_batched(V, f):
+    """V: [nb, k, D] complex64, f: [nb, D] complex128 (device).  Returns numpy [nb]."""
+    torch = _torch()
+    nb, k, D = V.shape
+    out = np.zeros(nb, np.float64)
+    check(_lib.lib().proj_loss_batched(_dev(V, torch.complex64, what="V"),
+                                       _dev(f, torch.complex128, nb * D, "f"), nb, k, D,
+                                       out.ctypes.data_as(C.POINTER(C.c_double)), _stream()),
+          "proj_loss_batched")
+    return out
+
+
+from .cnn import Cnn  # noqa: E402

@@ -1,0 +1,93 @@
+// Device-side helpers shared by the FDFD operator, the Krylov solver and the
+// predictor kernels: complex arithmetic on float2/double2, the wavefront
+// butterfly reduction and the error-reporting plumbing of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ddgmres.h"
+
+#define DD_BLOCK 256          // threads per workgroup for all field sweeps (4 waves)
+#define DD_WAVE 64
+
+// ---------------------------------------------------------------- complex ----
+template <typename T> struct cvec;
+template <> struct cvec<float> { using type = float2; };
+template <> struct cvec<double> { using type = double2; };
+template <typename T> using c2 = typename cvec<T>::type;
+
+template <typename V> __host__ __device__ __forceinline__ V cmk(decltype(V::x) re, decltype(V::x) im) {
+  V r; r.x = re; r.y = im; return r;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return cmk<V>(a.x + b.x, a.y + b.y); }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return cmk<V>(a.x - b.x, a.y - b.y); }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return cmk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) {
+  return cmk<V>(a.x * s, a.y * s);
+}
+// a - c*b
+template <typename V> __device__ __forceinline__ V cfnms(V a, V c, V b) {
+  return cmk<V>(a.x - (c.x * b.x - c.y * b.y), a.y - (c.x * b.y + c.y * b.x));
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { return cmk<V>(a.x, -a.y); }
+
+// ---------------------------------------------------------- reductions ------
+// One exchange step of the transposed butterfly: lanes that differ in bit
+// log2(CNT) swap halves of their CNT live values and add, so every lane keeps
+// CNT/2 partial sums.  Steps CNT = 32, 16, 8, 4, 2 leave in v[0] the wave sum
+// (over lane pairs) of value index (lane >> 1) & 31: 31 shuffles for 32
+// values instead of 32 * 6 with independent reductions.
+template <typename T, int CNT>
+__device__ __forceinline__ void butterfly_step(T (&v)[32], int lane) {
+  constexpr int H = CNT / 2;
+  const bool upper = (lane & CNT) != 0;
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    const T send = upper ? v[q] : v[q + H];
+    const T keep = upper ? v[q + H] : v[q];
+    v[q] = keep + __shfl_xor(send, CNT, DD_WAVE);
+  }
+  if constexpr (H > 1) butterfly_step<T, H>(v, lane);
+}
+
+// Block-level sum of 32 per-thread values (256 threads).  Result index i is
+// written by thread i (i < 32) into out[i].  Uses 4*32 values of LDS.
+template <typename T>
+__device__ __forceinline__ void block_sum32(T (&v)[32], T* lds, T* out) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  butterfly_step<T, 32>(v, lane);
+  const T s = v[0] + __shfl_xor(v[0], 1, DD_WAVE);
+  if ((lane & 1) == 0) lds[wave * 32 + (lane >> 1)] = s;
+  __syncthreads();
+  if (t < 32) out[t] = lds[t] + lds[32 + t] + lds[64 + t] + lds[96 + t];
+  __syncthreads();
+}
+
+// Block-level sum of one value per thread; thread 0 receives the total.
+template <typename T>
+__device__ __forceinline__ T block_sum1(T v, T* lds) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, DD_WAVE);
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  T r = (t == 0) ? (lds[0] + lds[1] + lds[2] + lds[3]) : T(0);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------- errors -------
+void dd_set_error(const char* fmt, ...);
+#define DD_HIP_CHECK(expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      dd_set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                   __LINE__);                                                     \
+      return DD_EHIP;                                                             \
+    }                                                                             \
+  } while (0)

@@ -1,0 +1,527 @@
+// Batched data-driven GMRES: workspace, augmentation setup and the cycle
+// loop (Sec. 2, Eqs. 2-5; supplement Sec. 1).  Kernels are in
+// solver_kernels.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "solver_kernels.h"
+
+struct dd_solver {
+  int nb = 0;
+  dd_solver_opts o{};
+  int R = 1;          // field elements per thread
+  int nchunks = 0;
+  std::vector<const fdfd_op*> ops;
+  std::vector<ProbDesc> hdesc;
+  std::vector<int> ksetup;  // augmenting columns given per problem
+  ProbDesc* ddesc = nullptr;
+  int* blk2prob = nullptr;
+  const void** dU = nullptr;  // device array of nb pointers for set_subspace
+  PlanDev P{};
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  int* pinned = nullptr;     // 2 status snapshots + 1 final
+  double* pinnedD = nullptr;
+  unsigned long long* pinnedK = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool has_subspace = false;
+};
+
+extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
+  if (!o) return;
+  o->inner = DD_C64;
+  o->cgs_passes = 2;
+  o->restart = 100;
+  o->kmax = 0;
+  o->elems_per_thread = 0;
+  o->hist_cap = 0;
+  o->check_every = 4;
+}
+
+static size_t inner_bytes(dd_prec p) { return p == DD_C128 ? 16 : 8; }
+
+template <typename X>
+static hipError_t dalloc(dd_solver* s, X** ptr, size_t count) {
+  const size_t b = std::max<size_t>(count * sizeof(X), 256);
+  hipError_t e = hipMalloc((void**)ptr, b);
+  if (e != hipSuccess) return e;
+  s->allocs.push_back((void*)*ptr);
+  s->bytes += b;
+  return hipMemset(*ptr, 0, b);
+}
+
+static void fill_desc_op(ProbDesc& d, const fdfd_op* op) {
+  d.nx = op->nx;
+  d.ny = op->ny;
+  d.D = op->D;
+  d.omega2 = op->omega * op->omega;
+  d.eps32 = op->eps32;
+  d.eps64 = op->eps64;
+  d.cf32 = op->cf32;
+  d.cf64 = op->cf64;
+}
+
+extern "C" void dd_solver_destroy(dd_solver* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : s->allocs) (void)hipFree(p);
+  if (s->pinned) (void)hipHostFree(s->pinned);
+  if (s->pinnedD) (void)hipHostFree(s->pinnedD);
+  if (s->pinnedK) (void)hipHostFree(s->pinnedK);
+  for (auto& e : s->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete s;
+}
+
+extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
+                                      dd_solver** out) {
+  if (!out) { dd_set_error("dd_solver_create: out is NULL"); return DD_EINVAL; }
+  *out = nullptr;
+  dd_solver_opts o;
+  dd_solver_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.check_every <= 0) o.check_every = 4;
+  if (!ops || nb < 1) { dd_set_error("dd_solver_create: need nb >= 1 operators"); return DD_EINVAL; }
+  for (int p = 0; p < nb; ++p)
+    if (!ops[p]) { dd_set_error("dd_solver_create: ops[%d] is NULL", p); return DD_EINVAL; }
+  if (o.restart < 1 || o.restart > DD_MAX_M) {
+    dd_set_error("dd_solver_create: restart must be in 1..%d", DD_MAX_M);
+    return DD_EINVAL;
+  }
+  if (o.kmax < 0 || o.kmax > DD_MAX_K) {
+    dd_set_error("dd_solver_create: kmax must be in 0..%d", DD_MAX_K);
+    return DD_EINVAL;
+  }
+  if (o.cgs_passes != 1 && o.cgs_passes != 2) {
+    dd_set_error("dd_solver_create: cgs_passes must be 1 or 2");
+    return DD_EINVAL;
+  }
+  if (o.inner != DD_C64 && o.inner != DD_C128) {
+    dd_set_error("dd_solver_create: unknown inner precision");
+    return DD_EINVAL;
+  }
+  if (o.hist_cap < 0) o.hist_cap = 0;
+  int R = o.elems_per_thread;
+  if (R != 0 && R != 1 && R != 2 && R != 4 && R != 8) {
+    dd_set_error("dd_solver_create: elems_per_thread must be 0, 1, 2, 4 or 8");
+    return DD_EINVAL;
+  }
+  if (R == 0) {
+    // largest R that still gives >= 2048 workgroups per sweep (8 per CU)
+    R = 1;
+    for (int cand : {8, 4, 2}) {
+      long long nch = 0;
+      for (int p = 0; p < nb; ++p) nch += (ops[p]->D + DD_BLOCK * cand - 1) / (DD_BLOCK * cand);
+      if (nch >= 2048) { R = cand; break; }
+    }
+  }
+  dd_solver* s = new dd_solver();
+  s->nb = nb;
+  s->o = o;
+  s->R = R;
+  s->ops.assign(ops, ops + nb);
+  s->hdesc.resize(nb);
+  s->ksetup.assign(nb, 0);
+  const int m = o.restart, K = o.kmax;
+  const int chunk = DD_BLOCK * R;
+  int blk = 0;
+  for (int p = 0; p < nb; ++p) {
+    ProbDesc& d = s->hdesc[p];
+    std::memset(&d, 0, sizeof(d));
+    fill_desc_op(d, ops[p]);
+    d.nblk = (d.D + chunk - 1) / chunk;
+    d.blk0 = blk;
+    d.Dp = d.nblk * chunk;
+    d.k = 0;
+    blk += d.nblk;
+  }
+  s->nchunks = blk;
+  const size_t ib = inner_bytes(o.inner);
+  const int NC = K + m + 1;
+  const int NV = ((2 * NC + 31) / 32) * 32 + 32;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+  // vectors
+  for (int p = 0; p < nb && e == hipSuccess; ++p) {
+    ProbDesc& d = s->hdesc[p];
+    char* basis = nullptr;
+    char* V = nullptr;
+    chk(dalloc(s, &basis, (size_t)(K + m + 1) * d.Dp * ib));
+    if (K > 0) chk(dalloc(s, &V, (size_t)K * d.Dp * ib));
+    double2* r = nullptr;
+    chk(dalloc(s, &r, (size_t)d.Dp));
+    d.basis = basis;
+    d.V = V;
+    d.r = r;
+  }
+  PlanDev& P = s->P;
+  P.nb = nb; P.m = m; P.kmax = K; P.NC = NC; P.NV = NV; P.hist_cap = o.hist_cap;
+  P.qslots = m + 1;
+  // Gram partial rows: bounded to 64 MB
+  {
+    const size_t per = (size_t)nb * std::max(1, gram_tiles(std::max(K, 1))) * 32 * sizeof(double);
+    int GB = (int)std::min<size_t>(32, std::max<size_t>(1, (64ull << 20) / per));
+    P.GB = GB;
+  }
+  std::vector<int> b2p(s->nchunks);
+  for (int p = 0; p < nb; ++p)
+    for (int c = 0; c < s->hdesc[p].nblk; ++c) b2p[s->hdesc[p].blk0 + c] = p;
+  ProbDesc* dd = nullptr;
+  int* db2p = nullptr;
+  if (e == hipSuccess) {
+    chk(dalloc(s, &dd, nb));
+    chk(dalloc(s, &db2p, s->nchunks));
+    chk(dalloc(s, &s->dU, nb));
+    chk(dalloc(s, &P.stI, (size_t)nb * ST_NI));
+    chk(dalloc(s, &P.stD, (size_t)nb * SD_ND));
+    chk(dalloc(s, &P.H, (size_t)nb * m * (m + 1)));
+    chk(dalloc(s, &P.Hraw, (size_t)nb * m * (m + 1)));
+    chk(dalloc(s, &P.Bc, (size_t)nb * m * std::max(K, 1)));
+    chk(dalloc(s, &P.g, (size_t)nb * (m + 1)));
+    chk(dalloc(s, &P.cs, (size_t)nb * m));
+    chk(dalloc(s, &P.sn, (size_t)nb * m));
+    chk(dalloc(s, &P.c0, (size_t)nb * std::max(K, 1)));
+    chk(dalloc(s, &P.coefA, (size_t)nb * NC));
+    chk(dalloc(s, &P.coefB, (size_t)nb * NC));
+    chk(dalloc(s, &P.hscale, (size_t)nb * (m + 1)));
+    chk(dalloc(s, &P.comb, (size_t)nb * (K + m)));
+    chk(dalloc(s, &P.Rinv, (size_t)nb * std::max(K * K, 1)));
+    chk(dalloc(s, &P.Tm, (size_t)nb * std::max(K * K, 1)));
+    chk(dalloc(s, &P.Gm, (size_t)nb * std::max(K * K, 1)));
+    chk(dalloc(s, &P.keep, (size_t)nb));
+    chk(dalloc(s, &P.bad, (size_t)nb));
+    double* part = nullptr;
+    chk(dalloc(s, &part, (size_t)s->nchunks * NV));
+    P.partial = part;
+    chk(dalloc(s, &P.gpart, (size_t)nb * P.GB * std::max(1, gram_tiles(std::max(K, 1))) * 32));
+    chk(dalloc(s, &P.counter, (size_t)nb));
+    chk(dalloc(s, &P.gcount, (size_t)s->nchunks));
+    chk(dalloc(s, &P.gsum, (size_t)s->nchunks * NV));
+    chk(dalloc(s, &P.hist, (size_t)nb * std::max(1, o.hist_cap)));
+  }
+  if (e == hipSuccess) {
+    chk(hipMemcpy(dd, s->hdesc.data(), sizeof(ProbDesc) * nb, hipMemcpyHostToDevice));
+    chk(hipMemcpy(db2p, b2p.data(), sizeof(int) * s->nchunks, hipMemcpyHostToDevice));
+    chk(hipHostMalloc((void**)&s->pinned, sizeof(int) * 3 * nb * ST_NI, hipHostMallocDefault));
+    chk(hipHostMalloc((void**)&s->pinnedD, sizeof(double) * nb * SD_ND, hipHostMallocDefault));
+    chk(hipHostMalloc((void**)&s->pinnedK, sizeof(unsigned long long) * nb, hipHostMallocDefault));
+    chk(hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming));
+    chk(hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming));
+  }
+  if (e != hipSuccess) {
+    dd_set_error("dd_solver_create: %s", hipGetErrorString(e));
+    dd_solver_destroy(s);
+    return e == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP;
+  }
+  s->ddesc = dd;
+  s->blk2prob = db2p;
+  P.desc = dd;
+  P.blk2prob = db2p;
+  *out = s;
+  return DD_OK;
+}
+
+extern "C" size_t dd_solver_device_bytes(const dd_solver* s) { return s ? s->bytes : 0; }
+
+extern "C" dd_status dd_solver_bind(dd_solver* s, const fdfd_op* const* ops) {
+  if (!s || !ops) { dd_set_error("dd_solver_bind: NULL argument"); return DD_EINVAL; }
+  for (int p = 0; p < s->nb; ++p) {
+    if (!ops[p] || ops[p]->nx != s->hdesc[p].nx || ops[p]->ny != s->hdesc[p].ny) {
+      dd_set_error("dd_solver_bind: operator %d missing or of a different grid size", p);
+      return DD_EINVAL;
+    }
+  }
+  for (int p = 0; p < s->nb; ++p) {
+    s->ops[p] = ops[p];
+    fill_desc_op(s->hdesc[p], ops[p]);
+    s->hdesc[p].k = 0;
+    s->ksetup[p] = 0;
+  }
+  s->has_subspace = false;
+  DD_HIP_CHECK(hipMemcpy(s->ddesc, s->hdesc.data(), sizeof(ProbDesc) * s->nb, hipMemcpyHostToDevice));
+  return DD_OK;
+}
+
+template <typename T>
+static void launch_setup(dd_solver* s, hipStream_t st) {
+  const int nb = s->nb, K = s->o.kmax;
+  PlanDev& P = s->P;
+  int maxD = 0;
+  for (auto& d : s->hdesc) maxD = std::max(maxD, d.Dp);
+  const int gx = std::min(64, (maxD + DD_BLOCK - 1) / DD_BLOCK);
+  k_copy_pad<T><<<dim3(gx, K, nb), DD_BLOCK, 0, st>>>(P, s->dU);
+  k_stencil_multi<T><<<dim3(gx, K, nb), DD_BLOCK, 0, st>>>(P);
+  for (int pass = 0; pass < 2; ++pass) {
+    k_gram<T><<<dim3(P.GB, nb), DD_BLOCK, 0, st>>>(P);
+    k_chol<<<nb, DD_BLOCK, 0, st>>>(P, pass);
+    k_combine_multi<T><<<dim3(gx, nb), DD_BLOCK, 0, st>>>(P);
+  }
+}
+
+extern "C" dd_status dd_solver_set_subspace(dd_solver* s, const void* const* U, const int* k,
+                                            hipStream_t stream) {
+  if (!s) { dd_set_error("dd_solver_set_subspace: NULL solver"); return DD_EINVAL; }
+  std::vector<const void*> hU(s->nb, nullptr);
+  bool any = false;
+  for (int p = 0; p < s->nb; ++p) {
+    int kp = (U && k) ? k[p] : 0;
+    if (kp < 0 || kp > s->o.kmax) {
+      dd_set_error("dd_solver_set_subspace: k[%d] = %d outside 0..kmax = %d", p, kp, s->o.kmax);
+      return DD_EINVAL;
+    }
+    if (kp > 0 && !U[p]) {
+      dd_set_error("dd_solver_set_subspace: U[%d] is NULL with k = %d", p, kp);
+      return DD_EINVAL;
+    }
+    s->hdesc[p].k = kp;
+    s->ksetup[p] = kp;
+    hU[p] = kp > 0 ? U[p] : nullptr;
+    any = any || kp > 0;
+  }
+  DD_HIP_CHECK(hipMemcpyAsync(s->ddesc, s->hdesc.data(), sizeof(ProbDesc) * s->nb,
+                              hipMemcpyHostToDevice, stream));
+  DD_HIP_CHECK(hipMemcpyAsync(s->dU, hU.data(), sizeof(void*) * s->nb, hipMemcpyHostToDevice,
+                              stream));
+  DD_HIP_CHECK(hipMemsetAsync(s->P.bad, 0, sizeof(unsigned long long) * s->nb, stream));
+  DD_HIP_CHECK(hipMemsetAsync(s->P.keep, 0, sizeof(unsigned long long) * s->nb, stream));
+  if (any) {
+    if (s->o.inner == DD_C64) launch_setup<float>(s, stream);
+    else launch_setup<double>(s, stream);
+    DD_HIP_CHECK(hipGetLastError());
+  }
+  // the host arrays above are pageable: finish the copies before they go away
+  DD_HIP_CHECK(hipStreamSynchronize(stream));
+  s->has_subspace = any;
+  return DD_OK;
+}
+
+template <typename T, int R>
+static void launch_step(dd_solver* s, int j, hipStream_t st) {
+  const int g = s->nchunks;
+  k_matvec_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j);
+  if (s->o.cgs_passes == 2) k_update_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI);
+  k_update_norm<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, s->o.cgs_passes == 2);
+}
+
+template <typename T, int R>
+static void launch_start(dd_solver* s, hipStream_t st) {
+  const int g = s->nchunks;
+  k_start_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P);
+  if (s->o.cgs_passes == 2) k_update_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START);
+  k_update_norm<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START, s->o.cgs_passes == 2);
+}
+
+template <typename T, int R>
+static dd_status run_cycles(dd_solver* s, hipStream_t st) {
+  const int nb = s->nb, m = s->o.restart, g = s->nchunks;
+  const size_t stbytes = sizeof(int) * nb * ST_NI;
+  int* snap[2] = {s->pinned, s->pinned + nb * ST_NI};
+  bool first = true;
+  for (;;) {
+    k_residual<R><<<g, DD_BLOCK, 0, st>>>(s->P, first ? 1 : 0);
+    first = false;
+    DD_HIP_CHECK(hipGetLastError());
+    DD_HIP_CHECK(hipMemcpyAsync(snap[0], s->P.stI, stbytes, hipMemcpyDeviceToHost, st));
+    DD_HIP_CHECK(hipStreamSynchronize(st));
+    int active = 0;
+    for (int p = 0; p < nb; ++p) active += snap[0][p * ST_NI + ST_ACTIVE];
+    if (active == 0) break;
+    launch_start<T, R>(s, st);
+    int pending = -1, grp = 0;
+    for (int j = 0; j < m; ++j) {
+      launch_step<T, R>(s, j, st);
+      if ((j + 1) % s->o.check_every == 0 && j + 1 < m) {
+        const int slot = (grp++) & 1;
+        DD_HIP_CHECK(hipMemcpyAsync(snap[slot], s->P.stI, stbytes, hipMemcpyDeviceToHost, st));
+        DD_HIP_CHECK(hipEventRecord(s->ev[slot], st));
+        if (pending >= 0) {
+          DD_HIP_CHECK(hipEventSynchronize(s->ev[pending]));
+          int act = 0;
+          for (int p = 0; p < nb; ++p) act += snap[pending][p * ST_NI + ST_ACTIVE];
+          if (act == 0) break;
+        }
+        pending = slot;
+      }
+    }
+    k_combine<T, R><<<g, DD_BLOCK, 0, st>>>(s->P);
+    DD_HIP_CHECK(hipGetLastError());
+  }
+  return DD_OK;
+}
+
+template <typename T>
+static dd_status run_cycles_T(dd_solver* s, hipStream_t st) {
+  switch (s->R) {
+    case 1: return run_cycles<T, 1>(s, st);
+    case 2: return run_cycles<T, 2>(s, st);
+    case 4: return run_cycles<T, 4>(s, st);
+    default: return run_cycles<T, 8>(s, st);
+  }
+}
+
+extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const void* const* x0,
+                                     double tol, int maxit, void* const* x, dd_info* info,
+                                     hipStream_t stream) {
+  if (!s || !b || !x) { dd_set_error("dd_solver_solve: NULL argument"); return DD_EINVAL; }
+  if (!(tol >= 0.0) || maxit < 0) {
+    dd_set_error("dd_solver_solve: need tol >= 0 and maxit >= 0");
+    return DD_EINVAL;
+  }
+  const int nb = s->nb;
+  for (int p = 0; p < nb; ++p) {
+    if (!b[p] || !x[p]) { dd_set_error("dd_solver_solve: b[%d] or x[%d] is NULL", p, p); return DD_EINVAL; }
+    s->hdesc[p].b = (const double2*)b[p];
+    s->hdesc[p].x = (double2*)x[p];
+  }
+  DD_HIP_CHECK(hipMemcpyAsync(s->ddesc, s->hdesc.data(), sizeof(ProbDesc) * nb,
+                              hipMemcpyHostToDevice, stream));
+  for (int p = 0; p < nb; ++p) {
+    const size_t bytes = sizeof(double2) * s->hdesc[p].D;
+    const void* x0p = x0 ? x0[p] : nullptr;
+    if (x0p) {
+      if (x0p != x[p]) DD_HIP_CHECK(hipMemcpyAsync(x[p], x0p, bytes, hipMemcpyDeviceToDevice, stream));
+    } else {
+      DD_HIP_CHECK(hipMemsetAsync(x[p], 0, bytes, stream));
+    }
+  }
+  s->P.tol = tol;
+  s->P.maxit = maxit;
+  k_init_state<<<(nb + 255) / 256, 256, 0, stream>>>(s->P);
+  DD_HIP_CHECK(hipGetLastError());
+  dd_status rc = (s->o.inner == DD_C64) ? run_cycles_T<float>(s, stream) : run_cycles_T<double>(s, stream);
+  if (rc != DD_OK) return rc;
+  int* fin = s->pinned + 2 * nb * ST_NI;
+  DD_HIP_CHECK(hipMemcpyAsync(fin, s->P.stI, sizeof(int) * nb * ST_NI, hipMemcpyDeviceToHost, stream));
+  DD_HIP_CHECK(hipMemcpyAsync(s->pinnedD, s->P.stD, sizeof(double) * nb * SD_ND, hipMemcpyDeviceToHost, stream));
+  DD_HIP_CHECK(hipMemcpyAsync(s->pinnedK, s->P.keep, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, stream));
+  DD_HIP_CHECK(hipStreamSynchronize(stream));
+  dd_status out = DD_OK;
+  for (int p = 0; p < nb; ++p) {
+    const int* st = fin + p * ST_NI;
+    const double* sd = s->pinnedD + p * SD_ND;
+    if (st[ST_FLAGS] & FLAG_ZERO_B)
+      DD_HIP_CHECK(hipMemsetAsync(x[p], 0, sizeof(double2) * s->hdesc[p].D, stream));
+    int kused = 0;
+    if (s->has_subspace && s->ksetup[p] > 0) kused = __builtin_popcountll(s->pinnedK[p]);
+    if (info) {
+      dd_info& I = info[p];
+      I.status = (st[ST_DONE] == DONE_CONVERGED) ? DD_OK : DD_NOT_CONVERGED;
+      I.iters = st[ST_ITERS];
+      I.restarts = st[ST_CYCLES];
+      I.k_used = kused;
+      I.fallback_plain = (s->ksetup[p] > 0 && kused == 0) ? 1 : 0;
+      I.matvecs = (s->has_subspace ? s->ksetup[p] : 0) + st[ST_ITERS] + st[ST_CYCLES] + 1;
+      I.rel_res_true = sd[SD_TRUE];
+      I.rel_res_est = sd[SD_EST];
+    }
+    if (st[ST_DONE] == DONE_NONFINITE) {
+      if (out == DD_OK || out == DD_NOT_CONVERGED) out = DD_ENONFINITE;
+    } else if (st[ST_DONE] != DONE_CONVERGED && out == DD_OK) {
+      out = DD_NOT_CONVERGED;
+    }
+  }
+  DD_HIP_CHECK(hipStreamSynchronize(stream));
+  if (out == DD_ENONFINITE) dd_set_error("dd_solver_solve: non-finite right-hand side or residual");
+  else if (out == DD_NOT_CONVERGED) dd_set_error("dd_solver_solve: iteration budget spent");
+  return out;
+}
+
+extern "C" dd_status dd_solver_history(const dd_solver* s, int p, double* out, int cap, int* n) {
+  if (!s || p < 0 || p >= s->nb || (!out && cap > 0)) {
+    dd_set_error("dd_solver_history: bad argument");
+    return DD_EINVAL;
+  }
+  int it = 0;
+  DD_HIP_CHECK(hipMemcpy(&it, s->P.stI + p * ST_NI + ST_ITERS, sizeof(int), hipMemcpyDeviceToHost));
+  const int cnt = std::min(std::min(it, s->o.hist_cap), cap);
+  if (cnt > 0)
+    DD_HIP_CHECK(hipMemcpy(out, s->P.hist + (size_t)p * s->o.hist_cap, sizeof(double) * cnt,
+                           hipMemcpyDeviceToHost));
+  if (n) *n = cnt;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_solver_debug_copy(const dd_solver* s, int p, int what, void* host_out,
+                                          size_t bytes) {
+  if (!s || p < 0 || p >= s->nb || !host_out) {
+    dd_set_error("dd_solver_debug_copy: bad argument");
+    return DD_EINVAL;
+  }
+  DD_HIP_CHECK(hipDeviceSynchronize());
+  const ProbDesc& d = s->hdesc[p];
+  const size_t ib = inner_bytes(s->o.inner);
+  const int K = s->o.kmax, m = s->o.restart, k = d.k;
+  char* dst = (char*)host_out;
+  if (what == 0 || what == 1) {
+    const int nvec = (what == 0) ? k : m + 1;
+    const int slot0 = (what == 0) ? K - k : K;
+    if (bytes != (size_t)nvec * d.D * ib) { dd_set_error("dd_solver_debug_copy: size mismatch"); return DD_EINVAL; }
+    for (int v = 0; v < nvec; ++v)
+      DD_HIP_CHECK(hipMemcpy(dst + (size_t)v * d.D * ib,
+                             (const char*)d.basis + (size_t)(slot0 + v) * d.Dp * ib, d.D * ib,
+                             hipMemcpyDeviceToHost));
+    return DD_OK;
+  }
+  if (what == 2) {
+    if (bytes != sizeof(double2) * m * (m + 1)) { dd_set_error("dd_solver_debug_copy: size mismatch"); return DD_EINVAL; }
+    DD_HIP_CHECK(hipMemcpy(dst, s->P.Hraw + (size_t)p * m * (m + 1), bytes, hipMemcpyDeviceToHost));
+    return DD_OK;
+  }
+  if (what == 3) {
+    if (bytes != sizeof(double2) * m * k) { dd_set_error("dd_solver_debug_copy: size mismatch"); return DD_EINVAL; }
+    for (int j = 0; j < m; ++j)
+      DD_HIP_CHECK(hipMemcpy(dst + sizeof(double2) * j * k, s->P.Bc + ((size_t)p * m + j) * K,
+                             sizeof(double2) * k, hipMemcpyDeviceToHost));
+    return DD_OK;
+  }
+  if (what == 4) {
+    if (bytes != sizeof(double2) * k * k) { dd_set_error("dd_solver_debug_copy: size mismatch"); return DD_EINVAL; }
+    for (int a = 0; a < k; ++a)
+      DD_HIP_CHECK(hipMemcpy(dst + sizeof(double2) * a * k, s->P.Rinv + ((size_t)p * K + a) * K,
+                             sizeof(double2) * k, hipMemcpyDeviceToHost));
+    return DD_OK;
+  }
+  dd_set_error("dd_solver_debug_copy: unknown array %d", what);
+  return DD_EINVAL;
+}
+
+extern "C" dd_status gmres_solve_batched(const fdfd_op* const* ops, int nb, const void* const* b,
+                                         const void* const* x0, const void* const* U, const int* k,
+                                         double tol, int restart, int maxit,
+                                         const dd_solver_opts* opts, void* const* x, dd_info* info,
+                                         hipStream_t stream) {
+  dd_solver_opts o;
+  dd_solver_opts_default(&o);
+  if (opts) o = *opts;
+  o.restart = restart;
+  int kmax = 0;
+  if (U && k)
+    for (int p = 0; p < nb; ++p) kmax = std::max(kmax, k[p]);
+  o.kmax = std::max(o.kmax, kmax);
+  dd_solver* s = nullptr;
+  dd_status rc = dd_solver_create(ops, nb, &o, &s);
+  if (rc != DD_OK) return rc;
+  if (kmax > 0) {
+    rc = dd_solver_set_subspace(s, U, k, stream);
+    if (rc != DD_OK) { dd_solver_destroy(s); return rc; }
+  }
+  rc = dd_solver_solve(s, b, x0, tol, maxit, x, info, stream);
+  dd_solver_destroy(s);
+  return rc;
+}
+
+extern "C" dd_status gmres_solve(const fdfd_op* op, const void* b, const void* x0, const void* U,
+                                 int k, double tol, int restart, int maxit,
+                                 const dd_solver_opts* opts, void* x, dd_info* info,
+                                 hipStream_t stream) {
+  const fdfd_op* ops[1] = {op};
+  const void* bs[1] = {b};
+  const void* x0s[1] = {x0};
+  const void* Us[1] = {U};
+  int ks[1] = {U ? k : 0};
+  void* xs[1] = {x};
+  return gmres_solve_batched(ops, 1, bs, x0 ? x0s : nullptr, U ? Us : nullptr, U ? ks : nullptr, tol,
+                             restart, maxit, opts, xs, info, stream);
+}

@@ -1,0 +1,818 @@
+// Device kernels of the batched data-driven GMRES solver.
+//
+// All field sweeps use the same decomposition: a problem's Dp padded elements
+// are cut into chunks of DD_BLOCK*R elements, one workgroup per chunk; thread t
+// of a chunk owns elements base + r*DD_BLOCK + t (r < R), so every vector access
+// is a coalesced 64-lane load and a thread always touches the same elements
+// of every basis vector (in-place updates need no synchronisation).
+// Cross-workgroup sums go through a partial-sum row per chunk; the last
+// workgroup of a problem to finish (atomic ticket) adds the rows in a fixed
+// order in FP64, so results are deterministic run to run.
+#pragma once
+
+#include "solver.h"
+
+template <typename T> struct OpP;
+template <> struct OpP<float> {
+  static __device__ __forceinline__ const float2* cf(const ProbDesc& d) { return d.cf32; }
+  static __device__ __forceinline__ const float* eps(const ProbDesc& d) { return d.eps32; }
+};
+template <> struct OpP<double> {
+  static __device__ __forceinline__ const double2* cf(const ProbDesc& d) { return d.cf64; }
+  static __device__ __forceinline__ const double* eps(const ProbDesc& d) { return d.eps64; }
+};
+
+template <typename T> __device__ __forceinline__ c2<T> to_c(double2 a) {
+  return cmk<c2<T>>((T)a.x, (T)a.y);
+}
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 dmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 ddiv(double2 a, double2 b) {
+  const double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+// ---------------------------------------------------------------------------
+// conj(B_v) . w for v < n over this thread's R elements, 16 vectors at a
+// time; block sums land in prow[2v], prow[2v+1].
+template <typename T, int R>
+__device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t Dp, int n,
+                                           const c2<T> (&w)[R], int base,
+                                           T* __restrict__ prow, T* lds) {
+  for (int v0 = 0; v0 < n; v0 += 16) {
+    T acc[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = T(0);
+#pragma unroll
+    for (int vv = 0; vv < 16; ++vv) {
+      if (v0 + vv < n) {
+        const c2<T>* bp = B + (size_t)(v0 + vv) * Dp + base + threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const c2<T> b = bp[r * DD_BLOCK];
+          acc[2 * vv] += b.x * w[r].x + b.y * w[r].y;
+          acc[2 * vv + 1] += b.x * w[r].y - b.y * w[r].x;
+        }
+      }
+    }
+    block_sum32<T>(acc, lds, prow + 2 * v0);
+  }
+}
+
+// Cross-workgroup sums in two levels with tickets.  Chunks of a problem are
+// grouped by DD_GROUP; the last workgroup of a group to arrive adds the
+// group's partial rows (all loads independent, so they are in flight
+// together) into an FP64 group row; the last group to finish adds the group
+// rows.  Returns true in that final workgroup, which then holds in
+// red[0..nvals) the FP64 sums over all of p's chunks.  The order of every
+// addition is fixed, so results are deterministic run to run.  Tickets are
+// reset by the workgroup that consumed them.
+#define DD_GROUP 32
+template <typename PT>
+__device__ bool last_block(const PlanDev& P, int p, int blk0, int nblk, int nvals,
+                           double* red) {
+  __shared__ int am_last;
+  const int chunk = blockIdx.x;
+  const int lc = chunk - blk0;
+  const int gs = (lc / DD_GROUP) * DD_GROUP;
+  const int ge = min(nblk, gs + DD_GROUP);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&P.gcount[blk0 + gs], 1);
+    am_last = (prev == ge - gs - 1);
+  }
+  __syncthreads();
+  if (!am_last) return false;
+  __threadfence();
+  {
+    const PT* part = (const PT*)P.partial + (size_t)(blk0 + gs) * P.NV;
+    double* grow = P.gsum + (size_t)(blk0 + gs) * P.NV;
+    const int cnt = ge - gs;
+    for (int v = threadIdx.x; v < nvals; v += DD_BLOCK) {
+      double a[DD_GROUP];
+#pragma unroll
+      for (int c = 0; c < DD_GROUP; ++c) a[c] = (c < cnt) ? (double)part[(size_t)c * P.NV + v] : 0.0;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < DD_GROUP; ++c) s += a[c];
+      grow[v] = s;
+    }
+  }
+  if (threadIdx.x == 0) P.gcount[blk0 + gs] = 0;
+  const int ngroups = (nblk + DD_GROUP - 1) / DD_GROUP;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&P.counter[p], 1);
+    am_last = (prev == ngroups - 1);
+  }
+  __syncthreads();
+  if (!am_last) return false;
+  __threadfence();
+  for (int v = threadIdx.x; v < nvals; v += DD_BLOCK) {
+    double s = 0.0;
+    int g = 0;
+    for (; g + 8 <= ngroups; g += 8) {
+      double a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = P.gsum[(size_t)(blk0 + (g + q) * DD_GROUP) * P.NV + v];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += a[q];
+    }
+    for (; g < ngroups; ++g) s += P.gsum[(size_t)(blk0 + g * DD_GROUP) * P.NV + v];
+    red[v] = s;
+  }
+  if (threadIdx.x == 0) P.counter[p] = 0;
+  __syncthreads();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Cycle end (supplement, eq:final_lsq and the decoupling it admits): with
+// q_1 = r~/||r~|| and Q orthogonal to C, the block least-squares problem
+// splits into the ordinary GMRES problem min ||beta e1 - H y|| (solved by the
+// Givens-rotated triangle) and x_aug = C^H r - B y; the update is
+// delta = V R^{-1} x_aug + Q y.  Writes the combine coefficients [z; y].
+__device__ void finish_cycle(const PlanDev& P, int p, int k, int n) {
+  __shared__ double2 yv[DD_MAX_M];
+  __shared__ double2 gl[DD_MAX_M + 1];
+  __shared__ double2 xa[DD_MAX_K];
+  const int t = threadIdx.x;
+  const int m = P.m;
+  const double2* H = P.H + (size_t)p * m * (m + 1);
+  for (int i = t; i < n; i += DD_BLOCK) gl[i] = P.g[(size_t)p * (m + 1) + i];
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    if (t == 0) yv[i] = ddiv(gl[i], H[(size_t)i * (m + 1) + i]);
+    __syncthreads();
+    const double2 yi = yv[i];
+    for (int l = t; l < i; l += DD_BLOCK) gl[l] = dsub(gl[l], dmul(H[(size_t)i * (m + 1) + l], yi));
+    __syncthreads();
+  }
+  if (t < k) {
+    double2 s = P.c0[(size_t)p * P.kmax + t];
+    const double2* Bc = P.Bc + (size_t)p * m * P.kmax;
+    for (int i = 0; i < n; ++i) s = dsub(s, dmul(Bc[(size_t)i * P.kmax + t], yv[i]));
+    xa[t] = s;
+  }
+  __syncthreads();
+  double2* comb = P.comb + (size_t)p * (P.kmax + m);
+  if (t < k) {
+    const double2* Ri = P.Rinv + (size_t)p * P.kmax * P.kmax;
+    double2 z = make_double2(0.0, 0.0);
+    for (int b = 0; b < k; ++b) z = dadd(z, dmul(Ri[(size_t)t * P.kmax + b], xa[b]));
+    comb[t] = z;
+  }
+  for (int i = t; i < n; i += DD_BLOCK) comb[k + i] = yv[i];
+  if (t == 0) {
+    int* st = P.stI + p * ST_NI;
+    st[ST_NCOMB] = n;
+    st[ST_PENDING] = 1;
+    st[ST_ACTIVE] = 0;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_init_state(PlanDev P) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P.nb) return;
+  for (int i = 0; i < ST_NI; ++i) P.stI[p * ST_NI + i] = 0;
+  for (int i = 0; i < SD_ND; ++i) P.stD[p * SD_ND + i] = 0.0;
+  P.counter[p] = 0;
+}
+
+// r = b - A x in FP64 with ||r||^2 and ||b||^2; the last workgroup decides
+// whether the problem has converged (||r|| <= tol ||b||), spent its budget,
+// or starts a new cycle.
+template <int R>
+__global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P, int first) {
+  const int chunk = blockIdx.x;
+  const int p = P.blk2prob[chunk];
+  int* st = P.stI + p * ST_NI;
+  if (st[ST_DONE] != DONE_RUNNING) return;
+  const ProbDesc d = P.desc[p];
+  const int base = (chunk - d.blk0) * DD_BLOCK * R;
+  double sr = 0.0, sb = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = base + r * DD_BLOCK + threadIdx.x;
+    double2 rr = make_double2(0.0, 0.0);
+    if (e < d.D) {
+      const double2 y = stencil_point<double, double>(d.x, e, d.nx, d.ny, d.cf64, d.eps64, d.omega2);
+      const double2 bb = d.b[e];
+      rr = dsub(bb, y);
+      sb += bb.x * bb.x + bb.y * bb.y;
+    }
+    d.r[e] = rr;
+    sr += rr.x * rr.x + rr.y * rr.y;
+  }
+  __shared__ double lds[8];
+  __shared__ double red[2];
+  const double tr = block_sum1<double>(sr, lds);
+  const double tb = block_sum1<double>(sb, lds);
+  double* prow = (double*)P.partial + (size_t)chunk * P.NV;
+  if (threadIdx.x == 0) { prow[0] = tr; prow[1] = tb; }
+  if (!last_block<double>(P, p, d.blk0, d.nblk, 2, red)) return;
+  if (threadIdx.x == 0) {
+    double* sd = P.stD + p * SD_ND;
+    const double rho = sqrt(red[0]);
+    if (first) sd[SD_BNORM] = sqrt(red[1]);
+    const double bn = sd[SD_BNORM];
+    sd[SD_RHO] = rho;
+    st[ST_PENDING] = 0;
+    st[ST_ACTIVE] = 0;
+    if (!isfinite(bn) || !isfinite(rho)) {
+      st[ST_DONE] = DONE_NONFINITE;
+      sd[SD_TRUE] = rho / bn;
+    } else if (bn == 0.0) {
+      st[ST_DONE] = DONE_CONVERGED;
+      st[ST_FLAGS] |= FLAG_ZERO_B;
+      sd[SD_TRUE] = 0.0;
+    } else {
+      sd[SD_TRUE] = rho / bn;
+      if (rho <= P.tol * bn) {
+        st[ST_DONE] = DONE_CONVERGED;
+      } else if (st[ST_ITERS] >= P.maxit) {
+        st[ST_DONE] = DONE_BUDGET;
+      } else {
+        st[ST_ACTIVE] = 1;
+        st[ST_CYCLES] += 1;
+        st[ST_J] = 0;
+      }
+    }
+  }
+}
+
+// Projected start, first pass: Q_0 = r / rho in the inner precision and the
+// dots C^H Q_0 (supplement: q_1 = b~/||b~||, b~ = P b, applied to the
+// cycle's residual).
+template <typename T, int R>
+__global__ __launch_bounds__(DD_BLOCK) void k_start_dot(PlanDev P) {
+  const int chunk = blockIdx.x;
+  const int p = P.blk2prob[chunk];
+  if (P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int base = (chunk - d.blk0) * DD_BLOCK * R;
+  const size_t Dp = d.Dp;
+  c2<T>* B = (c2<T>*)d.basis + (size_t)(P.kmax - d.k) * Dp;
+  const int n = d.k;
+  c2<T>* q0 = B + (size_t)n * Dp;
+  const double inv = 1.0 / P.stD[p * SD_ND + SD_RHO];
+  c2<T> wv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = base + r * DD_BLOCK + threadIdx.x;
+    const double2 rr = d.r[e];
+    wv[r] = cmk<c2<T>>((T)(rr.x * inv), (T)(rr.y * inv));
+    q0[e] = wv[r];
+  }
+  if (n == 0) return;
+  __shared__ T lds[128];
+  __shared__ double red[DD_NV_MAX];
+  T* prow = (T*)P.partial + (size_t)chunk * P.NV;
+  block_dots<T, R>(B, Dp, n, wv, base, prow, lds);
+  if (!last_block<T>(P, p, d.blk0, d.nblk, 2 * n, red)) return;
+  double2* cA = P.coefA + (size_t)p * P.NC;
+  for (int v = threadIdx.x; v < n; v += DD_BLOCK) cA[v] = make_double2(red[2 * v], red[2 * v + 1]);
+}
+
+// Arnoldi step j, first kernel: w = A q_j (q_j stored unnormalised, scaled on
+// the fly by hscale[j]) written to slot Q_{j+1}, and the dots [C Q_0..Q_j]^H w.
+template <typename T, int R>
+__global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
+  const int chunk = blockIdx.x;
+  const int p = P.blk2prob[chunk];
+  if (P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int base = (chunk - d.blk0) * DD_BLOCK * R;
+  const size_t Dp = d.Dp;
+  c2<T>* B = (c2<T>*)d.basis + (size_t)(P.kmax - d.k) * Dp;
+  const int n = d.k + j + 1;
+  const c2<T>* q = B + (size_t)(n - 1) * Dp;
+  c2<T>* w = B + (size_t)n * Dp;
+  const double hs = P.hscale[(size_t)p * (P.m + 1) + j];
+  c2<T> wv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = base + r * DD_BLOCK + threadIdx.x;
+    c2<T> y = cmk<c2<T>>(T(0), T(0));
+    if (e < d.D)
+      y = cscale(stencil_point<T>(q, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d), (T)d.omega2),
+                 (T)hs);
+    wv[r] = y;
+    w[e] = y;
+  }
+  __shared__ T lds[128];
+  __shared__ double red[DD_NV_MAX];
+  T* prow = (T*)P.partial + (size_t)chunk * P.NV;
+  block_dots<T, R>(B, Dp, n, wv, base, prow, lds);
+  if (!last_block<T>(P, p, d.blk0, d.nblk, 2 * n, red)) return;
+  double2* cA = P.coefA + (size_t)p * P.NC;
+  for (int v = threadIdx.x; v < n; v += DD_BLOCK) {
+    const double s = (v == n - 1) ? hs : 1.0;
+    cA[v] = make_double2(red[2 * v] * s, red[2 * v + 1] * s);
+  }
+}
+
+// w -= [C Q] coef over this thread's elements.  Slot nv (the deferred-
+// normalisation vector q_j) is scaled by hs on the way and written back
+// normalised.
+template <typename T, int R>
+__device__ __forceinline__ void block_update(c2<T>* __restrict__ B, size_t Dp, int n,
+                                             const c2<T>* coef, c2<T> (&wv)[R], int base,
+                                             int nv, T hs) {
+  for (int v = 0; v < n; ++v) {
+    c2<T>* bp = B + (size_t)v * Dp + base + threadIdx.x;
+    const c2<T> cv = coef[v];
+    if (v == nv) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const c2<T> b = cscale(bp[r * DD_BLOCK], hs);
+        bp[r * DD_BLOCK] = b;
+        wv[r] = cfnms(wv[r], cv, b);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) wv[r] = cfnms(wv[r], cv, bp[r * DD_BLOCK]);
+    }
+  }
+}
+
+// CGS2 middle kernel: first update with coefA, then the second-pass dots.
+template <typename T, int R>
+__global__ __launch_bounds__(DD_BLOCK) void k_update_dot(PlanDev P, int j, int mode) {
+  const int chunk = blockIdx.x;
+  const int p = P.blk2prob[chunk];
+  if (P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int n = (mode == MODE_START) ? d.k : d.k + j + 1;
+  if (n == 0) return;
+  const int base = (chunk - d.blk0) * DD_BLOCK * R;
+  const size_t Dp = d.Dp;
+  c2<T>* B = (c2<T>*)d.basis + (size_t)(P.kmax - d.k) * Dp;
+  c2<T>* w = B + (size_t)n * Dp;
+  const int nv = (mode == MODE_ARNOLDI) ? n - 1 : -1;
+  const T hs = (mode == MODE_ARNOLDI) ? (T)P.hscale[(size_t)p * (P.m + 1) + j] : T(1);
+  __shared__ c2<T> coef[DD_MAX_K + DD_MAX_M + 1];
+  const double2* cA = P.coefA + (size_t)p * P.NC;
+  for (int v = threadIdx.x; v < n; v += DD_BLOCK) coef[v] = to_c<T>(cA[v]);
+  __syncthreads();
+  c2<T> wv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) wv[r] = w[base + r * DD_BLOCK + threadIdx.x];
+  block_update<T, R>(B, Dp, n, coef, wv, base, nv, hs);
+#pragma unroll
+  for (int r = 0; r < R; ++r) w[base + r * DD_BLOCK + threadIdx.x] = wv[r];
+  __shared__ T lds[128];
+  __shared__ double red[DD_NV_MAX];
+  T* prow = (T*)P.partial + (size_t)chunk * P.NV;
+  block_dots<T, R>(B, Dp, n, wv, base, prow, lds);
+  if (!last_block<T>(P, p, d.blk0, d.nblk, 2 * n, red)) return;
+  double2* cB = P.coefB + (size_t)p * P.NC;
+  for (int v = threadIdx.x; v < n; v += DD_BLOCK) cB[v] = make_double2(red[2 * v], red[2 * v + 1]);
+}
+
+// Final update of a Gram-Schmidt step and ||w||^2; the last workgroup runs
+// the FP64 bookkeeping: in the start phase beta, c0 = C^H r; in an Arnoldi
+// step the new Hessenberg column, B column, Givens rotation and residual
+// estimate, and (at the cycle's end) the least-squares solve.
+template <typename T, int R>
+__global__ __launch_bounds__(DD_BLOCK) void k_update_norm(PlanDev P, int j, int mode,
+                                                          int cgs2) {
+  const int chunk = blockIdx.x;
+  const int p = P.blk2prob[chunk];
+  int* st = P.stI + p * ST_NI;
+  if (st[ST_ACTIVE] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int k = d.k;
+  const int n = (mode == MODE_START) ? k : k + j + 1;
+  const int base = (chunk - d.blk0) * DD_BLOCK * R;
+  const size_t Dp = d.Dp;
+  const int m = P.m;
+  c2<T>* B = (c2<T>*)d.basis + (size_t)(P.kmax - k) * Dp;
+  c2<T>* w = B + (size_t)n * Dp;
+  const int nv = (!cgs2 && mode == MODE_ARNOLDI) ? n - 1 : -1;
+  const T hs = (nv >= 0) ? (T)P.hscale[(size_t)p * (m + 1) + j] : T(1);
+  __shared__ c2<T> coef[DD_MAX_K + DD_MAX_M + 1];
+  const double2* cS = (cgs2 ? P.coefB : P.coefA) + (size_t)p * P.NC;
+  for (int v = threadIdx.x; v < n; v += DD_BLOCK) coef[v] = to_c<T>(cS[v]);
+  __syncthreads();
+  c2<T> wv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) wv[r] = w[base + r * DD_BLOCK + threadIdx.x];
+  block_update<T, R>(B, Dp, n, coef, wv, base, nv, hs);
+  T s2 = T(0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    w[base + r * DD_BLOCK + threadIdx.x] = wv[r];
+    s2 += wv[r].x * wv[r].x + wv[r].y * wv[r].y;
+  }
+  __shared__ T lds[8];
+  __shared__ double red[1];
+  const T tot = block_sum1<T>(s2, lds);
+  T* prow = (T*)P.partial + (size_t)chunk * P.NV;
+  if (threadIdx.x == 0) prow[0] = tot;
+  if (!last_block<T>(P, p, d.blk0, d.nblk, 1, red)) return;
+
+  // ---------------- FP64 bookkeeping, last workgroup of problem p ----------
+  __shared__ double2 col[DD_MAX_K + DD_MAX_M + 2];
+  __shared__ int fin, nfin;
+  const int t = threadIdx.x;
+  const double2* cA = P.coefA + (size_t)p * P.NC;
+  const double2* cB = P.coefB + (size_t)p * P.NC;
+  for (int v = t; v < n; v += DD_BLOCK) col[v] = cgs2 ? dadd(cA[v], cB[v]) : cA[v];
+  if (t == 0) fin = 0;
+  __syncthreads();
+  double* sd = P.stD + p * SD_ND;
+  const double nrm = sqrt(red[0]);
+  if (mode == MODE_START) {
+    const double rho = sd[SD_RHO];
+    for (int v = t; v < k; v += DD_BLOCK)
+      P.c0[(size_t)p * P.kmax + v] = make_double2(rho * col[v].x, rho * col[v].y);
+    if (t == 0) {
+      const double beta = nrm * rho;
+      sd[SD_BETA] = beta;
+      P.g[(size_t)p * (m + 1)] = make_double2(beta, 0.0);
+      P.hscale[(size_t)p * (m + 1)] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+      st[ST_J] = 0;
+      if (!(nrm > 0.0) || !isfinite(nrm)) { fin = 1; nfin = 0; }
+    }
+  } else {
+    double2* Hraw = P.Hraw + ((size_t)p * m + j) * (m + 1);
+    double2* Hc = P.H + ((size_t)p * m + j) * (m + 1);
+    double2* Bc = P.Bc + ((size_t)p * m + j) * P.kmax;
+    for (int v = t; v < k; v += DD_BLOCK) Bc[v] = col[v];
+    for (int i = t; i <= j; i += DD_BLOCK) Hraw[i] = col[k + i];
+    if (t == 0) {
+      Hraw[j + 1] = make_double2(nrm, 0.0);
+      double2* hcol = col + k;
+      const double* cs = P.cs + (size_t)p * m;
+      const double2* sn = P.sn + (size_t)p * m;
+      for (int i = 0; i < j; ++i) {
+        const double2 a = hcol[i], b = hcol[i + 1];
+        const double c = cs[i];
+        const double2 s = sn[i];
+        hcol[i] = dadd(make_double2(c * a.x, c * a.y), dmul(s, b));
+        hcol[i + 1] = dsub(make_double2(c * b.x, c * b.y), dmulc(s, a));
+      }
+      // new rotation zeroing the subdiagonal entry nrm
+      const double2 a = hcol[j];
+      const double aa = sqrt(a.x * a.x + a.y * a.y);
+      double c;
+      double2 s, rr;
+      if (aa == 0.0) {
+        c = 0.0; s = make_double2(1.0, 0.0); rr = make_double2(nrm, 0.0);
+      } else {
+        const double nu = sqrt(aa * aa + nrm * nrm);
+        const double2 al = make_double2(a.x / aa, a.y / aa);
+        c = aa / nu;
+        s = make_double2(al.x * nrm / nu, al.y * nrm / nu);
+        rr = make_double2(al.x * nu, al.y * nu);
+      }
+      hcol[j] = rr;
+      P.cs[(size_t)p * m + j] = c;
+      P.sn[(size_t)p * m + j] = s;
+      for (int i = 0; i <= j; ++i) Hc[i] = hcol[i];
+      Hc[j + 1] = make_double2(0.0, 0.0);
+      double2* g = P.g + (size_t)p * (m + 1);
+      const double2 gj = g[j];
+      g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+      g[j] = make_double2(c * gj.x, c * gj.y);
+      P.hscale[(size_t)p * (m + 1) + j + 1] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+      const int it = st[ST_ITERS] + 1;
+      st[ST_ITERS] = it;
+      st[ST_J] = j + 1;
+      const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+      const double bn = sd[SD_BNORM];
+      sd[SD_EST] = est / bn;
+      if (it <= P.hist_cap) P.hist[(size_t)p * P.hist_cap + it - 1] = est / bn;
+      if (est <= P.tol * bn || it >= P.maxit || !(nrm > 0.0) || !isfinite(nrm) || j + 1 == m) {
+        fin = 1;
+        nfin = j + 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (fin) finish_cycle(P, p, k, nfin);
+}
+
+// x += V z + Q y in FP64 for every problem whose cycle just ended.
+template <typename T, int R>
+__global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
+  const int chunk = blockIdx.x;
+  const int p = P.blk2prob[chunk];
+  const int* st = P.stI + p * ST_NI;
+  if (st[ST_PENDING] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int n = st[ST_NCOMB];
+  const int k = d.k;
+  const int base = (chunk - d.blk0) * DD_BLOCK * R;
+  const size_t Dp = d.Dp;
+  __shared__ double2 cf[DD_MAX_K + DD_MAX_M];
+  const double2* comb = P.comb + (size_t)p * (P.kmax + P.m);
+  for (int v = threadIdx.x; v < k + n; v += DD_BLOCK) cf[v] = comb[v];
+  __syncthreads();
+  const c2<T>* V = (const c2<T>*)d.V;
+  const c2<T>* Q = (const c2<T>*)d.basis + (size_t)P.kmax * Dp;
+  double2 acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = make_double2(0.0, 0.0);
+  for (int v = 0; v < k; ++v) {
+    const double2 c = cf[v];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const c2<T> b = V[(size_t)v * Dp + base + r * DD_BLOCK + threadIdx.x];
+      acc[r] = dadd(acc[r], dmul(c, make_double2((double)b.x, (double)b.y)));
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    const double2 c = cf[k + i];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const c2<T> b = Q[(size_t)i * Dp + base + r * DD_BLOCK + threadIdx.x];
+      acc[r] = dadd(acc[r], dmul(c, make_double2((double)b.x, (double)b.y)));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = base + r * DD_BLOCK + threadIdx.x;
+    if (e < d.D) d.x[e] = dadd(d.x[e], acc[r]);
+  }
+}
+
+// ============================ augmentation setup ============================
+// Copy the caller's vectors into the padded V slots; non-finite entries are
+// replaced by zero and mark their column as unusable.
+template <typename T>
+__global__ void k_copy_pad(PlanDev P, const void* const* U) {
+  const int p = blockIdx.z, v = blockIdx.y;
+  const ProbDesc d = P.desc[p];
+  if (v >= d.k) return;
+  const c2<T>* u = (const c2<T>*)U[p] + (size_t)v * d.D;
+  c2<T>* V = (c2<T>*)d.V + (size_t)v * d.Dp;
+  bool bad = false;
+  for (int e = blockIdx.x * DD_BLOCK + threadIdx.x; e < d.Dp; e += gridDim.x * DD_BLOCK) {
+    c2<T> a = cmk<c2<T>>(T(0), T(0));
+    if (e < d.D) {
+      a = u[e];
+      if (!isfinite(a.x) || !isfinite(a.y)) { bad = true; a = cmk<c2<T>>(T(0), T(0)); }
+    }
+    V[e] = a;
+  }
+  if (bad) atomicOr(&P.bad[p], 1ull << v);
+}
+
+// W_v = A V_v written into the C slots (right-aligned), all columns at once.
+template <typename T>
+__global__ void k_stencil_multi(PlanDev P) {
+  const int p = blockIdx.z, v = blockIdx.y;
+  const ProbDesc d = P.desc[p];
+  if (v >= d.k) return;
+  const c2<T>* x = (const c2<T>*)d.V + (size_t)v * d.Dp;
+  c2<T>* y = (c2<T>*)d.basis + (size_t)(P.kmax - d.k + v) * d.Dp;
+  for (int e = blockIdx.x * DD_BLOCK + threadIdx.x; e < d.Dp; e += gridDim.x * DD_BLOCK) {
+    c2<T> a = cmk<c2<T>>(T(0), T(0));
+    if (e < d.D) a = stencil_point<T>(x, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d), (T)d.omega2);
+    y[e] = a;
+  }
+}
+
+__host__ __device__ inline int gram_tiles(int k) {
+  const int t = (k + 3) / 4;
+  return t * (t + 1) / 2;
+}
+
+// Partial Gram matrices G = W^H W of the C slots, 4x4 complex tiles of the
+// upper triangle, FP64 accumulation; one row of partials per workgroup.
+template <typename T>
+__global__ __launch_bounds__(DD_BLOCK) void k_gram(PlanDev P) {
+  const int p = blockIdx.y;
+  const ProbDesc d = P.desc[p];
+  const int k = d.k;
+  if (k == 0) return;
+  const c2<T>* W = (const c2<T>*)d.basis + (size_t)(P.kmax - k) * d.Dp;
+  const int nt = (k + 3) / 4;
+  const int ntiles_max = gram_tiles(P.kmax);
+  __shared__ double lds[128];
+  int ti = 0;
+  for (int ta = 0; ta < nt; ++ta)
+    for (int tb = ta; tb < nt; ++tb, ++ti) {
+      double acc[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) acc[i] = 0.0;
+      for (int e = blockIdx.x * DD_BLOCK + threadIdx.x; e < d.D; e += gridDim.x * DD_BLOCK) {
+        double2 a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int va = ta * 4 + q, vb = tb * 4 + q;
+          const c2<T> xa = (va < k) ? W[(size_t)va * d.Dp + e] : cmk<c2<T>>(T(0), T(0));
+          const c2<T> xb = (vb < k) ? W[(size_t)vb * d.Dp + e] : cmk<c2<T>>(T(0), T(0));
+          a[q] = make_double2((double)xa.x, (double)xa.y);
+          b[q] = make_double2((double)xb.x, (double)xb.y);
+        }
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+          for (int qb = 0; qb < 4; ++qb) {
+            acc[2 * (qa * 4 + qb)] += a[qa].x * b[qb].x + a[qa].y * b[qb].y;
+            acc[2 * (qa * 4 + qb) + 1] += a[qa].x * b[qb].y - a[qa].y * b[qb].x;
+          }
+      }
+      block_sum32<double>(acc, lds,
+                          P.gpart + (((size_t)p * P.GB + blockIdx.x) * ntiles_max + ti) * 32);
+    }
+}
+
+// One workgroup per problem: reduce the Gram partials, Cholesky factor with
+// column dropping (pivot below 1e-6 of the largest column norm, or a column
+// already marked unusable), T = L^{-H} on the kept columns, R^{-1} <- R^{-1} T.
+__global__ __launch_bounds__(DD_BLOCK) void k_chol(PlanDev P, int pass) {
+  const int p = blockIdx.x;
+  const ProbDesc d = P.desc[p];
+  const int k = d.k;
+  const int t = threadIdx.x;
+  const int K = P.kmax;
+  if (k == 0) {
+    if (t == 0) P.keep[p] = 0ull;
+    return;
+  }
+  double2* G = P.Gm + (size_t)p * K * K;    // G, then L in its lower triangle
+  double2* Tm = P.Tm + (size_t)p * K * K;
+  double2* Ri = P.Rinv + (size_t)p * K * K;
+  const int nt = (k + 3) / 4;
+  const int ntiles_max = gram_tiles(K);
+  // reduce partials (fixed order over workgroups)
+  for (int idx = t; idx < gram_tiles(k) * 16; idx += DD_BLOCK) {
+    const int ti = idx >> 4, el = idx & 15;
+    int ta = 0, tb = 0, c = 0;
+    for (int a = 0; a < nt; ++a)
+      for (int b = a; b < nt; ++b, ++c)
+        if (c == ti) { ta = a; tb = b; }
+    const int qa = el >> 2, qb = el & 3;
+    const int ra = ta * 4 + qa, rb = tb * 4 + qb;
+    double sx = 0.0, sy = 0.0;
+    for (int g = 0; g < P.GB; ++g) {
+      const double* row = P.gpart + (((size_t)p * P.GB + g) * ntiles_max + ti) * 32;
+      sx += row[2 * el];
+      sy += row[2 * el + 1];
+    }
+    if (ra < k && rb < k) {
+      G[(size_t)ra * K + rb] = make_double2(sx, sy);
+      G[(size_t)rb * K + ra] = make_double2(sx, -sy);
+    }
+  }
+  __shared__ unsigned long long mask_s;
+  __shared__ double maxd_s;
+  __shared__ double2 Ljj;
+  __shared__ int drop_s;
+  if (t == 0) {
+    unsigned long long mask = (pass == 0) ? ~P.bad[p] : P.keep[p];
+    if (k < 64) mask &= (1ull << k) - 1ull;
+    double mx = 0.0;
+    for (int i = 0; i < k; ++i)
+      if ((mask >> i) & 1ull) {
+        const double gi = G[(size_t)i * K + i].x;
+        if (isfinite(gi) && gi > mx) mx = gi;
+        if (!isfinite(gi)) mask &= ~(1ull << i);
+      }
+    mask_s = mask;
+    maxd_s = sqrt(mx);
+  }
+  __syncthreads();
+  const double thr = 1e-6 * maxd_s;
+  for (int jj = 0; jj < k; ++jj) {
+    if (t == 0) {
+      drop_s = 0;
+      if (!((mask_s >> jj) & 1ull)) {
+        drop_s = 1;
+      } else {
+        double s = G[(size_t)jj * K + jj].x;
+        for (int l = 0; l < jj; ++l) {
+          const double2 v = G[(size_t)jj * K + l];
+          s -= v.x * v.x + v.y * v.y;
+        }
+        if (!(s > thr * thr) || !isfinite(s)) {
+          drop_s = 1;
+          mask_s &= ~(1ull << jj);
+        } else {
+          Ljj = make_double2(sqrt(s), 0.0);
+        }
+      }
+    }
+    __syncthreads();
+    if (drop_s) {
+      for (int i = t; i < k; i += DD_BLOCK) {
+        if (i >= jj) G[(size_t)i * K + jj] = make_double2(0.0, 0.0);   // column
+        if (i < jj) G[(size_t)jj * K + i] = make_double2(0.0, 0.0);    // row left of diag
+      }
+    } else {
+      const double ljj = Ljj.x;
+      for (int i = jj + 1 + t; i < k; i += DD_BLOCK) {
+        if (!((mask_s >> i) & 1ull)) continue;
+        double2 s = G[(size_t)i * K + jj];
+        for (int l = 0; l < jj; ++l) {
+          const double2 a = G[(size_t)i * K + l], b = G[(size_t)jj * K + l];
+          s = dsub(s, make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y));  // a conj(b)
+        }
+        G[(size_t)i * K + jj] = make_double2(s.x / ljj, s.y / ljj);
+      }
+      if (t == 0) G[(size_t)jj * K + jj] = Ljj;
+    }
+    __syncthreads();
+  }
+  // rows of dropped columns that were filled before the drop decision
+  for (int idx = t; idx < k * k; idx += DD_BLOCK) {
+    const int i = idx / k, l = idx % k;
+    if (l < i && !((mask_s >> i) & 1ull)) G[(size_t)i * K + l] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const unsigned long long mask = mask_s;
+  // T = L^{-H}: solve L^H T = I column by column (one thread per column o)
+  for (int o = t; o < k; o += DD_BLOCK) {
+    for (int a = k - 1; a >= 0; --a) {
+      double2 v = make_double2(0.0, 0.0);
+      if (((mask >> o) & 1ull) && ((mask >> a) & 1ull) && a <= o) {
+        v = make_double2(a == o ? 1.0 : 0.0, 0.0);
+        for (int l = a + 1; l <= o; ++l) {
+          if (!((mask >> l) & 1ull)) continue;
+          v = dsub(v, dmulc(G[(size_t)l * K + a], Tm[(size_t)l * K + o]));
+        }
+        const double laa = G[(size_t)a * K + a].x;
+        v = make_double2(v.x / laa, v.y / laa);
+      }
+      Tm[(size_t)a * K + o] = v;
+    }
+  }
+  __syncthreads();
+  if (pass == 0) {
+    for (int idx = t; idx < k * k; idx += DD_BLOCK) {
+      const int a = idx / k, o = idx % k;
+      Ri[(size_t)a * K + o] = Tm[(size_t)a * K + o];
+    }
+  } else {
+    // Ri <- Ri * Tm, row by row (each thread owns whole rows)
+    for (int a = t; a < k; a += DD_BLOCK) {
+      double2 rowv[DD_MAX_K];
+      for (int o = 0; o < k; ++o) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int l = 0; l < k; ++l) s = dadd(s, dmul(Ri[(size_t)a * K + l], Tm[(size_t)l * K + o]));
+        rowv[o] = s;
+      }
+      for (int o = 0; o < k; ++o) Ri[(size_t)a * K + o] = rowv[o];
+    }
+  }
+  if (t == 0) P.keep[p] = mask;
+}
+
+// C_o = sum_{i <= o} T[i][o] W_i in place over the C slots: output groups of
+// 16 are formed from the highest down, so a group only overwrites inputs
+// that no lower group needs.
+template <typename T>
+__global__ __launch_bounds__(DD_BLOCK) void k_combine_multi(PlanDev P) {
+  const int p = blockIdx.y;
+  const ProbDesc d = P.desc[p];
+  const int k = d.k;
+  if (k == 0) return;
+  const int K = P.kmax;
+  const unsigned long long mask = P.keep[p];
+  c2<T>* W = (c2<T>*)d.basis + (size_t)(K - k) * d.Dp;
+  const double2* Tm = P.Tm + (size_t)p * K * K;
+  __shared__ c2<T> Tg[DD_MAX_K * 16];
+  const int ngroups = (k + 15) / 16;
+  for (int g = ngroups - 1; g >= 0; --g) {
+    const int o0 = g * 16;
+    const int imax = min(k, o0 + 16);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < imax * 16; idx += DD_BLOCK) {
+      const int i = idx / 16, oo = idx % 16;
+      Tg[idx] = (o0 + oo < k) ? to_c<T>(Tm[(size_t)i * K + o0 + oo]) : cmk<c2<T>>(T(0), T(0));
+    }
+    __syncthreads();
+    for (int e = blockIdx.x * DD_BLOCK + threadIdx.x; e < d.Dp; e += gridDim.x * DD_BLOCK) {
+      c2<T> acc[16];
+#pragma unroll
+      for (int oo = 0; oo < 16; ++oo) acc[oo] = cmk<c2<T>>(T(0), T(0));
+      for (int i = 0; i < imax; ++i) {
+        if (!((mask >> i) & 1ull)) continue;
+        const c2<T> x = W[(size_t)i * d.Dp + e];
+#pragma unroll
+        for (int oo = 0; oo < 16; ++oo) {
+          const c2<T> c = Tg[i * 16 + oo];
+          acc[oo].x += c.x * x.x - c.y * x.y;
+          acc[oo].y += c.x * x.y + c.y * x.x;
+        }
+      }
+#pragma unroll
+      for (int oo = 0; oo < 16; ++oo)
+        if (o0 + oo < k) W[(size_t)(o0 + oo) * d.Dp + e] = acc[oo];
+    }
+  }
+}

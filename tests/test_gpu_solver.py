@@ -1,0 +1,243 @@
+"""GPU data-driven GMRES against the CPU oracle.
+
+Parity in complex128 mode: the GPU's residual history (Givens estimate / ||b||
+per Arnoldi step) against the oracle's least-squares residual history, the
+iteration counts, and the solutions.  In complex64 mode: the FP64 true residual
+recomputed by the oracle's assembled A, and the error against a sparse direct
+solve.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, fdfd, gmres, gmres_aug
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(ops, **kw):
+    from paper_1902_00090_amd import Solver
+    return Solver(ops, **kw)
+
+
+def _op(inst):
+    from paper_1902_00090_amd import FdfdOp
+    return FdfdOp.from_instance(inst)
+
+
+def _b(inst):
+    import torch
+    from gpu_util import to_dev
+    return to_dev(inst.b, torch.complex128)
+
+
+def tiny_instance(seed, nx=20, ny=16, npml=3):
+    rng = np.random.default_rng(seed)
+    eps = (2.085 + 10.165 * (rng.random((ny, nx)) < 0.4)).astype(np.float32)
+    inst = W.Instance(eps, W.random_complex(rng, nx * ny), nx, ny, 0.04, 1.55, npml,
+                      name=f"tiny{seed}")
+    return inst
+
+
+def test_small_binary_plain_c128_matches_oracle():
+    """64x64 binary problem, GMRES(50), complex128, tol 1e-8."""
+    inst = W.small_binary()
+    A = fdfd.assemble_instance(inst)
+    xo, io = gmres.gmres(A, inst.b, restart=50, tol=1e-8, maxit=20000)
+    s = _solver([_op(inst)], restart=50, inner="c128", hist_cap=20000)
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-8, maxit=20000)
+    x = x.cpu().numpy()
+    h = s.history(0)
+    assert st == 0 and info["status"] == 0
+    assert abs(info["iters"] - io["iters"]) <= 2, (info["iters"], io["iters"])
+    ho = np.array(io["history"])
+    n = min(len(h), len(ho), 400)
+    np.testing.assert_allclose(h[:n], ho[:n], rtol=1e-7)
+    assert np.linalg.norm(inst.b - A @ x) / np.linalg.norm(inst.b) <= 1e-8
+    assert info["rel_res_true"] <= 1e-8
+    xs = direct.sparse_solve(A, inst.b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-6
+
+
+@pytest.mark.parametrize("k", [0, 1, 4, 7])
+@pytest.mark.parametrize("restart", [200, 9])
+def test_tiny_augmented_history_c128(k, restart):
+    """Augmented GMRES on a 20x16 grid vs the oracle's literal block least squares."""
+    import torch
+    from gpu_util import to_dev
+    inst = tiny_instance(11 + k)
+    A = fdfd.assemble_instance(inst)
+    rng = np.random.default_rng(100 + k)
+    V = W.random_complex(rng, (inst.D, k))
+    xo, io = gmres_aug.gmres_aug(A, inst.b, V, restart=restart, tol=1e-10, maxit=6000)
+    s = _solver([_op(inst)], restart=restart, kmax=max(k, 1), inner="c128", hist_cap=6000)
+    if k:
+        s.set_subspace([to_dev(V.T, torch.complex128)])
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-10, maxit=6000)
+    assert st == 0
+    h = s.history(0)
+    ho = np.array(io["history"])
+    assert info["k_used"] == k
+    if restart >= 200:
+        # one cycle: the histories are the same sequence of minimisations
+        assert info["iters"] == io["iters"]
+        assert info["matvecs"] == io["matvecs"]
+        np.testing.assert_allclose(h, ho, rtol=1e-6, atol=1e-13)
+    else:
+        # ~200 restarts of GMRES(9) amplify rounding: the oracle itself, fed a
+        # right-hand side perturbed by 1e-15, moves its history by up to 9%
+        # (relative) after ~700 steps and its iteration count by 2.  So the
+        # first 300 steps are compared tightly and the end state loosely.
+        np.testing.assert_allclose(h[:300], ho[:300], rtol=1e-6, atol=1e-13)
+        assert abs(info["iters"] - io["iters"]) <= 0.02 * io["iters"]
+    x = x.cpu().numpy()
+    assert np.linalg.norm(inst.b - A @ x) / np.linalg.norm(inst.b) <= 1e-10
+    np.testing.assert_allclose(x, xo, rtol=0, atol=1e-7 * np.abs(xo).max())
+
+
+def test_augmented_invariants_c128():
+    """C orthonormal, C^H Q = 0, [C Q] orthonormal and A Q_i = Q_{i+1} H + C B
+    (supplement eq:arnoldi_matrix) on the GPU's own arrays."""
+    import torch
+    from gpu_util import to_dev
+    inst = tiny_instance(3)
+    A = fdfd.assemble_instance(inst)
+    k, m = 5, 30
+    V = W.random_complex(np.random.default_rng(7), (inst.D, k))
+    s = _solver([_op(inst)], restart=m, kmax=k, inner="c128")
+    s.set_subspace([to_dev(V.T, torch.complex128)])
+    s.solve([_b(inst)], tol=1e-30, maxit=m)
+    Cm = s.debug(0, "C").T
+    Q = s.debug(0, "Q").T
+    H = s.debug(0, "H").T          # (m+1) x m
+    B = s.debug(0, "B").T          # k x m
+    Rinv = s.debug(0, "Rinv")
+    # the last Krylov slot holds the new vector before its (deferred)
+    # normalisation; its norm is the last subdiagonal entry of H
+    np.testing.assert_allclose(np.linalg.norm(Q[:, m]), abs(H[m, m - 1]), rtol=1e-12)
+    Q[:, m] /= H[m, m - 1]
+    np.testing.assert_allclose(Cm.conj().T @ Cm, np.eye(k), atol=1e-12)
+    CQ = np.concatenate([Cm, Q], axis=1)
+    np.testing.assert_allclose(CQ.conj().T @ CQ, np.eye(k + m + 1), atol=1e-10)
+    AQ = A @ Q[:, :m]
+    np.testing.assert_allclose(AQ, Q @ H + Cm @ B, atol=1e-9 * np.abs(AQ).max())
+    # A V R^{-1} = C
+    np.testing.assert_allclose(A @ V @ Rinv, Cm, atol=1e-9)
+
+
+def test_subspace_invariance_and_plain_reduction():
+    """Iterates depend only on span(V); N = 0 is plain GMRES."""
+    import torch
+    from gpu_util import to_dev
+    inst = tiny_instance(5, nx=24, ny=20)
+    rng = np.random.default_rng(9)
+    V = W.random_complex(rng, (inst.D, 4))
+    M = W.random_complex(rng, (4, 4)) + 4 * np.eye(4)
+    hs = []
+    for VV in (V, V @ M):
+        s = _solver([_op(inst)], restart=40, kmax=4, inner="c128", hist_cap=500)
+        s.set_subspace([to_dev(VV.T, torch.complex128)])
+        _, (info,), _ = s.solve([_b(inst)], tol=1e-9, maxit=500)
+        hs.append(s.history(0))
+    n = min(len(hs[0]), len(hs[1]), 200)
+    np.testing.assert_allclose(hs[0][:n], hs[1][:n], rtol=1e-6, atol=1e-13)
+    # no subspace == plain oracle GMRES
+    A = fdfd.assemble_instance(inst)
+    _, io = gmres.gmres(A, inst.b, restart=40, tol=1e-9, maxit=500)
+    s = _solver([_op(inst)], restart=40, kmax=4, inner="c128", hist_cap=500)
+    s.set_subspace(None)
+    _, (info,), _ = s.solve([_b(inst)], tol=1e-9, maxit=500)
+    np.testing.assert_allclose(s.history(0)[:200], io["history"][:200], rtol=1e-6, atol=1e-13)
+
+
+def test_solution_in_span_converges_at_once():
+    import torch
+    from gpu_util import to_dev
+    inst = tiny_instance(8)
+    A = fdfd.assemble_instance(inst)
+    xs = direct.dense_solve(A, inst.b)
+    rng = np.random.default_rng(1)
+    a = W.random_complex(rng, inst.D)
+    V = np.stack([xs + a, a, W.random_complex(rng, inst.D)], axis=1)   # x* = v0 - v1
+    s = _solver([_op(inst)], restart=20, kmax=3, inner="c128")
+    s.set_subspace([to_dev(V.T, torch.complex128)])
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-9, maxit=100)
+    assert st == 0 and info["iters"] <= 1
+    assert np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs) < 1e-8
+
+
+def test_batched_uneven_matches_single():
+    """Problems of different grid sizes in one lockstep batch give the same
+    results as separate solves."""
+    insts = [tiny_instance(20 + i, nx=nx, ny=ny) for i, (nx, ny) in
+             enumerate([(20, 16), (33, 17), (48, 40), (12, 30)])]
+    s = _solver([_op(i) for i in insts], restart=30, inner="c128", hist_cap=8000)
+    xs, infos, st = s.solve([_b(i) for i in insts], tol=1e-9, maxit=8000)
+    assert st == 0
+    for p, inst in enumerate(insts):
+        A = fdfd.assemble_instance(inst)
+        _, io = gmres.gmres(A, inst.b, restart=30, tol=1e-9, maxit=8000)
+        # restarted runs amplify rounding (see test_tiny_augmented_history_c128)
+        assert abs(infos[p]["iters"] - io["iters"]) <= 0.02 * io["iters"]
+        np.testing.assert_allclose(s.history(p)[:200], io["history"][:200], rtol=1e-6, atol=1e-13)
+        assert np.linalg.norm(inst.b - A @ xs[p].cpu().numpy()) / np.linalg.norm(inst.b) <= 1e-9
+
+
+def test_edge_cases():
+    import torch
+    from gpu_util import to_dev
+    inst = tiny_instance(2)
+    op = _op(inst)
+    A = fdfd.assemble_instance(inst)
+    # b = 0 -> x = 0, converged, rel res 0
+    s = _solver([op], restart=10, kmax=3, inner="c128")
+    z = torch.zeros(inst.D, dtype=torch.complex128, device="cuda")
+    x0 = to_dev(np.ones(inst.D), torch.complex128)
+    (x,), (info,), st = s.solve([z], x0=[x0], tol=1e-8, maxit=50)
+    assert st == 0 and info["rel_res_true"] == 0.0 and float(x.abs().max()) == 0.0
+    # maxit = 0 -> not converged, x = x0 (zero)
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-8, maxit=0)
+    assert st == 1 and info["iters"] == 0 and float(x.abs().max()) == 0.0
+    # NaN subspace -> plain fallback
+    V = np.full((3, inst.D), np.nan, np.complex128)
+    s.set_subspace([to_dev(V, torch.complex128)])
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-8, maxit=2000)
+    assert st == 0 and info["fallback_plain"] == 1 and info["k_used"] == 0
+    assert np.linalg.norm(inst.b - A @ x.cpu().numpy()) / np.linalg.norm(inst.b) <= 1e-8
+    # duplicated columns -> one dropped
+    rng = np.random.default_rng(3)
+    v = W.random_complex(rng, (2, inst.D))
+    s.set_subspace([to_dev(np.stack([v[0], v[1], v[0]]), torch.complex128)])
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-8, maxit=2000)
+    assert st == 0 and info["k_used"] == 2
+    # restart = 1 still converges (slowly) or reports honestly
+    s1 = _solver([op], restart=1, inner="c128")
+    (x,), (info,), st = s1.solve([_b(inst)], tol=1e-3, maxit=5000)
+    assert (st == 0) == (info["rel_res_true"] <= 1e-3)
+    # resume: a solve split in two (x0 = first result) reaches the same answer
+    s2 = _solver([op], restart=10, inner="c128")
+    (xa,), (ia,), _ = s2.solve([_b(inst)], tol=1e-10, maxit=40)
+    (xb,), (ib,), st = s2.solve([_b(inst)], x0=[xa.clone()], tol=1e-10, maxit=5000)
+    (xc,), (ic,), _ = s2.solve([_b(inst)], tol=1e-10, maxit=5000)
+    assert st == 0
+    assert np.linalg.norm(xb.cpu().numpy() - xc.cpu().numpy()) / np.linalg.norm(xc.cpu().numpy()) < 1e-8
+
+
+def test_grating_c64_refined_to_tol():
+    """480x240 grating, complex64 inner iteration, FP64 residual restarts, tol 1e-6:
+    the true FP64 residual meets tol and the solution matches a sparse LU solve."""
+    inst = W.grating(1000)
+    A = fdfd.assemble_instance(inst)
+    s = _solver([_op(inst)], restart=100, inner="c64")
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-6, maxit=60000)
+    x = x.cpu().numpy()
+    rr = np.linalg.norm(inst.b - A @ x) / np.linalg.norm(inst.b)
+    print("grating c64:", info, "true", rr)
+    assert st == 0 and rr <= 1e-6
+    assert abs(rr - info["rel_res_true"]) <= 1e-3 * rr
+    xs = direct.sparse_solve(A, inst.b)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    print("error vs splu", err)
+    assert err < 1e-3
