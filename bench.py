@@ -1,0 +1,257 @@
+"""Benchmark: solves/s and matvecs to 1e-6 relative residual, data-driven
+(PCA-augmented) vs plain GMRES, one MI355X.
+
+Workload (one "step" = one pass of the whole hot path over one batch):
+  * a synthetic design-trajectory data set of 480 x 240 grating problems
+    (dx 25 nm, lambda 1.30 um, 20-cell PML), 8 trajectories x 32 steps, split
+    75 / 25 at random over all steps as the paper splits its data set;
+  * predictor training (outside the timed region): the training problems are
+    solved by this library's GPU solver, their fields form the snapshot
+    matrix, and pca_build returns the top-k (k = 20) principal components;
+  * timed step: for a batch of B = 64 evaluation problems, the augmentation
+    setup (A V, Cholesky QR twice) and augmented GMRES(100) in complex64 with
+    FP64 true-residual restarts to ||b - A x|| / ||b|| <= 1e-6;
+  * plain GMRES(100) on the same batch, timed once, for the comparison.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def first_below(h, thr):
+    idx = np.nonzero(np.asarray(h) <= thr)[0]
+    return int(idx[0]) + 1 if len(idx) else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--k", type=int, default=20)
+    ap.add_argument("--traj", type=int, default=8)
+    ap.add_argument("--traj-steps", type=int, default=32)
+    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--train-tol", type=float, default=1e-4)
+    ap.add_argument("--maxit", type=int, default=30000)
+    ap.add_argument("--cgs", type=int, default=1, help="Gram-Schmidt passes (1 or 2)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--oracle-check", type=int, default=2)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the problems of a batch are independent; see DESIGN.md for sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_1902_00090_amd import FdfdOp, Solver, pca_build
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = "cuda"
+
+    # ---------------- data
+    t0 = time.time()
+    data = W.trajectory_dataset(args.traj, args.traj_steps)
+    tr_idx, te_idx = W.split_train_test(len(data))
+    train = [data[i] for i in tr_idx]
+    test = [data[i] for i in te_idx][:args.batch]
+    B = len(test)
+    log(f"data: {len(data)} problems ({len(train)} train / {len(te_idx)} eval), "
+        f"{time.time() - t0:.1f}s")
+
+    # ---------------- predictor training: solve the training set on the GPU, PCA
+    t0 = time.time()
+    snaps = []
+    chunk = 64
+    for c0 in range(0, len(train), chunk):
+        part = train[c0:c0 + chunk]
+        ops = [FdfdOp.from_instance(i) for i in part]
+        bs = [torch.tensor(i.b, dtype=torch.complex128, device=dev) for i in part]
+        s = Solver(ops, restart=args.restart, cgs_passes=args.cgs)
+        xs, infos, st = s.solve(bs, tol=args.train_tol, maxit=args.maxit)
+        snaps.extend(x.to(torch.complex64) for x in xs)
+        s.close()
+        log(f"  train solves {c0 + len(part)}/{len(train)}: "
+            f"iters max {max(i['iters'] for i in infos)}")
+    Smat = torch.stack(snaps).contiguous()
+    U, sig = pca_build(Smat, args.k)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    del Smat, snaps
+    log(f"PCA: k={args.k} from {len(train)} solver-generated fields, {t_train:.1f}s; "
+        f"sigma[0]={sig[0]:.3e} sigma[k-1]/sigma[0]={sig[-1] / sig[0]:.3f}")
+
+    # ---------------- evaluation batch (inputs resident in HBM)
+    ops = [FdfdOp.from_instance(i) for i in test]
+    bs = [torch.tensor(i.b, dtype=torch.complex128, device=dev) for i in test]
+    xs = [torch.empty_like(b) for b in bs]
+    Ulist = [U] * B
+    aug = Solver(ops, restart=args.restart, kmax=args.k, cgs_passes=args.cgs,
+                 hist_cap=args.maxit)
+
+    def step():
+        aug.set_subspace(Ulist)
+        return aug.solve(bs, tol=args.tol, maxit=args.maxit, x=xs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    aug.profile(True)
+    infos = None
+    t0 = time.time()
+    for _ in range(args.steps):
+        _, infos, st = step()
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    ks = aug.kernel_stats()
+    aug.profile(False)
+    ms_per_step = 1000.0 * dt / args.steps
+    value = B * args.steps / dt
+    conv = all(i["status"] == 0 for i in infos)
+    worst = max(i["rel_res_true"] for i in infos)
+    it_aug = np.array([i["iters"] for i in infos])
+    mv_aug = np.array([i["matvecs"] for i in infos])
+    h_aug = [aug.history(p) for p in range(B)]
+    r1_aug = float(np.mean([h[0] for h in h_aug]))
+    th_aug = [first_below(h, 0.04) for h in h_aug]
+    log(f"augmented: {value:.3f} solves/s, {ms_per_step:.0f} ms/step, iters mean "
+        f"{it_aug.mean():.0f}, all converged {conv}, worst rel res {worst:.2e}")
+
+    # ---------------- plain GMRES on the same batch
+    plain = None
+    if not args.no_plain:
+        ps = Solver(ops, restart=args.restart, cgs_passes=args.cgs, hist_cap=args.maxit)
+        xp = [torch.empty_like(b) for b in bs]
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, pinf, pst = ps.solve(bs, tol=args.tol, maxit=args.maxit, x=xp)
+        torch.cuda.synchronize()
+        dtp = time.time() - t0
+        h_pl = [ps.history(p) for p in range(B)]
+        it_pl = np.array([i["iters"] for i in pinf])
+        plain = {
+            "solves_per_s": B / dtp, "ms_per_batch": 1000 * dtp,
+            "iters_mean": float(it_pl.mean()), "matvecs_mean": float(np.mean([i["matvecs"] for i in pinf])),
+            "all_converged": all(i["status"] == 0 for i in pinf),
+            "rel_res_after_1_iter_mean": float(np.mean([h[0] for h in h_pl])),
+            "iters_to_0.04_mean": float(np.mean([first_below(h, 0.04) or np.nan for h in h_pl])),
+        }
+        ps.close()
+        log(f"plain: {plain['solves_per_s']:.3f} solves/s, iters mean {plain['iters_mean']:.0f}")
+
+    # ---------------- error vs the FP64 oracle (sparse LU) on a subset
+    errs = []
+    if args.oracle_check > 0:
+        from oracle import direct, fdfd
+        for p in range(min(args.oracle_check, B)):
+            A = fdfd.assemble_instance(test[p])
+            xstar = direct.sparse_solve(A, test[p].b)
+            xg = xs[p].cpu().numpy()
+            errs.append(float(np.linalg.norm(xg - xstar) / np.linalg.norm(xstar)))
+        log(f"error vs sparse LU on {len(errs)} problems: {errs}")
+
+    # ---------------- roofline of the dominant sweep
+    name = max(ks, key=lambda n: ks[n][0])
+    ms_k, launches_k, bytes_k = ks[name]
+    achieved = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": {"matvec_dots": "k_matvec_dot", "second_pass": "k_update_dot",
+                           "update_norm": "k_update_norm"}[name],
+                "avg_launch_us": round(1000 * ms_k / max(1, launches_k), 2),
+                "launches": int(launches_k),
+                "algorithmic_bytes_per_launch": round(bytes_k / max(1, launches_k))}
+    sweeps = {n: {"ms": round(v[0], 2), "launches": int(v[1]),
+                  "GB_per_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+              for n, v in ks.items()}
+
+    # ---------------- CPU baseline: the oracle's augmented GMRES, bounded sample
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle import fdfd, gmres_aug
+        inst = test[0]
+        A = fdfd.assemble_instance(inst)
+        V = U.cpu().numpy().T.astype(np.complex128)
+        with threadpool_limits(limits=1):
+            t0 = time.time()
+            gmres_aug.gmres_aug(A, inst.b, V, restart=args.restart, tol=0.0,
+                                maxit=args.cpu_iters)
+            tc = time.time() - t0
+        t_iter = tc / args.cpu_iters
+        cpu = {"value": round(1.0 / (t_iter * float(it_aug.mean())), 6), "unit": "solves/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"oracle gmres_aug (complex128, numpy/scipy, 1 BLAS thread) on one "
+                         f"evaluation problem for {args.cpu_iters} Arnoldi steps ({tc:.1f}s, "
+                         f"{1000 * t_iter:.0f} ms/step incl. setup), scaled to the mean "
+                         f"{it_aug.mean():.0f} steps the GPU needed per solve"}
+        log(f"cpu baseline: {cpu['value']:.2e} solves/s ({tc:.1f}s sample)")
+
+    out = {
+        "metric": "solves/s and matvecs to 1e-6 rel. residual: augmented vs plain GMRES, 1 GPU",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"PCA-augmented GMRES({args.restart}) on {B} evaluation problems "
+                        f"(480x240 grating designs from {args.traj} synthetic design "
+                        f"trajectories x {args.traj_steps} steps, 75/25 split), k={args.k}, "
+                        f"tol {args.tol:g}, complex64 inner iteration with FP64 true-residual "
+                        f"restarts, {args.cgs} Gram-Schmidt pass(es)",
+            "batch": B, "grid": "480x240", "restart": args.restart, "k": args.k,
+            "tol": args.tol, "pca_train_problems": len(train),
+            "pca_train_seconds": round(t_train, 1),
+        },
+        "augmented": {
+            "solves_per_s": round(value, 4), "iters_mean": float(it_aug.mean()),
+            "matvecs_mean": float(mv_aug.mean()), "all_converged": conv,
+            "worst_rel_res_true": worst,
+            "rel_res_after_1_iter_mean": r1_aug,
+            "iters_to_0.04_mean": float(np.mean([t or np.nan for t in th_aug])),
+            "error_vs_sparse_lu": errs,
+        },
+        "plain": plain,
+        "speedup_wallclock": round(value / plain["solves_per_s"], 3) if plain else None,
+        "sweeps": sweeps,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

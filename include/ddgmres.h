@@ -105,6 +105,9 @@ typedef struct {
   int elems_per_thread; /* field elements per thread: 0 = auto, or 1, 2, 4, 8       */
   int hist_cap;         /* residual-history entries kept per problem (default 0)   */
   int check_every;      /* steps between host checks for an early cycle end (4)    */
+  int select_reorth;    /* with cgs_passes = 2: run the second pass only in steps  */
+                        /* where the first removed more than half of ||A q||^2    */
+                        /* (Kahan-Parlett "twice is enough" test); default 1      */
 } dd_solver_opts;
 
 /* Per-problem result (host struct). */
@@ -115,6 +118,7 @@ typedef struct {
   int restarts;        /* cycles started                                         */
   int k_used;          /* augmenting columns kept after rank checks             */
   int fallback_plain;  /* 1 if a subspace was given but no column was usable     */
+  int reorth_steps;    /* Arnoldi steps that took the second Gram-Schmidt pass   */
   double rel_res_true; /* ||b - A x|| / ||b|| recomputed in FP64 at the end      */
   double rel_res_est;  /* last Givens residual estimate / ||b||                  */
 } dd_info;
@@ -170,6 +174,24 @@ dd_status dd_solver_history(const dd_solver* s, int p, double* out, int cap, int
  * bytes must match the array size exactly; synchronises the device. */
 dd_status dd_solver_debug_copy(const dd_solver* s, int p, int what, void* host_out,
                                size_t bytes);
+
+/* Live timing of the three streaming sweeps of an Arnoldi step, recorded
+ * with HIP events on the solve stream around every launch while enabled:
+ * [0] stencil matvec + first Gram-Schmidt dots, [1] second Gram-Schmidt
+ * pass (update + dots), [2] final update + norm.  bytes[] are the
+ * algorithmic bytes those launches had to move (inner precision ib bytes per
+ * complex, eb per permittivity value, n = basis length of the step):
+ * [0] (2 ib + eb) D + ib D n, [1] ib D (2n + 2), [2] ib D (n + 2). */
+typedef struct {
+  double ms[3];
+  long long launches[3];
+  double bytes[3];
+} dd_kernel_stats;
+
+/* Enable (1) or disable (0) the timing; enabling resets the statistics. */
+dd_status dd_solver_profile(dd_solver* s, int enable);
+/* Host copy of the accumulated statistics. */
+dd_status dd_solver_kernel_stats(const dd_solver* s, dd_kernel_stats* out);
 
 /* Device bytes held by the solver workspace. */
 size_t dd_solver_device_bytes(const dd_solver* s);

@@ -96,7 +96,7 @@ class FdfdOp:
 
 
 def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hist_cap=0,
-          check_every=4):
+          check_every=4, select_reorth=True):
     o = _lib.dd_solver_opts()
     _lib.lib().dd_solver_opts_default(C.byref(o))
     o.inner = DD_C64 if inner == "c64" else DD_C128
@@ -106,6 +106,7 @@ def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hi
     o.elems_per_thread = int(elems_per_thread)
     o.hist_cap = int(hist_cap)
     o.check_every = int(check_every)
+    o.select_reorth = int(bool(select_reorth))
     return o
 
 
@@ -113,11 +114,11 @@ class Solver:
     """Batched data-driven GMRES over a list of operators (lockstep cycles)."""
 
     def __init__(self, ops, restart=100, kmax=0, inner="c64", cgs_passes=2,
-                 elems_per_thread=0, hist_cap=0, check_every=4):
+                 elems_per_thread=0, hist_cap=0, check_every=4, select_reorth=True):
         self.ops = list(ops)
         self.nb = len(self.ops)
         self.opts = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap,
-                          check_every)
+                          check_every, select_reorth)
         self.inner = inner
         self.restart, self.kmax = int(restart), int(kmax)
         h = C.c_void_p()
@@ -197,6 +198,17 @@ class Solver:
         check(_lib.lib().dd_solver_debug_copy(self._h, p, code, out.ctypes.data_as(C.c_void_p),
                                               out.nbytes), "dd_solver_debug_copy")
         return out
+
+    def profile(self, enable=True):
+        """Turn on live HIP-event timing of the streaming sweeps (resets stats)."""
+        check(_lib.lib().dd_solver_profile(self._h, int(bool(enable))), "dd_solver_profile")
+
+    def kernel_stats(self):
+        """{'matvec_dots'|'second_pass'|'update_norm': (ms, launches, bytes)}."""
+        ks = _lib.dd_kernel_stats()
+        check(_lib.lib().dd_solver_kernel_stats(self._h, C.byref(ks)), "dd_solver_kernel_stats")
+        names = ["matvec_dots", "second_pass", "update_norm"]
+        return {n: (ks.ms[i], ks.launches[i], ks.bytes[i]) for i, n in enumerate(names)}
 
     @property
     def device_bytes(self):

@@ -32,16 +32,22 @@ class dd_pml(C.Structure):
 class dd_solver_opts(C.Structure):
     _fields_ = [("inner", C.c_int), ("cgs_passes", C.c_int), ("restart", C.c_int),
                 ("kmax", C.c_int), ("elems_per_thread", C.c_int), ("hist_cap", C.c_int),
-                ("check_every", C.c_int)]
+                ("check_every", C.c_int), ("select_reorth", C.c_int)]
 
 
 class dd_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("matvecs", C.c_int),
                 ("restarts", C.c_int), ("k_used", C.c_int), ("fallback_plain", C.c_int),
+                ("reorth_steps", C.c_int),
                 ("rel_res_true", C.c_double), ("rel_res_est", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class dd_kernel_stats(C.Structure):
+    _fields_ = [("ms", C.c_double * 3), ("launches", C.c_longlong * 3),
+                ("bytes", C.c_double * 3)]
 
 
 P = C.c_void_p
@@ -63,6 +69,8 @@ _SIGS = {
     "dd_solver_history": (I, [P, I, C.POINTER(D), I, C.POINTER(I)]),
     "dd_solver_debug_copy": (I, [P, I, I, P, C.c_size_t]),
     "dd_solver_device_bytes": (C.c_size_t, [P]),
+    "dd_solver_profile": (I, [P, I]),
+    "dd_solver_kernel_stats": (I, [P, C.POINTER(dd_kernel_stats)]),
     "dd_solver_destroy": (None, [P]),
     "gmres_solve": (I, [P, P, P, P, I, D, I, I, C.POINTER(dd_solver_opts), P,
                         C.POINTER(dd_info), P]),

@@ -32,13 +32,16 @@ struct ProbDesc {
 };
 
 // Integer state per problem
-enum { ST_ACTIVE = 0, ST_J, ST_ITERS, ST_CYCLES, ST_DONE, ST_PENDING, ST_NCOMB, ST_FLAGS, ST_NI };
+enum { ST_ACTIVE = 0, ST_J, ST_ITERS, ST_CYCLES, ST_DONE, ST_PENDING, ST_NCOMB, ST_FLAGS, ST_REORTH,
+       ST_NREORTH, ST_NI };
 // ST_DONE values
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_BUDGET = 2, DONE_NONFINITE = 3 };
 // ST_FLAGS bits
 enum { FLAG_ZERO_B = 1 };
 // FP64 state per problem
-enum { SD_BNORM = 0, SD_RHO, SD_BETA, SD_TRUE, SD_EST, SD_ND = 8 };
+// SD_NSUM / SD_NSUM2: sums over Arnoldi steps of the basis length n = k + j + 1
+// (all steps / steps with a second pass), for the algorithmic byte counts.
+enum { SD_BNORM = 0, SD_RHO, SD_BETA, SD_TRUE, SD_EST, SD_NSUM, SD_NSUM2, SD_ND = 8 };
 
 enum { MODE_START = 0, MODE_ARNOLDI = 1 };
 
@@ -65,11 +68,9 @@ struct PlanDev {
   unsigned long long* bad;   // [nb] columns with non-finite entries
   void* partial;     // [nchunks][NV] inner-precision partial sums
   double* gpart;     // Gram partials [nb][GB][ntiles][32]
-  int* counter;      // [nb] ticket of the final reduction level
-  int* gcount;       // [nchunks] group tickets (used at group-start chunks)
-  double* gsum;      // [nchunks][NV] FP64 group sums (rows at group starts)
   double* hist;      // [nb][hist_cap]
   int nb, m, kmax, NC, NV, hist_cap, GB, qslots;
+  int reorth_mode;   // 0 one Gram-Schmidt pass, 1 always two, 2 two where needed
   double tol;
   int maxit;
 };

@@ -27,6 +27,13 @@ struct dd_solver {
   unsigned long long* pinnedK = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool has_subspace = false;
+  // live kernel timing (dd_solver_profile): event pairs around the three
+  // streaming sweeps of every Arnoldi step, read back at each host sync
+  bool prof = false;
+  std::vector<hipEvent_t> pev;
+  std::vector<int> pkind;
+  int pused = 0;
+  dd_kernel_stats ks{};
 };
 
 extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
@@ -38,6 +45,7 @@ extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
   o->elems_per_thread = 0;
   o->hist_cap = 0;
   o->check_every = 4;
+  o->select_reorth = 1;
 }
 
 static size_t inner_bytes(dd_prec p) { return p == DD_C128 ? 16 : 8; }
@@ -71,6 +79,8 @@ extern "C" void dd_solver_destroy(dd_solver* s) {
   if (s->pinnedD) (void)hipHostFree(s->pinnedD);
   if (s->pinnedK) (void)hipHostFree(s->pinnedK);
   for (auto& e : s->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : s->pev)
     if (e) (void)hipEventDestroy(e);
   delete s;
 }
@@ -159,6 +169,7 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
   PlanDev& P = s->P;
   P.nb = nb; P.m = m; P.kmax = K; P.NC = NC; P.NV = NV; P.hist_cap = o.hist_cap;
   P.qslots = m + 1;
+  P.reorth_mode = (o.cgs_passes == 1) ? 0 : (o.select_reorth ? 2 : 1);
   // Gram partial rows: bounded to 64 MB
   {
     const size_t per = (size_t)nb * std::max(1, gram_tiles(std::max(K, 1))) * 32 * sizeof(double);
@@ -196,9 +207,6 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     chk(dalloc(s, &part, (size_t)s->nchunks * NV));
     P.partial = part;
     chk(dalloc(s, &P.gpart, (size_t)nb * P.GB * std::max(1, gram_tiles(std::max(K, 1))) * 32));
-    chk(dalloc(s, &P.counter, (size_t)nb));
-    chk(dalloc(s, &P.gcount, (size_t)s->nchunks));
-    chk(dalloc(s, &P.gsum, (size_t)s->nchunks * NV));
     chk(dalloc(s, &P.hist, (size_t)nb * std::max(1, o.hist_cap)));
   }
   if (e == hipSuccess) {
@@ -297,20 +305,66 @@ extern "C" dd_status dd_solver_set_subspace(dd_solver* s, const void* const* U, 
   return DD_OK;
 }
 
-template <typename T, int R>
-static void launch_step(dd_solver* s, int j, hipStream_t st) {
-  const int g = s->nchunks;
-  k_matvec_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j);
-  if (s->o.cgs_passes == 2) k_update_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI);
-  k_update_norm<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, s->o.cgs_passes == 2);
+static void prof_mark(dd_solver* s, int kind, hipStream_t st) {
+  if (!s->prof || s->pused + 2 > (int)s->pev.size()) return;
+  (void)hipEventRecord(s->pev[s->pused], st);
+  s->pkind[s->pused / 2] = kind;
+}
+static void prof_end(dd_solver* s, hipStream_t st) {
+  if (!s->prof || s->pused + 2 > (int)s->pev.size()) return;
+  (void)hipEventRecord(s->pev[s->pused + 1], st);
+  s->pused += 2;
+}
+// Adds the elapsed times of the recorded pairs (the stream has been
+// synchronised by the caller) and recycles the events.
+static void prof_collect(dd_solver* s) {
+  for (int i = 0; i + 1 < s->pused; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->pev[i], s->pev[i + 1]) == hipSuccess) {
+      const int kd = s->pkind[i / 2];
+      s->ks.ms[kd] += ms;
+      s->ks.launches[kd] += 1;
+    }
+  }
+  s->pused = 0;
 }
 
+// One Arnoldi step: matvec + first-pass dots, their reduction (which also
+// decides the second pass), the optional second pass (only flagged problems
+// do work in it), the final update + norm and the FP64 bookkeeping.
+template <typename T, int R>
+static void launch_step(dd_solver* s, int j, hipStream_t st) {
+  const int g = s->nchunks, nb = s->nb;
+  prof_mark(s, 0, st);
+  k_matvec_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j);
+  prof_end(s, st);
+  k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
+  if (s->P.reorth_mode != 0) {
+    prof_mark(s, 1, st);
+    k_update_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI);
+    prof_end(s, st);
+    k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 1);
+  }
+  prof_mark(s, 2, st);
+  k_update_norm<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
+  prof_end(s, st);
+  k_post_norm<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
+}
+
+// Projected start; it always takes the second pass unless one pass is
+// requested, because a good subspace leaves r~ = r - C C^H r tiny against r.
 template <typename T, int R>
 static void launch_start(dd_solver* s, hipStream_t st) {
-  const int g = s->nchunks;
+  const int g = s->nchunks, nb = s->nb;
+  const int re = s->P.reorth_mode != 0;
   k_start_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P);
-  if (s->o.cgs_passes == 2) k_update_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START);
-  k_update_norm<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START, s->o.cgs_passes == 2);
+  k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START, 0);
+  if (re) {
+    k_update_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START);
+    k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START, 1);
+  }
+  k_update_norm<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START, re);
+  k_post_norm<T><<<nb, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START, re);
 }
 
 template <typename T, int R>
@@ -320,11 +374,13 @@ static dd_status run_cycles(dd_solver* s, hipStream_t st) {
   int* snap[2] = {s->pinned, s->pinned + nb * ST_NI};
   bool first = true;
   for (;;) {
-    k_residual<R><<<g, DD_BLOCK, 0, st>>>(s->P, first ? 1 : 0);
+    k_residual<R><<<g, DD_BLOCK, 0, st>>>(s->P);
+    k_post_residual<<<nb, DD_BLOCK, 0, st>>>(s->P, first ? 1 : 0);
     first = false;
     DD_HIP_CHECK(hipGetLastError());
     DD_HIP_CHECK(hipMemcpyAsync(snap[0], s->P.stI, stbytes, hipMemcpyDeviceToHost, st));
     DD_HIP_CHECK(hipStreamSynchronize(st));
+    prof_collect(s);
     int active = 0;
     for (int p = 0; p < nb; ++p) active += snap[0][p * ST_NI + ST_ACTIVE];
     if (active == 0) break;
@@ -398,6 +454,20 @@ extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const v
   DD_HIP_CHECK(hipMemcpyAsync(s->pinnedK, s->P.keep, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, stream));
   DD_HIP_CHECK(hipStreamSynchronize(stream));
   dd_status out = DD_OK;
+  if (s->prof) {
+    // algorithmic bytes of the timed sweeps (inner precision ib bytes per
+    // complex, eps eb bytes per cell): matvec + dots (2 ib + eb) D + ib D n;
+    // second pass ib D (2n + 2); final update ib D (n + 2)
+    const double ib = (double)inner_bytes(s->o.inner), eb = (s->o.inner == DD_C64) ? 4.0 : 8.0;
+    for (int p = 0; p < nb; ++p) {
+      const int* st = fin + p * ST_NI;
+      const double* sd = s->pinnedD + p * SD_ND;
+      const double D = s->hdesc[p].D, steps = st[ST_ITERS], st2 = st[ST_NREORTH];
+      s->ks.bytes[0] += (2 * ib + eb) * D * steps + ib * D * sd[SD_NSUM];
+      s->ks.bytes[1] += ib * D * (2 * sd[SD_NSUM2] + 2 * st2);
+      s->ks.bytes[2] += ib * D * (sd[SD_NSUM] + 2 * steps);
+    }
+  }
   for (int p = 0; p < nb; ++p) {
     const int* st = fin + p * ST_NI;
     const double* sd = s->pinnedD + p * SD_ND;
@@ -412,6 +482,7 @@ extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const v
       I.restarts = st[ST_CYCLES];
       I.k_used = kused;
       I.fallback_plain = (s->ksetup[p] > 0 && kused == 0) ? 1 : 0;
+      I.reorth_steps = st[ST_NREORTH];
       I.matvecs = (s->has_subspace ? s->ksetup[p] : 0) + st[ST_ITERS] + st[ST_CYCLES] + 1;
       I.rel_res_true = sd[SD_TRUE];
       I.rel_res_est = sd[SD_EST];
@@ -426,6 +497,26 @@ extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const v
   if (out == DD_ENONFINITE) dd_set_error("dd_solver_solve: non-finite right-hand side or residual");
   else if (out == DD_NOT_CONVERGED) dd_set_error("dd_solver_solve: iteration budget spent");
   return out;
+}
+
+extern "C" dd_status dd_solver_profile(dd_solver* s, int enable) {
+  if (!s) { dd_set_error("dd_solver_profile: NULL solver"); return DD_EINVAL; }
+  if (enable && s->pev.empty()) {
+    const int n = 6 * s->o.restart + 8;
+    s->pev.resize(n, nullptr);
+    s->pkind.resize(n / 2 + 1, 0);
+    for (auto& e : s->pev) DD_HIP_CHECK(hipEventCreate(&e));
+  }
+  s->prof = enable != 0;
+  s->pused = 0;
+  std::memset(&s->ks, 0, sizeof(s->ks));
+  return DD_OK;
+}
+
+extern "C" dd_status dd_solver_kernel_stats(const dd_solver* s, dd_kernel_stats* out) {
+  if (!s || !out) { dd_set_error("dd_solver_kernel_stats: NULL argument"); return DD_EINVAL; }
+  *out = s->ks;
+  return DD_OK;
 }
 
 extern "C" dd_status dd_solver_history(const dd_solver* s, int p, double* out, int cap, int* n) {

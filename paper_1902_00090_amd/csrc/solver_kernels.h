@@ -5,9 +5,11 @@
 // of a chunk owns elements base + r*DD_BLOCK + t (r < R), so every vector access
 // is a coalesced 64-lane load and a thread always touches the same elements
 // of every basis vector (in-place updates need no synchronisation).
-// Cross-workgroup sums go through a partial-sum row per chunk; the last
-// workgroup of a problem to finish (atomic ticket) adds the rows in a fixed
-// order in FP64, so results are deterministic run to run.
+// Cross-workgroup sums go through a partial-sum row per chunk, reduced in a
+// fixed order in FP64 by a small one-workgroup-per-problem kernel launched
+// after the sweep, so results are deterministic run to run and no sweep ever
+// communicates across workgroups (on this chip a device-scope fence inside a
+// kernel is a write-back of the XCD's L2).
 #pragma once
 
 #include "solver.h"
@@ -39,12 +41,19 @@ __device__ __forceinline__ double2 ddiv(double2 a, double2 b) {
 }
 
 // ---------------------------------------------------------------------------
-// conj(B_v) . w for v < n over this thread's R elements, 16 vectors at a
-// time; block sums land in prow[2v], prow[2v+1].
+// conj(B_v) . w for v < n over this workgroup's elements, 16 vectors at a
+// time.  Each wave folds its 16 partial dots with the transposed butterfly
+// into LDS (no workgroup barrier between groups, so the next group's loads
+// issue while the previous reduction finishes); one barrier at the end adds
+// the four waves' rows into prow[0 .. 2*round_up(n,16)).
+#define DD_LDSN (2 * (((DD_MAX_K + DD_MAX_M + 1) + 15) / 16) * 16 + 32)
+// An extra per-thread scalar (e.g. a squared norm) is summed alongside into
+// prow[2*round_up(n,16)].
 template <typename T, int R>
 __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t Dp, int n,
                                            const c2<T> (&w)[R], int base,
-                                           T* __restrict__ prow, T* lds) {
+                                           T* __restrict__ prow, T* lds, T extra = T(0)) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int v0 = 0; v0 < n; v0 += 16) {
     T acc[32];
 #pragma unroll
@@ -61,77 +70,42 @@ __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t D
         }
       }
     }
-    block_sum32<T>(acc, lds, prow + 2 * v0);
+    butterfly_step<T, 32>(acc, lane);
+    const T sum = acc[0] + __shfl_xor(acc[0], 1, DD_WAVE);
+    if ((lane & 1) == 0) lds[wave * DD_LDSN + 2 * v0 + (lane >> 1)] = sum;
   }
+  const int nv = 2 * ((n + 15) / 16) * 16;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) extra += __shfl_xor(extra, o, DD_WAVE);
+  if (lane == 0) lds[wave * DD_LDSN + nv] = extra;
+  __syncthreads();
+  for (int i = threadIdx.x; i <= nv; i += DD_BLOCK)
+    prow[i] = lds[i] + lds[DD_LDSN + i] + lds[2 * DD_LDSN + i] + lds[3 * DD_LDSN + i];
 }
 
-// Cross-workgroup sums in two levels with tickets.  Chunks of a problem are
-// grouped by DD_GROUP; the last workgroup of a group to arrive adds the
-// group's partial rows (all loads independent, so they are in flight
-// together) into an FP64 group row; the last group to finish adds the group
-// rows.  Returns true in that final workgroup, which then holds in
-// red[0..nvals) the FP64 sums over all of p's chunks.  The order of every
-// addition is fixed, so results are deterministic run to run.  Tickets are
-// reset by the workgroup that consumed them.
-#define DD_GROUP 32
+// FP64 sums over all of problem p's partial rows, added in chunk order (the
+// same order every run, so results are deterministic).  Called by a
+// one-workgroup-per-problem kernel after the sweep that wrote the rows has
+// finished: the kernel boundary makes the rows visible on every XCD, so no
+// device-scope fence (an L2 write-back on this chip) is ever issued inside
+// a sweep.
 template <typename PT>
-__device__ bool last_block(const PlanDev& P, int p, int blk0, int nblk, int nvals,
-                           double* red) {
-  __shared__ int am_last;
-  const int chunk = blockIdx.x;
-  const int lc = chunk - blk0;
-  const int gs = (lc / DD_GROUP) * DD_GROUP;
-  const int ge = min(nblk, gs + DD_GROUP);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(&P.gcount[blk0 + gs], 1);
-    am_last = (prev == ge - gs - 1);
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
-  {
-    const PT* part = (const PT*)P.partial + (size_t)(blk0 + gs) * P.NV;
-    double* grow = P.gsum + (size_t)(blk0 + gs) * P.NV;
-    const int cnt = ge - gs;
-    for (int v = threadIdx.x; v < nvals; v += DD_BLOCK) {
-      double a[DD_GROUP];
-#pragma unroll
-      for (int c = 0; c < DD_GROUP; ++c) a[c] = (c < cnt) ? (double)part[(size_t)c * P.NV + v] : 0.0;
-      double s = 0.0;
-#pragma unroll
-      for (int c = 0; c < DD_GROUP; ++c) s += a[c];
-      grow[v] = s;
-    }
-  }
-  if (threadIdx.x == 0) P.gcount[blk0 + gs] = 0;
-  const int ngroups = (nblk + DD_GROUP - 1) / DD_GROUP;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(&P.counter[p], 1);
-    am_last = (prev == ngroups - 1);
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
+__device__ void reduce_rows(const PlanDev& P, int blk0, int nblk, int nvals, double* red) {
+  const PT* part = (const PT*)P.partial + (size_t)blk0 * P.NV;
   for (int v = threadIdx.x; v < nvals; v += DD_BLOCK) {
     double s = 0.0;
-    int g = 0;
-    for (; g + 8 <= ngroups; g += 8) {
+    int c = 0;
+    for (; c + 8 <= nblk; c += 8) {
       double a[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a[q] = P.gsum[(size_t)(blk0 + (g + q) * DD_GROUP) * P.NV + v];
+      for (int q = 0; q < 8; ++q) a[q] = (double)part[(size_t)(c + q) * P.NV + v];
 #pragma unroll
       for (int q = 0; q < 8; ++q) s += a[q];
     }
-    for (; g < ngroups; ++g) s += P.gsum[(size_t)(blk0 + g * DD_GROUP) * P.NV + v];
+    for (; c < nblk; ++c) s += (double)part[(size_t)c * P.NV + v];
     red[v] = s;
   }
-  if (threadIdx.x == 0) P.counter[p] = 0;
   __syncthreads();
-  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -186,18 +160,14 @@ __global__ void k_init_state(PlanDev P) {
   if (p >= P.nb) return;
   for (int i = 0; i < ST_NI; ++i) P.stI[p * ST_NI + i] = 0;
   for (int i = 0; i < SD_ND; ++i) P.stD[p * SD_ND + i] = 0.0;
-  P.counter[p] = 0;
 }
 
-// r = b - A x in FP64 with ||r||^2 and ||b||^2; the last workgroup decides
-// whether the problem has converged (||r|| <= tol ||b||), spent its budget,
-// or starts a new cycle.
+// r = b - A x in FP64; partial rows hold ||r||^2 and ||b||^2.
 template <int R>
-__global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P, int first) {
+__global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P) {
   const int chunk = blockIdx.x;
   const int p = P.blk2prob[chunk];
-  int* st = P.stI + p * ST_NI;
-  if (st[ST_DONE] != DONE_RUNNING) return;
+  if (P.stI[p * ST_NI + ST_DONE] != DONE_RUNNING) return;
   const ProbDesc d = P.desc[p];
   const int base = (chunk - d.blk0) * DD_BLOCK * R;
   double sr = 0.0, sb = 0.0;
@@ -215,44 +185,52 @@ __global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P, int first) {
     sr += rr.x * rr.x + rr.y * rr.y;
   }
   __shared__ double lds[8];
-  __shared__ double red[2];
   const double tr = block_sum1<double>(sr, lds);
   const double tb = block_sum1<double>(sb, lds);
   double* prow = (double*)P.partial + (size_t)chunk * P.NV;
   if (threadIdx.x == 0) { prow[0] = tr; prow[1] = tb; }
-  if (!last_block<double>(P, p, d.blk0, d.nblk, 2, red)) return;
-  if (threadIdx.x == 0) {
-    double* sd = P.stD + p * SD_ND;
-    const double rho = sqrt(red[0]);
-    if (first) sd[SD_BNORM] = sqrt(red[1]);
-    const double bn = sd[SD_BNORM];
-    sd[SD_RHO] = rho;
-    st[ST_PENDING] = 0;
-    st[ST_ACTIVE] = 0;
-    if (!isfinite(bn) || !isfinite(rho)) {
-      st[ST_DONE] = DONE_NONFINITE;
-      sd[SD_TRUE] = rho / bn;
-    } else if (bn == 0.0) {
+}
+
+// One workgroup per problem: ||r||, ||b||; decides whether the problem has
+// converged (||r|| <= tol ||b||), spent its budget, or starts a new cycle.
+__global__ __launch_bounds__(DD_BLOCK) void k_post_residual(PlanDev P, int first) {
+  const int p = blockIdx.x;
+  int* st = P.stI + p * ST_NI;
+  if (st[ST_DONE] != DONE_RUNNING) return;
+  const ProbDesc d = P.desc[p];
+  __shared__ double red[2];
+  reduce_rows<double>(P, d.blk0, d.nblk, 2, red);
+  if (threadIdx.x != 0) return;
+  double* sd = P.stD + p * SD_ND;
+  const double rho = sqrt(red[0]);
+  if (first) sd[SD_BNORM] = sqrt(red[1]);
+  const double bn = sd[SD_BNORM];
+  sd[SD_RHO] = rho;
+  st[ST_PENDING] = 0;
+  st[ST_ACTIVE] = 0;
+  if (!isfinite(bn) || !isfinite(rho)) {
+    st[ST_DONE] = DONE_NONFINITE;
+    sd[SD_TRUE] = rho / bn;
+  } else if (bn == 0.0) {
+    st[ST_DONE] = DONE_CONVERGED;
+    st[ST_FLAGS] |= FLAG_ZERO_B;
+    sd[SD_TRUE] = 0.0;
+  } else {
+    sd[SD_TRUE] = rho / bn;
+    if (rho <= P.tol * bn) {
       st[ST_DONE] = DONE_CONVERGED;
-      st[ST_FLAGS] |= FLAG_ZERO_B;
-      sd[SD_TRUE] = 0.0;
+    } else if (st[ST_ITERS] >= P.maxit) {
+      st[ST_DONE] = DONE_BUDGET;
     } else {
-      sd[SD_TRUE] = rho / bn;
-      if (rho <= P.tol * bn) {
-        st[ST_DONE] = DONE_CONVERGED;
-      } else if (st[ST_ITERS] >= P.maxit) {
-        st[ST_DONE] = DONE_BUDGET;
-      } else {
-        st[ST_ACTIVE] = 1;
-        st[ST_CYCLES] += 1;
-        st[ST_J] = 0;
-      }
+      st[ST_ACTIVE] = 1;
+      st[ST_CYCLES] += 1;
+      st[ST_J] = 0;
     }
   }
 }
 
 // Projected start, first pass: Q_0 = r / rho in the inner precision and the
-// dots C^H Q_0 (supplement: q_1 = b~/||b~||, b~ = P b, applied to the
+// partial dots C^H Q_0 (supplement: q_1 = b~/||b~||, b~ = P b, applied to the
 // cycle's residual).
 template <typename T, int R>
 __global__ __launch_bounds__(DD_BLOCK) void k_start_dot(PlanDev P) {
@@ -275,17 +253,14 @@ __global__ __launch_bounds__(DD_BLOCK) void k_start_dot(PlanDev P) {
     q0[e] = wv[r];
   }
   if (n == 0) return;
-  __shared__ T lds[128];
-  __shared__ double red[DD_NV_MAX];
+  __shared__ T lds[4 * DD_LDSN];
   T* prow = (T*)P.partial + (size_t)chunk * P.NV;
   block_dots<T, R>(B, Dp, n, wv, base, prow, lds);
-  if (!last_block<T>(P, p, d.blk0, d.nblk, 2 * n, red)) return;
-  double2* cA = P.coefA + (size_t)p * P.NC;
-  for (int v = threadIdx.x; v < n; v += DD_BLOCK) cA[v] = make_double2(red[2 * v], red[2 * v + 1]);
 }
 
-// Arnoldi step j, first kernel: w = A q_j (q_j stored unnormalised, scaled on
-// the fly by hscale[j]) written to slot Q_{j+1}, and the dots [C Q_0..Q_j]^H w.
+// Arnoldi step j, first sweep: w = A q_j (q_j stored unnormalised, scaled on
+// the fly by hscale[j]) written to slot Q_{j+1}; partial dots [C Q_0..Q_j]^H w
+// and ||w||^2.
 template <typename T, int R>
 __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
   const int chunk = blockIdx.x;
@@ -310,15 +285,50 @@ __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
     wv[r] = y;
     w[e] = y;
   }
-  __shared__ T lds[128];
-  __shared__ double red[DD_NV_MAX];
+  T w2 = T(0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) w2 += wv[r].x * wv[r].x + wv[r].y * wv[r].y;
+  __shared__ T lds[4 * DD_LDSN];
   T* prow = (T*)P.partial + (size_t)chunk * P.NV;
-  block_dots<T, R>(B, Dp, n, wv, base, prow, lds);
-  if (!last_block<T>(P, p, d.blk0, d.nblk, 2 * n, red)) return;
-  double2* cA = P.coefA + (size_t)p * P.NC;
+  block_dots<T, R>(B, Dp, n, wv, base, prow, lds, w2);
+}
+
+// One workgroup per problem: the dot products of the sweep before, as FP64
+// coefficients (dst 0 -> coefA, 1 -> coefB).  After the first sweep of an
+// Arnoldi step it also rescales the dot with the deferred-normalisation
+// vector q_j and decides whether this step takes the second pass.
+template <typename PT>
+__global__ __launch_bounds__(DD_BLOCK) void k_post_dots(PlanDev P, int j, int mode, int dst) {
+  const int p = blockIdx.x;
+  int* st = P.stI + p * ST_NI;
+  if (st[ST_ACTIVE] == 0) return;
+  if (dst == 1 && mode == MODE_ARNOLDI && st[ST_REORTH] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int n = (mode == MODE_START) ? d.k : d.k + j + 1;
+  if (n == 0) return;
+  const int nvr = 2 * ((n + 15) / 16) * 16;
+  const bool first_arnoldi = (mode == MODE_ARNOLDI && dst == 0);
+  __shared__ double red[DD_NV_MAX];
+  __shared__ double cc_l[8];
+  reduce_rows<PT>(P, d.blk0, d.nblk, first_arnoldi ? nvr + 1 : 2 * n, red);
+  const double hs = first_arnoldi ? P.hscale[(size_t)p * (P.m + 1) + j] : 1.0;
+  double2* out = (dst == 0 ? P.coefA : P.coefB) + (size_t)p * P.NC;
+  double cc = 0.0;
   for (int v = threadIdx.x; v < n; v += DD_BLOCK) {
-    const double s = (v == n - 1) ? hs : 1.0;
-    cA[v] = make_double2(red[2 * v] * s, red[2 * v + 1] * s);
+    const double s = (first_arnoldi && v == n - 1) ? hs : 1.0;
+    const double2 c = make_double2(red[2 * v] * s, red[2 * v + 1] * s);
+    out[v] = c;
+    cc += c.x * c.x + c.y * c.y;
+  }
+  if (!first_arnoldi) return;
+  cc = block_sum1<double>(cc, cc_l);
+  if (threadIdx.x == 0) {
+    // Second Gram-Schmidt pass: never, always, or when the first pass removed
+    // more than half of ||w||^2 (||w - B c||^2 = ||w||^2 - ||c||^2 for an
+    // orthonormal B; "twice is enough" test of Kahan and Parlett).
+    int re = P.reorth_mode;
+    if (re == 2) re = (red[nvr] - cc < 0.5 * red[nvr]) ? 1 : 0;
+    st[ST_REORTH] = re;
   }
 }
 
@@ -329,29 +339,56 @@ template <typename T, int R>
 __device__ __forceinline__ void block_update(c2<T>* __restrict__ B, size_t Dp, int n,
                                              const c2<T>* coef, c2<T> (&wv)[R], int base,
                                              int nv, T hs) {
-  for (int v = 0; v < n; ++v) {
+  int v = 0;
+  // four vectors per round so that 4*R loads are in flight per thread
+  for (; v + 4 <= n; v += 4) {
+    c2<T> b[4][R];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const c2<T>* bp = B + (size_t)(v + u) * Dp + base + threadIdx.x;
+#pragma unroll
+      for (int r = 0; r < R; ++r) b[u][r] = bp[r * DD_BLOCK];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (v + u == nv) {
+        c2<T>* bp = B + (size_t)(v + u) * Dp + base + threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          b[u][r] = cscale(b[u][r], hs);
+          bp[r * DD_BLOCK] = b[u][r];
+        }
+      }
+      const c2<T> cv = coef[v + u];
+#pragma unroll
+      for (int r = 0; r < R; ++r) wv[r] = cfnms(wv[r], cv, b[u][r]);
+    }
+  }
+  for (; v < n; ++v) {
     c2<T>* bp = B + (size_t)v * Dp + base + threadIdx.x;
     const c2<T> cv = coef[v];
+    c2<T> b[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[r] = bp[r * DD_BLOCK];
     if (v == nv) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const c2<T> b = cscale(bp[r * DD_BLOCK], hs);
-        bp[r * DD_BLOCK] = b;
-        wv[r] = cfnms(wv[r], cv, b);
+        b[r] = cscale(b[r], hs);
+        bp[r * DD_BLOCK] = b[r];
       }
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) wv[r] = cfnms(wv[r], cv, bp[r * DD_BLOCK]);
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) wv[r] = cfnms(wv[r], cv, b[r]);
   }
 }
 
-// CGS2 middle kernel: first update with coefA, then the second-pass dots.
+// CGS2 middle sweep: first update with coefA, then the second-pass dots.
 template <typename T, int R>
 __global__ __launch_bounds__(DD_BLOCK) void k_update_dot(PlanDev P, int j, int mode) {
   const int chunk = blockIdx.x;
   const int p = P.blk2prob[chunk];
   if (P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
+  if (mode == MODE_ARNOLDI && P.stI[p * ST_NI + ST_REORTH] == 0) return;
   const ProbDesc d = P.desc[p];
   const int n = (mode == MODE_START) ? d.k : d.k + j + 1;
   if (n == 0) return;
@@ -371,36 +408,30 @@ __global__ __launch_bounds__(DD_BLOCK) void k_update_dot(PlanDev P, int j, int m
   block_update<T, R>(B, Dp, n, coef, wv, base, nv, hs);
 #pragma unroll
   for (int r = 0; r < R; ++r) w[base + r * DD_BLOCK + threadIdx.x] = wv[r];
-  __shared__ T lds[128];
-  __shared__ double red[DD_NV_MAX];
+  __shared__ T lds[4 * DD_LDSN];
   T* prow = (T*)P.partial + (size_t)chunk * P.NV;
   block_dots<T, R>(B, Dp, n, wv, base, prow, lds);
-  if (!last_block<T>(P, p, d.blk0, d.nblk, 2 * n, red)) return;
-  double2* cB = P.coefB + (size_t)p * P.NC;
-  for (int v = threadIdx.x; v < n; v += DD_BLOCK) cB[v] = make_double2(red[2 * v], red[2 * v + 1]);
 }
 
-// Final update of a Gram-Schmidt step and ||w||^2; the last workgroup runs
-// the FP64 bookkeeping: in the start phase beta, c0 = C^H r; in an Arnoldi
-// step the new Hessenberg column, B column, Givens rotation and residual
-// estimate, and (at the cycle's end) the least-squares solve.
+// Final update sweep of a Gram-Schmidt step; partial rows hold ||w||^2.
 template <typename T, int R>
 __global__ __launch_bounds__(DD_BLOCK) void k_update_norm(PlanDev P, int j, int mode,
-                                                          int cgs2) {
+                                                          int start_reorth) {
   const int chunk = blockIdx.x;
   const int p = P.blk2prob[chunk];
-  int* st = P.stI + p * ST_NI;
+  const int* st = P.stI + p * ST_NI;
   if (st[ST_ACTIVE] == 0) return;
+  // second pass done in this step (start: per launch; Arnoldi: per problem)
+  const int cgs2 = (mode == MODE_START) ? start_reorth : st[ST_REORTH];
   const ProbDesc d = P.desc[p];
   const int k = d.k;
   const int n = (mode == MODE_START) ? k : k + j + 1;
   const int base = (chunk - d.blk0) * DD_BLOCK * R;
   const size_t Dp = d.Dp;
-  const int m = P.m;
   c2<T>* B = (c2<T>*)d.basis + (size_t)(P.kmax - k) * Dp;
   c2<T>* w = B + (size_t)n * Dp;
   const int nv = (!cgs2 && mode == MODE_ARNOLDI) ? n - 1 : -1;
-  const T hs = (nv >= 0) ? (T)P.hscale[(size_t)p * (m + 1) + j] : T(1);
+  const T hs = (nv >= 0) ? (T)P.hscale[(size_t)p * (P.m + 1) + j] : T(1);
   __shared__ c2<T> coef[DD_MAX_K + DD_MAX_M + 1];
   const double2* cS = (cgs2 ? P.coefB : P.coefA) + (size_t)p * P.NC;
   for (int v = threadIdx.x; v < n; v += DD_BLOCK) coef[v] = to_c<T>(cS[v]);
@@ -416,13 +447,28 @@ __global__ __launch_bounds__(DD_BLOCK) void k_update_norm(PlanDev P, int j, int 
     s2 += wv[r].x * wv[r].x + wv[r].y * wv[r].y;
   }
   __shared__ T lds[8];
-  __shared__ double red[1];
   const T tot = block_sum1<T>(s2, lds);
   T* prow = (T*)P.partial + (size_t)chunk * P.NV;
   if (threadIdx.x == 0) prow[0] = tot;
-  if (!last_block<T>(P, p, d.blk0, d.nblk, 1, red)) return;
+}
 
-  // ---------------- FP64 bookkeeping, last workgroup of problem p ----------
+// One workgroup per problem: the FP64 bookkeeping after the final update
+// sweep.  Start phase: beta, c0 = C^H r.  Arnoldi step: the new Hessenberg
+// column, B column, Givens rotation and residual estimate, and at the
+// cycle's end the least-squares solve.
+template <typename PT>
+__global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mode,
+                                                        int start_reorth) {
+  const int p = blockIdx.x;
+  int* st = P.stI + p * ST_NI;
+  if (st[ST_ACTIVE] == 0) return;
+  const int cgs2 = (mode == MODE_START) ? start_reorth : st[ST_REORTH];
+  const ProbDesc d = P.desc[p];
+  const int k = d.k;
+  const int n = (mode == MODE_START) ? k : k + j + 1;
+  const int m = P.m;
+  __shared__ double red[1];
+  reduce_rows<PT>(P, d.blk0, d.nblk, 1, red);
   __shared__ double2 col[DD_MAX_K + DD_MAX_M + 2];
   __shared__ int fin, nfin;
   const int t = threadIdx.x;
@@ -489,6 +535,11 @@ __global__ __launch_bounds__(DD_BLOCK) void k_update_norm(PlanDev P, int j, int 
       P.hscale[(size_t)p * (m + 1) + j + 1] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
       const int it = st[ST_ITERS] + 1;
       st[ST_ITERS] = it;
+      if (cgs2) {
+        st[ST_NREORTH] += 1;
+        sd[SD_NSUM2] += (double)n;
+      }
+      sd[SD_NSUM] += (double)n;
       st[ST_J] = j + 1;
       const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
       const double bn = sd[SD_BNORM];

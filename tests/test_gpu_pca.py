@@ -1,0 +1,65 @@
+"""GPU principal-component basis and projection loss against the oracle
+(Sec. 3, PCA paragraph; eq:proj_loss)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, fdfd, losses, pca
+
+pytestmark = pytest.mark.gpu
+
+
+def _planted(seed, D, M, sig):
+    rng = np.random.default_rng(seed)
+    r = len(sig)
+    U, _ = np.linalg.qr(W.random_complex(rng, (D, r)))
+    Wm, _ = np.linalg.qr(W.random_complex(rng, (M, r)))
+    S = U @ np.diag(sig) @ Wm.conj().T + 1e-4 * W.random_complex(rng, (D, M))
+    return S.astype(np.complex64)
+
+
+@pytest.mark.parametrize("D,M,k", [(5000, 40, 6), (3001, 70, 12), (20000, 33, 1)])
+def test_pca_build_matches_svd(D, M, k):
+    import torch
+    from paper_1902_00090_amd import pca_build
+    sig = np.geomspace(100.0, 1.0, 16)
+    S = _planted(D + M, D, M, sig)
+    Ug, sg = pca_build(torch.tensor(S.T.copy(), device="cuda"), k)
+    Uo, so = pca.pca_basis(S.astype(np.complex128), k)
+    np.testing.assert_allclose(sg, so, rtol=1e-5)
+    Ug = Ug.cpu().numpy().T.astype(np.complex128)
+    np.testing.assert_allclose(Ug.conj().T @ Ug, np.eye(k), atol=1e-5)
+    assert pca.principal_angles(Ug, Uo).max() < 1e-3
+
+
+def test_pca_of_solved_fields():
+    """Basis from fields of a short synthetic design trajectory (solved by sparse
+    LU here): spans agree with the oracle SVD where the spectrum has a gap."""
+    import torch
+    from paper_1902_00090_amd import pca_build
+    traj = W.trajectory(5000, 500000, 12, 96, 48, 1.30)
+    X = np.stack([direct.sparse_solve(fdfd.assemble_instance(t), t.b) for t in traj], 1)
+    X = X.astype(np.complex64)
+    Uo, so = pca.pca_basis(X.astype(np.complex128), 6)
+    Ug, sg = pca_build(torch.tensor(X.T.copy(), device="cuda"), 6)
+    np.testing.assert_allclose(sg, so, rtol=1e-4)
+    Ug = Ug.cpu().numpy().T.astype(np.complex128)
+    _, s_all = pca.pca_basis(X.astype(np.complex128), 7)
+    # compare the leading directions separated from the next by a 10% gap
+    gap_ok = [i for i in range(1, 7) if s_all[i - 1] > 1.1 * s_all[i]]
+    kk = max(gap_ok)
+    assert pca.principal_angles(Ug[:, :kk], Uo[:, :kk]).max() < 1e-3
+
+
+def test_proj_loss_matches_oracle():
+    import torch
+    from paper_1902_00090_amd import proj_loss_batched
+    rng = np.random.default_rng(4)
+    nb, k, D = 3, 5, 4000
+    V = W.random_complex(rng, (nb, k, D)).astype(np.complex64)
+    f = W.random_complex(rng, (nb, D))
+    f[1] = V[1].T.astype(np.complex128) @ W.random_complex(rng, k)   # inside span -> 0
+    lg = proj_loss_batched(torch.tensor(V, device="cuda"), torch.tensor(f, device="cuda"))
+    lo = [losses.proj_loss(V[p].T.astype(np.complex128), f[p]) for p in range(nb)]
+    np.testing.assert_allclose(lg, lo, atol=1e-5)
+    assert abs(lg[1]) < 1e-5 and all(0 <= x <= 1 + 1e-6 for x in lg)

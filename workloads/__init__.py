@@ -192,6 +192,25 @@ def correlated_batch(n_traj: int = 8, steps: int = 32):
     return out
 
 
+def trajectory_dataset(n_traj: int, steps: int, seed0: int = 70_000, nx: int = 480,
+                       ny: int = 240, wavelength: float = 1.30):
+    """Synthetic design-trajectory data set: n_traj trajectories of `steps`
+    correlated grating designs each (trajectory t: seeds seed0 + t and
+    10*seed0 + 100 t + s)."""
+    out = []
+    for t in range(n_traj):
+        out.extend(trajectory(seed0 + t, 10 * seed0 + 100 * t, steps, nx, ny, wavelength))
+    return out
+
+
+def split_train_test(n: int, train_frac: float = 0.75, seed: int = 0):
+    """Random split of n examples into training and evaluation index lists
+    (the paper's data set is split 75 / 25 over all trajectory steps)."""
+    perm = np.random.default_rng(seed).permutation(n)
+    ntr = int(round(train_frac * n))
+    return sorted(perm[:ntr].tolist()), sorted(perm[ntr:].tolist())
+
+
 # Named seed ranges for the PCA / CNN workloads (all 480x240, 1.30 um).
 PCA_TRAIN_SEED0 = 10_000
 PCA_TEST_SEED0 = 20_000
