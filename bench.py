@@ -31,6 +31,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per Arnoldi-step launch of the final update sweep, from two
+# rocprofv3 --pmc passes (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after
+# calibration on a 1 GiB copy) over this workload; valid only for the kernel
+# sources they were taken with (see profiles/).
+MEASURED_TRAFFIC = {"kernel": "k_update_norm", "bytes_per_launch": 3.173e9,
+                    "sources_sha256_16": "c0f9737f07994d55"}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("solver_kernels.h", "op.h"):
+        with open(os.path.join(ROOT, "paper_1902_00090_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -59,6 +75,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--oracle-check", type=int, default=2)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB of a plain device-to-device copy run first (for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -74,6 +92,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     dev = "cuda"
+    if args.calibrate_copy > 0:
+        # a copy kernel of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # calibrate the counters of the solver's sweeps
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
 
     # ---------------- data
     t0 = time.time()
@@ -180,10 +208,15 @@ def main():
     name = max(ks, key=lambda n: ks[n][0])
     ms_k, launches_k, bytes_k = ks[name]
     achieved = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
+    kname = {"matvec_dots": "k_matvec_dot", "second_pass": "k_update_dot",
+             "update_norm": "k_update_norm"}[name]
+    traffic = None
+    if (kname == MEASURED_TRAFFIC["kernel"] and args.batch == 64 and args.k == 20 and
+            kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]):
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": {"matvec_dots": "k_matvec_dot", "second_pass": "k_update_dot",
-                           "update_norm": "k_update_norm"}[name],
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname,
                 "avg_launch_us": round(1000 * ms_k / max(1, launches_k), 2),
                 "launches": int(launches_k),
                 "algorithmic_bytes_per_launch": round(bytes_k / max(1, launches_k))}

@@ -1,0 +1,160 @@
+"""Float64 convolutional subspace predictor: forward, backward, MSE loss, Adam.
+
+Test infrastructure (oracle): see the package docstring.
+
+Sec. 3 (CNN paragraph) and Methods: a convolutional network maps the
+permittivity image to N complex fields v_1..v_N; complex quantities are
+images with a real and an imaginary channel; training uses Adam.  The
+architecture figure of the paper is not available; the layer list below is
+the reading used throughout (an encoder-decoder of eight 3x3 convolutions):
+
+    1->32, 32->64 (stride 2), 64->128 (stride 2), 128->128,
+    nearest x2 upsample + 128->64, nearest x2 upsample + 64->32, 32->32,
+    32->2k (linear); ReLU after every layer but the last; zero padding 1.
+
+Input normalisation: (eps - 2.085) / (12.25 - 2.085).  Output channel
+2j holds Re v_j and channel 2j+1 holds Im v_j.
+
+Tensors are NCHW float64; weights are [out, in, 3, 3] (cross-correlation, as
+every deep-learning convolution).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS_LO, EPS_HI = 2.085, 12.25
+
+
+def layer_list(k: int = 10):
+    """(cin, cout, stride, upsample_before, relu) per layer."""
+    return [(1, 32, 1, 0, 1), (32, 64, 2, 0, 1), (64, 128, 2, 0, 1), (128, 128, 1, 0, 1),
+            (128, 64, 1, 1, 1), (64, 32, 1, 1, 1), (32, 32, 1, 0, 1), (32, 2 * k, 1, 0, 0)]
+
+
+def normalise(eps):
+    return (np.asarray(eps, np.float64) - EPS_LO) / (EPS_HI - EPS_LO)
+
+
+def init_params(k: int = 10, seed: int = 0):
+    """He-uniform weights, zero biases (float64)."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for cin, cout, _, _, _ in layer_list(k):
+        bound = np.sqrt(6.0 / (cin * 9))
+        params.append([rng.uniform(-bound, bound, (cout, cin, 3, 3)), np.zeros(cout)])
+    return params
+
+
+def upsample2(x):
+    return x.repeat(2, axis=2).repeat(2, axis=3)
+
+
+def conv_forward(x, w, b, stride):
+    """out[n,o,y,x] = b[o] + sum_{c,dy,dx} w[o,c,dy,dx] xpad[n,c,y*s+dy,x*s+dx]."""
+    n, c, H, W = x.shape
+    Ho, Wo = (H - 1) // stride + 1, (W - 1) // stride + 1
+    xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)))
+    out = np.broadcast_to(b[None, :, None, None], (n, w.shape[0], Ho, Wo)).copy()
+    for dy in range(3):
+        for dx in range(3):
+            patch = xp[:, :, dy:dy + stride * (Ho - 1) + 1:stride, dx:dx + stride * (Wo - 1) + 1:stride]
+            out += np.einsum("nchw,oc->nohw", patch, w[:, :, dy, dx], optimize=True)
+    return out
+
+
+def conv_backward(x, w, dz, stride):
+    """Gradients of conv_forward w.r.t. x, w, b given dL/dout = dz."""
+    n, c, H, W = x.shape
+    Ho, Wo = dz.shape[2], dz.shape[3]
+    xp = np.pad(x, ((0, 0), (0, 0), (1, 1), (1, 1)))
+    dxp = np.zeros_like(xp)
+    dw = np.zeros_like(w)
+    for dy in range(3):
+        for dx in range(3):
+            sl = (slice(None), slice(None), slice(dy, dy + stride * (Ho - 1) + 1, stride),
+                  slice(dx, dx + stride * (Wo - 1) + 1, stride))
+            dw[:, :, dy, dx] = np.einsum("nohw,nchw->oc", dz, xp[sl], optimize=True)
+            dxp[sl] += np.einsum("nohw,oc->nchw", dz, w[:, :, dy, dx], optimize=True)
+    return dxp[:, :, 1:-1, 1:-1], dw, dz.sum(axis=(0, 2, 3))
+
+
+def forward(params, eps, k: int = 10):
+    """eps: [B, H, W] permittivity.  Returns (out [B, 2k, H, W], cache)."""
+    x = normalise(eps)[:, None]
+    cache = []
+    for (cin, cout, s, up, relu), (w, b) in zip(layer_list(k), params):
+        xin = upsample2(x) if up else x
+        z = conv_forward(xin, w, b, s)
+        y = np.maximum(z, 0.0) if relu else z
+        cache.append((x, xin, z))
+        x = y
+    return x, cache
+
+
+def mse(out, target):
+    d = out - target
+    return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def backward(params, cache, dout, k: int = 10):
+    """Gradients [[dw, db], ...] of the loss whose derivative w.r.t. the output is dout."""
+    grads = [None] * len(params)
+    dy = dout
+    for li in range(len(params) - 1, -1, -1):
+        cin, cout, s, up, relu = layer_list(k)[li]
+        x, xin, z = cache[li]
+        dz = dy * (z > 0) if relu else dy
+        dxin, dw, db = conv_backward(xin, params[li][0], dz, s)
+        grads[li] = [dw, db]
+        if up:
+            B, C, H2, W2 = dxin.shape
+            dxin = dxin.reshape(B, C, H2 // 2, 2, W2 // 2, 2).sum(axis=(3, 5))
+        dy = dxin
+    return grads
+
+
+def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba): state = {'t': int, 'm': [...], 'v': [...]} updated in place."""
+    if not state:
+        state.update(t=0, m=[[np.zeros_like(a) for a in p] for p in params],
+                     v=[[np.zeros_like(a) for a in p] for p in params])
+    state["t"] += 1
+    t = state["t"]
+    for p, g, m, v in zip(params, grads, state["m"], state["v"]):
+        for i in range(len(p)):
+            m[i][...] = b1 * m[i] + (1 - b1) * g[i]
+            v[i][...] = b2 * v[i] + (1 - b2) * g[i] * g[i]
+            mh = m[i] / (1 - b1 ** t)
+            vh = v[i] / (1 - b2 ** t)
+            p[i][...] = p[i] - lr * mh / (np.sqrt(vh) + eps)
+
+
+def fields_to_channels(U, H, W):
+    """U: [B, k, H*W] complex -> [B, 2k, H, W] real (re, im interleaved by channel)."""
+    B, k, _ = U.shape
+    out = np.empty((B, 2 * k, H, W))
+    out[:, 0::2] = U.real.reshape(B, k, H, W)
+    out[:, 1::2] = U.imag.reshape(B, k, H, W)
+    return out
+
+
+def channels_to_fields(Y):
+    B, C, H, W = Y.shape
+    return (Y[:, 0::2] + 1j * Y[:, 1::2]).reshape(B, C // 2, H * W)
+
+
+def local_pca_targets(F, window: int, k: int):
+    """Training targets for one trajectory (reading of the config: MSE against
+    the top-k local PCA projection).  F: [S, D] complex solutions of the steps
+    of one trajectory, each normalised to unit norm.  For step s, U_loc = the
+    top-k left singular vectors of the solutions of steps s-window..s+window;
+    target field j = u_j (u_j^H f_s).  Returns [S, k, D] complex."""
+    S, D = F.shape
+    out = np.zeros((S, k, D), np.complex128)
+    for s in range(S):
+        lo, hi = max(0, s - window), min(S, s + window + 1)
+        U, _, _ = np.linalg.svd(F[lo:hi].T, full_matrices=False)
+        kk = min(k, U.shape[1])
+        c = U[:, :kk].conj().T @ F[s]
+        out[s, :kk] = (U[:, :kk] * c[None, :]).T
+    return out
