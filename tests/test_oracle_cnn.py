@@ -1,0 +1,111 @@
+"""Pins of the float64 CNN oracle (Sec. 3 CNN paragraph; Methods: Adam)."""
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+from oracle import cnn
+
+
+def test_conv_single_channel_is_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((1, 1, 9, 13))
+    w = rng.standard_normal((1, 1, 3, 3))
+    b = np.array([0.3])
+    out = cnn.conv_forward(x, w, b, 1)
+    ref = correlate2d(x[0, 0], w[0, 0], mode="same", boundary="fill") + 0.3
+    np.testing.assert_allclose(out[0, 0], ref, atol=1e-12)
+
+
+def test_conv_stride2_is_subsampled_stride1():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 3, 8, 12))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    np.testing.assert_allclose(cnn.conv_forward(x, w, b, 2),
+                               cnn.conv_forward(x, w, b, 1)[:, :, ::2, ::2], atol=1e-12)
+
+
+def test_conv_backward_is_adjoint():
+    """<conv(x), z> - <b,sum z> = <x, dX(z)> and = <w, dW(z)> (linear in x and w)."""
+    rng = np.random.default_rng(2)
+    for s in (1, 2):
+        x = rng.standard_normal((2, 3, 8, 10))
+        w = rng.standard_normal((5, 3, 3, 3))
+        b = np.zeros(5)
+        y = cnn.conv_forward(x, w, b, s)
+        z = rng.standard_normal(y.shape)
+        dx, dw, db = cnn.conv_backward(x, w, z, s)
+        np.testing.assert_allclose(np.sum(y * z), np.sum(x * dx), rtol=1e-12)
+        np.testing.assert_allclose(np.sum(y * z), np.sum(w * dw), rtol=1e-12)
+        np.testing.assert_allclose(db, z.sum(axis=(0, 2, 3)), rtol=1e-12)
+
+
+def test_network_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    k = 2
+    params = cnn.init_params(k, seed=4)
+    for p in params:                      # non-zero biases so every term is exercised
+        p[1][...] = 0.05 * rng.standard_normal(p[1].shape)
+    eps = 2.085 + 10.165 * rng.random((2, 8, 12))
+    out, cache = cnn.forward(params, eps, k)
+    target = rng.standard_normal(out.shape)
+    loss, dout = cnn.mse(out, target)
+    grads = cnn.backward(params, cache, dout, k)
+    h = 1e-6
+    for li in range(8):
+        for which in (0, 1):
+            arr = params[li][which]
+            for _ in range(2):
+                idx = tuple(rng.integers(0, s) for s in arr.shape)
+                old = arr[idx]
+                arr[idx] = old + h
+                lp, _ = cnn.mse(cnn.forward(params, eps, k)[0], target)
+                arr[idx] = old - h
+                lm, _ = cnn.mse(cnn.forward(params, eps, k)[0], target)
+                arr[idx] = old
+                fd = (lp - lm) / (2 * h)
+                an = grads[li][which][idx]
+                assert abs(fd - an) <= 1e-6 * max(1e-8, abs(fd)) + 1e-11, (li, which, fd, an)
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments the first bias-corrected step is lr * g / (|g| + eps)."""
+    p = [[np.array([1.0, -2.0, 3.0])]]
+    g = [[np.array([0.5, -4.0, 1e-3])]]
+    st = {}
+    cnn.adam_step(p, g, st, lr=0.1)
+    np.testing.assert_allclose(p[0][0], [1.0 - 0.1 * 0.5 / (0.5 + 1e-8),
+                                         -2.0 + 0.1 * 4.0 / (4.0 + 1e-8),
+                                         3.0 - 0.1 * 1e-3 / (1e-3 + 1e-8)], rtol=1e-12)
+
+
+def test_local_pca_targets():
+    rng = np.random.default_rng(5)
+    S, D, k = 9, 40, 3
+    F = rng.standard_normal((S, D)) + 1j * rng.standard_normal((S, D))
+    F /= np.linalg.norm(F, axis=1, keepdims=True)
+    T = cnn.local_pca_targets(F, window=2, k=k)
+    for s in range(S):
+        lo, hi = max(0, s - 2), min(S, s + 3)
+        U, _, _ = np.linalg.svd(F[lo:hi].T, full_matrices=False)
+        Pf = U[:, :k] @ (U[:, :k].conj().T @ F[s])
+        np.testing.assert_allclose(T[s].sum(0), Pf, atol=1e-12)      # sum of targets = projection
+        G = T[s] @ T[s].conj().T                                     # targets mutually orthogonal
+        np.testing.assert_allclose(G - np.diag(np.diag(G)), 0, atol=1e-12)
+    # invariant under a per-step phase of the solutions
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, S))
+    T2 = cnn.local_pca_targets(F * ph[:, None], window=2, k=k)
+    np.testing.assert_allclose(T2, T * ph[:, None, None], atol=1e-10)
+    # a window of identical fields: the target reproduces the field
+    G = np.repeat(F[:1], 5, axis=0)
+    np.testing.assert_allclose(cnn.local_pca_targets(G, 1, 2)[2].sum(0), F[0], atol=1e-12)
+
+
+def test_channel_packing_roundtrip():
+    rng = np.random.default_rng(6)
+    U = rng.standard_normal((2, 3, 20)) + 1j * rng.standard_normal((2, 3, 20))
+    Y = cnn.fields_to_channels(U, 4, 5)
+    assert Y.shape == (2, 6, 4, 5)
+    np.testing.assert_allclose(Y[:, 0], U[:, 0].real.reshape(2, 4, 5))
+    np.testing.assert_allclose(Y[:, 1], U[:, 0].imag.reshape(2, 4, 5))
+    np.testing.assert_allclose(cnn.channels_to_fields(Y), U)
