@@ -1,5 +1,148 @@
-"""Convolutional subspace predictor binding (filled in with the CNN kernels)."""
+"""Binding of the convolutional subspace predictor (dd_cnn_* in the C ABI).
+
+Argument marshalling only: the forward pass, backward pass and Adam run in
+the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import check
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, numel, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous CUDA (HIP) tensor")
+    if t.dtype != dtype or t.numel() != numel:
+        raise ValueError(f"{what} must be {dtype} with {numel} elements")
+    return C.c_void_p(t.data_ptr())
 
 
 class Cnn:
-    pass
+    """Encoder-decoder CNN mapping permittivity [B, ny, nx] to k complex fields."""
+
+    def __init__(self, nx, ny, max_batch, k=10, seed=0):
+        self.nx, self.ny, self.max_batch, self.k = int(nx), int(ny), int(max_batch), int(k)
+        self.D = self.nx * self.ny
+        h = C.c_void_p()
+        check(_lib.lib().dd_cnn_create(self.nx, self.ny, self.max_batch, self.k,
+                                       C.c_ulonglong(seed), C.byref(h)), "dd_cnn_create")
+        self._h = h
+
+    def layers(self):
+        out = []
+        n = _lib.lib().dd_cnn_layer_info(self._h, -1, None, None, None, None, None)
+        for l in range(n):
+            v = [C.c_int() for _ in range(5)]
+            _lib.lib().dd_cnn_layer_info(self._h, l, *[C.byref(x) for x in v])
+            out.append(tuple(x.value for x in v))
+        return out
+
+    @property
+    def num_params(self):
+        return _lib.lib().dd_cnn_num_params(self._h)
+
+    def get_params(self):
+        out = np.zeros(self.num_params, np.float32)
+        check(_lib.lib().dd_cnn_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                           out.size), "dd_cnn_get_params")
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        check(_lib.lib().dd_cnn_set_params(self._h, flat.ctypes.data_as(C.POINTER(C.c_float)),
+                                           flat.size), "dd_cnn_set_params")
+
+    def predict(self, eps, U=None):
+        """eps: [B, ny, nx] float32 (device).  Returns U [B, k, D] complex64."""
+        torch = _torch()
+        B = eps.shape[0]
+        if U is None:
+            U = torch.empty((B, self.k, self.D), dtype=torch.complex64, device=eps.device)
+        check(_lib.lib().predict_subspace(self._h, _dev(eps, torch.float32, B * self.D, "eps"), B,
+                                          _dev(U, torch.complex64, B * self.k * self.D, "U"),
+                                          _stream()), "predict_subspace")
+        return U
+
+    def train_step(self, eps, target, lr=1e-3, b1=0.9, b2=0.999):
+        torch = _torch()
+        B = eps.shape[0]
+        loss = C.c_float()
+        check(_lib.lib().dd_cnn_train_step(
+            self._h, _dev(eps, torch.float32, B * self.D, "eps"),
+            _dev(target, torch.complex64, B * self.k * self.D, "target"), B, float(lr), float(b1),
+            float(b2), C.byref(loss), _stream()), "dd_cnn_train_step")
+        return loss.value
+
+    def grad(self, eps, target):
+        torch = _torch()
+        B = eps.shape[0]
+        loss = C.c_float()
+        g = np.zeros(self.num_params, np.float32)
+        check(_lib.lib().dd_cnn_grad(
+            self._h, _dev(eps, torch.float32, B * self.D, "eps"),
+            _dev(target, torch.complex64, B * self.k * self.D, "target"), B, C.byref(loss),
+            g.ctypes.data_as(C.POINTER(C.c_float)), g.size, _stream()), "dd_cnn_grad")
+        return loss.value, g
+
+    def activation(self, layer, B):
+        """Layer output (NHWC, float32) of the last forward pass; layer -1 = input."""
+        if layer == -1:
+            shape = (B, self.ny, self.nx)
+        else:
+            H, W = self.ny, self.nx
+            for l, (cin, cout, s, up, relu) in enumerate(self.layers()):
+                if up:
+                    H, W = 2 * H, 2 * W
+                elif s == 2:
+                    H, W = H // 2, W // 2
+                if l == layer:
+                    shape = (B, H, W, cout)
+                    break
+        out = np.zeros(shape, np.float32)
+        check(_lib.lib().dd_cnn_debug_activation(self._h, layer, B,
+                                                 out.ctypes.data_as(C.POINTER(C.c_float)),
+                                                 out.size), "dd_cnn_debug_activation")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().dd_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def flat_to_layers(flat, layers):
+    """Split the flat parameter vector into [[w (cout, cin, 3, 3), b (cout)], ...]."""
+    out, off = [], 0
+    for cin, cout, _, _, _ in layers:
+        nw = cout * cin * 9
+        w = flat[off:off + nw].reshape(cout, cin, 3, 3)
+        off += nw
+        b = flat[off:off + cout]
+        off += cout
+        out.append([w, b])
+    return out
+
+
+def layers_to_flat(params):
+    return np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for w, b in params])

@@ -1,0 +1,75 @@
+"""Host-side checks that need no GPU: the library loads and exports every
+function include/ddgmres.h declares; argument validation that happens before
+any device call; bench.py's single-GPU contract."""
+import ctypes as C
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddgmres.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:dd_status|void|int|size_t|char\s*\*)\s*\*?\s*(\w+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_paper_path():
+    names = declared_functions()
+    for n in ["fdfd_op_create", "fdfd_op_apply", "gmres_solve", "gmres_solve_batched",
+              "dd_solver_solve", "predict_subspace", "pca_build", "dd_cnn_train_step",
+              "dd_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1902_00090_amd import _lib
+    lib = C.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_operator_argument_validation_on_host():
+    from paper_1902_00090_amd import FdfdOp, DDError, _lib
+    eps = np.full((10, 10), 2.0, np.float32)
+    cases = [dict(omega=-1.0, dx=0.04, npml=2), dict(omega=4.0, dx=0.0, npml=2),
+             dict(omega=4.0, dx=0.04, npml=5), dict(omega=float("nan"), dx=0.04, npml=0)]
+    for kw in cases:
+        with pytest.raises(DDError) as ei:
+            FdfdOp(eps, **kw)
+        assert ei.value.status == _lib.DD_EINVAL
+    with pytest.raises(DDError):
+        FdfdOp(np.full((2, 10), 2.0, np.float32), 4.0, 0.04, 0)
+    bad = eps.copy()
+    bad[3, 3] = np.inf
+    with pytest.raises(DDError) as ei:
+        FdfdOp(bad, 4.0, 0.04, 2)
+    assert ei.value.status == _lib.DD_ENONFINITE
+    assert "not finite" in _lib.lib().dd_last_error().decode()
+
+
+def test_other_entry_points_reject_bad_arguments_on_host():
+    from paper_1902_00090_amd import _lib
+    lib = _lib.lib()
+    h = C.c_void_p()
+    assert lib.dd_solver_create(None, 0, None, C.byref(h)) == _lib.DD_EINVAL
+    assert lib.dd_cnn_create(30, 16, 1, 10, 0, C.byref(h)) == _lib.DD_EINVAL   # nx % 4 != 0
+    assert lib.dd_cnn_create(32, 16, 0, 10, 0, C.byref(h)) == _lib.DD_EINVAL   # max_batch 0
+    assert lib.pca_build(None, 10, 100, 3, None, None, None) == _lib.DD_EINVAL
+    assert lib.proj_loss_batched(None, None, 1, 1, 1, None, None) == _lib.DD_EINVAL
+    assert lib.dd_solver_kernel_stats(None, None) == _lib.DD_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
