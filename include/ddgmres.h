@@ -224,6 +224,16 @@ dd_status gmres_solve_batched(const fdfd_op* const* ops, int nb, const void* con
 dd_status pca_build(const void* S, int M, int D, int k, void* U, double* sigma,
                     hipStream_t stream);
 
+/* Training targets of the convolutional predictor from one trajectory of
+ * solution fields F [S][D] c64 (device): for step s, U_loc = the leading k
+ * left singular vectors of the unit-normalised fields of steps
+ * s-window .. s+window, and target j = u_j (u_j^H f_s) with f_s normalised
+ * (ordered by singular value, independent of the singular vectors' phases).
+ * T: [S][k][D] c64 output (device); targets beyond the window's rank are 0.
+ * Synchronises the stream. */
+dd_status local_pca_targets(const void* F, int S, int D, int window, int k, void* T,
+                            hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Projection loss of a subspace (Sec. 3, eq:proj_loss), batched evaluation
  * ------------------------------------------------------------------------

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import DD_C64, DD_C128, DDError, check, ptr_array
 
 __all__ = ["FdfdOp", "Solver", "gmres_solve", "gmres_solve_batched", "pca_build",
-           "proj_loss_batched", "Cnn", "DDError", "lib_path"]
+           "local_pca_targets", "proj_loss_batched", "Cnn", "DDError", "lib_path"]
 
 
 def lib_path() -> str:
@@ -266,6 +266,17 @@ def pca_build(S, k):
     check(_lib.lib().pca_build(_dev(S, torch.complex64, what="S"), M, D, k, _dev(U),
                                sig.ctypes.data_as(C.POINTER(C.c_double)), _stream()), "pca_build")
     return U, sig
+
+
+def local_pca_targets(F, window, k):
+    """F: [S, D] complex64 solution fields of one trajectory (device).
+    Returns T [S, k, D] complex64: target j of step s is u_j (u_j^H f_s)."""
+    torch = _torch()
+    S, D = F.shape
+    T = torch.empty((S, k, D), dtype=torch.complex64, device=F.device)
+    check(_lib.lib().local_pca_targets(_dev(F, torch.complex64, what="F"), S, D, int(window), int(k),
+                                       _dev(T), _stream()), "local_pca_targets")
+    return T
 
 
 def proj_loss_batched(V, f):

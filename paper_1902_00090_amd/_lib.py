@@ -78,6 +78,7 @@ _SIGS = {
                                 C.POINTER(dd_solver_opts), PP, C.POINTER(dd_info), P]),
     "pca_build": (I, [P, I, I, I, P, C.POINTER(D), P]),
     "proj_loss_batched": (I, [P, P, I, I, I, C.POINTER(D), P]),
+    "local_pca_targets": (I, [P, I, I, I, I, P, P]),
     "dd_cnn_create": (I, [I, I, I, I, C.c_ulonglong, PP]),
     "dd_cnn_destroy": (None, [P]),
     "dd_cnn_layer_info": (I, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(I),

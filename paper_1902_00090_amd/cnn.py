@@ -68,14 +68,21 @@ class Cnn:
                                            flat.size), "dd_cnn_set_params")
 
     def predict(self, eps, U=None):
-        """eps: [B, ny, nx] float32 (device).  Returns U [B, k, D] complex64."""
+        """eps: [B, ny, nx] float32 (device).  Returns U [B, k, D] complex64.
+        Batches larger than max_batch are run in chunks."""
         torch = _torch()
         B = eps.shape[0]
         if U is None:
             U = torch.empty((B, self.k, self.D), dtype=torch.complex64, device=eps.device)
-        check(_lib.lib().predict_subspace(self._h, _dev(eps, torch.float32, B * self.D, "eps"), B,
-                                          _dev(U, torch.complex64, B * self.k * self.D, "U"),
-                                          _stream()), "predict_subspace")
+        _dev(eps, torch.float32, B * self.D, "eps")
+        _dev(U, torch.complex64, B * self.k * self.D, "U")
+        for b0 in range(0, B, self.max_batch):
+            nb = min(self.max_batch, B - b0)
+            e = eps[b0:b0 + nb]
+            u = U[b0:b0 + nb]
+            check(_lib.lib().predict_subspace(self._h, C.c_void_p(e.data_ptr()), nb,
+                                              C.c_void_p(u.data_ptr()), _stream()),
+                  "predict_subspace")
         return U
 
     def train_step(self, eps, target, lr=1e-3, b1=0.9, b2=0.999):

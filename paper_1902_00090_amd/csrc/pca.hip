@@ -329,6 +329,29 @@ static dd_status gram_host(const float2* V, int k, int D, const double2* f, std:
   return DD_OK;
 }
 
+// G_ab = <F_a, F_b> (S x S, FP64) of S device rows of D complex64 values,
+// through the tiled Gram kernel.
+static dd_status gram_rows(const float2* F, int S, int D, std::vector<cd>& G, hipStream_t stream) {
+  const int nta = (S + PT - 1) / PT;
+  const int ntiles = nta * (nta + 1) / 2;
+  int nslices = std::max(1, std::min(256, 4096 / std::max(1, ntiles)));
+  nslices = std::min(nslices, std::max(1, D / PE));
+  double2 *part = nullptr, *dG = nullptr;
+  DD_HIP_CHECK(hipMalloc((void**)&part, sizeof(double2) * nslices * nta * nta * PT * PT));
+  DD_HIP_CHECK(hipMalloc((void**)&dG, sizeof(double2) * S * S));
+  k_pca_gram<<<dim3(nta, nta, nslices), 256, 0, stream>>>(F, S, D, nslices, part);
+  k_pca_gram_reduce<<<dim3((S + 255) / 256, S), 256, 0, stream>>>(part, S, nta, nslices, dG);
+  DD_HIP_CHECK(hipGetLastError());
+  std::vector<double2> h((size_t)S * S);
+  DD_HIP_CHECK(hipMemcpyAsync(h.data(), dG, sizeof(double2) * S * S, hipMemcpyDeviceToHost, stream));
+  DD_HIP_CHECK(hipStreamSynchronize(stream));
+  DD_HIP_CHECK(hipFree(part));
+  DD_HIP_CHECK(hipFree(dG));
+  G.resize((size_t)S * S);
+  for (size_t i = 0; i < G.size(); ++i) G[i] = cd(h[i].x, h[i].y);
+  return DD_OK;
+}
+
 // Cholesky G = L L^H of the leading k x k block (stride ld); returns false if
 // not positive definite.  T = L^{-H} (upper triangular, row-major k x k).
 static bool chol_inv(const std::vector<cd>& G, int ld, int k, std::vector<cd>& L,
@@ -425,6 +448,87 @@ extern "C" dd_status pca_build(const void* Sv, int M, int D, int k, void* Uv, do
   DD_HIP_CHECK(hipGetLastError());
   DD_HIP_CHECK(hipStreamSynchronize(stream));
   DD_HIP_CHECK(hipFree(dT));
+  return DD_OK;
+}
+
+// T[s][j] = sum_m coef[s][m][j] F[m] for the S steps of one trajectory:
+// coef is [S][S][k] (FP64, zero outside each step's window), one thread per
+// element, grid.y = (step, group of 16 outputs).
+__global__ __launch_bounds__(256) void k_local_combine(const float2* __restrict__ F, int S, int D,
+                                                       const double2* __restrict__ coef, int k,
+                                                       float2* __restrict__ T) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y / ((k + 15) / 16), o0 = (blockIdx.y % ((k + 15) / 16)) * 16;
+  if (e >= D) return;
+  double2 acc[16];
+#pragma unroll
+  for (int o = 0; o < 16; ++o) acc[o] = make_double2(0.0, 0.0);
+  for (int m = 0; m < S; ++m) {
+    const float2 f = F[(size_t)m * D + e];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+      if (o0 + o >= k) break;
+      const double2 c = coef[((size_t)s * S + m) * k + o0 + o];
+      acc[o].x += c.x * f.x - c.y * f.y;
+      acc[o].y += c.x * f.y + c.y * f.x;
+    }
+  }
+  for (int o = 0; o < 16 && o0 + o < k; ++o)
+    T[((size_t)s * k + o0 + o) * D + e] = make_float2((float)acc[o].x, (float)acc[o].y);
+}
+
+// Training targets of the convolutional predictor from one trajectory's
+// solution fields: for step s, U_loc = the leading k left singular vectors
+// of the (unit-normalised) fields of steps s-window..s+window, and target j
+// = u_j (u_j^H f_s).  With the window's Gram matrix G (from the trajectory
+// Gram matrix) = W diag(sigma^2) W^H, u_j = sum_m W_mj f_m / sigma_j and
+// u_j^H f_s = sum_m conj(W_mj) G_ms / sigma_j, so every target is a combination
+// of the trajectory's fields with coefficients from a small host problem.
+extern "C" dd_status local_pca_targets(const void* Fv, int S, int D, int window, int k,
+                                       void* Tv, hipStream_t stream) {
+  if (!Fv || !Tv || S < 1 || D < 1 || k < 1 || window < 0 || k > DD_MAX_KPCA) {
+    dd_set_error("local_pca_targets: bad argument");
+    return DD_EINVAL;
+  }
+  const float2* F = (const float2*)Fv;
+  // trajectory Gram matrix of the normalised fields (normalisation applied here)
+  std::vector<cd> G0;
+  dd_status rc = gram_rows(F, S, D, G0, stream);
+  if (rc != DD_OK) return rc;
+  std::vector<double> nrm(S);
+  for (int a = 0; a < S; ++a) nrm[a] = std::sqrt(std::max(G0[(size_t)a * S + a].real(), 1e-300));
+  std::vector<double2> hc((size_t)S * S * k, make_double2(0.0, 0.0));
+  for (int s = 0; s < S; ++s) {
+    const int lo = std::max(0, s - window), hi = std::min(S, s + window + 1), M = hi - lo;
+    std::vector<cd> G((size_t)M * M);
+    for (int a = 0; a < M; ++a)
+      for (int b = 0; b < M; ++b)
+        G[(size_t)a * M + b] = G0[(size_t)(lo + a) * S + lo + b] / (nrm[lo + a] * nrm[lo + b]);
+    const int kk = std::min(k, M);
+    std::vector<double> theta;
+    std::vector<cd> W;
+    lanczos_top(G, M, kk, theta, W);
+    for (int j = 0; j < kk; ++j) {
+      if (!(theta[j] > 1e-24 * std::max(theta[0], 1e-300))) continue;
+      const double sg = std::sqrt(theta[j]);
+      cd c = 0.0;  // u_j^H f_s (f_s normalised)
+      for (int m = 0; m < M; ++m) c += std::conj(W[(size_t)m * kk + j]) * G[(size_t)m * M + (s - lo)];
+      c /= sg;
+      for (int m = 0; m < M; ++m) {
+        // target_j = sum_m (W_mj / sigma_j) c f_m / ||f_m||  (fields normalised)
+        const cd v = W[(size_t)m * kk + j] / sg * c / nrm[lo + m];
+        hc[((size_t)s * S + lo + m) * k + j] = make_double2(v.real(), v.imag());
+      }
+    }
+  }
+  double2* coef = nullptr;
+  DD_HIP_CHECK(hipMalloc((void**)&coef, sizeof(double2) * hc.size()));
+  DD_HIP_CHECK(hipMemcpyAsync(coef, hc.data(), sizeof(double2) * hc.size(), hipMemcpyHostToDevice, stream));
+  k_local_combine<<<dim3((D + 255) / 256, S * ((k + 15) / 16)), 256, 0, stream>>>(F, S, D, coef, k,
+                                                                                  (float2*)Tv);
+  DD_HIP_CHECK(hipGetLastError());
+  DD_HIP_CHECK(hipStreamSynchronize(stream));
+  DD_HIP_CHECK(hipFree(coef));
   return DD_OK;
 }
 

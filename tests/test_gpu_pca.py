@@ -63,3 +63,24 @@ def test_proj_loss_matches_oracle():
     lo = [losses.proj_loss(V[p].T.astype(np.complex128), f[p]) for p in range(nb)]
     np.testing.assert_allclose(lg, lo, atol=1e-5)
     assert abs(lg[1]) < 1e-5 and all(0 <= x <= 1 + 1e-6 for x in lg)
+
+
+def test_local_pca_targets_match_oracle():
+    import torch
+    from paper_1902_00090_amd import local_pca_targets
+    from oracle import cnn as ocnn
+    traj = W.trajectory(5100, 510000, 10, 64, 32, 1.30)
+    F = np.stack([direct.sparse_solve(fdfd.assemble_instance(t), t.b) for t in traj]).astype(np.complex64)
+    Fn = F.astype(np.complex128)
+    Fn /= np.linalg.norm(Fn, axis=1, keepdims=True)
+    k, window = 3, 2
+    To = ocnn.local_pca_targets(Fn, window, k)
+    Tg = local_pca_targets(torch.tensor(F, device="cuda"), window, k).cpu().numpy()
+    # the targets' sum over j is the projection of f_s on span(U_loc): unique
+    np.testing.assert_allclose(Tg.sum(1), To.sum(1), atol=1e-4)
+    # individual targets are unique where the window's singular values are distinct
+    for s in range(len(traj)):
+        lo, hi = max(0, s - window), min(len(traj), s + window + 1)
+        sv = np.append(np.linalg.svd(Fn[lo:hi].T, compute_uv=False), 0.0)
+        if np.all(sv[:k] > 1.05 * sv[1:k + 1]):
+            np.testing.assert_allclose(Tg[s], To[s], atol=1e-4)
