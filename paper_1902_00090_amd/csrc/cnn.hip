@@ -258,26 +258,33 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
   }
 }
 
-// Layer-1 weight gradient partials: thread (co, tap) sums over a pixel slice.
+// Layer-1 weight gradient partials: thread (co, tap) sums over the rows
+// [r0, r1) of the batch (row = one image row), walking x without divisions.
 __global__ __launch_bounds__(320) void k_conv1_wgrad(const float* __restrict__ x0,
                                                      const bf16* __restrict__ dz, int B, int H,
-                                                     int W, int cout, int coutp, int per,
+                                                     int W, int cout, int coutp, int rows_per,
                                                      float* __restrict__ part) {
   const int t = threadIdx.x;
-  const int npix = B * H * W;
-  const int p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
+  const int r0 = blockIdx.x * rows_per, r1 = min(B * H, r0 + rows_per);
   if (t >= cout * 10) return;
   const int co = t / 10, tap = t % 10;  // tap 9 = bias
+  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
   float s = 0.f;
-  for (int p = p0; p < p1; ++p) {
-    const float g = bf2f(dz[(size_t)p * coutp + co]);
-    float xv = 1.f;
-    if (tap < 9) {
-      const int b = p / (H * W), rem = p - b * H * W, y = rem / W, x = rem - (rem / W) * W;
-      const int ys = y + tap / 3 - 1, xs = x + tap % 3 - 1;
-      xv = (ys >= 0 && ys < H && xs >= 0 && xs < W) ? x0[((size_t)b * H + ys) * W + xs] : 0.f;
+  for (int row = r0; row < r1; ++row) {
+    const int b = row / H, y = row - b * H;
+    const int ys = y + dy;
+    const bool rowok = (tap == 9) || (ys >= 0 && ys < H);
+    const float* xr = x0 + ((size_t)b * H + (rowok && tap < 9 ? ys : 0)) * W;
+    const bf16* g = dz + (size_t)row * W * coutp + co;
+    if (!rowok) continue;
+    for (int x = 0; x < W; ++x) {
+      float xv = 1.f;
+      if (tap < 9) {
+        const int xs = x + dx;
+        xv = (xs >= 0 && xs < W) ? xr[xs] : 0.f;
+      }
+      s += bf2f(g[(size_t)x * coutp]) * xv;
     }
-    s += g * xv;
   }
   part[(size_t)blockIdx.x * cout * 10 + t] = s;
 }
@@ -355,14 +362,24 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16* __restrict__ dz,
   }
 }
 
-// Bias-gradient partials: column sums of dz over a pixel slice.
+// Bias-gradient partials: column sums of dz over a pixel slice.  Thread t
+// handles channel t % Mr of pixels p0 + t / Mr + j * (256 / Mr), so a wave's
+// loads cover whole pixel rows (coalesced); the 256 / Mr lanes of a channel
+// are then added in a fixed order.
 __global__ __launch_bounds__(256) void k_bias_grad(const bf16* __restrict__ dz, int npix, int Mr,
                                                    int per, float* __restrict__ part) {
+  __shared__ float red[256];
   const int p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
-  for (int r = threadIdx.x; r < Mr; r += 256) {
-    float s = 0.f;
-    for (int p = p0; p < p1; ++p) s += bf2f(dz[(size_t)p * Mr + r]);
-    part[(size_t)blockIdx.x * Mr + r] = s;
+  const int G = 256 / Mr, c = threadIdx.x % Mr, g = threadIdx.x / Mr;
+  float s = 0.f;
+  if (g < G)
+    for (int p = p0 + g; p < p1; p += G) s += bf2f(dz[(size_t)p * Mr + c]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < Mr) {
+    float t = 0.f;
+    for (int q = 0; q < G; ++q) t += red[q * Mr + threadIdx.x];
+    part[(size_t)blockIdx.x * Mr + threadIdx.x] = t;
   }
 }
 
@@ -473,6 +490,9 @@ __global__ void k_pad_bias(const float* __restrict__ b, int cout, int coutp, flo
 // ============================================================ host side ====
 static int rup16(int c) { return (c + 15) / 16 * 16; }
 
+// pixels per weight-gradient slice: about 256 slices, multiples of 32
+static int wgrad_per(int npix) { return std::max(2048, ((npix + 255) / 256 + 31) / 32 * 32); }
+
 template <typename X>
 static hipError_t cnn_alloc(dd_cnn* n, X** p, size_t count) {
   hipError_t e = hipMalloc((void**)p, std::max<size_t>(count * sizeof(X), 256));
@@ -560,11 +580,13 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, unsigne
     }
     if (l < NL - 1) chk(cnn_alloc(n, &n->act[l], pix * L.coutp));
     chk(cnn_alloc(n, &n->dz[l], pix * L.coutp));
-    // weight-gradient partials: slices of 2048 output pixels
-    const size_t slices = (pix + 2047) / 2048;
+    // weight-gradient partials (slices as in backward())
+    // any batch B <= max_batch gives at most ~257 slices (wgrad_per)
+    const size_t per = (size_t)wgrad_per((int)pix);
+    const size_t slices = std::max<size_t>((pix + per - 1) / per, 260);
     if (l > 0) wp = std::max(wp, slices * 9 * L.coutp * L.cinp);
     wp = std::max(wp, slices * (size_t)L.coutp);
-    wp = std::max(wp, slices * (size_t)L.cout * 10);
+    wp = std::max(wp, (size_t)512 * L.cout * 10);
   }
   n->wpart_elems = wp;
   chk(cnn_alloc(n, &n->wpart, wp));
@@ -687,8 +709,8 @@ static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hip
   for (int l = NL - 1; l >= 1; --l) {
     const CnnLayer& L = n->L[l];
     const int npo = B * L.Hout * L.Wout;
-    // weight and bias gradients of layer l
-    const int per = 2048;
+    // weight and bias gradients of layer l: about 256 pixel slices
+    const int per = wgrad_per(npo);
     const int slices = (npo + per - 1) / per;
     k_conv_wgrad<<<dim3(slices, 9), 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout, L.Wout,
                                                    L.Hin, L.Win, L.coutp, L.cinp, L.mode, per,
@@ -711,9 +733,10 @@ static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hip
   }
   {
     const CnnLayer& L = n->L[0];
-    const int npo = B * D, per = 2048, slices = (npo + per - 1) / per;
-    k_conv1_wgrad<<<slices, 320, 0, st>>>(n->x0, n->dz[0], B, n->ny, n->nx, L.cout, L.coutp, per,
-                                          n->wpart);
+    const int rows = B * n->ny, rows_per = std::max(1, (rows + 511) / 512);
+    const int slices = (rows + rows_per - 1) / rows_per;
+    k_conv1_wgrad<<<slices, 320, 0, st>>>(n->x0, n->dz[0], B, n->ny, n->nx, L.cout, L.coutp,
+                                          rows_per, n->wpart);
     k_conv1_reduce<<<(L.cout * 10 + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout,
                                                               n->grads + L.woff, n->grads + L.boff);
   }
