@@ -102,12 +102,15 @@ typedef struct {
   int cgs_passes;       /* 1 = classical Gram-Schmidt, 2 = CGS2 (default)          */
   int restart;          /* m >= 1 (default 100)                                     */
   int kmax;             /* largest number of augmenting vectors, 0..64 (default 0) */
-  int elems_per_thread; /* field elements per thread: 0 = auto, or 1, 2, 4, 8       */
+  int elems_per_thread; /* field elements per thread: 1, 2, 4, 8; 0 = 8 for batches */
+                        /* of >= 512 chunks of 2048 elements, else 2 (default)    */
   int hist_cap;         /* residual-history entries kept per problem (default 0)   */
   int check_every;      /* steps between host checks for an early cycle end (4)    */
   int select_reorth;    /* with cgs_passes = 2: run the second pass only in steps  */
                         /* where the first removed more than half of ||A q||^2    */
                         /* (Kahan-Parlett "twice is enough" test); default 1      */
+  int use_graph;        /* 1 = replay groups of check_every Arnoldi steps as HIP   */
+                        /* graphs (captured on first use; default 0)              */
 } dd_solver_opts;
 
 /* Per-problem result (host struct). */
@@ -188,7 +191,16 @@ typedef struct {
   double bytes[3];
 } dd_kernel_stats;
 
-/* Enable (1) or disable (0) the timing; enabling resets the statistics. */
+/* Tile-shape autotuner: times one restart cycle of Arnoldi steps on ops for each
+ * elements-per-thread value in {1, 2, 4, 8} (restart, precision and
+ * Gram-Schmidt options from opts, right-hand sides of ones) and writes the
+ * fastest to *best; ms_per_step (host, may be NULL) receives the 4 timings.
+ * Allocates and frees its own workspace; synchronises the device. */
+dd_status dd_solver_autotune(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
+                             int* best, double* ms_per_step);
+
+/* Enable (1) or disable (0) the timing (graph replay is off while timing);
+ * enabling resets the statistics. */
 dd_status dd_solver_profile(dd_solver* s, int enable);
 /* Host copy of the accumulated statistics. */
 dd_status dd_solver_kernel_stats(const dd_solver* s, dd_kernel_stats* out);

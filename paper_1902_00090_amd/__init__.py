@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import DD_C64, DD_C128, DDError, check, ptr_array
 
-__all__ = ["FdfdOp", "Solver", "gmres_solve", "gmres_solve_batched", "pca_build",
+__all__ = ["FdfdOp", "Solver", "autotune", "gmres_solve", "gmres_solve_batched", "pca_build",
            "local_pca_targets", "proj_loss_batched", "Cnn", "DDError", "lib_path"]
 
 
@@ -96,7 +96,7 @@ class FdfdOp:
 
 
 def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hist_cap=0,
-          check_every=4, select_reorth=True):
+          check_every=4, select_reorth=True, use_graph=False):
     o = _lib.dd_solver_opts()
     _lib.lib().dd_solver_opts_default(C.byref(o))
     o.inner = DD_C64 if inner == "c64" else DD_C128
@@ -107,18 +107,31 @@ def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hi
     o.hist_cap = int(hist_cap)
     o.check_every = int(check_every)
     o.select_reorth = int(bool(select_reorth))
+    o.use_graph = int(bool(use_graph))
     return o
+
+
+def autotune(ops, restart=100, inner="c64", cgs_passes=2, select_reorth=True):
+    """Fastest elements-per-thread value for these operators, and the timings
+    (ms per Arnoldi step) of the candidates 1, 2, 4, 8."""
+    o = _opts(restart, 0, inner, cgs_passes, 0, 0, 4, select_reorth)
+    best = C.c_int()
+    ms = (C.c_double * 4)()
+    check(_lib.lib().dd_solver_autotune(ptr_array([op.handle for op in ops]), len(ops), C.byref(o),
+                                        C.byref(best), ms), "dd_solver_autotune")
+    return best.value, list(ms)
 
 
 class Solver:
     """Batched data-driven GMRES over a list of operators (lockstep cycles)."""
 
     def __init__(self, ops, restart=100, kmax=0, inner="c64", cgs_passes=2,
-                 elems_per_thread=0, hist_cap=0, check_every=4, select_reorth=True):
+                 elems_per_thread=0, hist_cap=0, check_every=4, select_reorth=True,
+                 use_graph=False):
         self.ops = list(ops)
         self.nb = len(self.ops)
         self.opts = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap,
-                          check_every, select_reorth)
+                          check_every, select_reorth, use_graph)
         self.inner = inner
         self.restart, self.kmax = int(restart), int(kmax)
         h = C.c_void_p()

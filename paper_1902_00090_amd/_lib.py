@@ -32,7 +32,7 @@ class dd_pml(C.Structure):
 class dd_solver_opts(C.Structure):
     _fields_ = [("inner", C.c_int), ("cgs_passes", C.c_int), ("restart", C.c_int),
                 ("kmax", C.c_int), ("elems_per_thread", C.c_int), ("hist_cap", C.c_int),
-                ("check_every", C.c_int), ("select_reorth", C.c_int)]
+                ("check_every", C.c_int), ("select_reorth", C.c_int), ("use_graph", C.c_int)]
 
 
 class dd_info(C.Structure):
@@ -70,6 +70,7 @@ _SIGS = {
     "dd_solver_debug_copy": (I, [P, I, I, P, C.c_size_t]),
     "dd_solver_device_bytes": (C.c_size_t, [P]),
     "dd_solver_profile": (I, [P, I]),
+    "dd_solver_autotune": (I, [PP, I, C.POINTER(dd_solver_opts), C.POINTER(I), C.POINTER(D)]),
     "dd_solver_kernel_stats": (I, [P, C.POINTER(dd_kernel_stats)]),
     "dd_solver_destroy": (None, [P]),
     "gmres_solve": (I, [P, P, P, P, I, D, I, I, C.POINTER(dd_solver_opts), P,

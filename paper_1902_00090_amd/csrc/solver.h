@@ -71,6 +71,6 @@ struct PlanDev {
   double* hist;      // [nb][hist_cap]
   int nb, m, kmax, NC, NV, hist_cap, GB, qslots;
   int reorth_mode;   // 0 one Gram-Schmidt pass, 1 always two, 2 two where needed
-  double tol;
-  int maxit;
+  const double* ctl;  // device [tol, maxit] of the current solve (kernel arguments
+                      // stay constant, so captured graphs remain valid)
 };

@@ -34,6 +34,14 @@ struct dd_solver {
   std::vector<int> pkind;
   int pused = 0;
   dd_kernel_stats ks{};
+  // solve controls (pinned host staging, device copy)
+  double* hctl = nullptr;
+  double* dctl = nullptr;
+  // HIP graphs of groups of check_every Arnoldi steps, captured on a private
+  // stream on first use and replayed on the caller's stream
+  hipStream_t cap = nullptr;
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
 };
 
 extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
@@ -46,6 +54,7 @@ extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
   o->hist_cap = 0;
   o->check_every = 4;
   o->select_reorth = 1;
+  o->use_graph = 0;
 }
 
 static size_t inner_bytes(dd_prec p) { return p == DD_C128 ? 16 : 8; }
@@ -82,6 +91,12 @@ extern "C" void dd_solver_destroy(dd_solver* s) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : s->pev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& g : s->execs)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto& g : s->graphs)
+    if (g) (void)hipGraphDestroy(g);
+  if (s->cap) (void)hipStreamDestroy(s->cap);
+  if (s->hctl) (void)hipHostFree(s->hctl);
   delete s;
 }
 
@@ -119,13 +134,13 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     return DD_EINVAL;
   }
   if (R == 0) {
-    // largest R that still gives >= 2048 workgroups per sweep (8 per CU)
-    R = 1;
-    for (int cand : {8, 4, 2}) {
-      long long nch = 0;
-      for (int p = 0; p < nb; ++p) nch += (ops[p]->D + DD_BLOCK * cand - 1) / (DD_BLOCK * cand);
-      if (nch >= 2048) { R = cand; break; }
-    }
+    // Measured by dd_solver_autotune on MI355X over full GMRES(100) cycles of
+    // 480 x 240 problems: one problem is fastest with 2 elements per thread
+    // (72 us/step vs 89-92 for 1 and 8), a batch of 64 with 8 (1.22 ms/step
+    // vs 1.47 for 1).  Large batches take 8, small ones 2.
+    long long nch8 = 0;
+    for (int p = 0; p < nb; ++p) nch8 += (ops[p]->D + DD_BLOCK * 8 - 1) / (DD_BLOCK * 8);
+    R = (nch8 >= 512) ? 8 : 2;
   }
   dd_solver* s = new dd_solver();
   s->nb = nb;
@@ -208,6 +223,7 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     P.partial = part;
     chk(dalloc(s, &P.gpart, (size_t)nb * P.GB * std::max(1, gram_tiles(std::max(K, 1))) * 32));
     chk(dalloc(s, &P.hist, (size_t)nb * std::max(1, o.hist_cap)));
+    chk(dalloc(s, &s->dctl, 2));
   }
   if (e == hipSuccess) {
     chk(hipMemcpy(dd, s->hdesc.data(), sizeof(ProbDesc) * nb, hipMemcpyHostToDevice));
@@ -215,6 +231,7 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     chk(hipHostMalloc((void**)&s->pinned, sizeof(int) * 3 * nb * ST_NI, hipHostMallocDefault));
     chk(hipHostMalloc((void**)&s->pinnedD, sizeof(double) * nb * SD_ND, hipHostMallocDefault));
     chk(hipHostMalloc((void**)&s->pinnedK, sizeof(unsigned long long) * nb, hipHostMallocDefault));
+    chk(hipHostMalloc((void**)&s->hctl, sizeof(double) * 2, hipHostMallocDefault));
     chk(hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming));
   }
@@ -227,6 +244,7 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
   s->blk2prob = db2p;
   P.desc = dd;
   P.blk2prob = db2p;
+  P.ctl = s->dctl;
   *out = s;
   return DD_OK;
 }
@@ -367,6 +385,29 @@ static void launch_start(dd_solver* s, hipStream_t st) {
   k_post_norm<T><<<nb, DD_BLOCK, 0, st>>>(s->P, 0, MODE_START, re);
 }
 
+// Captures (once) and launches the graph of Arnoldi steps [grp*ce, jend).
+template <typename T, int R>
+static dd_status launch_group_graph(dd_solver* s, int grp, int jend, hipStream_t st) {
+  const int ce = s->o.check_every;
+  if ((int)s->execs.size() <= grp) {
+    s->execs.resize(grp + 1, nullptr);
+    s->graphs.resize(grp + 1, nullptr);
+  }
+  if (!s->execs[grp]) {
+    if (!s->cap) DD_HIP_CHECK(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+    DD_HIP_CHECK(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+    for (int j = grp * ce; j < jend; ++j) launch_step<T, R>(s, j, s->cap);
+    hipGraph_t g = nullptr;
+    DD_HIP_CHECK(hipStreamEndCapture(s->cap, &g));
+    hipGraphExec_t ex = nullptr;
+    DD_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    s->graphs[grp] = g;
+    s->execs[grp] = ex;
+  }
+  DD_HIP_CHECK(hipGraphLaunch(s->execs[grp], st));
+  return DD_OK;
+}
+
 template <typename T, int R>
 static dd_status run_cycles(dd_solver* s, hipStream_t st) {
   const int nb = s->nb, m = s->o.restart, g = s->nchunks;
@@ -386,9 +427,20 @@ static dd_status run_cycles(dd_solver* s, hipStream_t st) {
     if (active == 0) break;
     launch_start<T, R>(s, st);
     int pending = -1, grp = 0;
+    const int ce = s->o.check_every;
+    const bool graph = s->o.use_graph && !s->prof;
     for (int j = 0; j < m; ++j) {
-      launch_step<T, R>(s, j, st);
-      if ((j + 1) % s->o.check_every == 0 && j + 1 < m) {
+      if (graph) {
+        // one graph per group of ce steps; j is the group's first step
+        if (j % ce == 0) {
+          dd_status rc = launch_group_graph<T, R>(s, j / ce, std::min(m, j + ce), st);
+          if (rc != DD_OK) return rc;
+        }
+        if ((j + 1) % ce != 0 && j + 1 < m) continue;
+      } else {
+        launch_step<T, R>(s, j, st);
+      }
+      if ((j + 1) % ce == 0 && j + 1 < m) {
         const int slot = (grp++) & 1;
         DD_HIP_CHECK(hipMemcpyAsync(snap[slot], s->P.stI, stbytes, hipMemcpyDeviceToHost, st));
         DD_HIP_CHECK(hipEventRecord(s->ev[slot], st));
@@ -442,8 +494,11 @@ extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const v
       DD_HIP_CHECK(hipMemsetAsync(x[p], 0, bytes, stream));
     }
   }
-  s->P.tol = tol;
-  s->P.maxit = maxit;
+  {
+    const double ctl[2] = {tol, (double)maxit};
+    std::memcpy(s->hctl, ctl, sizeof(ctl));
+    DD_HIP_CHECK(hipMemcpyAsync(s->dctl, s->hctl, sizeof(ctl), hipMemcpyHostToDevice, stream));
+  }
   k_init_state<<<(nb + 255) / 256, 256, 0, stream>>>(s->P);
   DD_HIP_CHECK(hipGetLastError());
   dd_status rc = (s->o.inner == DD_C64) ? run_cycles_T<float>(s, stream) : run_cycles_T<double>(s, stream);
@@ -497,6 +552,66 @@ extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const v
   if (out == DD_ENONFINITE) dd_set_error("dd_solver_solve: non-finite right-hand side or residual");
   else if (out == DD_NOT_CONVERGED) dd_set_error("dd_solver_solve: iteration budget spent");
   return out;
+}
+
+// Tile-shape autotuner: times a few Arnoldi steps of each candidate
+// elements-per-thread value on the given operators (right-hand sides of
+// ones, restart and precision from opts) and returns the fastest.
+extern "C" dd_status dd_solver_autotune(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
+                                        int* best, double* ms_per_step) {
+  if (!ops || nb < 1 || !best) { dd_set_error("dd_solver_autotune: bad argument"); return DD_EINVAL; }
+  dd_solver_opts o;
+  dd_solver_opts_default(&o);
+  if (opts) o = *opts;
+  o.hist_cap = 0;
+  o.kmax = 0;
+  const int cands[4] = {1, 2, 4, 8};
+  std::vector<double2*> bufs;
+  std::vector<void*> bp(nb), xp(nb);
+  dd_status rc = DD_OK;
+  for (int p = 0; p < nb && rc == DD_OK; ++p) {
+    double2 *b = nullptr, *x = nullptr;
+    if (hipMalloc((void**)&b, sizeof(double2) * ops[p]->D) != hipSuccess ||
+        hipMalloc((void**)&x, sizeof(double2) * ops[p]->D) != hipSuccess) {
+      dd_set_error("dd_solver_autotune: hipMalloc failed");
+      rc = DD_ENOMEM;
+    }
+    bufs.push_back(b);
+    bufs.push_back(x);
+    if (rc == DD_OK) k_fill_const<<<(ops[p]->D + 255) / 256, 256>>>(b, ops[p]->D, 1.0);
+    bp[p] = b;
+    xp[p] = x;
+  }
+  double bestms = 1e300;
+  // one full cycle, so that the basis grows to its full length
+  const int steps = o.restart;
+  for (int ci = 0; ci < 4 && rc == DD_OK; ++ci) {
+    o.elems_per_thread = cands[ci];
+    dd_solver* s = nullptr;
+    rc = dd_solver_create(ops, nb, &o, &s);
+    if (rc != DD_OK) break;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    // warm-up (also captures the graphs), then a timed solve of `steps` steps
+    dd_status r1 = dd_solver_solve(s, (const void* const*)bp.data(), nullptr, 0.0, steps, xp.data(), nullptr, 0);
+    (void)hipEventRecord(e0, 0);
+    dd_status r2 = dd_solver_solve(s, (const void* const*)bp.data(), nullptr, 0.0, steps, xp.data(), nullptr, 0);
+    (void)hipEventRecord(e1, 0);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dd_solver_destroy(s);
+    if (r1 < 0 || r2 < 0) { rc = r1 < 0 ? r1 : r2; break; }
+    const double per = ms / steps;
+    if (ms_per_step) ms_per_step[ci] = per;
+    if (per < bestms) { bestms = per; *best = cands[ci]; }
+  }
+  for (double2* b : bufs)
+    if (b) (void)hipFree(b);
+  return rc;
 }
 
 extern "C" dd_status dd_solver_profile(dd_solver* s, int enable) {

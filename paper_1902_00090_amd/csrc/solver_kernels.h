@@ -95,12 +95,12 @@ __device__ void reduce_rows(const PlanDev& P, int blk0, int nblk, int nvals, dou
   for (int v = threadIdx.x; v < nvals; v += DD_BLOCK) {
     double s = 0.0;
     int c = 0;
-    for (; c + 8 <= nblk; c += 8) {
-      double a[8];
+    for (; c + 16 <= nblk; c += 16) {
+      double a[16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a[q] = (double)part[(size_t)(c + q) * P.NV + v];
+      for (int q = 0; q < 16; ++q) a[q] = (double)part[(size_t)(c + q) * P.NV + v];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s += a[q];
+      for (int q = 0; q < 16; ++q) s += a[q];
     }
     for (; c < nblk; ++c) s += (double)part[(size_t)c * P.NV + v];
     red[v] = s;
@@ -155,6 +155,11 @@ __device__ void finish_cycle(const PlanDev& P, int p, int k, int n) {
 }
 
 // ---------------------------------------------------------------------------
+__global__ void k_fill_const(double2* __restrict__ v, int n, double re) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = make_double2(re, 0.0);
+}
+
 __global__ void k_init_state(PlanDev P) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P.nb) return;
@@ -217,9 +222,9 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_residual(PlanDev P, int first
     sd[SD_TRUE] = 0.0;
   } else {
     sd[SD_TRUE] = rho / bn;
-    if (rho <= P.tol * bn) {
+    if (rho <= P.ctl[0] * bn) {
       st[ST_DONE] = DONE_CONVERGED;
-    } else if (st[ST_ITERS] >= P.maxit) {
+    } else if (st[ST_ITERS] >= (int)P.ctl[1]) {
       st[ST_DONE] = DONE_BUDGET;
     } else {
       st[ST_ACTIVE] = 1;
@@ -545,7 +550,8 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
       const double bn = sd[SD_BNORM];
       sd[SD_EST] = est / bn;
       if (it <= P.hist_cap) P.hist[(size_t)p * P.hist_cap + it - 1] = est / bn;
-      if (est <= P.tol * bn || it >= P.maxit || !(nrm > 0.0) || !isfinite(nrm) || j + 1 == m) {
+      if (est <= P.ctl[0] * bn || it >= (int)P.ctl[1] || !(nrm > 0.0) || !isfinite(nrm) ||
+          j + 1 == m) {
         fin = 1;
         nfin = j + 1;
       }

@@ -243,3 +243,55 @@ def test_grating_c64_refined_to_tol():
     err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
     print("error vs splu", err)
     assert err < 1e-3
+
+
+def test_graph_replay_matches_direct_launches():
+    """Replaying captured groups of Arnoldi steps gives bit-identical results
+    to launching the same kernels one by one (both reduce in a fixed order)."""
+    import torch
+    from gpu_util import to_dev
+    insts = [tiny_instance(40 + i, nx=nx, ny=ny) for i, (nx, ny) in enumerate([(20, 16), (36, 28)])]
+    V = [W.random_complex(np.random.default_rng(50 + q), (3, inst.D)) for q, inst in enumerate(insts)]
+    out = []
+    for g in (True, False):
+        s = _solver([_op(i) for i in insts], restart=17, kmax=3, inner="c64", hist_cap=3000,
+                    use_graph=g)
+        s.set_subspace([to_dev(v, torch.complex64) for v in V])
+        xs, infos, st = s.solve([_b(i) for i in insts], tol=1e-7, maxit=3000)
+        out.append(([x.cpu().numpy() for x in xs], infos, [s.history(p) for p in range(2)]))
+        # a second solve on the same solver replays the captured graphs
+        xs2, infos2, _ = s.solve([_b(i) for i in insts], tol=1e-7, maxit=3000)
+        assert [i["iters"] for i in infos2] == [i["iters"] for i in infos]
+        np.testing.assert_array_equal(xs2[0].cpu().numpy(), xs[0].cpu().numpy())
+    (xa, ia, ha), (xb, ib, hb) = out
+    assert [i["iters"] for i in ia] == [i["iters"] for i in ib]
+    for p in range(2):
+        np.testing.assert_array_equal(xa[p], xb[p])
+        np.testing.assert_array_equal(ha[p], hb[p])
+
+
+def test_autotune_picks_a_candidate():
+    from paper_1902_00090_amd import autotune
+    insts = [W.grating(1000 + i) for i in range(2)]
+    best, ms = autotune([_op(i) for i in insts], restart=20, cgs_passes=1)
+    assert best in (1, 2, 4, 8) and all(t > 0 for t in ms)
+    assert ms[[1, 2, 4, 8].index(best)] == min(ms)
+
+
+@pytest.mark.parametrize("R", [1, 2, 4, 8])
+def test_tile_width_matches_oracle(R):
+    """Every elements-per-thread choice (chunks of 256 R elements; 96 x 61 = 5856
+    elements spans several chunks with a ragged tail) gives the oracle's
+    augmented residual history in complex128."""
+    import torch
+    from gpu_util import to_dev
+    inst = tiny_instance(60, nx=96, ny=61, npml=6)
+    A = fdfd.assemble_instance(inst)
+    V = W.random_complex(np.random.default_rng(61), (2, inst.D))
+    s = _solver([_op(inst)], restart=40, kmax=2, inner="c128", hist_cap=400,
+                elems_per_thread=R)
+    s.set_subspace([to_dev(V, torch.complex128)])
+    (x,), (info,), st = s.solve([_b(inst)], tol=1e-30, maxit=120)
+    _, io = gmres_aug.gmres_aug(A, inst.b, V.T, restart=40, tol=1e-30, maxit=120)
+    assert info["iters"] == 120
+    np.testing.assert_allclose(s.history(0)[:120], io["history"][:120], rtol=1e-7, atol=1e-14)
