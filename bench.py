@@ -57,6 +57,147 @@ def first_below(h, thr):
     return int(idx[0]) + 1 if len(idx) else None
 
 
+def arnoldi_bytes(D, iters, m, k, passes=1):
+    """Algorithmic HBM bytes of `iters` complex64 Arnoldi steps with restart m
+    and k augmenting vectors: step j of a cycle reads the stencil input and
+    eps and writes w (20 D), reads the k+j+1 basis vectors and w for the dots
+    and again for the update, and writes q_{j+1}: 16 D (k+j) + 44 D; each
+    further Gram-Schmidt pass adds 16 D (k+j) + 24 D."""
+    full, rem = divmod(int(iters), m)
+    def cyc(n):       # sum over j < n of (k + j)
+        return n * k + n * (n - 1) // 2
+    sj = full * cyc(m) + cyc(rem)
+    return (16 * D * sj + 44 * D * iters) + (passes - 1) * (16 * D * sj + 24 * D * iters)
+
+
+def cnn_flops_per_instance(net):
+    """2 x multiply-adds of the 3x3 convolutions of one forward pass."""
+    H, Wd, tot = net.ny, net.nx, 0
+    for cin, cout, s, up, _ in net.layers():
+        if up:
+            H, Wd = 2 * H, 2 * Wd
+        elif s == 2:
+            H, Wd = H // 2, Wd // 2
+        tot += 2 * 9 * cin * cout * H * Wd
+    return tot
+
+
+def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_aug, plain):
+    """Train the CNN on local-PCA targets of the training fields (grouped by
+    trajectory), predict k fields for every evaluation problem, solve the
+    evaluation batch augmented by them; inference is inside the timed region."""
+    from paper_1902_00090_amd import Cnn, Solver, local_pca_targets, proj_loss_batched
+    from paper_1902_00090_amd.train import train_cnn
+    k, D, B = args.cnn_k, test[0].D, len(test)
+    t0 = time.time()
+    traj_of = np.asarray(tr_idx) // args.traj_steps
+    targets = torch.empty((len(train), k, D), dtype=torch.complex64, device="cuda")
+    for t in np.unique(traj_of):
+        rows = np.nonzero(traj_of == t)[0]
+        r0, r1 = int(rows[0]), int(rows[-1]) + 1      # sorted indices: contiguous rows
+        targets[r0:r1] = local_pca_targets(Smat[r0:r1].contiguous(), args.cnn_window, k)
+    targets *= float(math.sqrt(D))                     # unit RMS per pixel
+    eps_tr = torch.tensor(np.stack([i.eps for i in train]), device="cuda")
+    net = Cnn(test[0].nx, test[0].ny, max_batch=32, k=k, seed=7)
+    losses = train_cnn(net, eps_tr, targets, args.cnn_steps, 32, lr=1e-3, seed=11)
+    torch.cuda.synchronize()
+    t_cnn_train = time.time() - t0
+    del targets, eps_tr
+    log(f"CNN: {args.cnn_steps} Adam steps on {len(train)} samples, {t_cnn_train:.1f}s, "
+        f"loss {losses[0]:.3e} -> {np.mean(losses[-20:]):.3e}")
+
+    eps_te = torch.tensor(np.stack([i.eps for i in test]), device="cuda")
+    Ucnn = torch.empty((B, k, D), dtype=torch.complex64, device="cuda")
+    net.predict(eps_te, Ucnn)                          # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    net.predict(eps_te, Ucnn)
+    e1.record()
+    torch.cuda.synchronize()
+    inf_ms = e0.elapsed_time(e1)
+    flops = cnn_flops_per_instance(net) * B
+    xs_stack = torch.stack(xs).contiguous()
+    lp_cnn = proj_loss_batched(Ucnn, xs_stack)
+    lp_pca = proj_loss_batched(U.unsqueeze(0).expand(B, -1, -1).contiguous(), xs_stack)
+    del xs_stack
+
+    s = Solver(ops, restart=args.restart, kmax=k, cgs_passes=args.cgs, hist_cap=args.maxit)
+    xc = [torch.empty_like(b) for b in bs]
+    Ul = [Ucnn[p] for p in range(B)]
+    s.set_subspace(Ul)
+    s.solve(bs, tol=args.tol, maxit=args.maxit, x=xc)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.time()
+    net.predict(eps_te, Ucnn)
+    s.set_subspace(Ul)
+    _, inf, _ = s.solve(bs, tol=args.tol, maxit=args.maxit, x=xc)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    h = [s.history(p) for p in range(B)]
+    s.close()
+    net.close()
+    it = np.array([i["iters"] for i in inf])
+    out = {
+        "solves_per_s_incl_inference": round(B / dt, 4),
+        "iters_mean": float(it.mean()),
+        "matvecs_mean": float(np.mean([i["matvecs"] for i in inf])),
+        "all_converged": all(i["status"] == 0 for i in inf),
+        "worst_rel_res_true": max(i["rel_res_true"] for i in inf),
+        "rel_res_after_1_iter_mean": float(np.mean([x[0] for x in h])),
+        "iters_to_0.04_mean": float(np.mean([first_below(x, 0.04) or np.nan for x in h])),
+        "k": k, "proj_loss_eval_mean": float(np.mean(lp_cnn)),
+        "pca_k%d_proj_loss_eval_mean" % args.k: float(np.mean(lp_pca)),
+        "train_samples": len(train), "train_steps": args.cnn_steps, "batch": 32,
+        "train_seconds": round(t_cnn_train, 1),
+        "train_loss_first_last": [float(losses[0]), float(np.mean(losses[-20:]))],
+        "inference_ms_batch": round(inf_ms, 3),
+        "inference_tflops": round(flops / (inf_ms * 1e-3) / 1e12, 1),
+        "inference_mfma_frac_bf16": round(flops / (inf_ms * 1e-3) / 1e12 / 2500.0, 4),
+        "flop_per_instance": flops // B,
+    }
+    log(f"CNN-augmented: {out['solves_per_s_incl_inference']:.3f} solves/s, iters mean "
+        f"{it.mean():.0f}, l_proj eval {out['proj_loss_eval_mean']:.3f} "
+        f"(PCA k={args.k}: {out['pca_k%d_proj_loss_eval_mean' % args.k]:.3f}), inference "
+        f"{inf_ms:.2f} ms for {B} ({out['inference_tflops']} TFLOP/s)")
+    return out
+
+
+def c3_leg(args, torch, W):
+    """8 trajectories x 32 steps of uneven grids (192x96, 320x160, 480x240;
+    1.30 / 1.55 um) in one lockstep batch, plain complex64 GMRES, step groups
+    replayed as HIP graphs."""
+    from paper_1902_00090_amd import FdfdOp, Solver
+    insts = W.correlated_batch(8, 32)
+    ops = [FdfdOp.from_instance(i) for i in insts]
+    bs = [torch.tensor(i.b, dtype=torch.complex128, device="cuda") for i in insts]
+    xs = [torch.empty_like(b) for b in bs]
+    s = Solver(ops, restart=args.restart, cgs_passes=args.cgs, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    _, inf, st = s.solve(bs, tol=args.tol, maxit=args.maxit, x=xs)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    s.close()
+    it = np.array([i["iters"] for i in inf])
+    mv = sum(i["matvecs"] for i in inf)
+    cells = sum(i.D for i in insts)
+    alg = sum(arnoldi_bytes(p.D, i["iters"], args.restart, 0, args.cgs) + 52 * p.D * i["restarts"]
+              for i, p in zip(inf, insts))
+    out = {
+        "problems": len(insts), "cells": cells, "solves_per_s": round(len(insts) / dt, 4),
+        "seconds": round(dt, 2), "matvecs_per_s": round(mv / dt, 1),
+        "cell_matvecs_per_s": round(sum(i["matvecs"] * p.D for i, p in zip(inf, insts)) / dt, 1),
+        "iters_min_mean_max": [int(it.min()), float(it.mean()), int(it.max())],
+        "all_converged": all(i["status"] == 0 for i in inf),
+        "worst_rel_res_true": max(i["rel_res_true"] for i in inf),
+        "algorithmic_GB_per_s_whole_solve": round(alg / dt / 1e9, 1),
+        "hbm_frac_whole_solve": round(alg / dt / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    log(f"uneven batch: {len(insts)} problems, {cells} cells, {dt:.1f}s, iters "
+        f"{out['iters_min_mean_max']}, {out['algorithmic_GB_per_s_whole_solve']} GB/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +216,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--oracle-check", type=int, default=2)
+    ap.add_argument("--no-cnn", action="store_true", help="skip the CNN-predictor leg")
+    ap.add_argument("--cnn-k", type=int, default=10)
+    ap.add_argument("--cnn-steps", type=int, default=400)
+    ap.add_argument("--cnn-window", type=int, default=8)
+    ap.add_argument("--no-c3", action="store_true", help="skip the uneven correlated batch")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device-to-device copy run first (for HBM counters)")
     args = ap.parse_args()
@@ -128,10 +274,10 @@ def main():
         log(f"  train solves {c0 + len(part)}/{len(train)}: "
             f"iters max {max(i['iters'] for i in infos)}")
     Smat = torch.stack(snaps).contiguous()
+    del snaps
     U, sig = pca_build(Smat, args.k)
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    del Smat, snaps
     log(f"PCA: k={args.k} from {len(train)} solver-generated fields, {t_train:.1f}s; "
         f"sigma[0]={sig[0]:.3e} sigma[k-1]/sigma[0]={sig[-1] / sig[0]:.3f}")
 
@@ -203,6 +349,18 @@ def main():
             xg = xs[p].cpu().numpy()
             errs.append(float(np.linalg.norm(xg - xstar) / np.linalg.norm(xstar)))
         log(f"error vs sparse LU on {len(errs)} problems: {errs}")
+
+    # ---------------- CNN predictor: trained on the same solver-generated fields
+    cnn = None
+    if not args.no_cnn:
+        cnn = cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_aug,
+                      plain)
+    del Smat
+
+    # ---------------- uneven correlated batch, plain GMRES, graph replay
+    c3 = None
+    if not args.no_c3:
+        c3 = c3_leg(args, torch, W)
 
     # ---------------- roofline of the dominant sweep
     name = max(ks, key=lambda n: ks[n][0])
@@ -282,6 +440,8 @@ def main():
         "sweeps": sweeps,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cnn_augmented": cnn,
+        "uneven_batch_plain": c3,
     }
     print(json.dumps(out), flush=True)
 

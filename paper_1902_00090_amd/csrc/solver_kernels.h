@@ -64,7 +64,7 @@ __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t D
         const c2<T>* bp = B + (size_t)(v0 + vv) * Dp + base + threadIdx.x;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const c2<T> b = bp[r * DD_BLOCK];
+          const c2<T> b = ld_stream(bp + r * DD_BLOCK);
           acc[2 * vv] += b.x * w[r].x + b.y * w[r].y;
           acc[2 * vv + 1] += b.x * w[r].y - b.y * w[r].x;
         }
@@ -352,7 +352,7 @@ __device__ __forceinline__ void block_update(c2<T>* __restrict__ B, size_t Dp, i
     for (int u = 0; u < 4; ++u) {
       const c2<T>* bp = B + (size_t)(v + u) * Dp + base + threadIdx.x;
 #pragma unroll
-      for (int r = 0; r < R; ++r) b[u][r] = bp[r * DD_BLOCK];
+      for (int r = 0; r < R; ++r) b[u][r] = ld_stream(bp + r * DD_BLOCK);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -374,7 +374,7 @@ __device__ __forceinline__ void block_update(c2<T>* __restrict__ B, size_t Dp, i
     const c2<T> cv = coef[v];
     c2<T> b[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) b[r] = bp[r * DD_BLOCK];
+    for (int r = 0; r < R; ++r) b[r] = ld_stream(bp + r * DD_BLOCK);
     if (v == nv) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
     const double2 c = cf[v];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const c2<T> b = V[(size_t)v * Dp + base + r * DD_BLOCK + threadIdx.x];
+      const c2<T> b = ld_stream(V + (size_t)v * Dp + base + r * DD_BLOCK + threadIdx.x);
       acc[r] = dadd(acc[r], dmul(c, make_double2((double)b.x, (double)b.y)));
     }
   }
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
     const double2 c = cf[k + i];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const c2<T> b = Q[(size_t)i * Dp + base + r * DD_BLOCK + threadIdx.x];
+      const c2<T> b = ld_stream(Q + (size_t)i * Dp + base + r * DD_BLOCK + threadIdx.x);
       acc[r] = dadd(acc[r], dmul(c, make_double2((double)b.x, (double)b.y)));
     }
   }
