@@ -14,4 +14,5 @@ Modules
   pca       -- principal-component basis of solution snapshots
   losses    -- projection and residual losses
   cnn       -- float64 convolutional predictor: forward, backward, Adam
+  eim       -- effective-index approximation of the field (the CNN's second input)
 """
