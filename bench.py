@@ -31,18 +31,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per Arnoldi-step launch of the final update sweep, from two
+# HBM bytes per Arnoldi-step launch of the two streaming sweeps, from two
 # rocprofv3 --pmc passes (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after
-# calibration on a 1 GiB copy) over this workload; valid only for the kernel
-# sources they were taken with (see profiles/).
-MEASURED_TRAFFIC = {"kernel": "k_update_norm", "bytes_per_launch": 3.173e9,
-                    "sources_sha256_16": "c0f9737f07994d55"}
+# calibration on a 1 GiB copy) over this workload (64 problems, k = 20); valid
+# only for the kernel sources they were taken with (see profiles/).
+MEASURED_TRAFFIC = {"bytes_per_launch": {"k_update_norm": 3.172e9, "k_matvec_dot": 3.189e9},
+                    "sources_sha256_16": "c01dbe04a5246b9f"}
 
 
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("solver_kernels.h", "op.h"):
+    for f in ("solver_kernels.h", "op.h", "common.h"):
         with open(os.path.join(ROOT, "paper_1902_00090_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -86,7 +86,8 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
     """Train the CNN on local-PCA targets of the training fields (grouped by
     trajectory), predict k fields for every evaluation problem, solve the
     evaluation batch augmented by them; inference is inside the timed region."""
-    from paper_1902_00090_amd import Cnn, Solver, local_pca_targets, proj_loss_batched
+    from paper_1902_00090_amd import (Cnn, FdfdOp, Solver, eim_field, local_pca_targets,
+                                      proj_loss_batched)
     from paper_1902_00090_amd.train import train_cnn
     k, D, B = args.cnn_k, test[0].D, len(test)
     t0 = time.time()
@@ -98,27 +99,53 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
         targets[r0:r1] = local_pca_targets(Smat[r0:r1].contiguous(), args.cnn_window, k)
     targets *= float(math.sqrt(D))                     # unit RMS per pixel
     eps_tr = torch.tensor(np.stack([i.eps for i in train]), device="cuda")
-    net = Cnn(test[0].nx, test[0].ny, max_batch=32, k=k, seed=7)
-    losses = train_cnn(net, eps_tr, targets, args.cnn_steps, 32, lr=1e-3, seed=11)
+    eim_tr = None
+    if args.cnn_inputs == 3:
+        tr_ops = [FdfdOp.from_instance(i) for i in train]
+        eim_tr = torch.empty((len(train), D), dtype=torch.complex64, device="cuda")
+        for c0 in range(0, len(train), 64):
+            eim_field(tr_ops[c0:c0 + 64],
+                      [torch.tensor(i.b, dtype=torch.complex128, device="cuda")
+                       for i in train[c0:c0 + 64]], out=eim_tr[c0:c0 + 64])
+        del tr_ops
+    net = Cnn(test[0].nx, test[0].ny, max_batch=32, k=k, seed=7, in_channels=args.cnn_inputs)
+    losses = train_cnn(net, eps_tr, targets, args.cnn_steps, 32, lr=1e-3, seed=11, eim=eim_tr)
     torch.cuda.synchronize()
     t_cnn_train = time.time() - t0
-    del targets, eps_tr
-    log(f"CNN: {args.cnn_steps} Adam steps on {len(train)} samples, {t_cnn_train:.1f}s, "
-        f"loss {losses[0]:.3e} -> {np.mean(losses[-20:]):.3e}")
+    del targets, eps_tr, eim_tr
+    log(f"CNN: {args.cnn_inputs} input planes, {args.cnn_steps} Adam steps on {len(train)} "
+        f"samples, {t_cnn_train:.1f}s, loss {losses[0]:.3e} -> {np.mean(losses[-20:]):.3e}")
 
     eps_te = torch.tensor(np.stack([i.eps for i in test]), device="cuda")
+    eim_te = None
+    if args.cnn_inputs == 3:
+        eim_te = torch.empty((B, D), dtype=torch.complex64, device="cuda")
+
+    def setup():
+        """Predictor inputs and inference: the per-problem setup of the CNN leg."""
+        if eim_te is not None:
+            eim_field(ops, bs, out=eim_te)
+        net.predict(eps_te, Ucnn, eim=eim_te)
+
     Ucnn = torch.empty((B, k, D), dtype=torch.complex64, device="cuda")
-    net.predict(eps_te, Ucnn)                          # warm-up
+    setup()                                            # warm-up
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    net.predict(eps_te, Ucnn)
+    net.predict(eps_te, Ucnn, eim=eim_te)
     e1.record()
     torch.cuda.synchronize()
     inf_ms = e0.elapsed_time(e1)
+    t0 = time.time()
+    setup()
+    torch.cuda.synchronize()
+    setup_ms = 1000 * (time.time() - t0)
     flops = cnn_flops_per_instance(net) * B
     xs_stack = torch.stack(xs).contiguous()
     lp_cnn = proj_loss_batched(Ucnn, xs_stack)
     lp_pca = proj_loss_batched(U.unsqueeze(0).expand(B, -1, -1).contiguous(), xs_stack)
+    lp_eim = None
+    if eim_te is not None:
+        lp_eim = proj_loss_batched(eim_te.unsqueeze(1).contiguous(), xs_stack)
     del xs_stack
 
     s = Solver(ops, restart=args.restart, kmax=k, cgs_passes=args.cgs, hist_cap=args.maxit)
@@ -128,7 +155,7 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
     s.solve(bs, tol=args.tol, maxit=args.maxit, x=xc)  # warm-up
     torch.cuda.synchronize()
     t0 = time.time()
-    net.predict(eps_te, Ucnn)
+    setup()
     s.set_subspace(Ul)
     _, inf, _ = s.solve(bs, tol=args.tol, maxit=args.maxit, x=xc)
     torch.cuda.synchronize()
@@ -145,12 +172,15 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
         "worst_rel_res_true": max(i["rel_res_true"] for i in inf),
         "rel_res_after_1_iter_mean": float(np.mean([x[0] for x in h])),
         "iters_to_0.04_mean": float(np.mean([first_below(x, 0.04) or np.nan for x in h])),
-        "k": k, "proj_loss_eval_mean": float(np.mean(lp_cnn)),
+        "k": k, "input_planes": args.cnn_inputs,
+        "proj_loss_eval_mean": float(np.mean(lp_cnn)),
+        "eim_field_alone_proj_loss_eval_mean": None if lp_eim is None else float(np.mean(lp_eim)),
         "pca_k%d_proj_loss_eval_mean" % args.k: float(np.mean(lp_pca)),
         "train_samples": len(train), "train_steps": args.cnn_steps, "batch": 32,
         "train_seconds": round(t_cnn_train, 1),
         "train_loss_first_last": [float(losses[0]), float(np.mean(losses[-20:]))],
         "inference_ms_batch": round(inf_ms, 3),
+        "setup_ms_batch_incl_eim": round(setup_ms, 3),
         "inference_tflops": round(flops / (inf_ms * 1e-3) / 1e12, 1),
         "inference_mfma_frac_bf16": round(flops / (inf_ms * 1e-3) / 1e12 / 2500.0, 4),
         "flop_per_instance": flops // B,
@@ -160,6 +190,52 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
         f"(PCA k={args.k}: {out['pca_k%d_proj_loss_eval_mean' % args.k]:.3f}), inference "
         f"{inf_ms:.2f} ms for {B} ({out['inference_tflops']} TFLOP/s)")
     return out
+
+
+def cnn_kernels_only(args, torch, W):
+    """Forward and training-step throughput of the predictor's kernels on
+    480 x 240 grating permittivities (weights at their seeded initialisation,
+    seeded random targets): the workload the MFMA-utilisation profile covers."""
+    from paper_1902_00090_amd import Cnn
+    insts = W.trajectory_dataset(2, 32)
+    eps = torch.tensor(np.stack([i.eps for i in insts]), device="cuda")
+    B, D = eps.shape[0], insts[0].D
+    net = Cnn(insts[0].nx, insts[0].ny, max_batch=B, k=args.cnn_k, seed=7,
+              in_channels=args.cnn_inputs)
+    rng = np.random.default_rng(5)
+    tgt = torch.tensor(W.random_complex(rng, (32, args.cnn_k, D)).astype(np.complex64),
+                       device="cuda")
+    eim = None
+    if args.cnn_inputs == 3:
+        eim = torch.tensor(W.random_complex(rng, (B, D)).astype(np.complex64), device="cuda")
+    U = torch.empty((B, args.cnn_k, D), dtype=torch.complex64, device="cuda")
+    n = args.cnn_kernels
+    e32 = None if eim is None else eim[:32].contiguous()
+    net.predict(eps, U, eim=eim)
+    net.train_step(eps[:32].contiguous(), tgt, eim=e32)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(n):
+        net.predict(eps, U, eim=eim)
+    e[1].record()
+    e1 = eps[:32].contiguous()
+    e[2].record()
+    for _ in range(n):
+        net.train_step(e1, tgt, lr=1e-4, eim=e32)
+    e[3].record()
+    torch.cuda.synchronize()
+    fwd_ms, tr_ms = e[0].elapsed_time(e[1]) / n, e[2].elapsed_time(e[3]) / n
+    f1 = cnn_flops_per_instance(net)
+    out = {"metric": "CNN predictor kernels, 480x240, 1 GPU",
+           "forward_ms_batch64": round(fwd_ms, 3),
+           "forward_tflops": round(f1 * B / (fwd_ms * 1e-3) / 1e12, 1),
+           "train_step_ms_batch32": round(tr_ms, 3),
+           "train_tflops_3x_forward": round(3 * f1 * 32 / (tr_ms * 1e-3) / 1e12, 1),
+           "bf16_dense_peak_tflops": 2500.0, "flop_per_instance_forward": f1, "reps": n,
+           "input_planes": args.cnn_inputs}
+    net.close()
+    print(json.dumps(out), flush=True)
 
 
 def c3_leg(args, torch, W):
@@ -220,7 +296,13 @@ def main():
     ap.add_argument("--cnn-k", type=int, default=10)
     ap.add_argument("--cnn-steps", type=int, default=400)
     ap.add_argument("--cnn-window", type=int, default=8)
+    ap.add_argument("--cnn-inputs", type=int, default=3, choices=(1, 3),
+                    help="CNN input planes: 3 = permittivity + effective-index field (the "
+                         "paper's input), 1 = permittivity only")
     ap.add_argument("--no-c3", action="store_true", help="skip the uneven correlated batch")
+    ap.add_argument("--cnn-kernels", type=int, default=0,
+                    help="only time N CNN forward passes (batch 64) and N training steps "
+                         "(batch 32) at 480x240, print one JSON line and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device-to-device copy run first (for HBM counters)")
     args = ap.parse_args()
@@ -248,6 +330,10 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
         del src, dst
+
+    if args.cnn_kernels > 0:
+        cnn_kernels_only(args, torch, W)
+        return
 
     # ---------------- data
     t0 = time.time()
@@ -369,9 +455,9 @@ def main():
     kname = {"matvec_dots": "k_matvec_dot", "second_pass": "k_update_dot",
              "update_norm": "k_update_norm"}[name]
     traffic = None
-    if (kname == MEASURED_TRAFFIC["kernel"] and args.batch == 64 and args.k == 20 and
-            kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]):
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    if (kname in MEASURED_TRAFFIC["bytes_per_launch"] and args.batch == 64 and args.k == 20
+            and args.cgs == 1 and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]):
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"][kname]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname,

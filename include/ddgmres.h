@@ -256,6 +256,29 @@ dd_status proj_loss_batched(const void* V, const void* f, int nb, int k, int D, 
                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Effective-index field (Sec. 3: the CNN's second input)
+ * ------------------------------------------------------------------------
+ * The paper gives its CNN an effective-index simulation of the field: a
+ * cheap approximation obtained from 1D solves of Maxwell's equations.  The
+ * separable reading computed here has three steps, for each problem p
+ * (operator ops[p], right-hand side b[p]):
+ *   1. phi_ix = fundamental mode (lowest eigenpair mu_ix, unit norm,
+ *      positive) of the column operator
+ *      -(second difference in y)/dx^2 - omega^2 eps(ix, .), with zero field
+ *      outside the column;
+ *   2. a solves the 1D equation along x.  It has the operator's stretched
+ *      x-differences (PML, periodic wrap) and mu_ix in place of
+ *      -omega^2 eps.  The source is j_ix = phi_ix^T b[:, ix];
+ *   3. F[iy][ix] = a_ix phi_ix(iy).
+ * All arithmetic is FP64.
+ *   b[p]: [D] c128 (device).
+ *   F[p]: [D] c64 output (device).
+ * Problems may have different grids.  Scratch memory is allocated and freed
+ * inside the call.  Synchronises the stream. */
+dd_status eim_field(const fdfd_op* const* ops, int nb, const void* const* b, void* const* F,
+                    hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Convolutional subspace predictor (Sec. 3, CNN paragraph; Methods)
  * ------------------------------------------------------------------------
  * Encoder-decoder of eight 3x3 convolutions on a [B][ny][nx] permittivity
@@ -266,11 +289,17 @@ dd_status proj_loss_batched(const void* V, const void* f, int nb, int k, int D, 
  * fields (channel 2j = real part, 2j+1 = imaginary part of v_j).
  */
 
-/* Create a network for input images of ny x nx (both multiples of 4) and up
- * to max_batch images per call, k output fields.  Weights are
- * initialised from seed (He-uniform, host RNG, documented in the source). */
-dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, unsigned long long seed,
-                        dd_cnn** out);
+/* Create a network for input images of ny x nx (both multiples of 4), up to
+ * max_batch images per call and k output fields.  in_channels selects the
+ * input:
+ *   - 1: the permittivity alone;
+ *   - 3: the permittivity plus the real and imaginary parts of the
+ *     effective-index field (eim_field).  The field is scaled to unit RMS per
+ *     pixel, per image.  The paper's CNN takes both inputs.
+ * Weights are initialised from seed (He-uniform, host RNG, documented in the
+ * source). */
+dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_channels,
+                        unsigned long long seed, dd_cnn** out);
 void dd_cnn_destroy(dd_cnn* net);
 
 /* Number of layers and, per layer (host out-params, may be NULL): input
@@ -284,25 +313,41 @@ size_t dd_cnn_num_params(const dd_cnn* net);
 dd_status dd_cnn_get_params(const dd_cnn* net, float* host_out, size_t count);
 dd_status dd_cnn_set_params(dd_cnn* net, const float* host_in, size_t count);
 
-/* Forward pass.  eps: [B][ny][nx] float32 permittivity (device); the input is
- * normalised as (eps - 2.085) / (12.25 - 2.085).  U: [B][k][ny*nx] c64
- * output fields (device).  B <= max_batch. */
+/* Forward pass of a one-input-channel network.
+ *   eps: [B][ny][nx] float32 permittivity (device).  The input is normalised
+ *        as (eps - 2.085) / (12.25 - 2.085).
+ *   U:   [B][k][ny*nx] c64 output fields (device).
+ *   B <= max_batch. */
 dd_status predict_subspace(dd_cnn* net, const float* eps, int B, void* U, hipStream_t stream);
 
-/* One training step on a batch: forward, mean-squared error against target
- * [B][k][ny*nx] c64 (device, same layout as U), backward, Adam update with
- * learning rate lr, betas (b1, b2), epsilon 1e-8.  *loss (host, may be NULL)
- * receives the batch loss (synchronises the stream when non-NULL). */
-dd_status dd_cnn_train_step(dd_cnn* net, const float* eps, const void* target, int B,
-                            float lr, float b1, float b2, float* loss, hipStream_t stream);
+/* Forward pass of a three-input-channel network.
+ *   eim: [B][ny*nx] c64 effective-index fields (device, from eim_field).
+ * Otherwise as predict_subspace. */
+dd_status predict_subspace_eim(dd_cnn* net, const float* eps, const void* eim, int B, void* U,
+                               hipStream_t stream);
 
-/* Gradient of the batch loss w.r.t. all parameters (no update), FP32 host
- * out[count] in the dd_cnn_get_params layout; for gradient checks. */
-dd_status dd_cnn_grad(dd_cnn* net, const float* eps, const void* target, int B, float* loss,
-                      float* host_grad, size_t count, hipStream_t stream);
+/* One training step on a batch:
+ *   1. forward pass;
+ *   2. mean-squared error against target [B][k][ny*nx] c64 (device, same
+ *      layout as U);
+ *   3. backward pass;
+ *   4. Adam update with learning rate lr, betas (b1, b2) and epsilon 1e-8.
+ * eim must be [B][ny*nx] c64 for a three-channel network and NULL for a
+ * one-channel one.  *loss (host, may be NULL) receives the batch loss.
+ * Synchronises the stream. */
+dd_status dd_cnn_train_step(dd_cnn* net, const float* eps, const void* eim, const void* target,
+                            int B, float lr, float b1, float b2, float* loss,
+                            hipStream_t stream);
 
-/* Copy the bf16 activations of layer l's output (NHWC, as float32) to host;
- * layer = -1 gives the normalised input.  For tests. */
+/* Gradient of the batch loss w.r.t. all parameters, with no update.
+ * host_grad receives count FP32 values (host) in the dd_cnn_get_params
+ * layout.  Used for gradient checks.  eim is as in dd_cnn_train_step. */
+dd_status dd_cnn_grad(dd_cnn* net, const float* eps, const void* eim, const void* target, int B,
+                      float* loss, float* host_grad, size_t count, hipStream_t stream);
+
+/* Copy the bf16 activations of layer l's output (NHWC, as float32) to host.
+ * layer = -1 gives the normalised input planes [B][in_channels][ny][nx].
+ * For tests. */
 dd_status dd_cnn_debug_activation(const dd_cnn* net, int layer, int B, float* host_out,
                                   size_t count);
 

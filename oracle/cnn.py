@@ -12,8 +12,12 @@ the reading used throughout (an encoder-decoder of eight 3x3 convolutions):
     nearest x2 upsample + 128->64, nearest x2 upsample + 64->32, 32->32,
     32->2k (linear); ReLU after every layer but the last; zero padding 1.
 
-Input normalisation: (eps - 2.085) / (12.25 - 2.085).  Output channel
-2j holds Re v_j and channel 2j+1 holds Im v_j.
+Input planes: (eps - 2.085) / (12.25 - 2.085), and, for the three-channel
+network the paper uses (permittivity plus effective-index field, Sec. 3),
+the real and imaginary parts of the effective-index field F scaled to unit
+RMS per pixel (F sqrt(D) / ||F||, per image; complex inputs as two real
+channels, Methods).  Output channel 2j holds Re v_j and channel 2j+1 holds
+Im v_j.
 
 Tensors are NCHW float64; weights are [out, in, 3, 3] (cross-correlation, as
 every deep-learning convolution).
@@ -25,9 +29,9 @@ import numpy as np
 EPS_LO, EPS_HI = 2.085, 12.25
 
 
-def layer_list(k: int = 10):
+def layer_list(k: int = 10, in_ch: int = 1):
     """(cin, cout, stride, upsample_before, relu) per layer."""
-    return [(1, 32, 1, 0, 1), (32, 64, 2, 0, 1), (64, 128, 2, 0, 1), (128, 128, 1, 0, 1),
+    return [(in_ch, 32, 1, 0, 1), (32, 64, 2, 0, 1), (64, 128, 2, 0, 1), (128, 128, 1, 0, 1),
             (128, 64, 1, 1, 1), (64, 32, 1, 1, 1), (32, 32, 1, 0, 1), (32, 2 * k, 1, 0, 0)]
 
 
@@ -35,11 +39,24 @@ def normalise(eps):
     return (np.asarray(eps, np.float64) - EPS_LO) / (EPS_HI - EPS_LO)
 
 
-def init_params(k: int = 10, seed: int = 0):
+def inputs(eps, eim=None):
+    """Network input planes [B, C, H, W]: C = 1 without, 3 with the
+    effective-index fields eim [B, H*W] (complex)."""
+    x = normalise(eps)[:, None]
+    if eim is None:
+        return x
+    B, H, W = x.shape[0], x.shape[2], x.shape[3]
+    F = np.asarray(eim, np.complex128).reshape(B, H, W)
+    nrm = np.sqrt((np.abs(F) ** 2).sum(axis=(1, 2)) / (H * W))
+    G = F / np.where(nrm > 0, nrm, np.inf)[:, None, None]
+    return np.concatenate([x, G.real[:, None], G.imag[:, None]], axis=1)
+
+
+def init_params(k: int = 10, seed: int = 0, in_ch: int = 1):
     """He-uniform weights, zero biases (float64)."""
     rng = np.random.default_rng(seed)
     params = []
-    for cin, cout, _, _, _ in layer_list(k):
+    for cin, cout, _, _, _ in layer_list(k, in_ch):
         bound = np.sqrt(6.0 / (cin * 9))
         params.append([rng.uniform(-bound, bound, (cout, cin, 3, 3)), np.zeros(cout)])
     return params
@@ -78,11 +95,12 @@ def conv_backward(x, w, dz, stride):
     return dxp[:, :, 1:-1, 1:-1], dw, dz.sum(axis=(0, 2, 3))
 
 
-def forward(params, eps, k: int = 10):
-    """eps: [B, H, W] permittivity.  Returns (out [B, 2k, H, W], cache)."""
-    x = normalise(eps)[:, None]
+def forward(params, eps, k: int = 10, eim=None):
+    """eps: [B, H, W] permittivity; eim: [B, H*W] effective-index fields for a
+    three-channel network.  Returns (out [B, 2k, H, W], cache)."""
+    x = inputs(eps, eim)
     cache = []
-    for (cin, cout, s, up, relu), (w, b) in zip(layer_list(k), params):
+    for (cin, cout, s, up, relu), (w, b) in zip(layer_list(k, x.shape[1]), params):
         xin = upsample2(x) if up else x
         z = conv_forward(xin, w, b, s)
         y = np.maximum(z, 0.0) if relu else z

@@ -304,4 +304,24 @@ def proj_loss_batched(V, f):
     return out
 
 
+def eim_field(ops, b, out=None):
+    """Effective-index fields (the CNN's second input) of the problems
+    (ops[p], b[p]); b: list of [D] complex128 device tensors.  Returns a list
+    of [D] complex64 tensors, or fills the rows of out ([nb, D] complex64)."""
+    torch = _torch()
+    nb = len(ops)
+    if len(b) != nb:
+        raise ValueError("one right-hand side per operator")
+    if out is None:
+        F = [torch.empty(op.D, dtype=torch.complex64, device=bb.device) for op, bb in zip(ops, b)]
+    else:
+        _dev(out, torch.complex64, what="out")
+        F = [out[p, :ops[p].D] for p in range(nb)]
+    opp = ptr_array([op._h.value for op in ops])
+    bp = ptr_array([_dev(bb, torch.complex128, ops[p].D, f"b[{p}]").value for p, bb in enumerate(b)])
+    fp = ptr_array([f.data_ptr() for f in F])
+    check(_lib.lib().eim_field(opp, nb, bp, fp, _stream()), "eim_field")
+    return F if out is None else out
+
+
 from .cnn import Cnn  # noqa: E402

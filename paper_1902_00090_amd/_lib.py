@@ -80,7 +80,8 @@ _SIGS = {
     "pca_build": (I, [P, I, I, I, P, C.POINTER(D), P]),
     "proj_loss_batched": (I, [P, P, I, I, I, C.POINTER(D), P]),
     "local_pca_targets": (I, [P, I, I, I, I, P, P]),
-    "dd_cnn_create": (I, [I, I, I, I, C.c_ulonglong, PP]),
+    "eim_field": (I, [PP, I, PP, PP, P]),
+    "dd_cnn_create": (I, [I, I, I, I, I, C.c_ulonglong, PP]),
     "dd_cnn_destroy": (None, [P]),
     "dd_cnn_layer_info": (I, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(I),
                               C.POINTER(I), C.POINTER(I)]),
@@ -88,9 +89,10 @@ _SIGS = {
     "dd_cnn_get_params": (I, [P, C.POINTER(C.c_float), C.c_size_t]),
     "dd_cnn_set_params": (I, [P, C.POINTER(C.c_float), C.c_size_t]),
     "predict_subspace": (I, [P, P, I, P, P]),
-    "dd_cnn_train_step": (I, [P, P, P, I, C.c_float, C.c_float, C.c_float,
+    "predict_subspace_eim": (I, [P, P, P, I, P, P]),
+    "dd_cnn_train_step": (I, [P, P, P, P, I, C.c_float, C.c_float, C.c_float,
                               C.POINTER(C.c_float), P]),
-    "dd_cnn_grad": (I, [P, P, P, I, C.POINTER(C.c_float), C.POINTER(C.c_float),
+    "dd_cnn_grad": (I, [P, P, P, P, I, C.POINTER(C.c_float), C.POINTER(C.c_float),
                         C.c_size_t, P]),
     "dd_cnn_debug_activation": (I, [P, I, I, C.POINTER(C.c_float), C.c_size_t]),
 }

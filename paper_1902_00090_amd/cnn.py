@@ -33,14 +33,17 @@ def _dev(t, dtype, numel, what):
 
 
 class Cnn:
-    """Encoder-decoder CNN mapping permittivity [B, ny, nx] to k complex fields."""
+    """Encoder-decoder CNN mapping permittivity [B, ny, nx] (and, with
+    in_channels=3, the effective-index field [B, ny*nx]) to k complex fields."""
 
-    def __init__(self, nx, ny, max_batch, k=10, seed=0):
+    def __init__(self, nx, ny, max_batch, k=10, seed=0, in_channels=1):
         self.nx, self.ny, self.max_batch, self.k = int(nx), int(ny), int(max_batch), int(k)
+        self.in_channels = int(in_channels)
         self.D = self.nx * self.ny
         h = C.c_void_p()
         check(_lib.lib().dd_cnn_create(self.nx, self.ny, self.max_batch, self.k,
-                                       C.c_ulonglong(seed), C.byref(h)), "dd_cnn_create")
+                                       self.in_channels, C.c_ulonglong(seed), C.byref(h)),
+              "dd_cnn_create")
         self._h = h
 
     def layers(self):
@@ -67,41 +70,60 @@ class Cnn:
         check(_lib.lib().dd_cnn_set_params(self._h, flat.ctypes.data_as(C.POINTER(C.c_float)),
                                            flat.size), "dd_cnn_set_params")
 
-    def predict(self, eps, U=None):
-        """eps: [B, ny, nx] float32 (device).  Returns U [B, k, D] complex64.
-        Batches larger than max_batch are run in chunks."""
+    def _eim(self, eim, B, off=0):
+        torch = _torch()
+        if self.in_channels == 1:
+            if eim is not None:
+                raise ValueError("this network takes the permittivity only")
+            return None
+        if eim is None:
+            raise ValueError("this network takes the effective-index field (eim)")
+        _dev(eim, torch.complex64, eim.shape[0] * self.D, "eim")
+        return C.c_void_p(eim[off:off + B].data_ptr())
+
+    def predict(self, eps, U=None, eim=None):
+        """eps: [B, ny, nx] float32 (device); eim: [B, ny*nx] complex64 for a
+        three-channel network.  Returns U [B, k, D] complex64.  Batches larger
+        than max_batch are run in chunks."""
         torch = _torch()
         B = eps.shape[0]
         if U is None:
             U = torch.empty((B, self.k, self.D), dtype=torch.complex64, device=eps.device)
         _dev(eps, torch.float32, B * self.D, "eps")
         _dev(U, torch.complex64, B * self.k * self.D, "U")
+        if eim is not None and eim.shape[0] != B:
+            raise ValueError("eim must have one field per image")
         for b0 in range(0, B, self.max_batch):
             nb = min(self.max_batch, B - b0)
             e = eps[b0:b0 + nb]
             u = U[b0:b0 + nb]
-            check(_lib.lib().predict_subspace(self._h, C.c_void_p(e.data_ptr()), nb,
-                                              C.c_void_p(u.data_ptr()), _stream()),
-                  "predict_subspace")
+            f = self._eim(eim, nb, b0)
+            if f is None:
+                rc = _lib.lib().predict_subspace(self._h, C.c_void_p(e.data_ptr()), nb,
+                                                 C.c_void_p(u.data_ptr()), _stream())
+            else:
+                rc = _lib.lib().predict_subspace_eim(self._h, C.c_void_p(e.data_ptr()), f, nb,
+                                                     C.c_void_p(u.data_ptr()), _stream())
+            check(rc, "predict_subspace")
         return U
 
-    def train_step(self, eps, target, lr=1e-3, b1=0.9, b2=0.999):
+    def train_step(self, eps, target, lr=1e-3, b1=0.9, b2=0.999, eim=None):
         torch = _torch()
         B = eps.shape[0]
         loss = C.c_float()
         check(_lib.lib().dd_cnn_train_step(
-            self._h, _dev(eps, torch.float32, B * self.D, "eps"),
+            self._h, _dev(eps, torch.float32, B * self.D, "eps"), self._eim(eim, B),
             _dev(target, torch.complex64, B * self.k * self.D, "target"), B, float(lr), float(b1),
             float(b2), C.byref(loss), _stream()), "dd_cnn_train_step")
         return loss.value
 
-    def grad(self, eps, target):
+    def grad(self, eps, target, eim=None):
         torch = _torch()
         B = eps.shape[0]
         loss = C.c_float()
         g = np.zeros(self.num_params, np.float32)
         check(_lib.lib().dd_cnn_grad(
-            self._h, _dev(eps, torch.float32, B * self.D, "eps"),
+            self._h, _dev(eps, torch.float32, B * self.D, "eps"), self._eim(eim, B),
             _dev(target, torch.complex64, B * self.k * self.D, "target"), B, C.byref(loss),
             g.ctypes.data_as(C.POINTER(C.c_float)), g.size, _stream()), "dd_cnn_grad")
         return loss.value, g
@@ -109,7 +131,7 @@ class Cnn:
     def activation(self, layer, B):
         """Layer output (NHWC, float32) of the last forward pass; layer -1 = input."""
         if layer == -1:
-            shape = (B, self.ny, self.nx)
+            shape = (B, self.in_channels, self.ny, self.nx)
         else:
             H, W = self.ny, self.nx
             for l, (cin, cout, s, up, relu) in enumerate(self.layers()):

@@ -53,13 +53,15 @@ struct CnnLayer {
 
 struct dd_cnn {
   int nx, ny, maxB, k;
+  int cin0;                  // input planes: 1 (permittivity) or 3 (+ effective-index field)
   CnnLayer L[NL];
   size_t nparams = 0;
   float *params = nullptr, *grads = nullptr, *am = nullptr, *av = nullptr;
   int adam_t = 0;
   bf16* wf[NL] = {};
   bf16* wb[NL] = {};
-  float* x0 = nullptr;       // normalised input [B][H][W]
+  float* x0 = nullptr;       // normalised input planes [B][cin0][H][W]
+  double* iscale = nullptr;  // [maxB] effective-index field scale sqrt(D) / ||F||
   bf16* act[NL] = {};        // act[l] = output of layer l (l < NL-1), NHWC bf16
   float* out = nullptr;      // last layer output [B][H][W][2k]
   bf16* dz[NL] = {};         // gradient w.r.t. the pre-activation of layer l
@@ -234,59 +236,73 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
 }
 
 // ------------------------------------------------------------- layer 1 ----
-// Cin = 1: direct FP32 arithmetic (9 taps), 32 output channels per pixel.
+// Cin = 1 or 3 input planes: direct FP32 arithmetic (9 taps per plane), 32
+// output channels per pixel.  x0 is planar [B][C][H][W].
 __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
                                                    const float* __restrict__ w,
-                                                   const float* __restrict__ bias, int B, int H,
-                                                   int W, int coutp, bf16* __restrict__ out) {
+                                                   const float* __restrict__ bias, int B, int C,
+                                                   int H, int W, int coutp,
+                                                   bf16* __restrict__ out) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= B * H * W) return;
   const int b = p / (H * W), rem = p - b * H * W, y = rem / W, x = rem - (rem / W) * W;
-  float xin[9];
-  for (int t = 0; t < 9; ++t) {
-    const int ys = y + t / 3 - 1, xs = x + t % 3 - 1;
-    xin[t] = (ys >= 0 && ys < H && xs >= 0 && xs < W) ? x0[((size_t)b * H + ys) * W + xs] : 0.f;
-  }
-  for (int c = 0; c < coutp; c += 4) {
+  float xin[3][9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ys = y + t / 3 - 1, xs = x + t % 3 - 1;
+      xin[c][t] = (c < C && ys >= 0 && ys < H && xs >= 0 && xs < W)
+                      ? x0[(((size_t)b * C + c) * H + ys) * W + xs] : 0.f;
+    }
+  for (int co = 0; co < coutp; co += 4) {
     bf16 h[4];
     for (int q = 0; q < 4; ++q) {
-      float s = bias[c + q];
-      for (int t = 0; t < 9; ++t) s += w[(c + q) * 9 + t] * xin[t];
+      float s = bias[co + q];
+      const float* wr = w + (size_t)(co + q) * C * 9;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (c < C)
+#pragma unroll
+          for (int t = 0; t < 9; ++t) s += wr[c * 9 + t] * xin[c][t];
       h[q] = (bf16)fmaxf(s, 0.f);
     }
-    *(u32x2*)(out + (size_t)p * coutp + c) = __builtin_bit_cast(u32x2, h);
+    *(u32x2*)(out + (size_t)p * coutp + co) = __builtin_bit_cast(u32x2, h);
   }
 }
 
-// Layer-1 weight gradient partials: thread (co, tap) sums over the rows
-// [r0, r1) of the batch (row = one image row), walking x without divisions.
-__global__ __launch_bounds__(320) void k_conv1_wgrad(const float* __restrict__ x0,
-                                                     const bf16* __restrict__ dz, int B, int H,
-                                                     int W, int cout, int coutp, int rows_per,
-                                                     float* __restrict__ part) {
-  const int t = threadIdx.x;
+// Layer-1 weight gradient partials: thread (co, j) with j = 9 ci + tap (j = 9C
+// is the bias) sums over the rows [r0, r1) of the batch (row = one image row),
+// walking x without divisions.  Block size: cout (9C + 1) rounded up to 64.
+__global__ __launch_bounds__(1024) void k_conv1_wgrad(const float* __restrict__ x0,
+                                                      const bf16* __restrict__ dz, int B, int C,
+                                                      int H, int W, int cout, int coutp,
+                                                      int rows_per, float* __restrict__ part) {
+  const int t = threadIdx.x, J = 9 * C + 1;
   const int r0 = blockIdx.x * rows_per, r1 = min(B * H, r0 + rows_per);
-  if (t >= cout * 10) return;
-  const int co = t / 10, tap = t % 10;  // tap 9 = bias
+  if (t >= cout * J) return;
+  const int co = t / J, j = t % J;
+  const bool isb = (j == 9 * C);
+  const int ci = isb ? 0 : j / 9, tap = isb ? 0 : j % 9;
   const int dy = tap / 3 - 1, dx = tap % 3 - 1;
   float s = 0.f;
   for (int row = r0; row < r1; ++row) {
     const int b = row / H, y = row - b * H;
     const int ys = y + dy;
-    const bool rowok = (tap == 9) || (ys >= 0 && ys < H);
-    const float* xr = x0 + ((size_t)b * H + (rowok && tap < 9 ? ys : 0)) * W;
-    const bf16* g = dz + (size_t)row * W * coutp + co;
+    const bool rowok = isb || (ys >= 0 && ys < H);
     if (!rowok) continue;
+    const float* xr = x0 + (((size_t)b * C + ci) * H + (isb ? 0 : ys)) * W;
+    const bf16* g = dz + (size_t)row * W * coutp + co;
     for (int x = 0; x < W; ++x) {
       float xv = 1.f;
-      if (tap < 9) {
+      if (!isb) {
         const int xs = x + dx;
         xv = (xs >= 0 && xs < W) ? xr[xs] : 0.f;
       }
       s += bf2f(g[(size_t)x * coutp]) * xv;
     }
   }
-  part[(size_t)blockIdx.x * cout * 10 + t] = s;
+  part[(size_t)blockIdx.x * cout * J + t] = s;
 }
 
 // --------------------------------------------------- weight gradients ----
@@ -368,18 +384,26 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16* __restrict__ dz,
 // are then added in a fixed order.
 __global__ __launch_bounds__(256) void k_bias_grad(const bf16* __restrict__ dz, int npix, int Mr,
                                                    int per, float* __restrict__ part) {
-  __shared__ float red[256];
+  // thread = (pixel lane g, group of 8 channels cg): 16-byte loads, G pixels
+  // per round; Mr is a multiple of 16
+  __shared__ float red[256 * 8];
   const int p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
-  const int G = 256 / Mr, c = threadIdx.x % Mr, g = threadIdx.x / Mr;
-  float s = 0.f;
+  const int CG = Mr / 8, G = 256 / CG, cg = threadIdx.x % CG, g = threadIdx.x / CG;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (g < G)
-    for (int p = p0 + g; p < p1; p += G) s += bf2f(dz[(size_t)p * Mr + c]);
-  red[threadIdx.x] = s;
+    for (int p = p0 + g; p < p1; p += G) {
+      const bf16x8 v = load8(dz + (size_t)p * Mr + 8 * cg);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s[q] += (float)v[q];
+    }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[threadIdx.x * 8 + q] = s[q];
   __syncthreads();
   if (threadIdx.x < Mr) {
+    const int c = threadIdx.x, cgc = c / 8, q = c % 8;
     float t = 0.f;
-    for (int q = 0; q < G; ++q) t += red[q * Mr + threadIdx.x];
-    part[(size_t)blockIdx.x * Mr + threadIdx.x] = t;
+    for (int gg = 0; gg < G; ++gg) t += red[(gg * CG + cgc) * 8 + q];
+    part[(size_t)blockIdx.x * Mr + c] = t;
   }
 }
 
@@ -401,21 +425,46 @@ __global__ void k_bgrad_reduce(const float* __restrict__ part, int nslices, int 
   for (int sl = 0; sl < nslices; ++sl) s += part[(size_t)sl * Mr + r];
   g[r] = s;
 }
-__global__ void k_conv1_reduce(const float* __restrict__ part, int nslices, int cout,
+__global__ void k_conv1_reduce(const float* __restrict__ part, int nslices, int cout, int C,
                                float* __restrict__ gw, float* __restrict__ gb) {
+  const int J = 9 * C + 1;
   const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= cout * 10) return;
+  if (t >= cout * J) return;
   float s = 0.f;
-  for (int sl = 0; sl < nslices; ++sl) s += part[(size_t)sl * cout * 10 + t];
-  const int co = t / 10, tap = t % 10;
-  if (tap < 9) gw[co * 9 + tap] = s;
+  for (int sl = 0; sl < nslices; ++sl) s += part[(size_t)sl * cout * J + t];
+  const int co = t / J, j = t % J;
+  if (j < 9 * C) gw[(size_t)co * 9 * C + j] = s;   // [cout][cin][3][3]
   else gb[co] = s;
 }
 
 // ------------------------------------------------ input, loss, output ----
-__global__ void k_normalise(const float* __restrict__ eps, int n, float* __restrict__ x0) {
+// Input planes [B][C][H][W]: plane 0 = (eps - 2.085) / (12.25 - 2.085); for
+// C = 3, planes 1 and 2 = real and imaginary part of the effective-index field
+// scaled to unit RMS per pixel (iscale[b] = sqrt(D) / ||F_b||).
+__global__ void k_inputs(const float* __restrict__ eps, const float2* __restrict__ eim,
+                         const double* __restrict__ iscale, int B, int D, int C,
+                         float* __restrict__ x0) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) x0[i] = (eps[i] - CNN_EPS_LO) / (CNN_EPS_HI - CNN_EPS_LO);
+  if (i >= B * D) return;
+  const int b = i / D, e = i - b * D;
+  x0[(size_t)b * C * D + e] = (eps[i] - CNN_EPS_LO) / (CNN_EPS_HI - CNN_EPS_LO);
+  if (C == 3) {
+    const float s = (float)iscale[b];
+    const float2 f = eim[i];
+    x0[((size_t)b * C + 1) * D + e] = f.x * s;
+    x0[((size_t)b * C + 2) * D + e] = f.y * s;
+  }
+}
+
+// iscale[b] = sqrt(D / sum |F_b|^2) (0 for an all-zero field); one block per problem
+__global__ __launch_bounds__(256) void k_eim_scale(const float2* __restrict__ eim, int D,
+                                                   double* __restrict__ iscale) {
+  const float2* f = eim + (size_t)blockIdx.x * D;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < D; e += 256) s += (double)f[e].x * f[e].x + (double)f[e].y * f[e].y;
+  __shared__ double lds[8];
+  s = block_sum1<double>(s, lds);
+  if (threadIdx.x == 0) iscale[blockIdx.x] = (s > 0.0) ? sqrt((double)D / s) : 0.0;
 }
 
 // loss partials and dz of the last (linear) layer: out [p][2k] FP32, target
@@ -428,15 +477,23 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out,
   float s = 0.f;
   if (p < B * D) {
     const int b = p / D, e = p - b * D;
-    for (int c = 0; c < coutp; ++c) {
-      float g = 0.f;
-      if (c < 2 * k) {
-        const float2 t = target[((size_t)b * k + c / 2) * D + e];
-        const float d = out[(size_t)p * 2 * k + c] - ((c & 1) ? t.y : t.x);
-        s += d * d;
-        g = scale * d;
+    const float* o = out + (size_t)p * 2 * k;
+    // coutp is a multiple of 16: the row of dz is written 8 channels (16 B) at a time
+    for (int c0 = 0; c0 < coutp; c0 += 8) {
+      bf16x8 h;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = c0 + q;
+        float g = 0.f;
+        if (c < 2 * k) {
+          const float2 t = target[((size_t)b * k + c / 2) * D + e];
+          const float d = o[c] - ((c & 1) ? t.y : t.x);
+          s += d * d;
+          g = scale * d;
+        }
+        h[q] = (bf16)g;
       }
-      dz[(size_t)p * coutp + c] = (bf16)g;
+      *(u32x4*)(dz + (size_t)p * coutp + c0) = __builtin_bit_cast(u32x4, h);
     }
   }
   __shared__ float lds[8];
@@ -522,17 +579,19 @@ static dd_status pack_all(dd_cnn* n, hipStream_t st) {
   return DD_OK;
 }
 
-extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, unsigned long long seed,
-                                   dd_cnn** out) {
+extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_channels,
+                                   unsigned long long seed, dd_cnn** out) {
   if (!out) { dd_set_error("dd_cnn_create: out is NULL"); return DD_EINVAL; }
   *out = nullptr;
-  if (nx < 4 || ny < 4 || nx % 4 || ny % 4 || max_batch < 1 || k < 1 || 2 * k > 64) {
-    dd_set_error("dd_cnn_create: need nx, ny multiples of 4, max_batch >= 1, 1 <= k <= 32");
+  if (nx < 4 || ny < 4 || nx % 4 || ny % 4 || max_batch < 1 || k < 1 || 2 * k > 64 ||
+      (in_channels != 1 && in_channels != 3)) {
+    dd_set_error("dd_cnn_create: need nx, ny multiples of 4, max_batch >= 1, 1 <= k <= 32 "
+                 "and 1 or 3 input channels");
     return DD_EINVAL;
   }
   dd_cnn* n = new dd_cnn();
-  n->nx = nx; n->ny = ny; n->maxB = max_batch; n->k = k;
-  const int spec[NL][5] = {{1, 32, 1, 0, 1}, {32, 64, 2, 0, 1}, {64, 128, 2, 0, 1},
+  n->nx = nx; n->ny = ny; n->maxB = max_batch; n->k = k; n->cin0 = in_channels;
+  const int spec[NL][5] = {{in_channels, 32, 1, 0, 1}, {32, 64, 2, 0, 1}, {64, 128, 2, 0, 1},
                            {128, 128, 1, 0, 1}, {128, 64, 1, 1, 1}, {64, 32, 1, 1, 1},
                            {32, 32, 1, 0, 1}, {32, 2 * k, 1, 0, 0}};
   int H = ny, W = nx;
@@ -541,7 +600,7 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, unsigne
     CnnLayer& L = n->L[l];
     L.cin = spec[l][0]; L.cout = spec[l][1]; L.stride = spec[l][2]; L.up = spec[l][3];
     L.relu = spec[l][4];
-    L.cinp = (L.cin == 1) ? 1 : rup16(L.cin);
+    L.cinp = (l == 0) ? L.cin : rup16(L.cin);
     L.coutp = std::max(32, rup16(L.cout));
     L.Hin = H; L.Win = W;
     if (L.up) { L.Hout = 2 * H; L.Wout = 2 * W; }
@@ -569,7 +628,8 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, unsigne
   chk(cnn_alloc(n, &n->am, off + 64));
   chk(cnn_alloc(n, &n->av, off + 64));
   const size_t D = (size_t)nx * ny;
-  chk(cnn_alloc(n, &n->x0, (size_t)max_batch * D));
+  chk(cnn_alloc(n, &n->x0, (size_t)max_batch * D * in_channels));
+  chk(cnn_alloc(n, &n->iscale, (size_t)max_batch));
   size_t wp = 0;
   for (int l = 0; l < NL && e == hipSuccess; ++l) {
     const CnnLayer& L = n->L[l];
@@ -586,7 +646,7 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, unsigne
     const size_t slices = std::max<size_t>((pix + per - 1) / per, 260);
     if (l > 0) wp = std::max(wp, slices * 9 * L.coutp * L.cinp);
     wp = std::max(wp, slices * (size_t)L.coutp);
-    wp = std::max(wp, (size_t)512 * L.cout * 10);
+    wp = std::max(wp, (size_t)512 * L.cout * (9 * L.cin + 1));
   }
   n->wpart_elems = wp;
   chk(cnn_alloc(n, &n->wpart, wp));
@@ -670,14 +730,17 @@ static void gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_t st)
   }
 }
 
-static dd_status forward(dd_cnn* n, const float* eps, int B, hipStream_t st, float* biaspad) {
+static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hipStream_t st,
+                         float* biaspad) {
   const int D = n->nx * n->ny;
-  k_normalise<<<(B * D + 255) / 256, 256, 0, st>>>(eps, B * D, n->x0);
+  if (n->cin0 == 3) k_eim_scale<<<B, 256, 0, st>>>((const float2*)eim, D, n->iscale);
+  k_inputs<<<(B * D + 255) / 256, 256, 0, st>>>(eps, (const float2*)eim, n->iscale, B, D, n->cin0,
+                                                 n->x0);
   {
     const CnnLayer& L = n->L[0];
     k_conv1_fwd<<<(B * D + 255) / 256, 256, 0, st>>>(n->x0, n->params + L.woff,
-                                                      n->params + L.boff, B, n->ny, n->nx,
-                                                      L.coutp, n->act[0]);
+                                                      n->params + L.boff, B, n->cin0, n->ny,
+                                                      n->nx, L.coutp, n->act[0]);
   }
   for (int l = 1; l < NL; ++l) {
     const CnnLayer& L = n->L[l];
@@ -735,10 +798,12 @@ static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hip
     const CnnLayer& L = n->L[0];
     const int rows = B * n->ny, rows_per = std::max(1, (rows + 511) / 512);
     const int slices = (rows + rows_per - 1) / rows_per;
-    k_conv1_wgrad<<<slices, 320, 0, st>>>(n->x0, n->dz[0], B, n->ny, n->nx, L.cout, L.coutp,
-                                          rows_per, n->wpart);
-    k_conv1_reduce<<<(L.cout * 10 + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout,
-                                                              n->grads + L.woff, n->grads + L.boff);
+    const int nt = L.cout * (9 * n->cin0 + 1);
+    k_conv1_wgrad<<<slices, (nt + 63) / 64 * 64, 0, st>>>(n->x0, n->dz[0], B, n->cin0, n->ny,
+                                                          n->nx, L.cout, L.coutp, rows_per,
+                                                          n->wpart);
+    k_conv1_reduce<<<(nt + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
+                                                     n->grads + L.woff, n->grads + L.boff);
   }
   DD_HIP_CHECK(hipGetLastError());
   if (loss) {
@@ -752,20 +817,27 @@ static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hip
   return DD_OK;
 }
 
-static dd_status check_batch(const dd_cnn* n, const void* eps, int B, const char* who) {
+static dd_status check_batch(const dd_cnn* n, const void* eps, const void* eim, int B,
+                             const char* who) {
   if (!n || !eps || B < 1 || B > n->maxB) {
     dd_set_error("%s: need a network, eps and 1 <= B <= max_batch (%d)", who, n ? n->maxB : 0);
+    return DD_EINVAL;
+  }
+  if ((n->cin0 == 3) != (eim != nullptr)) {
+    dd_set_error("%s: this network takes %s", who,
+                 n->cin0 == 3 ? "the effective-index field (eim must not be NULL)"
+                              : "the permittivity only (eim must be NULL)");
     return DD_EINVAL;
   }
   return DD_OK;
 }
 
-extern "C" dd_status predict_subspace(dd_cnn* n, const float* eps, int B, void* U,
-                                      hipStream_t st) {
-  dd_status rc = check_batch(n, eps, B, "predict_subspace");
+static dd_status predict(dd_cnn* n, const float* eps, const void* eim, int B, void* U,
+                         hipStream_t st, const char* who) {
+  dd_status rc = check_batch(n, eps, eim, B, who);
   if (rc != DD_OK) return rc;
-  if (!U) { dd_set_error("predict_subspace: U is NULL"); return DD_EINVAL; }
-  rc = forward(n, eps, B, st, n->biaspad);
+  if (!U) { dd_set_error("%s: U is NULL", who); return DD_EINVAL; }
+  rc = forward(n, eps, eim, B, st, n->biaspad);
   if (rc != DD_OK) return rc;
   const int D = n->nx * n->ny;
   k_to_fields<<<(B * D + 255) / 256, 256, 0, st>>>(n->out, B, D, n->k, (float2*)U);
@@ -774,15 +846,27 @@ extern "C" dd_status predict_subspace(dd_cnn* n, const float* eps, int B, void* 
   return DD_OK;
 }
 
-extern "C" dd_status dd_cnn_grad(dd_cnn* n, const float* eps, const void* target, int B,
-                                 float* loss, float* host_grad, size_t count, hipStream_t st) {
-  dd_status rc = check_batch(n, eps, B, "dd_cnn_grad");
+extern "C" dd_status predict_subspace(dd_cnn* n, const float* eps, int B, void* U,
+                                      hipStream_t st) {
+  return predict(n, eps, nullptr, B, U, st, "predict_subspace");
+}
+
+extern "C" dd_status predict_subspace_eim(dd_cnn* n, const float* eps, const void* eim, int B,
+                                          void* U, hipStream_t st) {
+  if (!eim) { dd_set_error("predict_subspace_eim: eim is NULL"); return DD_EINVAL; }
+  return predict(n, eps, eim, B, U, st, "predict_subspace_eim");
+}
+
+extern "C" dd_status dd_cnn_grad(dd_cnn* n, const float* eps, const void* eim, const void* target,
+                                 int B, float* loss, float* host_grad, size_t count,
+                                 hipStream_t st) {
+  dd_status rc = check_batch(n, eps, eim, B, "dd_cnn_grad");
   if (rc != DD_OK) return rc;
   if (!target || (host_grad && count != n->nparams)) {
     dd_set_error("dd_cnn_grad: bad target or gradient size");
     return DD_EINVAL;
   }
-  rc = forward(n, eps, B, st, n->biaspad);
+  rc = forward(n, eps, eim, B, st, n->biaspad);
   if (rc != DD_OK) return rc;
   rc = backward(n, target, B, loss, st);
   if (rc != DD_OK) return rc;
@@ -793,15 +877,16 @@ extern "C" dd_status dd_cnn_grad(dd_cnn* n, const float* eps, const void* target
   return DD_OK;
 }
 
-extern "C" dd_status dd_cnn_train_step(dd_cnn* n, const float* eps, const void* target, int B,
-                                       float lr, float b1, float b2, float* loss, hipStream_t st) {
-  dd_status rc = check_batch(n, eps, B, "dd_cnn_train_step");
+extern "C" dd_status dd_cnn_train_step(dd_cnn* n, const float* eps, const void* eim,
+                                       const void* target, int B, float lr, float b1, float b2,
+                                       float* loss, hipStream_t st) {
+  dd_status rc = check_batch(n, eps, eim, B, "dd_cnn_train_step");
   if (rc != DD_OK) return rc;
   if (!target || !(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f)) {
     dd_set_error("dd_cnn_train_step: bad target or Adam parameters");
     return DD_EINVAL;
   }
-  rc = forward(n, eps, B, st, n->biaspad);
+  rc = forward(n, eps, eim, B, st, n->biaspad);
   if (rc != DD_OK) return rc;
   rc = backward(n, target, B, loss, st);
   if (rc != DD_OK) return rc;
@@ -825,7 +910,8 @@ extern "C" dd_status dd_cnn_debug_activation(const dd_cnn* n, int layer, int B, 
   DD_HIP_CHECK(hipDeviceSynchronize());
   const size_t D = (size_t)n->nx * n->ny;
   if (layer == -1) {
-    if (count != B * D) { dd_set_error("dd_cnn_debug_activation: count must be %zu", B * D); return DD_EINVAL; }
+    const size_t cnt = B * D * n->cin0;
+    if (count != cnt) { dd_set_error("dd_cnn_debug_activation: count must be %zu", cnt); return DD_EINVAL; }
     DD_HIP_CHECK(hipMemcpy(host, n->x0, sizeof(float) * count, hipMemcpyDeviceToHost));
     return DD_OK;
   }

@@ -42,9 +42,11 @@ def trajectory_targets(fields, traj_len, window=8, k=10, rms=1.0):
     return out * float(rms * np.sqrt(D))
 
 
-def train_cnn(net, eps, targets, steps, batch, lr=1e-3, b1=0.9, b2=0.999, seed=0, log=None):
+def train_cnn(net, eps, targets, steps, batch, lr=1e-3, b1=0.9, b2=0.999, seed=0, log=None,
+              eim=None):
     """Adam on mini-batches drawn without replacement (reshuffled every epoch).
-    eps: [N, ny, nx] float32, targets: [N, k, D] complex64 (device)."""
+    eps: [N, ny, nx] float32, targets: [N, k, D] complex64, eim: [N, D]
+    complex64 effective-index fields for a three-channel network (device)."""
     import torch
     N = eps.shape[0]
     rng = np.random.default_rng(seed)
@@ -55,7 +57,8 @@ def train_cnn(net, eps, targets, steps, batch, lr=1e-3, b1=0.9, b2=0.999, seed=0
         idx = torch.as_tensor(order[pos:pos + batch], device=eps.device)
         pos += batch
         loss = net.train_step(eps.index_select(0, idx).contiguous(),
-                              targets.index_select(0, idx).contiguous(), lr, b1, b2)
+                              targets.index_select(0, idx).contiguous(), lr, b1, b2,
+                              eim=None if eim is None else eim.index_select(0, idx).contiguous())
         losses.append(loss)
         if log and (it % max(1, steps // 10) == 0 or it == steps - 1):
             log(f"  cnn step {it}: loss {loss:.4e}")

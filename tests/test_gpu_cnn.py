@@ -19,11 +19,11 @@ def _bf16(a):
     return r.astype(np.uint32).view(np.float32)
 
 
-def _setup(nx, ny, B, k, seed):
+def _setup(nx, ny, B, k, seed, in_ch=1):
     import torch
     from paper_1902_00090_amd import Cnn
     from paper_1902_00090_amd.cnn import flat_to_layers
-    net = Cnn(nx, ny, B, k, seed=seed)
+    net = Cnn(nx, ny, B, k, seed=seed, in_channels=in_ch)
     rng = np.random.default_rng(seed)
     flat = net.get_params()
     layers = net.layers()
@@ -38,7 +38,12 @@ def _setup(nx, ny, B, k, seed):
     for li in range(1, 8):
         op[li][0] = _bf16(op[li][0]).astype(np.float64)
     eps = (2.085 + 10.165 * rng.random((B, ny, nx))).astype(np.float32)
-    return net, op, eps, torch.tensor(eps, device="cuda")
+    if in_ch == 1:
+        return net, op, eps, torch.tensor(eps, device="cuda")
+    # a seeded complex field of uneven amplitude stands in for the effective-index input
+    eim = ((rng.standard_normal((B, nx * ny)) + 1j * rng.standard_normal((B, nx * ny))) *
+           np.linspace(0.5, 3.0, B)[:, None]).astype(np.complex64)
+    return net, op, eps, torch.tensor(eps, device="cuda"), eim, torch.tensor(eim, device="cuda")
 
 
 def _rel(a, b):
@@ -106,3 +111,52 @@ def test_adam_step_and_training_reduces_loss():
     np.testing.assert_allclose(p1, ref, atol=2e-7)
     losses = [net.train_step(eps_d, tgt, lr=1e-3) for _ in range(60)]
     assert losses[-1] < 0.7 * losses[0], (losses[0], losses[-1])
+
+
+def test_three_channel_forward_and_gradients_match_oracle():
+    """Permittivity plus effective-index field (the paper's CNN input): the
+    input planes, every layer, the output and all gradients against the
+    oracle at identical weights."""
+    import torch
+    from paper_1902_00090_amd.cnn import flat_to_layers
+    nx, ny, B, k = 24, 16, 3, 4
+    net, op, eps, eps_d, eim, eim_d = _setup(nx, ny, B, k, seed=9, in_ch=3)
+    assert net.layers()[0][0] == 3
+    U = net.predict(eps_d, eim=eim_d).cpu().numpy()
+    out, cache = ocnn.forward(op, eps.astype(np.float64), k, eim=eim.astype(np.complex128))
+    x_ref = ocnn.inputs(eps.astype(np.float64), eim.astype(np.complex128))
+    np.testing.assert_allclose(net.activation(-1, B), x_ref, rtol=2e-6, atol=2e-6)
+    for li in range(8):
+        a_gpu = net.activation(li, B)
+        z = cache[li][2]
+        a_ref = np.maximum(z, 0) if li < 7 else z
+        assert _rel(a_gpu.transpose(0, 3, 1, 2), a_ref) < 3e-2, li
+    assert _rel(U, ocnn.channels_to_fields(out)) < 3e-2
+    rng = np.random.default_rng(12)
+    tgt = ((rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny)))
+           * 0.1).astype(np.complex64)
+    loss, g = net.grad(eps_d, torch.tensor(tgt, device="cuda"), eim=eim_d)
+    lo, dout = ocnn.mse(out, ocnn.fields_to_channels(tgt.astype(np.complex128), ny, nx))
+    go = ocnn.backward(op, cache, dout, k)
+    assert abs(loss - lo) < 1e-2 * lo
+    gg = flat_to_layers(g.astype(np.float64), net.layers())
+    for li in range(8):
+        assert _rel(gg[li][0], go[li][0]) < 6e-2, ("w", li, _rel(gg[li][0], go[li][0]))
+        assert _rel(gg[li][1], go[li][1]) < 6e-2, ("b", li, _rel(gg[li][1], go[li][1]))
+
+
+def test_channel_count_is_enforced():
+    import torch
+    from paper_1902_00090_amd import DDError
+    net, op, eps, eps_d = _setup(24, 16, 1, 2, seed=1)
+    with pytest.raises(ValueError):
+        net.predict(eps_d, eim=torch.zeros((1, 24 * 16), dtype=torch.complex64, device="cuda"))
+    net3, _, _, e3, _, f3 = _setup(24, 16, 1, 2, seed=1, in_ch=3)
+    with pytest.raises(ValueError):
+        net3.predict(e3)
+    from paper_1902_00090_amd import _lib
+    U = torch.empty((1, 2, 24 * 16), dtype=torch.complex64, device="cuda")
+    import ctypes as C
+    rc = _lib.lib().predict_subspace(net3._h, C.c_void_p(e3.data_ptr()), 1,
+                                     C.c_void_p(U.data_ptr()), None)
+    assert rc == _lib.DD_EINVAL

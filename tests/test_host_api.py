@@ -61,8 +61,11 @@ def test_other_entry_points_reject_bad_arguments_on_host():
     lib = _lib.lib()
     h = C.c_void_p()
     assert lib.dd_solver_create(None, 0, None, C.byref(h)) == _lib.DD_EINVAL
-    assert lib.dd_cnn_create(30, 16, 1, 10, 0, C.byref(h)) == _lib.DD_EINVAL   # nx % 4 != 0
-    assert lib.dd_cnn_create(32, 16, 0, 10, 0, C.byref(h)) == _lib.DD_EINVAL   # max_batch 0
+    assert lib.dd_cnn_create(30, 16, 1, 10, 1, 0, C.byref(h)) == _lib.DD_EINVAL   # nx % 4 != 0
+    assert lib.dd_cnn_create(32, 16, 0, 10, 1, 0, C.byref(h)) == _lib.DD_EINVAL   # max_batch 0
+    assert lib.dd_cnn_create(32, 16, 1, 10, 2, 0, C.byref(h)) == _lib.DD_EINVAL   # 2 channels
+    assert lib.eim_field(None, 0, None, None, None) == _lib.DD_EINVAL
+    assert lib.predict_subspace_eim(None, None, None, 1, None, None) == _lib.DD_EINVAL
     assert lib.pca_build(None, 10, 100, 3, None, None, None) == _lib.DD_EINVAL
     assert lib.proj_loss_batched(None, None, 1, 1, 1, None, None) == _lib.DD_EINVAL
     assert lib.dd_solver_kernel_stats(None, None) == _lib.DD_EINVAL

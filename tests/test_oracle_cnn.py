@@ -40,14 +40,18 @@ def test_conv_backward_is_adjoint():
         np.testing.assert_allclose(db, z.sum(axis=(0, 2, 3)), rtol=1e-12)
 
 
-def test_network_gradient_matches_finite_differences():
+@pytest.mark.parametrize("in_ch", [1, 3])
+def test_network_gradient_matches_finite_differences(in_ch):
     rng = np.random.default_rng(3)
     k = 2
-    params = cnn.init_params(k, seed=4)
+    params = cnn.init_params(k, seed=4, in_ch=in_ch)
     for p in params:                      # non-zero biases so every term is exercised
         p[1][...] = 0.05 * rng.standard_normal(p[1].shape)
     eps = 2.085 + 10.165 * rng.random((2, 8, 12))
-    out, cache = cnn.forward(params, eps, k)
+    eim = None
+    if in_ch == 3:
+        eim = rng.standard_normal((2, 96)) + 1j * rng.standard_normal((2, 96))
+    out, cache = cnn.forward(params, eps, k, eim=eim)
     target = rng.standard_normal(out.shape)
     loss, dout = cnn.mse(out, target)
     grads = cnn.backward(params, cache, dout, k)
@@ -59,13 +63,16 @@ def test_network_gradient_matches_finite_differences():
                 idx = tuple(rng.integers(0, s) for s in arr.shape)
                 old = arr[idx]
                 arr[idx] = old + h
-                lp, _ = cnn.mse(cnn.forward(params, eps, k)[0], target)
+                lp, _ = cnn.mse(cnn.forward(params, eps, k, eim=eim)[0], target)
                 arr[idx] = old - h
-                lm, _ = cnn.mse(cnn.forward(params, eps, k)[0], target)
+                lm, _ = cnn.mse(cnn.forward(params, eps, k, eim=eim)[0], target)
                 arr[idx] = old
                 fd = (lp - lm) / (2 * h)
                 an = grads[li][which][idx]
-                assert abs(fd - an) <= 1e-6 * max(1e-8, abs(fd)) + 1e-11, (li, which, fd, an)
+                # central differences with h = 1e-6 carry a rounding error of about
+                # eps_mach * loss / h (1e-10 for the loss of the three-plane input)
+                tol_abs = 1e-11 if in_ch == 1 else 2e-10
+                assert abs(fd - an) <= 1e-6 * max(1e-8, abs(fd)) + tol_abs, (li, which, fd, an)
 
 
 def test_adam_first_step_closed_form():
@@ -109,3 +116,19 @@ def test_channel_packing_roundtrip():
     np.testing.assert_allclose(Y[:, 0], U[:, 0].real.reshape(2, 4, 5))
     np.testing.assert_allclose(Y[:, 1], U[:, 0].imag.reshape(2, 4, 5))
     np.testing.assert_allclose(cnn.channels_to_fields(Y), U)
+
+
+def test_effective_index_input_planes():
+    """Input planes 1 and 2 are the field's real and imaginary parts at unit
+    RMS per image; a zero field gives zero planes."""
+    rng = np.random.default_rng(5)
+    eps = 2.085 + 10.165 * rng.random((2, 4, 6))
+    F = rng.standard_normal((2, 24)) + 1j * rng.standard_normal((2, 24))
+    F[1] = 0.0
+    x = cnn.inputs(eps, 3.0 * F)
+    assert x.shape == (2, 3, 4, 6)
+    np.testing.assert_allclose(x[0, 1] ** 2 + x[0, 2] ** 2, (np.abs(F[0]) ** 2).reshape(4, 6)
+                               / np.mean(np.abs(F[0]) ** 2), rtol=1e-12)
+    np.testing.assert_allclose(np.mean(x[0, 1] ** 2 + x[0, 2] ** 2), 1.0, rtol=1e-12)
+    assert np.all(x[1, 1:] == 0.0)
+    np.testing.assert_allclose(x[:, 0], cnn.normalise(eps), rtol=0)
