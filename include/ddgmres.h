@@ -256,6 +256,21 @@ dd_status proj_loss_batched(const void* V, const void* f, int nb, int k, int D, 
                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Residual loss of a subspace (Sec. 3, eq:res_loss), batched evaluation
+ * ------------------------------------------------------------------------
+ * l_p = min_c ||A_p V_p c - b_p||^2 / ||b_p||^2, computed as
+ * 1 - b^H P_W b / ||b||^2 with W = A V.  The FP64 Gram matrix of [W b] is
+ * formed on the device; the k x k Cholesky solve runs on the host.  A
+ * rank-deficient W gets a tiny ridge.
+ *   ops[p]:  operator of problem p.
+ *   b[p]:    [D] c128 (device).
+ *   V[p]:    [k][D] c64 (device).
+ *   out:     [nb] (host), clamped to [0, 1].
+ * Problems may have different grids.  Synchronises the stream. */
+dd_status res_loss_batched(const fdfd_op* const* ops, const void* const* b, const void* const* V,
+                           int nb, int k, double* out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Effective-index field (Sec. 3: the CNN's second input)
  * ------------------------------------------------------------------------
  * The paper gives its CNN an effective-index simulation of the field: a
@@ -344,6 +359,25 @@ dd_status dd_cnn_train_step(dd_cnn* net, const float* eps, const void* eim, cons
  * layout.  Used for gradient checks.  eim is as in dd_cnn_train_step. */
 dd_status dd_cnn_grad(dd_cnn* net, const float* eps, const void* eim, const void* target, int B,
                       float* loss, float* host_grad, size_t count, hipStream_t stream);
+
+/* Residual-loss training (Sec. 3, eq:res_loss; unsupervised).  The loss is
+ * the batch mean of l_res of each image's predicted fields against its own
+ * operator ops[p] (grid ny x nx) and right-hand side b[p] ([D] c128, device).
+ * The gradient with respect to the fields is -(A^H r) c^H / ||b||^2 per
+ * image, with c the least-squares coefficients and r = b - A V c.  It runs
+ * through the network's backward pass, then an Adam update as in
+ * dd_cnn_train_step.  eim is as in dd_cnn_train_step.  *loss (host, may be
+ * NULL) receives the batch mean.  Synchronises the stream. */
+dd_status dd_cnn_train_step_res(dd_cnn* net, const float* eps, const void* eim,
+                                const fdfd_op* const* ops, const void* const* b, int B, float lr,
+                                float b1, float b2, float* loss, hipStream_t stream);
+
+/* Gradient of the batch residual loss with respect to all parameters, with
+ * no update.  host_grad (host, count values) uses the dd_cnn_get_params
+ * layout.  For gradient checks. */
+dd_status dd_cnn_grad_res(dd_cnn* net, const float* eps, const void* eim,
+                          const fdfd_op* const* ops, const void* const* b, int B, float* loss,
+                          float* host_grad, size_t count, hipStream_t stream);
 
 /* Copy the bf16 activations of layer l's output (NHWC, as float32) to host.
  * layer = -1 gives the normalised input planes [B][in_channels][ny][nx].

@@ -324,4 +324,19 @@ def eim_field(ops, b, out=None):
     return F if out is None else out
 
 
+def res_loss_batched(ops, b, V):
+    """Residual loss (eq:res_loss) of V[p] ([k, D] complex64) for the problems
+    (ops[p], b[p] [D] complex128), all device tensors.  Returns numpy [nb]."""
+    torch = _torch()
+    nb = len(ops)
+    k = V[0].shape[0]
+    out = np.zeros(nb, np.float64)
+    opp = ptr_array([op._h.value for op in ops])
+    bp = ptr_array([_dev(bb, torch.complex128, ops[p].D, f"b[{p}]").value for p, bb in enumerate(b)])
+    vp = ptr_array([_dev(v, torch.complex64, k * ops[p].D, f"V[{p}]").value for p, v in enumerate(V)])
+    check(_lib.lib().res_loss_batched(opp, bp, vp, nb, k, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                      _stream()), "res_loss_batched")
+    return out
+
+
 from .cnn import Cnn  # noqa: E402

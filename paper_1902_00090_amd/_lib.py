@@ -81,6 +81,11 @@ _SIGS = {
     "proj_loss_batched": (I, [P, P, I, I, I, C.POINTER(D), P]),
     "local_pca_targets": (I, [P, I, I, I, I, P, P]),
     "eim_field": (I, [PP, I, PP, PP, P]),
+    "res_loss_batched": (I, [PP, PP, PP, I, I, C.POINTER(D), P]),
+    "dd_cnn_train_step_res": (I, [P, P, P, PP, PP, I, C.c_float, C.c_float, C.c_float,
+                                  C.POINTER(C.c_float), P]),
+    "dd_cnn_grad_res": (I, [P, P, P, PP, PP, I, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                            C.c_size_t, P]),
     "dd_cnn_create": (I, [I, I, I, I, I, C.c_ulonglong, PP]),
     "dd_cnn_destroy": (None, [P]),
     "dd_cnn_layer_info": (I, [P, I, C.POINTER(I), C.POINTER(I), C.POINTER(I),

@@ -128,6 +128,39 @@ class Cnn:
             g.ctypes.data_as(C.POINTER(C.c_float)), g.size, _stream()), "dd_cnn_grad")
         return loss.value, g
 
+    def _ops_b(self, ops, b, B):
+        torch = _torch()
+        if len(ops) != B or len(b) != B:
+            raise ValueError("one operator and one right-hand side per image")
+        opp = _lib.ptr_array([op._h.value for op in ops])
+        bp = _lib.ptr_array([_dev(bb, torch.complex128, self.D, f"b[{p}]").value
+                             for p, bb in enumerate(b)])
+        return opp, bp
+
+    def train_step_res(self, eps, ops, b, lr=1e-3, b1=0.9, b2=0.999, eim=None):
+        """One Adam step on the residual loss (eq:res_loss) of the batch:
+        ops / b are the images' operators and right-hand sides."""
+        torch = _torch()
+        B = eps.shape[0]
+        opp, bp = self._ops_b(ops, b, B)
+        loss = C.c_float()
+        check(_lib.lib().dd_cnn_train_step_res(
+            self._h, _dev(eps, torch.float32, B * self.D, "eps"), self._eim(eim, B), opp, bp, B,
+            float(lr), float(b1), float(b2), C.byref(loss), _stream()), "dd_cnn_train_step_res")
+        return loss.value
+
+    def grad_res(self, eps, ops, b, eim=None):
+        torch = _torch()
+        B = eps.shape[0]
+        opp, bp = self._ops_b(ops, b, B)
+        loss = C.c_float()
+        g = np.zeros(self.num_params, np.float32)
+        check(_lib.lib().dd_cnn_grad_res(
+            self._h, _dev(eps, torch.float32, B * self.D, "eps"), self._eim(eim, B), opp, bp, B,
+            C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float)), g.size, _stream()),
+            "dd_cnn_grad_res")
+        return loss.value, g
+
     def activation(self, layer, B):
         """Layer output (NHWC, float32) of the last forward pass; layer -1 = input."""
         if layer == -1:

@@ -30,6 +30,8 @@
 #include <vector>
 
 #include "common.h"
+#include "op.h"
+#include "resloss.h"
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -62,6 +64,9 @@ struct dd_cnn {
   bf16* wb[NL] = {};
   float* x0 = nullptr;       // normalised input planes [B][cin0][H][W]
   double* iscale = nullptr;  // [maxB] effective-index field scale sqrt(D) / ||F||
+  // residual-loss scratch (allocated on first use): V = output fields, W = A V,
+  // r = b - W c, s = A^H r
+  float2 *rl_V = nullptr, *rl_W = nullptr, *rl_r = nullptr, *rl_s = nullptr;
   bf16* act[NL] = {};        // act[l] = output of layer l (l < NL-1), NHWC bf16
   float* out = nullptr;      // last layer output [B][H][W][2k]
   bf16* dz[NL] = {};         // gradient w.r.t. the pre-activation of layer l
@@ -760,15 +765,9 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
   return DD_OK;
 }
 
-// loss + backward; grads land in n->grads.  *loss receives the batch MSE.
-static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hipStream_t st) {
-  const int D = n->nx * n->ny;
-  const int k = n->k;
-  const CnnLayer& LL = n->L[NL - 1];
-  const float scale = 2.0f / ((float)B * D * 2 * k);
-  const int nlb = (B * D + 255) / 256;
-  k_mse<<<nlb, 256, 0, st>>>(n->out, (const float2*)target, B, D, k, LL.coutp, scale,
-                             n->dz[NL - 1], n->lpart);
+// Backward pass from the gradient of the last layer's pre-activation in
+// dz[NL-1]; parameter gradients land in n->grads.
+static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
   for (int l = NL - 1; l >= 1; --l) {
     const CnnLayer& L = n->L[l];
     const int npo = B * L.Hout * L.Wout;
@@ -805,6 +804,21 @@ static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hip
     k_conv1_reduce<<<(nt + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
                                                      n->grads + L.woff, n->grads + L.boff);
   }
+  DD_HIP_CHECK(hipGetLastError());
+  return DD_OK;
+}
+
+// loss + backward; grads land in n->grads.  *loss receives the batch MSE.
+static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hipStream_t st) {
+  const int D = n->nx * n->ny;
+  const int k = n->k;
+  const CnnLayer& LL = n->L[NL - 1];
+  const float scale = 2.0f / ((float)B * D * 2 * k);
+  const int nlb = (B * D + 255) / 256;
+  k_mse<<<nlb, 256, 0, st>>>(n->out, (const float2*)target, B, D, k, LL.coutp, scale,
+                             n->dz[NL - 1], n->lpart);
+  dd_status rc = backward_from_dz(n, B, st);
+  if (rc != DD_OK) return rc;
   DD_HIP_CHECK(hipGetLastError());
   if (loss) {
     std::vector<float> lp(nlb);
@@ -889,6 +903,91 @@ extern "C" dd_status dd_cnn_train_step(dd_cnn* n, const float* eps, const void* 
   rc = forward(n, eps, eim, B, st, n->biaspad);
   if (rc != DD_OK) return rc;
   rc = backward(n, target, B, loss, st);
+  if (rc != DD_OK) return rc;
+  n->adam_t += 1;
+  const float c1 = 1.f - std::pow(b1, (float)n->adam_t);
+  const float c2 = 1.f - std::pow(b2, (float)n->adam_t);
+  k_adam<<<(unsigned)((n->nparams + 255) / 256), 256, 0, st>>>(n->params, n->grads, n->am, n->av,
+                                                                n->nparams, lr, b1, b2, c1, c2, 1e-8f);
+  rc = pack_all(n, st);
+  if (rc != DD_OK) return rc;
+  DD_HIP_CHECK(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+// Residual-loss step (Sec. 3, eq:res_loss): forward, the loss of every image's
+// predicted fields against its own operator and right-hand side, the
+// gradient through A^H into the last layer, backward.  *loss = batch mean.
+static dd_status res_step(dd_cnn* n, const float* eps, const void* eim,
+                          const fdfd_op* const* ops, const void* const* b, int B, float* loss,
+                          hipStream_t st, const char* who) {
+  dd_status rc = check_batch(n, eps, eim, B, who);
+  if (rc != DD_OK) return rc;
+  if (!ops || !b) { dd_set_error("%s: need ops and b", who); return DD_EINVAL; }
+  for (int p = 0; p < B; ++p)
+    if (!ops[p] || !b[p] || ops[p]->nx != n->nx || ops[p]->ny != n->ny) {
+      dd_set_error("%s: problem %d needs an operator of %d x %d and b", who, p, n->nx, n->ny);
+      return DD_EINVAL;
+    }
+  const size_t D = (size_t)n->nx * n->ny;
+  if (!n->rl_V) {
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+    chk(cnn_alloc(n, &n->rl_V, (size_t)n->maxB * n->k * D));
+    chk(cnn_alloc(n, &n->rl_W, (size_t)n->maxB * n->k * D));
+    chk(cnn_alloc(n, &n->rl_r, (size_t)n->maxB * D));
+    chk(cnn_alloc(n, &n->rl_s, (size_t)n->maxB * D));
+    if (e != hipSuccess) {
+      dd_set_error("%s: %s", who, hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP;
+    }
+  }
+  rc = forward(n, eps, eim, B, st, n->biaspad);
+  if (rc != DD_OK) return rc;
+  k_to_fields<<<(unsigned)((B * D + 255) / 256), 256, 0, st>>>(n->out, B, (int)D, n->k, n->rl_V);
+  DD_HIP_CHECK(hipGetLastError());
+  std::vector<const void*> Vp(B);
+  for (int p = 0; p < B; ++p) Vp[p] = n->rl_V + (size_t)p * n->k * D;
+  std::vector<double> lv(B);
+  rc = res_loss_core(ops, b, Vp.data(), B, n->k, n->rl_W, n->rl_r, n->rl_s, lv.data(),
+                     n->dz[NL - 1], n->L[NL - 1].coutp, 1.0 / B, st);
+  if (rc != DD_OK) return rc;
+  rc = backward_from_dz(n, B, st);
+  if (rc != DD_OK) return rc;
+  if (loss) {
+    double s = 0.0;
+    for (double v : lv) s += v;
+    *loss = (float)(s / B);
+  }
+  return DD_OK;
+}
+
+extern "C" dd_status dd_cnn_grad_res(dd_cnn* n, const float* eps, const void* eim,
+                                     const fdfd_op* const* ops, const void* const* b, int B,
+                                     float* loss, float* host_grad, size_t count,
+                                     hipStream_t st) {
+  if (n && host_grad && count != n->nparams) {
+    dd_set_error("dd_cnn_grad_res: gradient size must be %zu", n->nparams);
+    return DD_EINVAL;
+  }
+  dd_status rc = res_step(n, eps, eim, ops, b, B, loss, st, "dd_cnn_grad_res");
+  if (rc != DD_OK) return rc;
+  if (host_grad) {
+    DD_HIP_CHECK(hipMemcpyAsync(host_grad, n->grads, sizeof(float) * count, hipMemcpyDeviceToHost, st));
+  }
+  DD_HIP_CHECK(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+extern "C" dd_status dd_cnn_train_step_res(dd_cnn* n, const float* eps, const void* eim,
+                                           const fdfd_op* const* ops, const void* const* b, int B,
+                                           float lr, float b1, float b2, float* loss,
+                                           hipStream_t st) {
+  if (!(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f)) {
+    dd_set_error("dd_cnn_train_step_res: bad Adam parameters");
+    return DD_EINVAL;
+  }
+  dd_status rc = res_step(n, eps, eim, ops, b, B, loss, st, "dd_cnn_train_step_res");
   if (rc != DD_OK) return rc;
   n->adam_t += 1;
   const float c1 = 1.f - std::pow(b1, (float)n->adam_t);

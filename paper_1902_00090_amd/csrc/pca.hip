@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.h"
+#include "gram.h"
 
 #define DD_MAX_KPCA 64
 
@@ -304,8 +305,8 @@ __global__ __launch_bounds__(256) void k_small_combine(float2* __restrict__ V, i
   }
 }
 
-static dd_status gram_host(const float2* V, int k, int D, const double2* f, std::vector<cd>& G,
-                           hipStream_t stream) {
+dd_status gram_host(const float2* V, int k, int D, const double2* f, std::vector<cd>& G,
+                    hipStream_t stream) {
   const int K1 = k + 1;
   const int nslices = std::max(1, std::min(256, D / 4096));
   double2* part = nullptr;
@@ -354,8 +355,8 @@ static dd_status gram_rows(const float2* F, int S, int D, std::vector<cd>& G, hi
 
 // Cholesky G = L L^H of the leading k x k block (stride ld); returns false if
 // not positive definite.  T = L^{-H} (upper triangular, row-major k x k).
-static bool chol_inv(const std::vector<cd>& G, int ld, int k, std::vector<cd>& L,
-                     std::vector<cd>& T) {
+bool chol_inv(const std::vector<cd>& G, int ld, int k, std::vector<cd>& L,
+              std::vector<cd>& T) {
   L.assign((size_t)k * k, cd(0.0));
   for (int j = 0; j < k; ++j) {
     double d = G[(size_t)j * ld + j].real();

@@ -1,0 +1,222 @@
+// Residual loss of a predicted subspace and its gradient (Sec. 3, eq:res_loss).
+//
+// Definition, per problem:
+//     l = min_c ||A V c - b||^2 / ||b||^2 = 1 - b^H P b / ||b||^2,
+// with W = A V and P the orthogonal projector on span(W).
+//
+// Gradient.  Let c = W^+ b be the minimiser and r = b - W c the residual.
+// Then d(b^H P b) = 2 Re(r^H dW c), so the conjugate (Wirtinger) gradient is
+//     dl / d conj(W) = -r c^H / ||b||^2.
+// Through W = A V it becomes
+//     dl / d conj(V) = -(A^H r) c^H / ||b||^2.
+// This needs one adjoint matvec per problem.  The gradient with respect to the
+// real and imaginary parts of V is twice its real and imaginary part.
+//
+// Kernels:
+//   * k_rl_apply: W = A V for all k vectors (the operator's stencil).
+//   * k_rl_resid: r = b - W c, with c solved on the host from the (k+1)^2
+//     FP64 Gram matrix of [W b] (gram_host).
+//   * k_rl_adjoint: s = A^H r, the transposed stencil, conjugated.
+//   * k_rl_dz: writes the CNN's last-layer gradient (bf16, NHWC).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "common.h"
+#include "gram.h"
+#include "op.h"
+#include "resloss.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+struct RlDesc {
+  int nx, ny, D;
+  float omega2;
+  const float2* cf;     // stencil coefficients (FP32 copy)
+  const float* eps;     // [D]
+  const float2* V;      // [k][D]
+  float2* W;            // [k][D]
+  const double2* b;     // [D]
+  float2* r;            // [D]
+  float2* s;            // [D]
+  const double2* c;     // [k] minimiser
+};
+
+__global__ __launch_bounds__(256) void k_rl_apply(const RlDesc* __restrict__ desc) {
+  const RlDesc d = desc[blockIdx.z];
+  const int e = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (e >= d.D) return;
+  d.W[(size_t)j * d.D + e] =
+      stencil_point<float, float>(d.V + (size_t)j * d.D, e, d.nx, d.ny, d.cf, d.eps, d.omega2);
+}
+
+__global__ __launch_bounds__(256) void k_rl_resid(const RlDesc* __restrict__ desc, int k) {
+  const RlDesc d = desc[blockIdx.y];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= d.D) return;
+  double2 v = d.b[e];
+  for (int j = 0; j < k; ++j) {
+    const float2 w = d.W[(size_t)j * d.D + e];
+    const double2 c = d.c[j];
+    v.x -= c.x * w.x - c.y * w.y;
+    v.y -= c.x * w.y + c.y * w.x;
+  }
+  d.r[e] = make_float2((float)v.x, (float)v.y);
+}
+
+// (A^H y)_c = conj(A_cc) y_c - conj(cxm_e) y_e - conj(cxp_w) y_w - conj(cym_n) y_n
+//             - conj(cyp_s) y_s, with A_cc = cxm_c + cxp_c + cym_c + cyp_c - omega^2 eps_c
+// and e, w, n, s the periodic neighbours of c (row e holds -cxm_e at column c, ...).
+__global__ __launch_bounds__(256) void k_rl_adjoint(const RlDesc* __restrict__ desc) {
+  const RlDesc d = desc[blockIdx.y];
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= d.D) return;
+  const int nx = d.nx, ny = d.ny;
+  const int iy = c / nx, ix = c - iy * nx;
+  const int ixe = (ix == nx - 1) ? 0 : ix + 1, ixw = (ix == 0) ? nx - 1 : ix - 1;
+  const int iyn = (iy == ny - 1) ? 0 : iy + 1, iys = (iy == 0) ? ny - 1 : iy - 1;
+  const float2* cf = d.cf;
+  const float2 cxm = cf[ix], cxp = cf[nx + ix], cym = cf[2 * nx + iy], cyp = cf[2 * nx + ny + iy];
+  float2 acc = make_float2(cxm.x + cxp.x + cym.x + cyp.x - d.omega2 * d.eps[c],
+                           cxm.y + cxp.y + cym.y + cyp.y);
+  const float2* y = d.r;
+  float2 out = cmul(cconj(acc), y[c]);
+  out = csub(out, cmul(cconj(cf[ixe]), y[iy * nx + ixe]));
+  out = csub(out, cmul(cconj(cf[nx + ixw]), y[iy * nx + ixw]));
+  out = csub(out, cmul(cconj(cf[2 * nx + iyn]), y[iyn * nx + ix]));
+  out = csub(out, cmul(cconj(cf[2 * nx + ny + iys]), y[iys * nx + ix]));
+  d.s[c] = out;
+}
+
+// dz[p][2j] = Re(s_e a_j), dz[p][2j+1] = Im(s_e a_j), p = problem * D + e, where
+// a_j = -2 scale conj(c_j) / ||b||^2 (coef holds a); channels >= 2k are zero.
+__global__ __launch_bounds__(256) void k_rl_dz(const RlDesc* __restrict__ desc, int k, int coutp,
+                                               const double2* __restrict__ coef,
+                                               __bf16* __restrict__ dz) {
+  const int pb = blockIdx.y;
+  const RlDesc d = desc[pb];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= d.D) return;
+  const float2 s = d.s[e];
+  __bf16* o = dz + ((size_t)pb * d.D + e) * coutp;
+  for (int ch = 0; ch < coutp; ++ch) {
+    float g = 0.f;
+    if (ch < 2 * k) {
+      const double2 a = coef[(size_t)pb * k + ch / 2];
+      g = (ch & 1) ? (float)(s.x * a.y + s.y * a.x) : (float)(s.x * a.x - s.y * a.y);
+    }
+    o[ch] = (__bf16)g;
+  }
+}
+
+// Minimiser c and loss of one problem from the Gram matrix of [W b].
+bool solve_small(const std::vector<cd>& G, int k, std::vector<cd>& c, double& loss, double& bb) {
+  const int K1 = k + 1;
+  bb = G[(size_t)k * K1 + k].real();
+  std::vector<cd> L, T, Gr = G;
+  bool ok = chol_inv(Gr, K1, k, L, T);
+  double shift = 0.0, dmax = 0.0;
+  for (int j = 0; j < k; ++j) dmax = std::max(dmax, G[(size_t)j * K1 + j].real());
+  for (int tries = 0; !ok && tries < 4; ++tries) {   // rank-deficient W: tiny ridge
+    shift = (shift == 0.0) ? 1e-13 * std::max(dmax, 1e-300) : shift * 1e3;
+    Gr = G;
+    for (int j = 0; j < k; ++j) Gr[(size_t)j * K1 + j] += shift;
+    ok = chol_inv(Gr, K1, k, L, T);
+  }
+  c.assign(k, cd(0.0));
+  if (!ok || !(bb > 0.0)) { loss = (bb > 0.0) ? 1.0 : 0.0; return ok; }
+  // c = T T^H g with g = W^H b (column k of G)
+  std::vector<cd> t(k, cd(0.0));
+  for (int o = 0; o < k; ++o)
+    for (int a = 0; a <= o; ++a) t[o] += std::conj(T[(size_t)a * k + o]) * G[(size_t)a * K1 + k];
+  double q = 0.0;
+  for (int o = 0; o < k; ++o) q += std::norm(t[o]);
+  for (int a = 0; a < k; ++a)
+    for (int o = a; o < k; ++o) c[a] += T[(size_t)a * k + o] * t[o];
+  loss = std::min(1.0, std::max(0.0, 1.0 - q / bb));
+  return true;
+}
+
+}  // namespace
+
+dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const void* const* V,
+                        int nb, int k, float2* Wbuf, float2* rbuf, float2* sbuf, double* loss,
+                        __bf16* dz, int coutp, double scale, hipStream_t st) {
+  std::vector<RlDesc> hd(nb);
+  int maxD = 0;
+  size_t offW = 0, offR = 0;
+  for (int p = 0; p < nb; ++p) {
+    const fdfd_op* op = ops[p];
+    RlDesc& d = hd[p];
+    d.nx = op->nx; d.ny = op->ny; d.D = op->D;
+    d.omega2 = (float)(op->omega * op->omega);
+    d.cf = op->cf32; d.eps = op->eps32;
+    d.V = (const float2*)V[p]; d.W = Wbuf + offW;
+    d.b = (const double2*)b[p];
+    d.r = rbuf ? rbuf + offR : nullptr;
+    d.s = sbuf ? sbuf + offR : nullptr;
+    offW += (size_t)k * op->D;
+    offR += (size_t)op->D;
+    maxD = std::max(maxD, op->D);
+  }
+  RlDesc* dd = nullptr;
+  double2* dc = nullptr;
+  DD_HIP_CHECK(hipMalloc((void**)&dd, sizeof(RlDesc) * nb));
+  DD_HIP_CHECK(hipMalloc((void**)&dc, sizeof(double2) * 2 * (size_t)nb * k));
+  for (int p = 0; p < nb; ++p) hd[p].c = dc + (size_t)p * k;
+  DD_HIP_CHECK(hipMemcpyAsync(dd, hd.data(), sizeof(RlDesc) * nb, hipMemcpyHostToDevice, st));
+  k_rl_apply<<<dim3((maxD + 255) / 256, k, nb), 256, 0, st>>>(dd);
+  DD_HIP_CHECK(hipGetLastError());
+  std::vector<double2> hc((size_t)2 * nb * k, make_double2(0.0, 0.0));
+  for (int p = 0; p < nb; ++p) {
+    std::vector<cd> G, c;
+    dd_status rc = gram_host(hd[p].W, k, hd[p].D, hd[p].b, G, st);
+    if (rc != DD_OK) { (void)hipFree(dd); (void)hipFree(dc); return rc; }
+    double l = 1.0, bb = 0.0;
+    solve_small(G, k, c, l, bb);
+    loss[p] = l;
+    for (int j = 0; j < k; ++j) {
+      hc[(size_t)p * k + j] = make_double2(c[j].real(), c[j].imag());
+      // d(scale l)/d Re V = 2 scale Re(dl/d conj V), likewise for Im
+      const cd a = (bb > 0.0) ? -2.0 * scale * std::conj(c[j]) / bb : cd(0.0);
+      hc[(size_t)(nb + p) * k + j] = make_double2(a.real(), a.imag());
+    }
+  }
+  if (dz) {
+    DD_HIP_CHECK(hipMemcpyAsync(dc, hc.data(), sizeof(double2) * hc.size(), hipMemcpyHostToDevice, st));
+    k_rl_resid<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k);
+    k_rl_adjoint<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd);
+    k_rl_dz<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k, coutp, dc + (size_t)nb * k, dz);
+    DD_HIP_CHECK(hipGetLastError());
+  }
+  DD_HIP_CHECK(hipStreamSynchronize(st));
+  DD_HIP_CHECK(hipFree(dd));
+  DD_HIP_CHECK(hipFree(dc));
+  return DD_OK;
+}
+
+extern "C" dd_status res_loss_batched(const fdfd_op* const* ops, const void* const* b,
+                                      const void* const* V, int nb, int k, double* out,
+                                      hipStream_t stream) {
+  if (!ops || !b || !V || !out || nb < 1 || k < 1 || k > 64) {
+    dd_set_error("res_loss_batched: need ops, b, V, out, nb >= 1 and 1 <= k <= 64");
+    return DD_EINVAL;
+  }
+  size_t tot = 0;
+  for (int p = 0; p < nb; ++p) {
+    if (!ops[p] || !b[p] || !V[p]) {
+      dd_set_error("res_loss_batched: problem %d has a NULL operator, b or V", p);
+      return DD_EINVAL;
+    }
+    tot += (size_t)ops[p]->D;
+  }
+  float2* Wb = nullptr;
+  DD_HIP_CHECK(hipMalloc((void**)&Wb, sizeof(float2) * tot * k));
+  dd_status rc = res_loss_core(ops, b, V, nb, k, Wb, nullptr, nullptr, out, nullptr, 0, 0.0,
+                               stream);
+  (void)hipFree(Wb);
+  return rc;
+}

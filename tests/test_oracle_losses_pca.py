@@ -60,3 +60,28 @@ def test_pca_recovers_planted_subspace():
     assert pca.principal_angles(Uk, U[:, :4]).max() < 1e-7
     # principal angles of a space with itself are zero, of orthogonal spaces pi/2
     assert pca.principal_angles(U[:, :2], U[:, 2:4]).min() > 1.5
+
+
+def test_res_loss_gradient_matches_finite_differences():
+    """The conjugate gradient G of the residual loss: the real-part derivative
+    is 2 Re G and the imaginary-part derivative 2 Im G (central differences on
+    the loss itself, which is independent of the gradient formula)."""
+    inst = _tiny(3)
+    A = fdfd.assemble_instance(inst)
+    rng = np.random.default_rng(4)
+    V = W.random_complex(rng, (inst.D, 3))
+    l0, G = losses.res_loss_grad(A, V, inst.b)
+    np.testing.assert_allclose(l0, losses.res_loss(A, V, inst.b), rtol=1e-12)
+    h = 1e-6
+    for _ in range(8):
+        i, j = rng.integers(0, inst.D), rng.integers(0, 3)
+        for unit, part in ((1.0, G.real), (1j, G.imag)):
+            Vp, Vm = V.copy(), V.copy()
+            Vp[i, j] += h * unit
+            Vm[i, j] -= h * unit
+            fd = (losses.res_loss(A, Vp, inst.b) - losses.res_loss(A, Vm, inst.b)) / (2 * h)
+            assert abs(fd - 2 * part[i, j]) <= 1e-6 * abs(fd) + 1e-9, (fd, 2 * part[i, j])
+    # a subspace holding the solution is a minimum: zero loss and zero gradient
+    xs = np.linalg.solve(A.toarray(), inst.b)
+    l1, G1 = losses.res_loss_grad(A, np.stack([xs, V[:, 0]], 1), inst.b)
+    assert l1 < 1e-20 and np.abs(G1).max() < 1e-8
