@@ -82,39 +82,47 @@ def cnn_flops_per_instance(net):
     return tot
 
 
-def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_aug, plain):
-    """Train the CNN on local-PCA targets of the training fields (grouped by
-    trajectory), predict k fields for every evaluation problem, solve the
-    evaluation batch augmented by them; inference is inside the timed region."""
+def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_aug, plain,
+            loss_mode):
+    """Train the CNN on the training problems, predict k fields for every
+    evaluation problem, solve the evaluation batch augmented by them; the
+    effective-index field and inference are inside the timed region.
+    loss_mode "proj": MSE against local-PCA targets of the training fields
+    (grouped by trajectory); "res": the unsupervised residual loss."""
     from paper_1902_00090_amd import (Cnn, FdfdOp, Solver, eim_field, local_pca_targets,
-                                      proj_loss_batched)
-    from paper_1902_00090_amd.train import train_cnn
+                                      proj_loss_batched, res_loss_batched)
+    from paper_1902_00090_amd.train import train_cnn, train_cnn_res
     k, D, B = args.cnn_k, test[0].D, len(test)
     t0 = time.time()
-    traj_of = np.asarray(tr_idx) // args.traj_steps
-    targets = torch.empty((len(train), k, D), dtype=torch.complex64, device="cuda")
-    for t in np.unique(traj_of):
-        rows = np.nonzero(traj_of == t)[0]
-        r0, r1 = int(rows[0]), int(rows[-1]) + 1      # sorted indices: contiguous rows
-        targets[r0:r1] = local_pca_targets(Smat[r0:r1].contiguous(), args.cnn_window, k)
-    targets *= float(math.sqrt(D))                     # unit RMS per pixel
+    targets = None
+    if loss_mode == "proj":
+        traj_of = np.asarray(tr_idx) // args.traj_steps
+        targets = torch.empty((len(train), k, D), dtype=torch.complex64, device="cuda")
+        for t in np.unique(traj_of):
+            rows = np.nonzero(traj_of == t)[0]
+            r0, r1 = int(rows[0]), int(rows[-1]) + 1      # sorted indices: contiguous rows
+            targets[r0:r1] = local_pca_targets(Smat[r0:r1].contiguous(), args.cnn_window, k)
+        targets *= float(math.sqrt(D))                     # unit RMS per pixel
     eps_tr = torch.tensor(np.stack([i.eps for i in train]), device="cuda")
+    tr_ops = [FdfdOp.from_instance(i) for i in train]
+    tr_bs = [torch.tensor(i.b, dtype=torch.complex128, device="cuda") for i in train]
     eim_tr = None
     if args.cnn_inputs == 3:
-        tr_ops = [FdfdOp.from_instance(i) for i in train]
         eim_tr = torch.empty((len(train), D), dtype=torch.complex64, device="cuda")
         for c0 in range(0, len(train), 64):
-            eim_field(tr_ops[c0:c0 + 64],
-                      [torch.tensor(i.b, dtype=torch.complex128, device="cuda")
-                       for i in train[c0:c0 + 64]], out=eim_tr[c0:c0 + 64])
-        del tr_ops
+            eim_field(tr_ops[c0:c0 + 64], tr_bs[c0:c0 + 64], out=eim_tr[c0:c0 + 64])
     net = Cnn(test[0].nx, test[0].ny, max_batch=32, k=k, seed=7, in_channels=args.cnn_inputs)
-    losses = train_cnn(net, eps_tr, targets, args.cnn_steps, 32, lr=1e-3, seed=11, eim=eim_tr)
+    if loss_mode == "proj":
+        losses = train_cnn(net, eps_tr, targets, args.cnn_steps, 32, lr=1e-3, seed=11, eim=eim_tr)
+    else:
+        losses = train_cnn_res(net, eps_tr, tr_ops, tr_bs, args.cnn_steps, 32, lr=1e-3, seed=11,
+                               eim=eim_tr)
     torch.cuda.synchronize()
     t_cnn_train = time.time() - t0
-    del targets, eps_tr, eim_tr
-    log(f"CNN: {args.cnn_inputs} input planes, {args.cnn_steps} Adam steps on {len(train)} "
-        f"samples, {t_cnn_train:.1f}s, loss {losses[0]:.3e} -> {np.mean(losses[-20:]):.3e}")
+    del targets, eps_tr, eim_tr, tr_ops, tr_bs
+    log(f"CNN ({loss_mode} loss): {args.cnn_inputs} input planes, {args.cnn_steps} Adam steps on "
+        f"{len(train)} samples, {t_cnn_train:.1f}s, loss {losses[0]:.3e} -> "
+        f"{np.mean(losses[-20:]):.3e}")
 
     eps_te = torch.tensor(np.stack([i.eps for i in test]), device="cuda")
     eim_te = None
@@ -147,12 +155,12 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
     if eim_te is not None:
         lp_eim = proj_loss_batched(eim_te.unsqueeze(1).contiguous(), xs_stack)
     del xs_stack
+    lr_cnn = res_loss_batched(ops, bs, [Ucnn[p] for p in range(B)])
+    lr_pca = res_loss_batched(ops, bs, [U] * B)
 
     s = Solver(ops, restart=args.restart, kmax=k, cgs_passes=args.cgs, hist_cap=args.maxit)
     xc = [torch.empty_like(b) for b in bs]
     Ul = [Ucnn[p] for p in range(B)]
-    s.set_subspace(Ul)
-    s.solve(bs, tol=args.tol, maxit=args.maxit, x=xc)  # warm-up
     torch.cuda.synchronize()
     t0 = time.time()
     setup()
@@ -172,7 +180,9 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
         "worst_rel_res_true": max(i["rel_res_true"] for i in inf),
         "rel_res_after_1_iter_mean": float(np.mean([x[0] for x in h])),
         "iters_to_0.04_mean": float(np.mean([first_below(x, 0.04) or np.nan for x in h])),
-        "k": k, "input_planes": args.cnn_inputs,
+        "k": k, "input_planes": args.cnn_inputs, "training_loss": loss_mode,
+        "res_loss_eval_mean": float(np.mean(lr_cnn)),
+        "pca_k%d_res_loss_eval_mean" % args.k: float(np.mean(lr_pca)),
         "proj_loss_eval_mean": float(np.mean(lp_cnn)),
         "eim_field_alone_proj_loss_eval_mean": None if lp_eim is None else float(np.mean(lp_eim)),
         "pca_k%d_proj_loss_eval_mean" % args.k: float(np.mean(lp_pca)),
@@ -185,7 +195,7 @@ def cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_
         "inference_mfma_frac_bf16": round(flops / (inf_ms * 1e-3) / 1e12 / 2500.0, 4),
         "flop_per_instance": flops // B,
     }
-    log(f"CNN-augmented: {out['solves_per_s_incl_inference']:.3f} solves/s, iters mean "
+    log(f"CNN-augmented ({loss_mode}): {out['solves_per_s_incl_inference']:.3f} solves/s, iters mean "
         f"{it.mean():.0f}, l_proj eval {out['proj_loss_eval_mean']:.3f} "
         f"(PCA k={args.k}: {out['pca_k%d_proj_loss_eval_mean' % args.k]:.3f}), inference "
         f"{inf_ms:.2f} ms for {B} ({out['inference_tflops']} TFLOP/s)")
@@ -296,6 +306,9 @@ def main():
     ap.add_argument("--cnn-k", type=int, default=10)
     ap.add_argument("--cnn-steps", type=int, default=400)
     ap.add_argument("--cnn-window", type=int, default=8)
+    ap.add_argument("--cnn-loss", default="both", choices=("proj", "res", "both"),
+                    help="CNN training loss: local-PCA targets (MSE, projection), the "
+                         "unsupervised residual loss, or one leg each")
     ap.add_argument("--cnn-inputs", type=int, default=3, choices=(1, 3),
                     help="CNN input planes: 3 = permittivity + effective-index field (the "
                          "paper's input), 1 = permittivity only")
@@ -439,8 +452,9 @@ def main():
     # ---------------- CNN predictor: trained on the same solver-generated fields
     cnn = None
     if not args.no_cnn:
-        cnn = cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U, it_aug,
-                      plain)
+        modes = ("proj", "res") if args.cnn_loss == "both" else (args.cnn_loss,)
+        cnn = {m: cnn_leg(args, torch, W, data, tr_idx, train, test, Smat, ops, bs, xs, U,
+                          it_aug, plain, m) for m in modes}
     del Smat
 
     # ---------------- uneven correlated batch, plain GMRES, graph replay

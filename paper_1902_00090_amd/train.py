@@ -63,3 +63,27 @@ def train_cnn(net, eps, targets, steps, batch, lr=1e-3, b1=0.9, b2=0.999, seed=0
         if log and (it % max(1, steps // 10) == 0 or it == steps - 1):
             log(f"  cnn step {it}: loss {loss:.4e}")
     return losses
+
+
+def train_cnn_res(net, eps, ops, bs, steps, batch, lr=1e-3, b1=0.9, b2=0.999, seed=0, log=None,
+                  eim=None):
+    """Unsupervised training on the residual loss (Sec. 3, eq:res_loss): each
+    sample is a permittivity with its operator and right-hand side, no solved
+    field.  Mini-batches without replacement, reshuffled every epoch."""
+    import torch
+    N = eps.shape[0]
+    rng = np.random.default_rng(seed)
+    order, pos, losses = rng.permutation(N), 0, []
+    for it in range(steps):
+        if pos + batch > N:
+            order, pos = rng.permutation(N), 0
+        sel = order[pos:pos + batch]
+        idx = torch.as_tensor(sel, device=eps.device)
+        pos += batch
+        loss = net.train_step_res(eps.index_select(0, idx).contiguous(), [ops[i] for i in sel],
+                                  [bs[i] for i in sel], lr, b1, b2,
+                                  eim=None if eim is None else eim.index_select(0, idx).contiguous())
+        losses.append(loss)
+        if log and (it % max(1, steps // 10) == 0 or it == steps - 1):
+            log(f"  cnn step {it}: residual loss {loss:.4e}")
+    return losses
