@@ -248,6 +248,39 @@ def cnn_kernels_only(args, torch, W):
     print(json.dumps(out), flush=True)
 
 
+def recycle_leg(args, torch, data):
+    """Design steps 0..N-1 of every benchmark trajectory, one lockstep batch per
+    step: augmented by the fields of the previous steps of the same trajectory,
+    against plain GMRES on the same schedule."""
+    from paper_1902_00090_amd.recycle import solve_trajectories
+    S = args.traj_steps
+    trajs = [data[t * S:t * S + args.recycle] for t in range(args.traj)]
+    out = {}
+    for mode in ("recycled", "plain"):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, inf, hist = solve_trajectories(trajs, window=args.recycle_window, tol=args.tol,
+                                          restart=args.restart, maxit=args.maxit,
+                                          cgs_passes=args.cgs, recycle=(mode == "recycled"),
+                                          hist_cap=args.maxit)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        later = [(t, s) for t in range(len(trajs)) for s in range(1, args.recycle)]
+        out[mode] = {
+            "seconds": round(dt, 2),
+            "solves_per_s": round(len(trajs) * args.recycle / dt, 4),
+            "iters_mean_steps_ge_1": float(np.mean([inf[t][s]["iters"] for t, s in later])),
+            "rel_res_after_1_iter_mean_steps_ge_1": float(np.mean([hist[t][s][0] for t, s in later])),
+            "iters_to_0.04_mean_steps_ge_1": float(np.mean(
+                [first_below(hist[t][s], 0.04) or np.nan for t, s in later])),
+            "all_converged": all(i["status"] == 0 for row in inf for i in row),
+        }
+        log(f"trajectory {mode}: {dt:.1f}s, {out[mode]}")
+    out["steps"] = args.recycle
+    out["window"] = args.recycle_window
+    return out
+
+
 def c3_leg(args, torch, W):
     """8 trajectories x 32 steps of uneven grids (192x96, 320x160, 480x240;
     1.30 / 1.55 um) in one lockstep batch, plain complex64 GMRES, step groups
@@ -313,6 +346,10 @@ def main():
                     help="CNN input planes: 3 = permittivity + effective-index field (the "
                          "paper's input), 1 = permittivity only")
     ap.add_argument("--no-c3", action="store_true", help="skip the uneven correlated batch")
+    ap.add_argument("--recycle", type=int, default=0,
+                    help="also run trajectory recycling over the first N design steps of "
+                         "every trajectory (augment step s by the fields of steps < s)")
+    ap.add_argument("--recycle-window", type=int, default=5)
     ap.add_argument("--cnn-kernels", type=int, default=0,
                     help="only time N CNN forward passes (batch 64) and N training steps "
                          "(batch 32) at 480x240, print one JSON line and exit")
@@ -457,6 +494,11 @@ def main():
                           it_aug, plain, m) for m in modes}
     del Smat
 
+    # ---------------- trajectory recycling (optional)
+    rec = None
+    if args.recycle > 0:
+        rec = recycle_leg(args, torch, data)
+
     # ---------------- uneven correlated batch, plain GMRES, graph replay
     c3 = None
     if not args.no_c3:
@@ -542,6 +584,7 @@ def main():
         "cpu_baseline": cpu,
         "cnn_augmented": cnn,
         "uneven_batch_plain": c3,
+        "trajectory_recycling": rec,
     }
     print(json.dumps(out), flush=True)
 
