@@ -240,6 +240,96 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
   }
 }
 
+// ---------------------------------------- LDS-tiled forward convolution ----
+// Forward pass of the stride-1 layers, plain (MAP_S1) or after a x2 nearest
+// upsample (MAP_UP).  A workgroup computes a 4 x 64 tile of output pixels of
+// one image for all M = 16 MT output channels.  For every 32 input channels
+// the 6 x 66 input patch (halo included; zero padding and the upsampling are
+// resolved while staging) is written once to LDS and read there by all nine
+// taps, so each source value is fetched from memory once instead of nine
+// times.  Wave w owns output row w of the tile (four pixel tiles of 16).  The
+// weights come from the L2-resident packed copy.  Operand layouts are those of
+// k_conv_gemm.
+#define CT_TH 4
+#define CT_TW 64
+#define CT_PH (CT_TH + 2)
+#define CT_PW (CT_TW + 2)
+#define CT_PS 40   // bf16 per staged pixel: 32 channels + 8 of padding (80-byte stride)
+template <int MT>
+__global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 patch[CT_PH * CT_PW * CT_PS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * CT_TW, y0 = blockIdx.y * CT_TH, b = blockIdx.z;
+  const int Hq = a.Hq, Wq = a.Wq;
+  const bool up = (a.mode == MAP_UP);
+  f32x4 acc[MT][4];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kq = 8 * (lane >> 4);
+  for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
+    for (int u = threadIdx.x; u < CT_PH * CT_PW * 4; u += 256) {
+      const int pix = u >> 2, q = u & 3;
+      const int py = pix / CT_PW, px = pix - py * CT_PW;
+      const int uy = y0 + py - 1, ux = x0 + px - 1;   // conv-input grid (= output grid)
+      u32x4 v = u32x4{0u, 0u, 0u, 0u};
+      if (uy >= 0 && uy < Hq && ux >= 0 && ux < Wq) {
+        const int sy = up ? (uy >> 1) : uy, sx = up ? (ux >> 1) : ux;
+        v = *(const u32x4*)(a.src + ((size_t)(b * a.Hs + sy) * a.Ws + sx) * a.Ksrc + c0 + 8 * q);
+      }
+      *(u32x4*)(patch + pix * CT_PS + 8 * q) = v;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t - 3 * (t / 3);
+      bf16x8 bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bv[j] = *(const bf16x8*)(patch + ((wave + dy) * CT_PW + 16 * j + (lane & 15) + dx) * CT_PS + kq);
+      const bf16* wt = a.W + (size_t)t * a.M * a.Ksrc + c0 + kq;
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        const bf16x8 av = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int y = y0 + wave;
+  if (y >= Hq) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int x = x0 + 16 * j + (lane & 15);
+    if (x >= Wq) continue;
+    const size_t p = ((size_t)b * Hq + y) * Wq + x;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const int r0 = i * 16 + 4 * (lane >> 4);
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v[q] = acc[i][j][q] + a.bias[r0 + q];
+        if (a.relu) v[q] = fmaxf(v[q], 0.f);
+      }
+      if (a.outf) {
+        float* o = a.outf + p * a.nreal + r0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (r0 + q < a.nreal) o[q] = v[q];
+      } else {
+        bf16 h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = (bf16)v[q];
+        *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- layer 1 ----
 // Cin = 1 or 3 input planes: direct FP32 arithmetic (9 taps per plane), 32
 // output channels per pixel.  x0 is planar [B][C][H][W].
@@ -720,6 +810,15 @@ static void launch_gemm(const GemmArgs& a, int npix, hipStream_t st) {
 
 static void gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_t st) {
   const int MT = a.M / 16;
+  if (!bwd && (a.mode == MAP_S1 || a.mode == MAP_UP) && a.Ksrc % 32 == 0) {
+    const dim3 grid((a.Wq + CT_TW - 1) / CT_TW, (a.Hq + CT_TH - 1) / CT_TH, a.B);
+    switch (MT) {
+      case 2: k_conv_tile<2><<<grid, 256, 0, st>>>(a); break;
+      case 4: k_conv_tile<4><<<grid, 256, 0, st>>>(a); break;
+      default: k_conv_tile<8><<<grid, 256, 0, st>>>(a); break;
+    }
+    return;
+  }
   if (!bwd) {
     switch (MT) {
       case 2: launch_gemm<2, 8, false>(a, npix, st); break;
