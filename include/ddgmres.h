@@ -42,6 +42,18 @@ typedef enum {
 
 typedef enum { DD_C64 = 0, DD_C128 = 1 } dd_prec;
 
+/* Diagonal preconditioners of the comparison in the paper's supplement
+ * (Table 1, data-free preconditioners).  The solver iterates on
+ * A' = P_L A P_R, b' = P_L b, and recovers x = P_R x'.
+ *   DD_PRECOND_JACOBI: P_L = diag(A)^{-1}, P_R = I.
+ *   DD_PRECOND_PML:    P_L = S^{1/2}, P_R = S^{-1/2}, where
+ *                      S = diag(s_x(i) s_y(j)) holds the PML stretch factors.
+ *                      S A is complex symmetric, so P_L A P_R is complex
+ *                      symmetric with the spectrum of A.  This is the reading
+ *                      of the grid-spacing preconditioner of the paper's
+ *                      Ref. 17. */
+typedef enum { DD_PRECOND_NONE = 0, DD_PRECOND_JACOBI = 1, DD_PRECOND_PML = 2 } dd_precond;
+
 /* PML description (host struct).  The profile is sigma(d) = sigma_max (d/n)^m
  * with sigma_max = -(m+1) ln_R / (2 n dx), d = depth in cells (integer and
  * half-integer positions, clamped to n).  The paper names PML without
@@ -111,6 +123,10 @@ typedef struct {
                         /* (Kahan-Parlett "twice is enough" test); default 1      */
   int use_graph;        /* 1 = replay groups of check_every Arnoldi steps as HIP   */
                         /* graphs (captured on first use; default 0)              */
+  int precond;          /* dd_precond (default DD_PRECOND_NONE).  With a left     */
+                        /* preconditioner the Givens estimate, the history and    */
+                        /* rel_res_est are those of P_L r / ||P_L b||; convergence */
+                        /* is still decided by the FP64 ||b - A x|| / ||b||        */
 } dd_solver_opts;
 
 /* Per-problem result (host struct). */

@@ -95,8 +95,11 @@ class FdfdOp:
             pass
 
 
+PRECONDS = {None: 0, "none": 0, "jacobi": 1, "pml": 2}
+
+
 def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hist_cap=0,
-          check_every=4, select_reorth=True, use_graph=False):
+          check_every=4, select_reorth=True, use_graph=False, precond=None):
     o = _lib.dd_solver_opts()
     _lib.lib().dd_solver_opts_default(C.byref(o))
     o.inner = DD_C64 if inner == "c64" else DD_C128
@@ -108,6 +111,7 @@ def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hi
     o.check_every = int(check_every)
     o.select_reorth = int(bool(select_reorth))
     o.use_graph = int(bool(use_graph))
+    o.precond = PRECONDS[precond]
     return o
 
 
@@ -127,11 +131,12 @@ class Solver:
 
     def __init__(self, ops, restart=100, kmax=0, inner="c64", cgs_passes=2,
                  elems_per_thread=0, hist_cap=0, check_every=4, select_reorth=True,
-                 use_graph=False):
+                 use_graph=False, precond=None):
+        """precond: None, "jacobi" or "pml" (diagonal preconditioners, see the C header)."""
         self.ops = list(ops)
         self.nb = len(self.ops)
         self.opts = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap,
-                          check_every, select_reorth, use_graph)
+                          check_every, select_reorth, use_graph, precond)
         self.inner = inner
         self.restart, self.kmax = int(restart), int(kmax)
         h = C.c_void_p()

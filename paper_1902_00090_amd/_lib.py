@@ -32,7 +32,8 @@ class dd_pml(C.Structure):
 class dd_solver_opts(C.Structure):
     _fields_ = [("inner", C.c_int), ("cgs_passes", C.c_int), ("restart", C.c_int),
                 ("kmax", C.c_int), ("elems_per_thread", C.c_int), ("hist_cap", C.c_int),
-                ("check_every", C.c_int), ("select_reorth", C.c_int), ("use_graph", C.c_int)]
+                ("check_every", C.c_int), ("select_reorth", C.c_int), ("use_graph", C.c_int),
+                ("precond", C.c_int)]
 
 
 class dd_info(C.Structure):

@@ -95,6 +95,15 @@ extern "C" dd_status fdfd_op_create(const float* eps, int nx, int ny, double ome
   std::vector<std::complex<double>> cxm, cxp, cym, cyp;
   axis_coeffs(nx, P.npml_x, dx, omega, P.grade_m, P.ln_R, cxm, cxp);
   axis_coeffs(ny, P.npml_y, dx, omega, P.grade_m, P.ln_R, cym, cyp);
+  std::vector<double2> s64(nx + ny);
+  for (int i = 0; i < nx; ++i) {
+    const std::complex<double> v = stretch_at(i, nx, P.npml_x, dx, omega, P.grade_m, P.ln_R);
+    s64[i] = make_double2(v.real(), v.imag());
+  }
+  for (int j = 0; j < ny; ++j) {
+    const std::complex<double> v = stretch_at(j, ny, P.npml_y, dx, omega, P.grade_m, P.ln_R);
+    s64[nx + j] = make_double2(v.real(), v.imag());
+  }
   const int NC = 2 * nx + 2 * ny;
   std::vector<double2> c64(NC);
   std::vector<float2> c32(NC);
@@ -113,11 +122,14 @@ extern "C" dd_status fdfd_op_create(const float* eps, int nx, int ny, double ome
   fdfd_op* op = new fdfd_op();
   op->nx = nx; op->ny = ny; op->D = D; op->omega = omega; op->dx = dx; op->pml = P;
   op->eps32 = nullptr; op->eps64 = nullptr; op->cf32 = nullptr; op->cf64 = nullptr;
+  op->s64 = nullptr;
+  hipError_t e5 = hipMalloc(&op->s64, sizeof(double2) * (nx + ny));
   hipError_t e1 = hipMalloc(&op->eps32, sizeof(float) * D);
   hipError_t e2 = hipMalloc(&op->eps64, sizeof(double) * D);
   hipError_t e3 = hipMalloc(&op->cf32, sizeof(float2) * NC);
   hipError_t e4 = hipMalloc(&op->cf64, sizeof(double2) * NC);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess ||
+      e5 != hipSuccess) {
     dd_set_error("fdfd_op_create: hipMalloc failed");
     fdfd_op_destroy(op);
     return DD_ENOMEM;
@@ -126,7 +138,9 @@ extern "C" dd_status fdfd_op_create(const float* eps, int nx, int ny, double ome
   hipError_t c2_ = hipMemcpy(op->eps64, e64.data(), sizeof(double) * D, hipMemcpyHostToDevice);
   hipError_t c3 = hipMemcpy(op->cf32, c32.data(), sizeof(float2) * NC, hipMemcpyHostToDevice);
   hipError_t c4 = hipMemcpy(op->cf64, c64.data(), sizeof(double2) * NC, hipMemcpyHostToDevice);
-  if (c1 != hipSuccess || c2_ != hipSuccess || c3 != hipSuccess || c4 != hipSuccess) {
+  hipError_t c5 = hipMemcpy(op->s64, s64.data(), sizeof(double2) * (nx + ny), hipMemcpyHostToDevice);
+  if (c1 != hipSuccess || c2_ != hipSuccess || c3 != hipSuccess || c4 != hipSuccess ||
+      c5 != hipSuccess) {
     dd_set_error("fdfd_op_create: hipMemcpy failed");
     fdfd_op_destroy(op);
     return DD_EHIP;
@@ -141,6 +155,7 @@ extern "C" void fdfd_op_destroy(fdfd_op* op) {
   if (op->eps64) (void)hipFree(op->eps64);
   if (op->cf32) (void)hipFree(op->cf32);
   if (op->cf64) (void)hipFree(op->cf64);
+  if (op->s64) (void)hipFree(op->s64);
   delete op;
 }
 

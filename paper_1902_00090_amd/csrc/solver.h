@@ -29,6 +29,12 @@ struct ProbDesc {
   double2* r;
   const double2* b;  // caller's right-hand side [D]
   double2* x;        // caller's solution [D]
+  // diagonal preconditioner A' = P_L A P_R (NULL when absent), [Dp] each:
+  // inner-precision copies for the Arnoldi sweeps, FP64 for the residual and x
+  const void* pl;
+  const void* pr;
+  const double2* pl64;
+  const double2* pr64;
 };
 
 // Integer state per problem
@@ -41,7 +47,10 @@ enum { FLAG_ZERO_B = 1 };
 // FP64 state per problem
 // SD_NSUM / SD_NSUM2: sums over Arnoldi steps of the basis length n = k + j + 1
 // (all steps / steps with a second pass), for the algorithmic byte counts.
-enum { SD_BNORM = 0, SD_RHO, SD_BETA, SD_TRUE, SD_EST, SD_NSUM, SD_NSUM2, SD_ND = 8 };
+// SD_PRHO / SD_PBNORM: ||P_L r|| and ||P_L b|| (= SD_RHO, SD_BNORM without a
+// left preconditioner), the norms of the preconditioned cycle.
+enum { SD_BNORM = 0, SD_RHO, SD_BETA, SD_TRUE, SD_EST, SD_NSUM, SD_NSUM2, SD_PRHO, SD_PBNORM,
+       SD_ND = 10 };
 
 enum { MODE_START = 0, MODE_ARNOLDI = 1 };
 

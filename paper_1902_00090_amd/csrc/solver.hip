@@ -42,7 +42,24 @@ struct dd_solver {
   hipStream_t cap = nullptr;
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> execs;
+  // diagonal preconditioner buffers per problem (FP64 and FP32 copies)
+  struct PcBuf { double2 *pl64, *pr64; float2 *pl32, *pr32; };
+  std::vector<PcBuf> pcbuf;
 };
+
+// Fill the preconditioner arrays of every problem from its bound operator.
+static hipError_t precond_init(dd_solver* s) {
+  if (s->o.precond == DD_PRECOND_NONE) return hipSuccess;
+  for (int p = 0; p < s->nb; ++p) {
+    const auto& b = s->pcbuf[p];
+    const int gx = std::min(256, (s->hdesc[p].Dp + DD_BLOCK - 1) / DD_BLOCK);
+    k_precond_init<<<gx, DD_BLOCK>>>(s->P, p, s->o.precond, s->ops[p]->s64, b.pl64, b.pr64,
+                                     b.pl32, b.pr32);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e;
+}
 
 extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
   if (!o) return;
@@ -55,6 +72,7 @@ extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
   o->check_every = 4;
   o->select_reorth = 1;
   o->use_graph = 0;
+  o->precond = DD_PRECOND_NONE;
 }
 
 static size_t inner_bytes(dd_prec p) { return p == DD_C128 ? 16 : 8; }
@@ -128,6 +146,11 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     return DD_EINVAL;
   }
   if (o.hist_cap < 0) o.hist_cap = 0;
+  if (o.precond != DD_PRECOND_NONE && o.precond != DD_PRECOND_JACOBI &&
+      o.precond != DD_PRECOND_PML) {
+    dd_set_error("dd_solver_create: unknown preconditioner %d", o.precond);
+    return DD_EINVAL;
+  }
   int R = o.elems_per_thread;
   if (R != 0 && R != 1 && R != 2 && R != 4 && R != 8) {
     dd_set_error("dd_solver_create: elems_per_thread must be 0, 1, 2, 4 or 8");
@@ -180,6 +203,20 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     d.basis = basis;
     d.V = V;
     d.r = r;
+    if (o.precond != DD_PRECOND_NONE) {
+      double2 *pl64 = nullptr, *pr64 = nullptr;
+      float2 *pl32 = nullptr, *pr32 = nullptr;
+      chk(dalloc(s, &pl64, (size_t)d.Dp));
+      chk(dalloc(s, &pr64, (size_t)d.Dp));
+      chk(dalloc(s, &pl32, (size_t)d.Dp));
+      chk(dalloc(s, &pr32, (size_t)d.Dp));
+      d.pl64 = pl64;
+      d.pr64 = (o.precond == DD_PRECOND_PML) ? pr64 : nullptr;
+      d.pl = (o.inner == DD_C64) ? (const void*)pl32 : (const void*)pl64;
+      d.pr = (o.precond == DD_PRECOND_PML)
+                 ? ((o.inner == DD_C64) ? (const void*)pr32 : (const void*)pr64) : nullptr;
+      s->pcbuf.push_back({pl64, pr64, pl32, pr32});
+    }
   }
   PlanDev& P = s->P;
   P.nb = nb; P.m = m; P.kmax = K; P.NC = NC; P.NV = NV; P.hist_cap = o.hist_cap;
@@ -245,6 +282,12 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
   P.desc = dd;
   P.blk2prob = db2p;
   P.ctl = s->dctl;
+  e = precond_init(s);
+  if (e != hipSuccess) {
+    dd_set_error("dd_solver_create: %s", hipGetErrorString(e));
+    dd_solver_destroy(s);
+    return DD_EHIP;
+  }
   *out = s;
   return DD_OK;
 }
@@ -267,6 +310,7 @@ extern "C" dd_status dd_solver_bind(dd_solver* s, const fdfd_op* const* ops) {
   }
   s->has_subspace = false;
   DD_HIP_CHECK(hipMemcpy(s->ddesc, s->hdesc.data(), sizeof(ProbDesc) * s->nb, hipMemcpyHostToDevice));
+  DD_HIP_CHECK(precond_init(s));
   return DD_OK;
 }
 
@@ -354,7 +398,8 @@ template <typename T, int R>
 static void launch_step(dd_solver* s, int j, hipStream_t st) {
   const int g = s->nchunks, nb = s->nb;
   prof_mark(s, 0, st);
-  k_matvec_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j);
+  if (s->o.precond != DD_PRECOND_NONE) k_matvec_dot<T, R, true><<<g, DD_BLOCK, 0, st>>>(s->P, j);
+  else k_matvec_dot<T, R, false><<<g, DD_BLOCK, 0, st>>>(s->P, j);
   prof_end(s, st);
   k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
   if (s->P.reorth_mode != 0) {

@@ -167,7 +167,8 @@ __global__ void k_init_state(PlanDev P) {
   for (int i = 0; i < SD_ND; ++i) P.stD[p * SD_ND + i] = 0.0;
 }
 
-// r = b - A x in FP64; partial rows hold ||r||^2 and ||b||^2.
+// r = b - A x in FP64; partial rows hold ||r||^2, ||b||^2 and, with a left
+// preconditioner, ||P_L r||^2 and ||P_L b||^2.
 template <int R>
 __global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P) {
   const int chunk = blockIdx.x;
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P) {
   if (P.stI[p * ST_NI + ST_DONE] != DONE_RUNNING) return;
   const ProbDesc d = P.desc[p];
   const int base = (chunk - d.blk0) * DD_BLOCK * R;
-  double sr = 0.0, sb = 0.0;
+  double sr = 0.0, sb = 0.0, spr = 0.0, spb = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int e = base + r * DD_BLOCK + threadIdx.x;
@@ -185,6 +186,12 @@ __global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P) {
       const double2 bb = d.b[e];
       rr = dsub(bb, y);
       sb += bb.x * bb.x + bb.y * bb.y;
+      if (d.pl64) {
+        const double2 l = d.pl64[e];
+        const double2 lr = dmul(l, rr), lb = dmul(l, bb);
+        spr += lr.x * lr.x + lr.y * lr.y;
+        spb += lb.x * lb.x + lb.y * lb.y;
+      }
     }
     d.r[e] = rr;
     sr += rr.x * rr.x + rr.y * rr.y;
@@ -192,8 +199,10 @@ __global__ __launch_bounds__(DD_BLOCK) void k_residual(PlanDev P) {
   __shared__ double lds[8];
   const double tr = block_sum1<double>(sr, lds);
   const double tb = block_sum1<double>(sb, lds);
+  const double tpr = block_sum1<double>(spr, lds);
+  const double tpb = block_sum1<double>(spb, lds);
   double* prow = (double*)P.partial + (size_t)chunk * P.NV;
-  if (threadIdx.x == 0) { prow[0] = tr; prow[1] = tb; }
+  if (threadIdx.x == 0) { prow[0] = tr; prow[1] = tb; prow[2] = tpr; prow[3] = tpb; }
 }
 
 // One workgroup per problem: ||r||, ||b||; decides whether the problem has
@@ -203,14 +212,18 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_residual(PlanDev P, int first
   int* st = P.stI + p * ST_NI;
   if (st[ST_DONE] != DONE_RUNNING) return;
   const ProbDesc d = P.desc[p];
-  __shared__ double red[2];
-  reduce_rows<double>(P, d.blk0, d.nblk, 2, red);
+  __shared__ double red[4];
+  reduce_rows<double>(P, d.blk0, d.nblk, 4, red);
   if (threadIdx.x != 0) return;
   double* sd = P.stD + p * SD_ND;
   const double rho = sqrt(red[0]);
-  if (first) sd[SD_BNORM] = sqrt(red[1]);
+  if (first) {
+    sd[SD_BNORM] = sqrt(red[1]);
+    sd[SD_PBNORM] = d.pl64 ? sqrt(red[3]) : sd[SD_BNORM];
+  }
   const double bn = sd[SD_BNORM];
   sd[SD_RHO] = rho;
+  sd[SD_PRHO] = d.pl64 ? sqrt(red[2]) : rho;
   st[ST_PENDING] = 0;
   st[ST_ACTIVE] = 0;
   if (!isfinite(bn) || !isfinite(rho)) {
@@ -248,12 +261,12 @@ __global__ __launch_bounds__(DD_BLOCK) void k_start_dot(PlanDev P) {
   c2<T>* B = (c2<T>*)d.basis + (size_t)(P.kmax - d.k) * Dp;
   const int n = d.k;
   c2<T>* q0 = B + (size_t)n * Dp;
-  const double inv = 1.0 / P.stD[p * SD_ND + SD_RHO];
+  const double inv = 1.0 / P.stD[p * SD_ND + SD_PRHO];
   c2<T> wv[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int e = base + r * DD_BLOCK + threadIdx.x;
-    const double2 rr = d.r[e];
+    const double2 rr = d.pl64 ? dmul(d.pl64[e], d.r[e]) : d.r[e];
     wv[r] = cmk<c2<T>>((T)(rr.x * inv), (T)(rr.y * inv));
     q0[e] = wv[r];
   }
@@ -266,7 +279,8 @@ __global__ __launch_bounds__(DD_BLOCK) void k_start_dot(PlanDev P) {
 // Arnoldi step j, first sweep: w = A q_j (q_j stored unnormalised, scaled on
 // the fly by hscale[j]) written to slot Q_{j+1}; partial dots [C Q_0..Q_j]^H w
 // and ||w||^2.
-template <typename T, int R>
+// PC: the problem carries a diagonal preconditioner, w = P_L A P_R q_j.
+template <typename T, int R, bool PC = false>
 __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
   const int chunk = blockIdx.x;
   const int p = P.blk2prob[chunk];
@@ -284,9 +298,20 @@ __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
   for (int r = 0; r < R; ++r) {
     const int e = base + r * DD_BLOCK + threadIdx.x;
     c2<T> y = cmk<c2<T>>(T(0), T(0));
-    if (e < d.D)
-      y = cscale(stencil_point<T>(q, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d), (T)d.omega2),
-                 (T)hs);
+    if (e < d.D) {
+      if (PC) {
+        const c2<T>* pr = (const c2<T>*)d.pr;
+        const c2<T>* pl = (const c2<T>*)d.pl;
+        y = pr ? stencil_point_scaled<T>(q, pr, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d),
+                                         (T)d.omega2)
+               : stencil_point<T>(q, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d), (T)d.omega2);
+        if (pl) y = cmul(pl[e], y);
+        y = cscale(y, (T)hs);
+      } else {
+        y = cscale(stencil_point<T>(q, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d), (T)d.omega2),
+                   (T)hs);
+      }
+    }
     wv[r] = y;
     w[e] = y;
   }
@@ -485,7 +510,7 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
   double* sd = P.stD + p * SD_ND;
   const double nrm = sqrt(red[0]);
   if (mode == MODE_START) {
-    const double rho = sd[SD_RHO];
+    const double rho = sd[SD_PRHO];
     for (int v = t; v < k; v += DD_BLOCK)
       P.c0[(size_t)p * P.kmax + v] = make_double2(rho * col[v].x, rho * col[v].y);
     if (t == 0) {
@@ -547,7 +572,7 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
       sd[SD_NSUM] += (double)n;
       st[ST_J] = j + 1;
       const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
-      const double bn = sd[SD_BNORM];
+      const double bn = sd[SD_PBNORM];
       sd[SD_EST] = est / bn;
       if (it <= P.hist_cap) P.hist[(size_t)p * P.hist_cap + it - 1] = est / bn;
       if (est <= P.ctl[0] * bn || it >= (int)P.ctl[1] || !(nrm > 0.0) || !isfinite(nrm) ||
@@ -590,18 +615,72 @@ __global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
       acc[r] = dadd(acc[r], dmul(c, make_double2((double)b.x, (double)b.y)));
     }
   }
-  for (int i = 0; i < n; ++i) {
-    const double2 c = cf[k + i];
+  if (!d.pr64) {
+    for (int i = 0; i < n; ++i) {
+      const double2 c = cf[k + i];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const c2<T> b = ld_stream(Q + (size_t)i * Dp + base + r * DD_BLOCK + threadIdx.x);
-      acc[r] = dadd(acc[r], dmul(c, make_double2((double)b.x, (double)b.y)));
+      for (int r = 0; r < R; ++r) {
+        const c2<T> b = ld_stream(Q + (size_t)i * Dp + base + r * DD_BLOCK + threadIdx.x);
+        acc[r] = dadd(acc[r], dmul(c, make_double2((double)b.x, (double)b.y)));
+      }
     }
+  } else {
+    // right preconditioner: the Krylov part lives in the scaled variable
+    double2 aq[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) aq[r] = make_double2(0.0, 0.0);
+    for (int i = 0; i < n; ++i) {
+      const double2 c = cf[k + i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const c2<T> b = ld_stream(Q + (size_t)i * Dp + base + r * DD_BLOCK + threadIdx.x);
+        aq[r] = dadd(aq[r], dmul(c, make_double2((double)b.x, (double)b.y)));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      acc[r] = dadd(acc[r], dmul(d.pr64[base + r * DD_BLOCK + threadIdx.x], aq[r]));
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int e = base + r * DD_BLOCK + threadIdx.x;
     if (e < d.D) d.x[e] = dadd(d.x[e], acc[r]);
+  }
+}
+
+// Diagonal preconditioner of problem p, [Dp] elements, zero in the padding.
+// Jacobi (left): P_L = diag(A)^{-1} with diag(A)_c = cxm + cxp + cym + cyp -
+// omega^2 eps_c.  PML scaling: P_L = S^{1/2}, P_R = S^{-1/2} with
+// S = diag(s_x(i) s_y(j)) (integer-node stretch factors s64), the diagonal
+// that makes S A complex symmetric; P_L A P_R is then complex symmetric with
+// the spectrum of A.  Principal square roots (Re s > 0).
+__global__ void k_precond_init(PlanDev P, int p, int type, const double2* __restrict__ s64,
+                               double2* pl64, double2* pr64, float2* pl32, float2* pr32) {
+  const ProbDesc d = P.desc[p];
+  for (int e = blockIdx.x * DD_BLOCK + threadIdx.x; e < d.Dp; e += gridDim.x * DD_BLOCK) {
+    double2 l = make_double2(0.0, 0.0), rr = make_double2(0.0, 0.0);
+    if (e < d.D) {
+      const int iy = e / d.nx, ix = e - iy * d.nx;
+      if (type == DD_PRECOND_JACOBI) {
+        const double2* cf = d.cf64;
+        const double2 dg = make_double2(
+            cf[ix].x + cf[d.nx + ix].x + cf[2 * d.nx + iy].x + cf[2 * d.nx + d.ny + iy].x -
+                d.omega2 * d.eps64[e],
+            cf[ix].y + cf[d.nx + ix].y + cf[2 * d.nx + iy].y + cf[2 * d.nx + d.ny + iy].y);
+        l = ddiv(make_double2(1.0, 0.0), dg);
+      } else {
+        const double2 sv = dmul(s64[ix], s64[d.nx + iy]);
+        const double a = sqrt(sv.x * sv.x + sv.y * sv.y);
+        const double re = sqrt(0.5 * (a + sv.x));
+        const double im = copysign(sqrt(fmax(0.0, 0.5 * (a - sv.x))), sv.y);
+        l = make_double2(re, im);
+        rr = ddiv(make_double2(1.0, 0.0), l);
+      }
+    }
+    pl64[e] = l;
+    pr64[e] = rr;
+    pl32[e] = make_float2((float)l.x, (float)l.y);
+    pr32[e] = make_float2((float)rr.x, (float)rr.y);
   }
 }
 
@@ -637,7 +716,10 @@ __global__ void k_stencil_multi(PlanDev P) {
   c2<T>* y = (c2<T>*)d.basis + (size_t)(P.kmax - d.k + v) * d.Dp;
   for (int e = blockIdx.x * DD_BLOCK + threadIdx.x; e < d.Dp; e += gridDim.x * DD_BLOCK) {
     c2<T> a = cmk<c2<T>>(T(0), T(0));
-    if (e < d.D) a = stencil_point<T>(x, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d), (T)d.omega2);
+    if (e < d.D) {
+      a = stencil_point<T>(x, e, d.nx, d.ny, OpP<T>::cf(d), OpP<T>::eps(d), (T)d.omega2);
+      if (d.pl) a = cmul(((const c2<T>*)d.pl)[e], a);   // W = P_L A U (U given in x-space)
+    }
     y[e] = a;
   }
 }
