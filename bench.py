@@ -248,6 +248,37 @@ def cnn_kernels_only(args, torch, W):
     print(json.dumps(out), flush=True)
 
 
+def precond_leg(args, torch, ops, bs, U):
+    """The evaluation batch with the supplement's diagonal preconditioners
+    (Jacobi; PML grid-spacing scaling), without and with the PCA basis."""
+    from paper_1902_00090_amd import Solver
+    B = len(ops)
+    out = {}
+    for kind in ("jacobi", "pml"):
+        for aug in (False, True):
+            s = Solver(ops, restart=args.restart, kmax=args.k if aug else 0, cgs_passes=args.cgs,
+                       hist_cap=args.maxit, precond=kind)
+            if aug:
+                s.set_subspace([U] * B)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            _, inf, _ = s.solve(bs, tol=args.tol, maxit=args.maxit)
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+            h = [s.history(p) for p in range(B)]
+            s.close()
+            key = kind + ("+pca" if aug else "")
+            out[key] = {
+                "solves_per_s": round(B / dt, 4),
+                "iters_mean": float(np.mean([i["iters"] for i in inf])),
+                "all_converged": all(i["status"] == 0 for i in inf),
+                "worst_rel_res_true": max(i["rel_res_true"] for i in inf),
+                "precond_rel_res_after_1_iter_mean": float(np.mean([x[0] for x in h])),
+            }
+            log(f"precond {key}: {out[key]}")
+    return out
+
+
 def recycle_leg(args, torch, data):
     """Design steps 0..N-1 of every benchmark trajectory, one lockstep batch per
     step: augmented by the fields of the previous steps of the same trajectory,
@@ -350,6 +381,9 @@ def main():
                     help="also run trajectory recycling over the first N design steps of "
                          "every trajectory (augment step s by the fields of steps < s)")
     ap.add_argument("--recycle-window", type=int, default=5)
+    ap.add_argument("--precond", action="store_true",
+                    help="also solve the evaluation batch with the Jacobi and PML-scaling "
+                         "diagonal preconditioners, plain and PCA-augmented")
     ap.add_argument("--cnn-kernels", type=int, default=0,
                     help="only time N CNN forward passes (batch 64) and N training steps "
                          "(batch 32) at 480x240, print one JSON line and exit")
@@ -494,6 +528,11 @@ def main():
                           it_aug, plain, m) for m in modes}
     del Smat
 
+    # ---------------- diagonal preconditioners (optional)
+    pre = None
+    if args.precond:
+        pre = precond_leg(args, torch, ops, bs, U)
+
     # ---------------- trajectory recycling (optional)
     rec = None
     if args.recycle > 0:
@@ -585,6 +624,7 @@ def main():
         "cnn_augmented": cnn,
         "uneven_batch_plain": c3,
         "trajectory_recycling": rec,
+        "diagonal_preconditioners": pre,
     }
     print(json.dumps(out), flush=True)
 
