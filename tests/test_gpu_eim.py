@@ -64,3 +64,16 @@ def test_separable_case_is_the_2d_solution():
     f = spla.spsolve(A.tocsc(), b)
     Fg = Fg.cpu().numpy().astype(np.complex128)
     assert np.linalg.norm(Fg - f) / np.linalg.norm(f) < 1e-6
+
+
+def test_odd_grids_and_pml_on_one_axis():
+    """Grids that are not multiples of the launch tiles, and an operator with
+    no y-PML (the effective-index field only uses the x stretching)."""
+    import torch
+    from paper_1902_00090_amd import FdfdOp, eim_field
+    insts = [W.grating(1010, nx=97, ny=43, npml=7), W.grating(1011, nx=130, ny=61, npml=12)]
+    ops = [FdfdOp.from_instance(insts[0]), FdfdOp(insts[1].eps, insts[1].omega, insts[1].dx,
+                                                  insts[1].npml, npml_y=0)]
+    F = eim_field(ops, [torch.tensor(i.b, device="cuda") for i in insts])
+    for f, inst in zip(F, insts):
+        _check(f.cpu().numpy().astype(np.complex128), eim.eim_instance(inst))

@@ -54,3 +54,30 @@ def test_preconditioned_grating_c64_reaches_tol(kind):
     assert st == 0 and rr <= 1e-6 and abs(rr - info["rel_res_true"]) <= 1e-3 * rr
     xs = direct.sparse_solve(A, inst.b)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-4
+
+
+def test_preconditioned_graph_replay_and_uneven_batch():
+    """Preconditioned solves of problems of different grids in one lockstep
+    batch, with graph replay: the same iterates as direct launches and as the
+    problems solved one by one."""
+    import torch
+    from gpu_util import to_dev
+    from paper_1902_00090_amd import FdfdOp, Solver
+    insts = [_tiny(80), _tiny(81, nx=36, ny=28), _tiny(82, nx=12, ny=30)]
+    ops = [FdfdOp.from_instance(i) for i in insts]
+    bs = [to_dev(i.b, torch.complex128) for i in insts]
+    res = []
+    for g in (True, False):
+        s = Solver(ops, restart=15, inner="c64", precond="pml", use_graph=g, hist_cap=4000)
+        xs, infos, st = s.solve(bs, tol=1e-7, maxit=4000)
+        assert st == 0
+        res.append(([x.cpu().numpy() for x in xs], [i["iters"] for i in infos]))
+    assert res[0][1] == res[1][1]
+    for a, b in zip(res[0][0], res[1][0]):
+        np.testing.assert_array_equal(a, b)
+    for p, inst in enumerate(insts):
+        s1 = Solver([ops[p]], restart=15, inner="c64", precond="pml")
+        (x1,), (i1,), _ = s1.solve([bs[p]], tol=1e-7, maxit=4000)
+        A = fdfd.assemble_instance(inst)
+        for x in (res[1][0][p], x1.cpu().numpy()):
+            assert np.linalg.norm(inst.b - A @ x) / np.linalg.norm(inst.b) <= 1e-7

@@ -118,3 +118,18 @@ def test_residual_loss_training_reduces_the_loss():
     print("residual-loss training:", losses_[0], "->", np.mean(losses_[-10:]), "eval", lr_.mean())
     assert np.mean(losses_[-10:]) < 0.8 * losses_[0]
     assert abs(lr_.mean() - np.mean(losses_[-2:])) < 0.1
+
+
+def test_res_loss_single_vector_and_zero_subspace():
+    """k = 1 against the oracle, and an all-zero V (rank zero) gives loss 1."""
+    import torch
+    from paper_1902_00090_amd import res_loss_batched
+    inst = W.grating(1005, nx=96, ny=48)
+    ops, bs = _ops_b([inst, inst])
+    rng = np.random.default_rng(8)
+    v = W.random_complex(rng, (1, inst.D)).astype(np.complex64)
+    z = np.zeros((1, inst.D), np.complex64)
+    lg = res_loss_batched(ops, bs, [torch.tensor(v, device="cuda"), torch.tensor(z, device="cuda")])
+    lo = losses.res_loss(fdfd.assemble_instance(inst), v.T.astype(np.complex128), inst.b)
+    np.testing.assert_allclose(lg[0], lo, rtol=1e-4)
+    assert lg[1] == 1.0
