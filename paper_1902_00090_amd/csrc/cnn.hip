@@ -473,6 +473,156 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf16* __restrict__ dz,
   }
 }
 
+// Weight gradients of the stride-1 and upsampling layers whose output rows are
+// whole multiples of 32 pixels, all nine taps per workgroup.  A workgroup walks
+// row segments of 32 output pixels.  Per segment it stages, transposed in LDS:
+//  * dz of the segment once, [r][pixel];
+//  * the three source rows of the conv input, each in three copies shifted by
+//    one column, so that every tap reads its x operand at the same 16-byte
+//    aligned offsets.
+// It then issues the 9 (Mr/16)(Nc/16) MFMA tiles of the segment, spread over
+// the four waves.  Compared with one workgroup per tap, dz is staged once
+// instead of nine times, a source row is fetched once for three taps, and there
+// are nine times as many products per barrier.  Partials use k_conv_wgrad's
+// [slice][tap][r][c] layout.
+#define WR_MR 32
+#define WR_NC 64
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_conv_wgrad_rows(const bf16* __restrict__ dz,
+                                                         const bf16* __restrict__ x, int B,
+                                                         int Hout, int Wout, int Hin, int Win,
+                                                         int mode, int segs_per,
+                                                         float* __restrict__ part) {
+  constexpr int Mr = 16 * MT, Nc = 16 * NT, NTILE = 9 * MT * NT, PER_WAVE = (NTILE + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16 As[WR_MR][40];
+  __shared__ __attribute__((aligned(16))) bf16 Xs[9][WR_NC][40];   // [3 dy * 3 dx][c][pixel]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int W32 = Wout / 32;
+  const int nseg = B * Hout * W32;
+  const int s0 = blockIdx.x * segs_per, s1 = min(nseg, s0 + segs_per);
+  const bool up = (mode == MAP_UP);
+  f32x4 acc[PER_WAVE];
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kq = 8 * (lane >> 4);
+  for (int sg = s0; sg < s1; ++sg) {
+    const int b = sg / (Hout * W32), rem = sg - b * Hout * W32;
+    const int y = rem / W32, x0 = (rem - y * W32) * 32;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 32 * (Mr / 8); idx += 256) {
+      const int pp = idx / (Mr / 8), cg = (idx % (Mr / 8)) * 8;
+      const bf16x8 v = load8(dz + (((size_t)b * Hout + y) * Wout + x0 + pp) * Mr + cg);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[cg + q][pp] = v[q];
+    }
+    for (int idx = threadIdx.x; idx < 3 * 34 * (Nc / 8); idx += 256) {
+      const int dy = idx / (34 * (Nc / 8)), r2 = idx - dy * 34 * (Nc / 8);
+      const int j = r2 / (Nc / 8), cg = (r2 % (Nc / 8)) * 8;
+      const int uy = y + dy - 1, ux = x0 + j - 1;   // conv-input grid (= output grid)
+      bf16x8 v = zero8();
+      if (uy >= 0 && uy < Hout && ux >= 0 && ux < Wout) {
+        const int sy = up ? (uy >> 1) : uy, sx = up ? (ux >> 1) : ux;
+        v = load8(x + (((size_t)b * Hin + sy) * Win + sx) * Nc + cg);
+      }
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int k = j - dx;   // this value is pixel k of tap (dy, dx)
+        if (k >= 0 && k < 32) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) Xs[dy * 3 + dx][cg + q][k] = v[q];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER_WAVE; ++i) {
+      const int t = wave + 4 * i;
+      if (t < NTILE) {
+        const int tap = t / (MT * NT), rr = t - tap * MT * NT, ti = rr / NT, tj = rr - ti * NT;
+        const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kq];
+        const bf16x8 bv = *(const bf16x8*)&Xs[tap][tj * 16 + (lane & 15)][kq];
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i) {
+    const int t = wave + 4 * i;
+    if (t < NTILE) {
+      const int tap = t / (MT * NT), rr = t - tap * MT * NT, ti = rr / NT, tj = rr - ti * NT;
+      float* out = part + (((size_t)blockIdx.x * 9 + tap) * Mr) * Nc;
+      const int c = tj * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[i][q];
+    }
+  }
+}
+
+// Layer-1 weight and bias gradients as one GEMM over row segments of 32
+// pixels: dW[co][j] = sum_p dz[p][co] u[p][j], where u[p] is the pixel's
+// 9 C input values (plane-major, tap-minor, the [cout][cin][3][3] order of
+// the weights), then 1 for the bias, then zeros up to 32 columns.  dz and u
+// are staged transposed in LDS (u rounded to bf16), one MFMA tile per wave and
+// segment, FP32 accumulation.  Needs W % 32 == 0, coutp == 32 and 9 C + 1 <= 32.
+// Partials [slice][32][32].
+__global__ __launch_bounds__(256) void k_conv1_wgrad_rows(const float* __restrict__ x0,
+                                                          const bf16* __restrict__ dz, int B,
+                                                          int C, int H, int W, int segs_per,
+                                                          float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) bf16 As[32][40];
+  __shared__ __attribute__((aligned(16))) bf16 Us[32][40];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int W32 = W / 32, nseg = B * H * W32;
+  const int s0 = blockIdx.x * segs_per, s1 = min(nseg, s0 + segs_per);
+  const int ti = wave >> 1, tj = wave & 1;   // the four 16 x 16 tiles of the 32 x 32 result
+  const int J = 9 * C;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kq = 8 * (lane >> 4);
+  for (int sg = s0; sg < s1; ++sg) {
+    const int b = sg / (H * W32), rem = sg - b * H * W32;
+    const int y = rem / W32, xb = (rem - y * W32) * 32;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 32 * 4; idx += 256) {
+      const int pp = idx >> 2, cg = (idx & 3) * 8;
+      const bf16x8 v = load8(dz + (((size_t)b * H + y) * W + xb + pp) * 32 + cg);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[cg + q][pp] = v[q];
+    }
+    for (int idx = threadIdx.x; idx < 32 * 32; idx += 256) {
+      const int j = idx >> 5, k = idx & 31;   // consecutive threads: consecutive pixels
+      float v = 0.f;
+      if (j < J) {
+        const int ci = j / 9, t = j - 9 * ci;
+        const int ys = y + t / 3 - 1, xs = xb + k + t % 3 - 1;
+        if (ys >= 0 && ys < H && xs >= 0 && xs < W) v = x0[(((size_t)b * C + ci) * H + ys) * W + xs];
+      } else if (j == J) {
+        v = 1.f;
+      }
+      Us[j][k] = (bf16)v;
+    }
+    __syncthreads();
+    const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kq];
+    const bf16x8 bv = *(const bf16x8*)&Us[tj * 16 + (lane & 15)][kq];
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+  float* out = part + (size_t)blockIdx.x * 32 * 32;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[(ti * 16 + 4 * (lane >> 4) + q) * 32 + tj * 16 + (lane & 15)] = acc[q];
+}
+
+// Sum the [slice][32][32] partials of k_conv1_wgrad_rows in slice order.
+__global__ void k_conv1_rows_reduce(const float* __restrict__ part, int nslices, int cout, int C,
+                                    float* __restrict__ gw, float* __restrict__ gb) {
+  const int J = 9 * C;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= cout * (J + 1)) return;
+  const int co = t / (J + 1), j = t % (J + 1);
+  float s = 0.f;
+  for (int sl = 0; sl < nslices; ++sl) s += part[((size_t)sl * 32 + co) * 32 + j];
+  if (j < J) gw[(size_t)co * J + j] = s;
+  else gb[co] = s;
+}
+
 // Bias-gradient partials: column sums of dz over a pixel slice.  Thread t
 // handles channel t % Mr of pixels p0 + t / Mr + j * (256 / Mr), so a wave's
 // loads cover whole pixel rows (coalesced); the 256 / Mr lanes of a channel
@@ -873,11 +1023,29 @@ static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
     // weight and bias gradients of layer l: about 256 pixel slices
     const int per = wgrad_per(npo);
     const int slices = (npo + per - 1) / per;
-    k_conv_wgrad<<<dim3(slices, 9), 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout, L.Wout,
-                                                   L.Hin, L.Win, L.coutp, L.cinp, L.mode, per,
-                                                   n->wpart);
+    const bool rows = (L.mode == MAP_S1 || L.mode == MAP_UP) && L.Wout % 32 == 0 &&
+                      L.coutp == 32 && (L.cinp == 32 || L.cinp == 64);
+    int wslices = slices;
+    if (rows) {
+      // row segments of 32 output pixels, at most `slices` workgroups
+      const int nseg = B * L.Hout * (L.Wout / 32);
+      const int sp = (nseg + slices - 1) / slices;
+      wslices = (nseg + sp - 1) / sp;
+      if (L.cinp == 32)
+        k_conv_wgrad_rows<2, 2><<<wslices, 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout,
+                                                         L.Wout, L.Hin, L.Win, L.mode, sp,
+                                                         n->wpart);
+      else
+        k_conv_wgrad_rows<2, 4><<<wslices, 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout,
+                                                         L.Wout, L.Hin, L.Win, L.mode, sp,
+                                                         n->wpart);
+    } else {
+      k_conv_wgrad<<<dim3(slices, 9), 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout, L.Wout,
+                                                     L.Hin, L.Win, L.coutp, L.cinp, L.mode, per,
+                                                     n->wpart);
+    }
     const int tot = L.cout * L.cin * 9;
-    k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.coutp, L.cinp, L.cout,
+    k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, st>>>(n->wpart, wslices, L.coutp, L.cinp, L.cout,
                                                       L.cin, n->grads + L.woff);
     k_bias_grad<<<slices, 256, 0, st>>>(n->dz[l], npo, L.coutp, per, n->wpart);
     k_bgrad_reduce<<<1, 256, 0, st>>>(n->wpart, slices, L.coutp, L.cout, n->grads + L.boff);
@@ -894,14 +1062,23 @@ static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
   }
   {
     const CnnLayer& L = n->L[0];
-    const int rows = B * n->ny, rows_per = std::max(1, (rows + 511) / 512);
-    const int slices = (rows + rows_per - 1) / rows_per;
     const int nt = L.cout * (9 * n->cin0 + 1);
-    k_conv1_wgrad<<<slices, (nt + 63) / 64 * 64, 0, st>>>(n->x0, n->dz[0], B, n->cin0, n->ny,
-                                                          n->nx, L.cout, L.coutp, rows_per,
-                                                          n->wpart);
-    k_conv1_reduce<<<(nt + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
-                                                     n->grads + L.woff, n->grads + L.boff);
+    if (n->nx % 32 == 0 && L.coutp == 32 && 9 * n->cin0 + 1 <= 32) {
+      const int nseg = B * n->ny * (n->nx / 32);
+      const int sp = (nseg + 255) / 256, slices = (nseg + sp - 1) / sp;
+      k_conv1_wgrad_rows<<<slices, 256, 0, st>>>(n->x0, n->dz[0], B, n->cin0, n->ny, n->nx, sp,
+                                                 n->wpart);
+      k_conv1_rows_reduce<<<(nt + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
+                                                            n->grads + L.woff, n->grads + L.boff);
+    } else {
+      const int rows = B * n->ny, rows_per = std::max(1, (rows + 511) / 512);
+      const int slices = (rows + rows_per - 1) / rows_per;
+      k_conv1_wgrad<<<slices, (nt + 63) / 64 * 64, 0, st>>>(n->x0, n->dz[0], B, n->cin0, n->ny,
+                                                            n->nx, L.cout, L.coutp, rows_per,
+                                                            n->wpart);
+      k_conv1_reduce<<<(nt + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
+                                                       n->grads + L.woff, n->grads + L.boff);
+    }
   }
   DD_HIP_CHECK(hipGetLastError());
   return DD_OK;

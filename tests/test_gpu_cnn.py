@@ -74,10 +74,13 @@ def test_forward_full_size_sampled():
     assert _rel(U, ocnn.channels_to_fields(out)) < 3e-2
 
 
-def test_gradients_match_oracle():
+@pytest.mark.parametrize("nx,ny", [(24, 16), (64, 32)])
+def test_gradients_match_oracle(nx, ny):
+    """24 x 16 takes the per-tap weight-gradient kernel everywhere; at 64 x 32
+    the full-resolution layers (6-8) take the row-segment kernel."""
     import torch
     from paper_1902_00090_amd.cnn import flat_to_layers
-    nx, ny, B, k = 24, 16, 2, 10
+    B, k = 2, 10
     net, op, eps, eps_d = _setup(nx, ny, B, k, seed=3)
     rng = np.random.default_rng(11)
     tgt = (rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny))) * 0.1
@@ -113,13 +116,15 @@ def test_adam_step_and_training_reduces_loss():
     assert losses[-1] < 0.7 * losses[0], (losses[0], losses[-1])
 
 
-def test_three_channel_forward_and_gradients_match_oracle():
+@pytest.mark.parametrize("nx,ny", [(24, 16), (64, 32)])
+def test_three_channel_forward_and_gradients_match_oracle(nx, ny):
     """Permittivity plus effective-index field (the paper's CNN input): the
     input planes, every layer, the output and all gradients against the
-    oracle at identical weights."""
+    oracle at identical weights (64 x 32 takes the row-segment weight-gradient
+    kernels of layers 1 and 6-8)."""
     import torch
     from paper_1902_00090_amd.cnn import flat_to_layers
-    nx, ny, B, k = 24, 16, 3, 4
+    B, k = 3, 4
     net, op, eps, eps_d, eim, eim_d = _setup(nx, ny, B, k, seed=9, in_ch=3)
     assert net.layers()[0][0] == 3
     U = net.predict(eps_d, eim=eim_d).cpu().numpy()
