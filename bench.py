@@ -248,6 +248,32 @@ def cnn_kernels_only(args, torch, W):
     print(json.dumps(out), flush=True)
 
 
+def single_leg(args, torch, ops, bs, U):
+    """The first evaluation problem solved alone (the single-solve
+    configuration): plain and PCA-augmented GMRES(100), step groups replayed
+    as HIP graphs."""
+    from paper_1902_00090_amd import Solver
+    out = {}
+    for aug in (False, True):
+        s = Solver([ops[0]], restart=args.restart, kmax=args.k if aug else 0,
+                   cgs_passes=args.cgs, use_graph=True)
+        if aug:
+            s.set_subspace([U])
+        s.solve([bs[0]], tol=args.tol, maxit=args.maxit)       # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, (inf,), _ = s.solve([bs[0]], tol=args.tol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        s.close()
+        out["augmented" if aug else "plain"] = {
+            "seconds": round(dt, 3), "iters": inf["iters"],
+            "us_per_iter": round(1e6 * dt / max(1, inf["iters"]), 1),
+            "converged": inf["status"] == 0}
+    log(f"single problem: {out}")
+    return out
+
+
 def precond_leg(args, torch, ops, bs, U):
     """The evaluation batch with the supplement's diagonal preconditioners
     (Jacobi; PML grid-spacing scaling), without and with the PCA basis."""
@@ -509,6 +535,9 @@ def main():
         ps.close()
         log(f"plain: {plain['solves_per_s']:.3f} solves/s, iters mean {plain['iters_mean']:.0f}")
 
+    # ---------------- one problem alone (latency-bound), plain and augmented
+    single = single_leg(args, torch, ops, bs, U)
+
     # ---------------- error vs the FP64 oracle (sparse LU) on a subset
     errs = []
     if args.oracle_check > 0:
@@ -621,6 +650,7 @@ def main():
         "sweeps": sweeps,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "single_problem": single,
         "cnn_augmented": cnn,
         "uneven_batch_plain": c3,
         "trajectory_recycling": rec,

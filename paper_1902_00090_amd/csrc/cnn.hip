@@ -242,7 +242,10 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
 
 // ---------------------------------------- LDS-tiled forward convolution ----
 // Forward pass of the stride-1 layers, plain (MAP_S1) or after a x2 nearest
-// upsample (MAP_UP).  A workgroup computes a 4 x 64 tile of output pixels of
+// upsample (MAP_UP), and (BWD) the backward-data pass of the plain stride-1
+// layers: the gradient at a layer-input pixel gathers dz through the kernel
+// rotated by 180 degrees (tap t reads weight tap 8 - t of the transposed
+// copy), masked by the ReLU of the layer input.  A workgroup computes a 4 x 64 tile of output pixels of
 // one image for all M = 16 MT output channels.  For every 32 input channels
 // the 6 x 66 input patch (halo included; zero padding and the upsampling are
 // resolved while staging) is written once to LDS and read there by all nine
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
 #define CT_PH (CT_TH + 2)
 #define CT_PW (CT_TW + 2)
 #define CT_PS 40   // bf16 per staged pixel: 32 channels + 8 of padding (80-byte stride)
-template <int MT>
+template <int MT, bool BWD = false>
 __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) bf16 patch[CT_PH * CT_PW * CT_PS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         bv[j] = *(const bf16x8*)(patch + ((wave + dy) * CT_PW + 16 * j + (lane & 15) + dx) * CT_PS + kq);
-      const bf16* wt = a.W + (size_t)t * a.M * a.Ksrc + c0 + kq;
+      const bf16* wt = a.W + (size_t)(BWD ? 8 - t : t) * a.M * a.Ksrc + c0 + kq;
 #pragma unroll
       for (int i = 0; i < MT; ++i) {
         const bf16x8 av = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
@@ -312,10 +315,14 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
       float v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        v[q] = acc[i][j][q] + a.bias[r0 + q];
-        if (a.relu) v[q] = fmaxf(v[q], 0.f);
+        if (BWD) {
+          v[q] = (bf2f(a.mask[p * a.M + r0 + q]) > 0.f) ? acc[i][j][q] : 0.f;
+        } else {
+          v[q] = acc[i][j][q] + a.bias[r0 + q];
+          if (a.relu) v[q] = fmaxf(v[q], 0.f);
+        }
       }
-      if (a.outf) {
+      if (!BWD && a.outf) {
         float* o = a.outf + p * a.nreal + r0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -966,6 +973,15 @@ static void gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_t st)
       case 2: k_conv_tile<2><<<grid, 256, 0, st>>>(a); break;
       case 4: k_conv_tile<4><<<grid, 256, 0, st>>>(a); break;
       default: k_conv_tile<8><<<grid, 256, 0, st>>>(a); break;
+    }
+    return;
+  }
+  if (bwd && a.mode == MAP_S1 && a.Ksrc % 32 == 0) {
+    const dim3 grid((a.Wq + CT_TW - 1) / CT_TW, (a.Hq + CT_TH - 1) / CT_TH, a.B);
+    switch (MT) {
+      case 2: k_conv_tile<2, true><<<grid, 256, 0, st>>>(a); break;
+      case 4: k_conv_tile<4, true><<<grid, 256, 0, st>>>(a); break;
+      default: k_conv_tile<8, true><<<grid, 256, 0, st>>>(a); break;
     }
     return;
   }
