@@ -338,7 +338,7 @@ def recycle_leg(args, torch, data):
     return out
 
 
-def c3_leg(args, torch, W):
+def uneven_leg(args, torch, W):
     """8 trajectories x 32 steps of uneven grids (192x96, 320x160, 480x240;
     1.30 / 1.55 um) in one lockstep batch, plain complex64 GMRES, step groups
     replayed as HIP graphs."""
@@ -402,7 +402,7 @@ def main():
     ap.add_argument("--cnn-inputs", type=int, default=3, choices=(1, 3),
                     help="CNN input planes: 3 = permittivity + effective-index field (the "
                          "paper's input), 1 = permittivity only")
-    ap.add_argument("--no-c3", action="store_true", help="skip the uneven correlated batch")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven correlated batch")
     ap.add_argument("--recycle", type=int, default=0,
                     help="also run trajectory recycling over the first N design steps of "
                          "every trajectory (augment step s by the fields of steps < s)")
@@ -419,7 +419,8 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the problems of a batch are independent; see DESIGN.md for sharding)",
+              "(the problems of a batch are independent and would be split across GPUs "
+              "with no communication during the solve)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -568,9 +569,9 @@ def main():
         rec = recycle_leg(args, torch, data)
 
     # ---------------- uneven correlated batch, plain GMRES, graph replay
-    c3 = None
-    if not args.no_c3:
-        c3 = c3_leg(args, torch, W)
+    uneven = None
+    if not args.no_uneven:
+        uneven = uneven_leg(args, torch, W)
 
     # ---------------- roofline of the dominant sweep
     name = max(ks, key=lambda n: ks[n][0])
@@ -652,7 +653,7 @@ def main():
         "cpu_baseline": cpu,
         "single_problem": single,
         "cnn_augmented": cnn,
-        "uneven_batch_plain": c3,
+        "uneven_batch_plain": uneven,
         "trajectory_recycling": rec,
         "diagonal_preconditioners": pre,
     }
