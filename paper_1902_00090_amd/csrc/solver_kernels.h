@@ -89,21 +89,40 @@ __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t D
 // finished: the kernel boundary makes the rows visible on every XCD, so no
 // device-scope fence (an L2 write-back on this chip) is ever issued inside
 // a sweep.
+// With few values (the norms, a handful of dots) G = 256 / nvals threads
+// (at most 64) share one value: thread group g sums the chunk range
+// [g per, (g+1) per) and the G group sums are added in group order, so the
+// result is the same every run and the serial chain of dependent loads is G
+// times shorter (one problem of 480 x 240 in 512-element chunks has 225 rows).
 template <typename PT>
 __device__ void reduce_rows(const PlanDev& P, int blk0, int nblk, int nvals, double* red) {
   const PT* part = (const PT*)P.partial + (size_t)blk0 * P.NV;
-  for (int v = threadIdx.x; v < nvals; v += DD_BLOCK) {
+  __shared__ double grp[DD_BLOCK];
+  const int G = (nvals >= DD_BLOCK) ? 1 : min(64, DD_BLOCK / nvals);
+  const int per = (nblk + G - 1) / G;
+  for (int tv = threadIdx.x; tv < ((G == 1) ? nvals : G * nvals); tv += DD_BLOCK) {
+    const int v = (G == 1) ? tv : tv % nvals, g = (G == 1) ? 0 : tv / nvals;
+    const int c0 = g * per, c1 = min(nblk, c0 + per);
     double s = 0.0;
-    int c = 0;
-    for (; c + 16 <= nblk; c += 16) {
+    int c = c0;
+    for (; c + 16 <= c1; c += 16) {
       double a[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) a[q] = (double)part[(size_t)(c + q) * P.NV + v];
 #pragma unroll
       for (int q = 0; q < 16; ++q) s += a[q];
     }
-    for (; c < nblk; ++c) s += (double)part[(size_t)c * P.NV + v];
-    red[v] = s;
+    for (; c < c1; ++c) s += (double)part[(size_t)c * P.NV + v];
+    if (G == 1) red[v] = s;
+    else grp[tv] = s;
+  }
+  if (G > 1) {
+    __syncthreads();
+    for (int v = threadIdx.x; v < nvals; v += DD_BLOCK) {
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) s += grp[g * nvals + v];
+      red[v] = s;
+    }
   }
   __syncthreads();
 }
