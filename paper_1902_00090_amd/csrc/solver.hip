@@ -159,8 +159,9 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
   if (R == 0) {
     // Measured by dd_solver_autotune on MI355X over full GMRES(100) cycles of
     // 480 x 240 problems: one problem is fastest with 2 elements per thread
-    // (72 us/step vs 89-92 for 1 and 8), a batch of 64 with 8 (1.22 ms/step
-    // vs 1.47 for 1).  Large batches take 8, small ones 2.
+    // (60 us/step against 63-77 for 1, 4 and 8); a batch of 64 takes 1.13-1.15
+    // ms/step with 2, 4 or 8 against 1.35 with 1.  Large batches take 8 (the
+    // fewest partial rows per problem), small ones 2.
     long long nch8 = 0;
     for (int p = 0; p < nb; ++p) nch8 += (ops[p]->D + DD_BLOCK * 8 - 1) / (DD_BLOCK * 8);
     R = (nch8 >= 512) ? 8 : 2;
