@@ -236,12 +236,24 @@ def cnn_kernels_only(args, torch, W):
     e[3].record()
     torch.cuda.synchronize()
     fwd_ms, tr_ms = e[0].elapsed_time(e[1]) / n, e[2].elapsed_time(e[3]) / n
+    # residual-loss step: the operators and right-hand sides of the 32 images
+    from paper_1902_00090_amd import FdfdOp
+    ops = [FdfdOp.from_instance(i) for i in insts[:32]]
+    bs = [torch.tensor(i.b, dtype=torch.complex128, device="cuda") for i in insts[:32]]
+    net.train_step_res(e1, ops, bs, lr=1e-4, eim=e32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        net.train_step_res(e1, ops, bs, lr=1e-4, eim=e32)
+    torch.cuda.synchronize()
+    res_ms = (time.perf_counter() - t0) * 1e3 / n
     f1 = cnn_flops_per_instance(net)
     out = {"metric": "CNN predictor kernels, 480x240, 1 GPU",
            "forward_ms_batch64": round(fwd_ms, 3),
            "forward_tflops": round(f1 * B / (fwd_ms * 1e-3) / 1e12, 1),
            "train_step_ms_batch32": round(tr_ms, 3),
            "train_tflops_3x_forward": round(3 * f1 * 32 / (tr_ms * 1e-3) / 1e12, 1),
+           "train_step_res_ms_batch32": round(res_ms, 3),
            "bf16_dense_peak_tflops": 2500.0, "flop_per_instance_forward": f1, "reps": n,
            "input_planes": args.cnn_inputs}
     net.close()

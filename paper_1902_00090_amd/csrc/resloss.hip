@@ -14,8 +14,9 @@
 //
 // Kernels:
 //   * k_rl_apply: W = A V for all k vectors (the operator's stencil).
-//   * k_rl_resid: r = b - W c, with c solved on the host from the (k+1)^2
-//     FP64 Gram matrix of [W b] (gram_host).
+//   * k_rl_gram / k_rl_gram_reduce: the (k+1)^2 FP64 Gram matrix of [W b]
+//     of every problem; c is solved from it on the host.
+//   * k_rl_resid: r = b - W c.
 //   * k_rl_adjoint: s = A^H r, the transposed stencil, conjugated.
 //   * k_rl_dz: writes the CNN's last-layer gradient (bf16, NHWC).
 #include <algorithm>
@@ -24,7 +25,7 @@
 #include <vector>
 
 #include "common.h"
-#include "gram.h"
+#include "gram.h"   // chol_inv
 #include "op.h"
 #include "resloss.h"
 
@@ -112,6 +113,88 @@ __global__ __launch_bounds__(256) void k_rl_dz(const RlDesc* __restrict__ desc, 
   }
 }
 
+// Gram matrix G_ab = x_a^H x_b of [W b] (x_a = W_a for a < k, x_k = b) for
+// every problem at once, FP64 sums.  One workgroup per (element slice,
+// problem) stages chunks of GE elements of all k+1 vectors in LDS (element
+// major, so lanes holding consecutive b read consecutive words) and each
+// thread accumulates up to RL_MAXP of the (k+1)(k+2)/2 pairs a <= b in
+// registers: every vector is read from HBM once.  part: [problem][slice][pair].
+constexpr int RL_GE = 32;
+constexpr int RL_LD = 65;                       // k + 1 <= 65, odd stride
+constexpr int RL_MAXP = (65 * 66 / 2 + 255) / 256;
+
+__device__ __forceinline__ void rl_pair(int q, int K1, int& a, int& b) {
+  a = 0;
+  while (q >= K1 - a) { q -= K1 - a; ++a; }
+  b = a + q;
+}
+
+__global__ __launch_bounds__(256) void k_rl_gram(const RlDesc* __restrict__ desc, int k, int nslices,
+                                                 double2* __restrict__ part) {
+  __shared__ double2 xs[RL_GE * RL_LD];
+  const int K1 = k + 1, np = K1 * (K1 + 1) / 2, t = threadIdx.x;
+  const int slice = blockIdx.x, p = blockIdx.y;
+  const RlDesc d = desc[p];
+  const int per = ((d.D + nslices - 1) / nslices + RL_GE - 1) / RL_GE * RL_GE;
+  const int e0 = slice * per, e1 = min(d.D, e0 + per);
+  int pa[RL_MAXP], pb[RL_MAXP];
+  double sx[RL_MAXP], sy[RL_MAXP];
+#pragma unroll
+  for (int q = 0; q < RL_MAXP; ++q) {
+    pa[q] = pb[q] = 0;
+    if (q * 256 + t < np) rl_pair(q * 256 + t, K1, pa[q], pb[q]);
+    sx[q] = sy[q] = 0.0;
+  }
+  for (int c0 = e0; c0 < e1; c0 += RL_GE) {
+    __syncthreads();
+    for (int i = t; i < K1 * RL_GE; i += 256) {
+      const int v = i / RL_GE, el = i - v * RL_GE, e = c0 + el;
+      double2 x = make_double2(0.0, 0.0);
+      if (e < e1) {
+        if (v < k) {
+          const float2 w = d.W[(size_t)v * d.D + e];
+          x = make_double2(w.x, w.y);
+        } else {
+          x = d.b[e];
+        }
+      }
+      xs[el * RL_LD + v] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RL_MAXP; ++q) {
+      if (q * 256 + t < np) {
+        double ax = 0.0, ay = 0.0;
+        for (int el = 0; el < RL_GE; ++el) {
+          const double2 xa = xs[el * RL_LD + pa[q]], xb = xs[el * RL_LD + pb[q]];
+          ax += xa.x * xb.x + xa.y * xb.y;
+          ay += xa.x * xb.y - xa.y * xb.x;
+        }
+        sx[q] += ax;
+        sy[q] += ay;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RL_MAXP; ++q)
+    if (q * 256 + t < np)
+      part[((size_t)p * nslices + slice) * np + q * 256 + t] = make_double2(sx[q], sy[q]);
+}
+
+// Sum of the slice partials in slice order: out[problem][pair].
+__global__ __launch_bounds__(256) void k_rl_gram_reduce(const double2* __restrict__ part, int np,
+                                                        int nslices, double2* __restrict__ out) {
+  const int q = blockIdx.x * 256 + threadIdx.x, p = blockIdx.y;
+  if (q >= np) return;
+  double sx = 0.0, sy = 0.0;
+  for (int sl = 0; sl < nslices; ++sl) {
+    const double2 v = part[((size_t)p * nslices + sl) * np + q];
+    sx += v.x;
+    sy += v.y;
+  }
+  out[(size_t)p * np + q] = make_double2(sx, sy);
+}
+
 // Minimiser c and loss of one problem from the Gram matrix of [W b].
 bool solve_small(const std::vector<cd>& G, int k, std::vector<cd>& c, double& loss, double& bb) {
   const int K1 = k + 1;
@@ -171,10 +254,30 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
   k_rl_apply<<<dim3((maxD + 255) / 256, k, nb), 256, 0, st>>>(dd);
   DD_HIP_CHECK(hipGetLastError());
   std::vector<double2> hc((size_t)2 * nb * k, make_double2(0.0, 0.0));
+  // Gram matrices of [W b], all problems in one launch
+  const int K1 = k + 1, np = K1 * (K1 + 1) / 2;
+  int minD = maxD;
+  for (const auto& d : hd) minD = std::min(minD, d.D);
+  const int nslices = std::max(1, std::min({256, (2048 + nb - 1) / nb, minD / (8 * RL_GE)}));
+  double2* gp = nullptr;
+  const size_t ngp = (size_t)nb * nslices * np;
+  DD_HIP_CHECK(hipMalloc((void**)&gp, sizeof(double2) * (ngp + (size_t)nb * np)));
+  double2* gsum = gp + ngp;
+  k_rl_gram<<<dim3(nslices, nb), 256, 0, st>>>(dd, k, nslices, gp);
+  k_rl_gram_reduce<<<dim3((np + 255) / 256, nb), 256, 0, st>>>(gp, np, nslices, gsum);
+  DD_HIP_CHECK(hipGetLastError());
+  std::vector<double2> hg((size_t)nb * np);
+  DD_HIP_CHECK(hipMemcpyAsync(hg.data(), gsum, sizeof(double2) * hg.size(), hipMemcpyDeviceToHost, st));
+  DD_HIP_CHECK(hipStreamSynchronize(st));
+  DD_HIP_CHECK(hipFree(gp));
   for (int p = 0; p < nb; ++p) {
-    std::vector<cd> G, c;
-    dd_status rc = gram_host(hd[p].W, k, hd[p].D, hd[p].b, G, st);
-    if (rc != DD_OK) { (void)hipFree(dd); (void)hipFree(dc); return rc; }
+    std::vector<cd> G((size_t)K1 * K1, cd(0.0)), c;
+    for (int a = 0, q = 0; a < K1; ++a)
+      for (int b = a; b < K1; ++b, ++q) {
+        const double2 v = hg[(size_t)p * np + q];
+        G[(size_t)a * K1 + b] = cd(v.x, v.y);
+        G[(size_t)b * K1 + a] = cd(v.x, -v.y);
+      }
     double l = 1.0, bb = 0.0;
     solve_small(G, k, c, l, bb);
     loss[p] = l;
