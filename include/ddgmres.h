@@ -396,7 +396,9 @@ dd_status dd_cnn_grad_res(dd_cnn* net, const float* eps, const void* eim,
                           float* host_grad, size_t count, hipStream_t stream);
 
 /* Copy the bf16 activations of layer l's output (NHWC, as float32) to host.
- * layer = -1 gives the normalised input planes [B][in_channels][ny][nx].
+ * layer = -1 gives the normalised input planes [B][in_channels][ny][nx].  The
+ * last layer's FP32 output is read from where the last forward pass wrote it
+ * (the caller's U for a prediction, which must still be allocated).
  * For tests. */
 dd_status dd_cnn_debug_activation(const dd_cnn* net, int layer, int B, float* host_out,
                                   size_t count);

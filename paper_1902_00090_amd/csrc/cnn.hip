@@ -47,7 +47,7 @@ enum { MAP_S1 = 0, MAP_S2 = 1, MAP_UP = 2 };
 
 struct CnnLayer {
   int cin, cout, stride, up, relu;
-  int cinp, coutp;           // padded channel counts (multiples of 16; cin 1 stays 1)
+  int cinp, coutp;           // padded channel counts (32, 64 or 128; layer 1's cin stays 1 or 3)
   int Hin, Win, Hout, Wout;  // per-image grid sizes
   size_t woff, boff;         // offsets of weights / bias in the parameter vector
   int mode;                  // MAP_S1, MAP_S2 or MAP_UP
@@ -56,19 +56,23 @@ struct CnnLayer {
 struct dd_cnn {
   int nx, ny, maxB, k;
   int cin0;                  // input planes: 1 (permittivity) or 3 (+ effective-index field)
+  int ncu = 1;               // compute units of the device the network was created on
   CnnLayer L[NL];
   size_t nparams = 0;
   float *params = nullptr, *grads = nullptr, *am = nullptr, *av = nullptr;
   int adam_t = 0;
   bf16* wf[NL] = {};
   bf16* wb[NL] = {};
+  bf16* wu[NL] = {};         // upsampled layers: effective backward-data weights [16][cinp][coutp]
   float* x0 = nullptr;       // normalised input planes [B][cin0][H][W]
   double* iscale = nullptr;  // [maxB] effective-index field scale sqrt(D) / ||F||
+  double* espart = nullptr;  // [maxB][ES_SLICES] partial sums of |F|^2
   // residual-loss scratch (allocated on first use): V = output fields, W = A V,
   // r = b - W c, s = A^H r
-  float2 *rl_V = nullptr, *rl_W = nullptr, *rl_r = nullptr, *rl_s = nullptr;
+  float2 *rl_W = nullptr, *rl_r = nullptr, *rl_s = nullptr;
   bf16* act[NL] = {};        // act[l] = output of layer l (l < NL-1), NHWC bf16
-  float* out = nullptr;      // last layer output [B][H][W][2k]
+  float* out = nullptr;      // last layer output: complex fields [B][k][D] (FP32 pairs)
+  const float* last_fields = nullptr;   // where the last forward pass wrote its fields
   bf16* dz[NL] = {};         // gradient w.r.t. the pre-activation of layer l
   float* wpart = nullptr;    // split partial weight gradients
   size_t wpart_elems = 0;
@@ -104,26 +108,30 @@ __device__ __forceinline__ bool fwd_src(int mode, int y, int x, int dy, int dx, 
 }
 
 // Backward-data gather: for layer-input pixel (y, x) and entry e, the layer-
-// output pixel whose gradient reaches it through tap e % 9 (for upsampled
-// layers e / 9 picks one of the four upsampled positions of (y, x)).
+// output pixel whose gradient reaches it through weight tap `tap`.
+//  * stride 1 and 2: tap e (one of the nine);
+//  * upsampled layers: the gradient of the x2 nearest upsample sums the four
+//    upsampled positions (2y + sy, 2x + sx), each seen by nine taps; grouped by
+//    the dz offset (oy, ox) = (sy - dy + 1, sx - dx + 1) in -1..2 these are 16
+//    entries e = 4 (oy + 1) + (ox + 1) reading dz at (2y + oy, 2x + ox) with an
+//    effective weight summed over the taps of that offset (k_pack_up_weights).
 __device__ __forceinline__ bool bwd_src(int mode, int e, int y, int x, int Hout, int Wout,
                                         int& py, int& px, int& tap) {
-  tap = e % 9;
+  if (mode == MAP_UP) {
+    tap = e;
+    py = 2 * y + e / 4 - 1; px = 2 * x + e % 4 - 1;
+    return py >= 0 && py < Hout && px >= 0 && px < Wout;
+  }
+  tap = e;
   const int dy = tap / 3, dx = tap % 3;
   if (mode == MAP_S1) {
     py = y - dy + 1; px = x - dx + 1;
     return py >= 0 && py < Hout && px >= 0 && px < Wout;
-  } else if (mode == MAP_S2) {
-    const int ty = y - dy + 1, tx = x - dx + 1;
-    if (ty < 0 || tx < 0 || (ty & 1) || (tx & 1)) return false;
-    py = ty >> 1; px = tx >> 1;
-    return py < Hout && px < Wout;
-  } else {
-    const int s = e / 9;
-    const int uy = 2 * y + (s >> 1), ux = 2 * x + (s & 1);
-    py = uy - dy + 1; px = ux - dx + 1;
-    return py >= 0 && py < Hout && px >= 0 && px < Wout;
   }
+  const int ty = y - dy + 1, tx = x - dx + 1;   // MAP_S2
+  if (ty < 0 || tx < 0 || (ty & 1) || (tx & 1)) return false;
+  py = ty >> 1; px = tx >> 1;
+  return py < Hout && px < Wout;
 }
 
 // ------------------------------------------------- implicit GEMM (MFMA) ----
@@ -139,8 +147,8 @@ struct GemmArgs {
   const float* bias;     // forward only
   const bf16* mask;      // backward: layer input activations (ReLU mask)
   bf16* out;             // bf16 result (NHWC, M channels)
-  float* outf;           // final layer: FP32 result with nreal channels
-  int nreal;             // channels of outf
+  float* outf;           // final layer: complex fields [B][nreal / 2][Hq Wq] (FP32 pairs)
+  int nreal;             // real channels of the final layer (2 k)
   int B, Hq, Wq;         // grid of the result pixels
   int Hs, Ws;            // grid of the source pixels
   int Hout, Wout;        // layer output grid (for the map functions)
@@ -148,6 +156,19 @@ struct GemmArgs {
   int M;                 // result channels (= 16 MT)
   int mode, entries, relu;
 };
+
+// Final-layer epilogue: channels r0..r0+3 of pixel e of image b are (Re, Im)
+// of fields r0 / 2 and r0 / 2 + 1; they go to the complex field layout
+// [B][kf][D] (16 lanes with consecutive pixels write 128 contiguous bytes).
+__device__ __forceinline__ void store_fields(float* outf, int kf, int D, int b, int e, int r0,
+                                             const float* v) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = r0 / 2 + h;
+    if (j < kf)
+      *(float2*)(outf + (((size_t)b * kf + j) * D + e) * 2) = make_float2(v[2 * h], v[2 * h + 1]);
+  }
+}
 
 template <int MT, int NT, bool BWD>
 __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
@@ -187,7 +208,7 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
       }
       if (ok) srcp[j] = a.src + ((size_t)(pb[j] * a.Hs + sy) * a.Ws + sx) * a.Ksrc;
     }
-    if (BWD) tap = e % 9;
+    if (BWD) tap = e;   // same for every lane (bwd_src)
     const bf16* wt = a.W + (size_t)tap * a.M * a.Ksrc;
     for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
       bf16x8 bv[NT];
@@ -226,16 +247,88 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
           if (!(bf2f(mk[q]) > 0.f)) v[q] = 0.f;
       }
       if (a.outf) {
-        float* o = a.outf + (size_t)p * a.nreal + r0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (r0 + q < a.nreal) o[q] = v[q];
+        const int D = a.Hq * a.Wq, b = p / D;
+        store_fields(a.outf, a.nreal / 2, D, b, p - b * D, r0, v);
       } else {
         bf16 h[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) h[q] = (bf16)v[q];
         *(u32x2*)(a.out + (size_t)p * a.M + r0) = __builtin_bit_cast(u32x2, h);
       }
+    }
+  }
+}
+
+// Backward data of the stride-2 layers.  A layer-input pixel (y, x) receives
+// dz only through the taps with y + 1 - dy and x + 1 - dx even: one tap per
+// dimension at even y (x), two at odd.  A wave takes NT tiles of 16 pixels of
+// one row and one column parity (x = 2 xh + par), so its tap set is uniform
+// and only those 1, 2 or 4 taps are applied (instead of all nine with most
+// gathers masked).  Layouts, weights and the ReLU mask are k_conv_gemm's.
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_bwd_s2(GemmArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int Wh = (a.Wq + 1) / 2, ngr = ((Wh + 15) / 16 + NT - 1) / NT;   // x-tiles per parity
+  const int nitems = a.B * a.Hq * 2 * ngr;
+  const int item = blockIdx.x * 4 + wave;
+  if (item >= nitems) return;   // no barriers below
+  const int g = item % ngr, par = (item / ngr) & 1, row = item / (2 * ngr);
+  const int y = row % a.Hq, b = row / a.Hq;
+  int xs[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int xh = (g * NT + j) * 16 + (lane & 15);
+    xs[j] = (2 * xh + par < a.Wq) ? 2 * xh + par : -1;
+  }
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kq = 8 * (lane >> 4);
+  const int dy0 = (y & 1) ? 0 : 1, ndy = (y & 1) ? 2 : 1;
+  const int dx0 = par ? 0 : 1, ndx = par ? 2 : 1;
+  for (int iy = 0; iy < ndy; ++iy) {
+    const int dy = dy0 + 2 * iy, ty = y + 1 - dy;
+    if (ty < 0 || (ty >> 1) >= a.Hs) continue;
+    const int py = ty >> 1;
+    for (int ix = 0; ix < ndx; ++ix) {
+      const int dx = dx0 + 2 * ix, tap = 3 * dy + dx;
+      const bf16* srcp[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int tx = xs[j] + 1 - dx;
+        srcp[j] = (xs[j] >= 0 && tx >= 0 && (tx >> 1) < a.Ws)
+                      ? a.src + ((size_t)(b * a.Hs + py) * a.Ws + (tx >> 1)) * a.Ksrc
+                      : nullptr;
+      }
+      const bf16* wt = a.W + (size_t)tap * a.M * a.Ksrc;
+      for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
+        bf16x8 bv[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bv[j] = srcp[j] ? load8(srcp[j] + c0 + kq) : zero8();
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+          const bf16x8 av = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc + c0 + kq);
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    if (xs[j] < 0) continue;
+    const size_t p = ((size_t)b * a.Hq + y) * a.Wq + xs[j];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const int r0 = i * 16 + 4 * (lane >> 4);
+      const bf16* mk = a.mask + p * a.M + r0;
+      bf16 h[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = (bf16)((bf2f(mk[q]) > 0.f) ? acc[i][j][q] : 0.f);
+      *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
     }
   }
 }
@@ -323,10 +416,7 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
         }
       }
       if (!BWD && a.outf) {
-        float* o = a.outf + p * a.nreal + r0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (r0 + q < a.nreal) o[q] = v[q];
+        store_fields(a.outf, a.nreal / 2, Hq * Wq, b, y * Wq + x, r0, v);
       } else {
         bf16 h[4];
 #pragma unroll
@@ -338,8 +428,10 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
 }
 
 // ------------------------------------------------------------- layer 1 ----
-// Cin = 1 or 3 input planes: direct FP32 arithmetic (9 taps per plane), 32
-// output channels per pixel.  x0 is planar [B][C][H][W].
+// Cin = 1 or 3 input planes: direct FP32 arithmetic (9 taps per plane), one
+// thread per pixel for all output channels (the weights are then uniform
+// across the wave and come through the scalar cache); 16-byte stores of 8
+// channels.  x0 is planar [B][C][H][W].
 __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
                                                    const float* __restrict__ w,
                                                    const float* __restrict__ bias, int B, int C,
@@ -357,9 +449,10 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
       xin[c][t] = (c < C && ys >= 0 && ys < H && xs >= 0 && xs < W)
                       ? x0[(((size_t)b * C + c) * H + ys) * W + xs] : 0.f;
     }
-  for (int co = 0; co < coutp; co += 4) {
-    bf16 h[4];
-    for (int q = 0; q < 4; ++q) {
+  for (int co = 0; co < coutp; co += 8) {
+    bf16x8 h;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
       float s = bias[co + q];
       const float* wr = w + (size_t)(co + q) * C * 9;
 #pragma unroll
@@ -369,7 +462,7 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
           for (int t = 0; t < 9; ++t) s += wr[c * 9 + t] * xin[c][t];
       h[q] = (bf16)fmaxf(s, 0.f);
     }
-    *(u32x2*)(out + (size_t)p * coutp + co) = __builtin_bit_cast(u32x2, h);
+    *(u32x4*)(out + (size_t)p * coutp + co) = __builtin_bit_cast(u32x4, h);
   }
 }
 
@@ -408,156 +501,155 @@ __global__ __launch_bounds__(1024) void k_conv1_wgrad(const float* __restrict__ 
 }
 
 // --------------------------------------------------- weight gradients ----
-// dW[tap][r][c] = sum_p dz[p][r] * x[map(p, tap)][c] for one tap (grid.y) and
-// a slice of output pixels (grid.x); dz and x tiles of 32 pixels are staged
-// transposed in LDS so that MFMA operands are 16-byte reads.  r < Mr (coutp),
-// c < Nc (cinp); C tiles (Mr/16 x Nc/16) are split over the 4 waves.
-#define WG_MAXC 128
-__global__ __launch_bounds__(256) void k_conv_wgrad(const bf16* __restrict__ dz,
-                                                    const bf16* __restrict__ x, int B,
-                                                    int Hout, int Wout, int Hin, int Win,
-                                                    int Mr, int Nc, int mode, int per,
-                                                    float* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) bf16 As[WG_MAXC][40];  // [r][pixel], padded rows
-  __shared__ __attribute__((aligned(16))) bf16 Bs[WG_MAXC][40];  // [c][pixel]
-  const int tap = blockIdx.y, dy = tap / 3, dx = tap % 3;
+// Weight gradients of a 3x3 layer of any map (stride 1, stride 2, upsampling)
+// as GEMMs over stages of 32 S consecutive output pixels (flattened b, y, x
+// order; the last stage is ragged).  Work items: (pixel slice, channel block
+// of NB = 16 NT input channels, dy), dy fastest.  Per stage the workgroup
+// stages in LDS,
+// transposed to [channel][pixel]:
+//  * dz of the stage, all Mr = 16 MT output channels;
+//  * for the three taps (dy, 0..2), the layer input at each pixel's source,
+//    NB channels from channel n0.
+// A staging block is 8 pixels x 8 channels: loaded with 16-byte reads,
+// transposed in registers, stored with 16-byte writes.  The next stage's
+// blocks are loaded while the current stage's MFMAs run.  Partials:
+// weights [slice][tap][r][c], bias [slice][r].
+template <int MT, int NT, int S>
+__global__ __launch_bounds__(256) void k_conv_wgrad_seg(const bf16* __restrict__ dz,
+                                                        const bf16* __restrict__ x, int B,
+                                                        int Hout, int Wout, int Hin, int Win,
+                                                        int Nc, int mode, int stages_per,
+                                                        int nwork, float* __restrict__ part,
+                                                        float* __restrict__ bpart) {
+  constexpr int Mr = 16 * MT, NB = 16 * NT, PX = 32 * S, LD = PX + 8;
+  constexpr int ABLK = (PX / 8) * (Mr / 8);         // dz blocks of a stage
+  constexpr int XBLK = 3 * (PX / 8) * (NB / 8);     // input blocks of a stage (3 taps)
+  constexpr int NBLK = ABLK + XBLK, BPT = (NBLK + 255) / 256;
+  constexpr int NTILE = 3 * MT * NT, PER_WAVE = (NTILE + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16 As[Mr][LD];
+  __shared__ __attribute__((aligned(16))) bf16 Xs[3][NB][LD];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int npix = B * Hout * Wout;
-  const int p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
-  const int tr = Mr / 16, tc = Nc / 16, ntiles = tr * tc;
-  constexpr int MAXT = (WG_MAXC / 16) * (WG_MAXC / 16) / 4;
-  f32x4 acc[MAXT];
-  for (int i = 0; i < MAXT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int pc = p0; pc < p1; pc += 32) {
-    __syncthreads();
-    // stage 32 pixels: dz rows (Mr channels) and x at the tap's source pixel
-    for (int idx = threadIdx.x; idx < 32 * (Mr / 8); idx += 256) {
-      const int pp = idx / (Mr / 8), cg = (idx % (Mr / 8)) * 8;
-      const int p = pc + pp;
-      bf16x8 v = zero8();
-      if (p < p1) v = load8(dz + (size_t)p * Mr + cg);
+  // 1D grid, a multiple of 8 long: consecutive work items (the three dy and
+  // the channel blocks of one pixel slice) go to the same XCD, whose L2 then
+  // serves their shared dz and input rows.
+  const int w = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (w >= nwork) return;
+  const int nblk = Nc / NB;
+  const int dy = w % 3, n0 = ((w / 3) % nblk) * NB, slice = w / (3 * nblk);
+  const int HW = Hout * Wout, npix = B * HW, nst = (npix + PX - 1) / PX;
+  const int s0 = slice * stages_per, s1 = min(nst, s0 + stages_per);
+  bf16x8 reg[BPT][8];
+  auto load = [&](int sg) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) As[cg + q][pp] = v[q];
-    }
-    for (int idx = threadIdx.x; idx < 32 * (Nc / 8); idx += 256) {
-      const int pp = idx / (Nc / 8), cg = (idx % (Nc / 8)) * 8;
-      const int p = pc + pp;
-      bf16x8 v = zero8();
-      if (p < p1) {
-        const int b = p / (Hout * Wout), rem = p - b * Hout * Wout;
-        const int y = rem / Wout, xx = rem - (rem / Wout) * Wout;
-        int ys, xs;
-        if (fwd_src(mode, y, xx, dy, dx, Hin, Win, Hout, Wout, ys, xs))
-          v = load8(x + ((size_t)(b * Hin + ys) * Win + xs) * Nc + cg);
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      const bool isA = blk < ABLK;
+      int pg, cg, dx = 0;
+      if (isA) {
+        pg = blk / (Mr / 8); cg = (blk % (Mr / 8)) * 8;
+      } else {
+        const int r = blk - ABLK, r2 = r % ((PX / 8) * (NB / 8));
+        dx = r / ((PX / 8) * (NB / 8)); pg = r2 / (NB / 8); cg = (r2 % (NB / 8)) * 8;
       }
+      int p = sg * PX + pg * 8;
+      int b = p / HW, rem = p - b * HW, y = rem / Wout, xx = rem - y * Wout;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) Bs[cg + q][pp] = v[q];
-    }
-    __syncthreads();
-    const int kq = 8 * (lane >> 4);
-#pragma unroll
-    for (int i = 0; i < MAXT; ++i) {
-      const int t = wave + 4 * i;
-      if (t < ntiles) {
-        const int ti = t / tc, tj = t % tc;
-        const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kq];
-        const bf16x8 bv = *(const bf16x8*)&Bs[tj * 16 + (lane & 15)][kq];
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+      for (int i = 0; i < 8; ++i) {
+        bf16x8 v = zero8();
+        if (blk < NBLK && p < npix) {
+          if (isA) {
+            v = load8(dz + (size_t)p * Mr + cg);
+          } else {
+            int ys, xs;
+            if (fwd_src(mode, y, xx, dy, dx, Hin, Win, Hout, Wout, ys, xs))
+              v = load8(x + ((size_t)(b * Hin + ys) * Win + xs) * Nc + n0 + cg);
+          }
+        }
+        reg[bi][i] = v;
+        ++p;
+        if (++xx == Wout) { xx = 0; if (++y == Hout) { y = 0; ++b; } }
       }
     }
-  }
-  // partial layout [slice][tap][r][c]
-  float* out = part + (((size_t)blockIdx.x * 9 + tap) * Mr) * Nc;
-#pragma unroll
-  for (int i = 0; i < MAXT; ++i) {
-    const int t = wave + 4 * i;
-    if (t < ntiles) {
-      const int ti = t / tc, tj = t % tc;
-      const int c = tj * 16 + (lane & 15);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[i][q];
-    }
-  }
-}
-
-// Weight gradients of the stride-1 and upsampling layers whose output rows are
-// whole multiples of 32 pixels, all nine taps per workgroup.  A workgroup walks
-// row segments of 32 output pixels.  Per segment it stages, transposed in LDS:
-//  * dz of the segment once, [r][pixel];
-//  * the three source rows of the conv input, each in three copies shifted by
-//    one column, so that every tap reads its x operand at the same 16-byte
-//    aligned offsets.
-// It then issues the 9 (Mr/16)(Nc/16) MFMA tiles of the segment, spread over
-// the four waves.  Compared with one workgroup per tap, dz is staged once
-// instead of nine times, a source row is fetched once for three taps, and there
-// are nine times as many products per barrier.  Partials use k_conv_wgrad's
-// [slice][tap][r][c] layout.
-#define WR_MR 32
-#define WR_NC 64
-template <int MT, int NT>
-__global__ __launch_bounds__(256) void k_conv_wgrad_rows(const bf16* __restrict__ dz,
-                                                         const bf16* __restrict__ x, int B,
-                                                         int Hout, int Wout, int Hin, int Win,
-                                                         int mode, int segs_per,
-                                                         float* __restrict__ part) {
-  constexpr int Mr = 16 * MT, Nc = 16 * NT, NTILE = 9 * MT * NT, PER_WAVE = (NTILE + 3) / 4;
-  __shared__ __attribute__((aligned(16))) bf16 As[WR_MR][40];
-  __shared__ __attribute__((aligned(16))) bf16 Xs[9][WR_NC][40];   // [3 dy * 3 dx][c][pixel]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int W32 = Wout / 32;
-  const int nseg = B * Hout * W32;
-  const int s0 = blockIdx.x * segs_per, s1 = min(nseg, s0 + segs_per);
-  const bool up = (mode == MAP_UP);
+  };
   f32x4 acc[PER_WAVE];
 #pragma unroll
   for (int i = 0; i < PER_WAVE; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the slice's (dy 0, first channel block) item also sums dz over its pixels
+  // (the bias gradient) as dz^T times a column of ones
+  constexpr int BT = (MT + 3) / 4;
+  const bool bias = (dy == 0 && n0 == 0);
+  f32x4 accb[BT];
+#pragma unroll
+  for (int i = 0; i < BT; ++i) accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.f;
   const int kq = 8 * (lane >> 4);
+  if (s0 < s1) load(s0);
   for (int sg = s0; sg < s1; ++sg) {
-    const int b = sg / (Hout * W32), rem = sg - b * Hout * W32;
-    const int y = rem / W32, x0 = (rem - y * W32) * 32;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 32 * (Mr / 8); idx += 256) {
-      const int pp = idx / (Mr / 8), cg = (idx % (Mr / 8)) * 8;
-      const bf16x8 v = load8(dz + (((size_t)b * Hout + y) * Wout + x0 + pp) * Mr + cg);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) As[cg + q][pp] = v[q];
-    }
-    for (int idx = threadIdx.x; idx < 3 * 34 * (Nc / 8); idx += 256) {
-      const int dy = idx / (34 * (Nc / 8)), r2 = idx - dy * 34 * (Nc / 8);
-      const int j = r2 / (Nc / 8), cg = (r2 % (Nc / 8)) * 8;
-      const int uy = y + dy - 1, ux = x0 + j - 1;   // conv-input grid (= output grid)
-      bf16x8 v = zero8();
-      if (uy >= 0 && uy < Hout && ux >= 0 && ux < Wout) {
-        const int sy = up ? (uy >> 1) : uy, sx = up ? (ux >> 1) : ux;
-        v = load8(x + (((size_t)b * Hin + sy) * Win + sx) * Nc + cg);
-      }
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      if (blk < NBLK) {
+        bf16* dst;
+        if (blk < ABLK) {
+          dst = &As[(blk % (Mr / 8)) * 8][(blk / (Mr / 8)) * 8];
+        } else {
+          const int r = blk - ABLK, r2 = r % ((PX / 8) * (NB / 8));
+          dst = &Xs[r / ((PX / 8) * (NB / 8))][(r2 % (NB / 8)) * 8][(r2 / (NB / 8)) * 8];
+        }
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int k = j - dx;   // this value is pixel k of tap (dy, dx)
-        if (k >= 0 && k < 32) {
+        for (int q = 0; q < 8; ++q) {
+          bf16x8 w;
 #pragma unroll
-          for (int q = 0; q < 8; ++q) Xs[dy * 3 + dx][cg + q][k] = v[q];
+          for (int i = 0; i < 8; ++i) w[i] = reg[bi][i][q];
+          *(bf16x8*)(dst + q * LD) = w;
         }
       }
     }
     __syncthreads();
+    if (sg + 1 < s1) load(sg + 1);
 #pragma unroll
-    for (int i = 0; i < PER_WAVE; ++i) {
-      const int t = wave + 4 * i;
-      if (t < NTILE) {
-        const int tap = t / (MT * NT), rr = t - tap * MT * NT, ti = rr / NT, tj = rr - ti * NT;
-        const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kq];
-        const bf16x8 bv = *(const bf16x8*)&Xs[tap][tj * 16 + (lane & 15)][kq];
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+    for (int kk = 0; kk < S; ++kk) {
+#pragma unroll
+      for (int i = 0; i < PER_WAVE; ++i) {
+        const int tt = wave + 4 * i;
+        if (tt < NTILE) {
+          const int tdx = tt / (MT * NT), rr = tt - tdx * MT * NT, ti = rr / NT, tj = rr - ti * NT;
+          const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
+          const bf16x8 bv = *(const bf16x8*)&Xs[tdx][tj * 16 + (lane & 15)][kk * 32 + kq];
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+        }
+      }
+      if (bias) {
+#pragma unroll
+        for (int i = 0; i < BT; ++i) {
+          const int ti = wave + 4 * i;
+          if (ti < MT) {
+            const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
+            accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb[i], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  if (bias) {
+#pragma unroll
+    for (int i = 0; i < BT; ++i) {
+      const int ti = wave + 4 * i;
+      if (ti < MT && (lane & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bpart[(size_t)slice * Mr + ti * 16 + 4 * (lane >> 4) + q] = accb[i][q];
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < PER_WAVE; ++i) {
-    const int t = wave + 4 * i;
-    if (t < NTILE) {
-      const int tap = t / (MT * NT), rr = t - tap * MT * NT, ti = rr / NT, tj = rr - ti * NT;
-      float* out = part + (((size_t)blockIdx.x * 9 + tap) * Mr) * Nc;
+    const int tt = wave + 4 * i;
+    if (tt < NTILE) {
+      const int tdx = tt / (MT * NT), rr = tt - tdx * MT * NT, ti = rr / NT, tj = rr - ti * NT;
+      float* out = part + (((size_t)slice * 9 + dy * 3 + tdx) * Mr) * Nc + n0;
       const int c = tj * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[i][q];
@@ -617,65 +709,65 @@ __global__ __launch_bounds__(256) void k_conv1_wgrad_rows(const float* __restric
   for (int q = 0; q < 4; ++q) out[(ti * 16 + 4 * (lane >> 4) + q) * 32 + tj * 16 + (lane & 15)] = acc[q];
 }
 
-// Sum the [slice][32][32] partials of k_conv1_wgrad_rows in slice order.
-__global__ void k_conv1_rows_reduce(const float* __restrict__ part, int nslices, int cout, int C,
-                                    float* __restrict__ gw, float* __restrict__ gb) {
-  const int J = 9 * C;
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= cout * (J + 1)) return;
-  const int co = t / (J + 1), j = t % (J + 1);
+// Sum over slices of [slice][nent] partials for 16 consecutive entries per
+// workgroup: 16 slice groups (slices g, g + 16, ...) added in group order.
+__device__ __forceinline__ float slice_sum16(const float* __restrict__ part, int nslices, int nent,
+                                             int ent, float (*red)[16]) {
+  const int j = threadIdx.x & 15, grp = threadIdx.x >> 4;
   float s = 0.f;
-  for (int sl = 0; sl < nslices; ++sl) s += part[((size_t)sl * 32 + co) * 32 + j];
-  if (j < J) gw[(size_t)co * J + j] = s;
-  else gb[co] = s;
+  if (ent < nent)
+    for (int sl = grp; sl < nslices; sl += 16) s += part[(size_t)sl * nent + ent];
+  red[grp][j] = s;
+  __syncthreads();
+  float t = 0.f;
+  if (grp == 0)
+    for (int g = 0; g < 16; ++g) t += red[g][j];
+  return t;
 }
 
-// Bias-gradient partials: column sums of dz over a pixel slice.  Thread t
-// handles channel t % Mr of pixels p0 + t / Mr + j * (256 / Mr), so a wave's
-// loads cover whole pixel rows (coalesced); the 256 / Mr lanes of a channel
-// are then added in a fixed order.
-__global__ __launch_bounds__(256) void k_bias_grad(const bf16* __restrict__ dz, int npix, int Mr,
-                                                   int per, float* __restrict__ part) {
-  // thread = (pixel lane g, group of 8 channels cg): 16-byte loads, G pixels
-  // per round; Mr is a multiple of 16
-  __shared__ float red[256 * 8];
-  const int p0 = blockIdx.x * per, p1 = min(npix, p0 + per);
-  const int CG = Mr / 8, G = 256 / CG, cg = threadIdx.x % CG, g = threadIdx.x / CG;
-  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (g < G)
-    for (int p = p0 + g; p < p1; p += G) {
-      const bf16x8 v = load8(dz + (size_t)p * Mr + 8 * cg);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s[q] += (float)v[q];
-    }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) red[threadIdx.x * 8 + q] = s[q];
-  __syncthreads();
-  if (threadIdx.x < Mr) {
-    const int c = threadIdx.x, cgc = c / 8, q = c % 8;
-    float t = 0.f;
-    for (int gg = 0; gg < G; ++gg) t += red[(gg * CG + cgc) * 8 + q];
-    part[(size_t)blockIdx.x * Mr + c] = t;
+// Sum the [slice][32][32] partials of k_conv1_wgrad_rows (16 entries per block).
+__global__ __launch_bounds__(256) void k_conv1_rows_reduce(const float* __restrict__ part,
+                                                           int nslices, int cout, int C,
+                                                           float* __restrict__ gw,
+                                                           float* __restrict__ gb) {
+  __shared__ float red[16][16];
+  const int J = 9 * C;
+  const int ent = blockIdx.x * 16 + (threadIdx.x & 15);
+  const float s = slice_sum16(part, nslices, 32 * 32, ent, red);
+  const int co = ent / 32, j = ent % 32;
+  if ((threadIdx.x >> 4) == 0 && co < cout && j <= J) {
+    if (j < J) gw[(size_t)co * J + j] = s;
+    else gb[co] = s;
   }
 }
 
-// Sum the slices (fixed order) into the FP32 gradient in [cout][cin][3][3] order.
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int nslices, int Mr, int Nc,
-                               int cout, int cin, float* __restrict__ g) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= cout * cin * 9) return;
-  const int co = idx / (cin * 9), rem = idx % (cin * 9), ci = rem / 9, tap = rem % 9;
+// Sum the slices (fixed order) into the FP32 gradient in [cout][cin][3][3]
+// order.  A workgroup takes 64 consecutive partial entries ([tap][r][c]
+// order, coalesced reads) and four slice groups (slices g, g + 4, ...), which
+// are then added in group order.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nslices,
+                                                      int Mr, int Nc, int cout, int cin,
+                                                      float* __restrict__ g) {
+  __shared__ float red[4][64];
+  const int j = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int ent = blockIdx.x * 64 + j, nent = 9 * Mr * Nc;
   float s = 0.f;
-  for (int sl = 0; sl < nslices; ++sl) s += part[(((size_t)sl * 9 + tap) * Mr + co) * Nc + ci];
-  g[idx] = s;
+  if (ent < nent)
+    for (int sl = grp; sl < nslices; sl += 4) s += part[(size_t)sl * nent + ent];
+  red[grp][j] = s;
+  __syncthreads();
+  if (grp == 0 && ent < nent) {
+    const int tap = ent / (Mr * Nc), rem = ent - tap * Mr * Nc, co = rem / Nc, ci = rem - co * Nc;
+    if (co < cout && ci < cin)
+      g[((size_t)co * cin + ci) * 9 + tap] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+  }
 }
-__global__ void k_bgrad_reduce(const float* __restrict__ part, int nslices, int Mr, int cout,
-                               float* __restrict__ g) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= cout) return;
-  float s = 0.f;
-  for (int sl = 0; sl < nslices; ++sl) s += part[(size_t)sl * Mr + r];
-  g[r] = s;
+__global__ __launch_bounds__(256) void k_bgrad_reduce(const float* __restrict__ part, int nslices,
+                                                      int Mr, int cout, float* __restrict__ g) {
+  __shared__ float red[16][16];
+  const int r = blockIdx.x * 16 + (threadIdx.x & 15);
+  const float s = slice_sum16(part, nslices, Mr, r, red);
+  if ((threadIdx.x >> 4) == 0 && r < cout) g[r] = s;
 }
 __global__ void k_conv1_reduce(const float* __restrict__ part, int nslices, int cout, int C,
                                float* __restrict__ gw, float* __restrict__ gb) {
@@ -708,59 +800,66 @@ __global__ void k_inputs(const float* __restrict__ eps, const float2* __restrict
   }
 }
 
-// iscale[b] = sqrt(D / sum |F_b|^2) (0 for an all-zero field); one block per problem
-__global__ __launch_bounds__(256) void k_eim_scale(const float2* __restrict__ eim, int D,
-                                                   double* __restrict__ iscale) {
-  const float2* f = eim + (size_t)blockIdx.x * D;
+// iscale[b] = sqrt(D / sum |F_b|^2) (0 for an all-zero field), in two steps:
+// ES_SLICES partial sums per problem (grid (ES_SLICES, B)), then their sum in
+// slice order.
+#define ES_SLICES 64
+__global__ __launch_bounds__(256) void k_eim_scale_part(const float2* __restrict__ eim, int D,
+                                                        double* __restrict__ part) {
+  const float2* f = eim + (size_t)blockIdx.y * D;
+  const int per = (D + ES_SLICES - 1) / ES_SLICES, e0 = blockIdx.x * per, e1 = min(D, e0 + per);
   double s = 0.0;
-  for (int e = threadIdx.x; e < D; e += 256) s += (double)f[e].x * f[e].x + (double)f[e].y * f[e].y;
+  for (int e = e0 + threadIdx.x; e < e1; e += 256) {
+    const float2 v = f[e];
+    s += (double)v.x * v.x + (double)v.y * v.y;
+  }
   __shared__ double lds[8];
   s = block_sum1<double>(s, lds);
-  if (threadIdx.x == 0) iscale[blockIdx.x] = (s > 0.0) ? sqrt((double)D / s) : 0.0;
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * ES_SLICES + blockIdx.x] = s;
+}
+__global__ void k_eim_scale(const double* __restrict__ part, int B, int D,
+                            double* __restrict__ iscale) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  double s = 0.0;
+  for (int i = 0; i < ES_SLICES; ++i) s += part[(size_t)b * ES_SLICES + i];
+  iscale[b] = (s > 0.0) ? sqrt((double)D / s) : 0.0;
 }
 
-// loss partials and dz of the last (linear) layer: out [p][2k] FP32, target
-// [B][k][D] complex64; dz = 2 (out - t) / count in bf16 with coutp channels.
+// loss partials and dz of the last (linear) layer: out and target are complex
+// fields [B][k][D]; dz = 2 (out - t) / count in bf16 with coutp channels.
+// One thread per (pixel, group of 8 channels) (coutp is a multiple of 32), so
+// that a pixel's dz row is written by consecutive threads 16 B at a time.
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out,
                                              const float2* __restrict__ target, int B, int D,
                                              int k, int coutp, float scale,
                                              bf16* __restrict__ dz, float* __restrict__ lpart) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int CG = coutp / 8;
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
   float s = 0.f;
-  if (p < B * D) {
+  if (t < (long)B * D * CG) {
+    const int p = (int)(t / CG), c0 = (int)(t - (long)p * CG) * 8;
     const int b = p / D, e = p - b * D;
-    const float* o = out + (size_t)p * 2 * k;
-    // coutp is a multiple of 16: the row of dz is written 8 channels (16 B) at a time
-    for (int c0 = 0; c0 < coutp; c0 += 8) {
-      bf16x8 h;
+    const float2* o = (const float2*)out + (size_t)b * k * D + e;   // field j at o[j D]
+    bf16x8 h;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int c = c0 + q;
-        float g = 0.f;
-        if (c < 2 * k) {
-          const float2 t = target[((size_t)b * k + c / 2) * D + e];
-          const float d = o[c] - ((c & 1) ? t.y : t.x);
-          s += d * d;
-          g = scale * d;
-        }
-        h[q] = (bf16)g;
+    for (int q = 0; q < 4; ++q) {
+      const int j = c0 / 2 + q;
+      float gx = 0.f, gy = 0.f;
+      if (j < k) {
+        const float2 v = o[(size_t)j * D], tv = target[((size_t)b * k + j) * D + e];
+        const float dx = v.x - tv.x, dy = v.y - tv.y;
+        s += dx * dx + dy * dy;
+        gx = scale * dx; gy = scale * dy;
       }
-      *(u32x4*)(dz + (size_t)p * coutp + c0) = __builtin_bit_cast(u32x4, h);
+      h[2 * q] = (bf16)gx;
+      h[2 * q + 1] = (bf16)gy;
     }
+    *(u32x4*)(dz + (size_t)p * coutp + c0) = __builtin_bit_cast(u32x4, h);
   }
   __shared__ float lds[8];
   s = block_sum1<float>(s, lds);
   if (threadIdx.x == 0) lpart[blockIdx.x] = s;
-}
-
-__global__ void k_to_fields(const float* __restrict__ out, int B, int D, int k,
-                            float2* __restrict__ U) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= B * D) return;
-  const int b = p / D, e = p - b * D;
-  for (int j = 0; j < k; ++j)
-    U[((size_t)b * k + j) * D + e] = make_float2(out[(size_t)p * 2 * k + 2 * j],
-                                                  out[(size_t)p * 2 * k + 2 * j + 1]);
 }
 
 // ------------------------------------------------------- parameters ----
@@ -790,6 +889,31 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Effective backward-data weights of an upsampled layer (bwd_src):
+// wu[e][ci][co] = sum of w[co][ci][dy][dx] over the taps whose dz offset is
+// (oy, ox) = (e / 4 - 1, e % 4 - 1), i.e. sy = oy + dy - 1 and sx = ox + dx - 1
+// in {0, 1}; FP32 sums rounded once to bf16.
+__global__ void k_pack_up_weights(const float* __restrict__ w, int cout, int cin, int coutp,
+                                  int cinp, bf16* __restrict__ wu) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= 16 * cinp * coutp) return;
+  const int e = idx / (cinp * coutp), rem = idx % (cinp * coutp);
+  const int ci = rem / coutp, co = rem % coutp;
+  const int oy = e / 4 - 1, ox = e % 4 - 1;
+  float v = 0.f;
+  if (co < cout && ci < cin)
+    for (int dy = 0; dy < 3; ++dy) {
+      const int sy = oy + dy - 1;
+      if (sy < 0 || sy > 1) continue;
+      for (int dx = 0; dx < 3; ++dx) {
+        const int sx = ox + dx - 1;
+        if (sx < 0 || sx > 1) continue;
+        v += w[((size_t)co * cin + ci) * 9 + dy * 3 + dx];
+      }
+    }
+  wu[idx] = (bf16)v;
+}
+
 // bias for layers whose coutp > cout: a zero-padded FP32 copy
 __global__ void k_pad_bias(const float* __restrict__ b, int cout, int coutp, float* __restrict__ bp) {
   const int i = threadIdx.x;
@@ -797,10 +921,10 @@ __global__ void k_pad_bias(const float* __restrict__ b, int cout, int coutp, flo
 }
 
 // ============================================================ host side ====
-static int rup16(int c) { return (c + 15) / 16 * 16; }
+// MFMA kernels take 32, 64 or 128 channels (the K loop steps 32 channels)
+static int rup32(int c) { return (c + 31) / 32 * 32; }
 
 // pixels per weight-gradient slice: about 256 slices, multiples of 32
-static int wgrad_per(int npix) { return std::max(2048, ((npix + 255) / 256 + 31) / 32 * 32); }
 
 template <typename X>
 static hipError_t cnn_alloc(dd_cnn* n, X** p, size_t count) {
@@ -826,6 +950,9 @@ static dd_status pack_all(dd_cnn* n, hipStream_t st) {
     const int tot = 9 * L.coutp * L.cinp;
     k_pack_weights<<<(tot + 255) / 256, 256, 0, st>>>(n->params + L.woff, L.cout, L.cin, L.coutp,
                                                       L.cinp, n->wf[l], n->wb[l]);
+    if (L.up)
+      k_pack_up_weights<<<(16 * L.cinp * L.coutp + 255) / 256, 256, 0, st>>>(
+          n->params + L.woff, L.cout, L.cin, L.coutp, L.cinp, n->wu[l]);
   }
   DD_HIP_CHECK(hipGetLastError());
   return DD_OK;
@@ -843,6 +970,13 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_
   }
   dd_cnn* n = new dd_cnn();
   n->nx = nx; n->ny = ny; n->maxB = max_batch; n->k = k; n->cin0 = in_channels;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu > 0)
+      n->ncu = ncu;
+  }
   const int spec[NL][5] = {{in_channels, 32, 1, 0, 1}, {32, 64, 2, 0, 1}, {64, 128, 2, 0, 1},
                            {128, 128, 1, 0, 1}, {128, 64, 1, 1, 1}, {64, 32, 1, 1, 1},
                            {32, 32, 1, 0, 1}, {32, 2 * k, 1, 0, 0}};
@@ -852,8 +986,8 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_
     CnnLayer& L = n->L[l];
     L.cin = spec[l][0]; L.cout = spec[l][1]; L.stride = spec[l][2]; L.up = spec[l][3];
     L.relu = spec[l][4];
-    L.cinp = (l == 0) ? L.cin : rup16(L.cin);
-    L.coutp = std::max(32, rup16(L.cout));
+    L.cinp = (l == 0) ? L.cin : rup32(L.cin);
+    L.coutp = rup32(L.cout);
     L.Hin = H; L.Win = W;
     if (L.up) { L.Hout = 2 * H; L.Wout = 2 * W; }
     else if (L.stride == 2) { L.Hout = H / 2; L.Wout = W / 2; }
@@ -882,6 +1016,7 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_
   const size_t D = (size_t)nx * ny;
   chk(cnn_alloc(n, &n->x0, (size_t)max_batch * D * in_channels));
   chk(cnn_alloc(n, &n->iscale, (size_t)max_batch));
+  chk(cnn_alloc(n, &n->espart, (size_t)max_batch * ES_SLICES));
   size_t wp = 0;
   for (int l = 0; l < NL && e == hipSuccess; ++l) {
     const CnnLayer& L = n->L[l];
@@ -889,21 +1024,26 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_
     if (l > 0) {
       chk(cnn_alloc(n, &n->wf[l], (size_t)9 * L.coutp * L.cinp));
       chk(cnn_alloc(n, &n->wb[l], (size_t)9 * L.coutp * L.cinp));
+      if (L.up) chk(cnn_alloc(n, &n->wu[l], (size_t)16 * L.coutp * L.cinp));
     }
     if (l < NL - 1) chk(cnn_alloc(n, &n->act[l], pix * L.coutp));
     chk(cnn_alloc(n, &n->dz[l], pix * L.coutp));
-    // weight-gradient partials (slices as in backward())
-    // any batch B <= max_batch gives at most ~257 slices (wgrad_per)
-    const size_t per = (size_t)wgrad_per((int)pix);
-    const size_t slices = std::max<size_t>((pix + per - 1) / per, 260);
-    if (l > 0) wp = std::max(wp, slices * 9 * L.coutp * L.cinp);
-    wp = std::max(wp, slices * (size_t)L.coutp);
-    wp = std::max(wp, (size_t)512 * L.cout * (9 * L.cin + 1));
+    // gradient partials: k_conv_wgrad_seg runs at most 8 workgroups per CU
+    // (256 threads each) over 3 dy and the 64-channel blocks; layer 1 uses
+    // [slice][32][32] (at most 8 slices per CU) or its per-row-block fallback
+    if (l > 0) {
+      const size_t nblk = (size_t)std::max(1, L.cinp / 64);
+      const size_t sl = std::max<size_t>(1, (size_t)8 * n->ncu / (3 * nblk));
+      wp = std::max(wp, sl * ((size_t)9 * L.coutp * L.cinp + L.coutp));
+    } else {
+      wp = std::max(wp, (size_t)8 * n->ncu * 32 * 32);
+      wp = std::max(wp, (size_t)512 * L.cout * (9 * L.cin + 1));
+    }
   }
   n->wpart_elems = wp;
   chk(cnn_alloc(n, &n->wpart, wp));
   chk(cnn_alloc(n, &n->out, (size_t)max_batch * D * 2 * k));
-  chk(cnn_alloc(n, &n->lpart, (size_t)max_batch * D / 256 + 256));
+  chk(cnn_alloc(n, &n->lpart, (size_t)max_batch * D * 8 / 256 + 256));   // k_mse: coutp / 8 <= 8
   chk(cnn_alloc(n, &n->biaspad, (size_t)256 * NL));
   if (e == hipSuccess) chk(hipMemcpy(n->params, hp.data(), sizeof(float) * off, hipMemcpyHostToDevice));
   if (e != hipSuccess) {
@@ -965,45 +1105,67 @@ static void launch_gemm(const GemmArgs& a, int npix, hipStream_t st) {
   k_conv_gemm<MT, NT, BWD><<<(npix + per_block - 1) / per_block, 256, 0, st>>>(a);
 }
 
-static void gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_t st) {
+static dd_status gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_t st) {
   const int MT = a.M / 16;
-  if (!bwd && (a.mode == MAP_S1 || a.mode == MAP_UP) && a.Ksrc % 32 == 0) {
+  if ((MT != 2 && MT != 4 && MT != 8) || a.M % 16 || a.Ksrc % 32) {
+    dd_set_error("dd_cnn: no convolution kernel for %d result / %d source channels", a.M, a.Ksrc);
+    return DD_EINVAL;
+  }
+  if (!bwd && (a.mode == MAP_S1 || a.mode == MAP_UP)) {
     const dim3 grid((a.Wq + CT_TW - 1) / CT_TW, (a.Hq + CT_TH - 1) / CT_TH, a.B);
     switch (MT) {
       case 2: k_conv_tile<2><<<grid, 256, 0, st>>>(a); break;
       case 4: k_conv_tile<4><<<grid, 256, 0, st>>>(a); break;
-      default: k_conv_tile<8><<<grid, 256, 0, st>>>(a); break;
+      case 8: k_conv_tile<8><<<grid, 256, 0, st>>>(a); break;
     }
-    return;
+    return DD_OK;
   }
-  if (bwd && a.mode == MAP_S1 && a.Ksrc % 32 == 0) {
+  if (bwd && a.mode == MAP_S1) {
     const dim3 grid((a.Wq + CT_TW - 1) / CT_TW, (a.Hq + CT_TH - 1) / CT_TH, a.B);
     switch (MT) {
       case 2: k_conv_tile<2, true><<<grid, 256, 0, st>>>(a); break;
       case 4: k_conv_tile<4, true><<<grid, 256, 0, st>>>(a); break;
-      default: k_conv_tile<8, true><<<grid, 256, 0, st>>>(a); break;
+      case 8: k_conv_tile<8, true><<<grid, 256, 0, st>>>(a); break;
     }
-    return;
+    return DD_OK;
+  }
+  if (bwd && a.mode == MAP_S2) {
+    // wave items: (image, row, column parity, group of NT x-tiles of 16)
+    auto items = [&](int NT) {
+      const int ntile = ((a.Wq + 1) / 2 + 15) / 16;
+      return a.B * a.Hq * 2 * ((ntile + NT - 1) / NT);
+    };
+    switch (MT) {
+      case 2: k_bwd_s2<2, 8><<<(items(8) + 3) / 4, 256, 0, st>>>(a); break;
+      case 4: k_bwd_s2<4, 4><<<(items(4) + 3) / 4, 256, 0, st>>>(a); break;
+      case 8: k_bwd_s2<8, 2><<<(items(2) + 3) / 4, 256, 0, st>>>(a); break;
+    }
+    return DD_OK;
   }
   if (!bwd) {
     switch (MT) {
       case 2: launch_gemm<2, 8, false>(a, npix, st); break;
       case 4: launch_gemm<4, 4, false>(a, npix, st); break;
-      default: launch_gemm<8, 2, false>(a, npix, st); break;
+      case 8: launch_gemm<8, 2, false>(a, npix, st); break;
     }
   } else {
     switch (MT) {
       case 2: launch_gemm<2, 8, true>(a, npix, st); break;
       case 4: launch_gemm<4, 4, true>(a, npix, st); break;
-      default: launch_gemm<8, 2, true>(a, npix, st); break;
+      case 8: launch_gemm<8, 2, true>(a, npix, st); break;
     }
   }
+  return DD_OK;
 }
 
+// fields: destination of the complex output fields [B][k][D] (n->out if NULL)
 static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hipStream_t st,
-                         float* biaspad) {
+                         float* biaspad, void* fields = nullptr) {
   const int D = n->nx * n->ny;
-  if (n->cin0 == 3) k_eim_scale<<<B, 256, 0, st>>>((const float2*)eim, D, n->iscale);
+  if (n->cin0 == 3) {
+    k_eim_scale_part<<<dim3(ES_SLICES, B), 256, 0, st>>>((const float2*)eim, D, n->espart);
+    k_eim_scale<<<(B + 255) / 256, 256, 0, st>>>(n->espart, B, D, n->iscale);
+  }
   k_inputs<<<(B * D + 255) / 256, 256, 0, st>>>(eps, (const float2*)eim, n->iscale, B, D, n->cin0,
                                                  n->x0);
   {
@@ -1022,12 +1184,64 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
     a.B = B; a.Hq = L.Hout; a.Wq = L.Wout;
     a.Hs = L.Hin; a.Ws = L.Win; a.Hout = L.Hout; a.Wout = L.Wout;
     a.Ksrc = L.cinp; a.M = L.coutp; a.mode = L.mode; a.entries = 9; a.relu = L.relu;
-    if (l == NL - 1) { a.outf = n->out; a.nreal = L.cout; }
+    if (l == NL - 1) {
+      a.outf = fields ? (float*)fields : n->out;
+      a.nreal = L.cout;
+      n->last_fields = a.outf;
+    }
     else a.out = n->act[l];
-    gemm_dispatch(a, B * L.Hout * L.Wout, false, st);
+    const dd_status rc = gemm_dispatch(a, B * L.Hout * L.Wout, false, st);
+    if (rc != DD_OK) return rc;
   }
   DD_HIP_CHECK(hipGetLastError());
   return DD_OK;
+}
+
+// Weight- and bias-gradient partials of layer l >= 1 through
+// k_conv_wgrad_seg; returns the number of pixel slices written to n->wpart
+// (weights [slice][9][coutp][cinp], then bias [slice][coutp]), 0 (nothing
+// launched) for channel counts it has no instance for.
+template <int MT, int NT, int S>
+static int launch_wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
+  const CnnLayer& L = n->L[l];
+  const int Mr = 16 * MT, Nc = L.cinp, nblk = Nc / (16 * NT);
+  // resident workgroups per CU, queried once per instance
+  static int cap = 0;
+  if (cap == 0) {
+    int c = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_conv_wgrad_seg<MT, NT, S>, 256, 0) !=
+            hipSuccess || c < 1)
+      c = 1;
+    cap = c;
+  }
+  const int npix = B * L.Hout * L.Wout, nst = (npix + 32 * S - 1) / (32 * S);
+  // one round of resident workgroups, within the partial buffer (weights, then bias)
+  int slices = std::max(1, cap * n->ncu / (3 * nblk));
+  slices = (int)std::min<size_t>((size_t)slices, n->wpart_elems / ((size_t)9 * Mr * Nc + Mr));
+  slices = std::max(1, std::min(slices, nst));
+  const int sp = (nst + slices - 1) / slices;
+  slices = (nst + sp - 1) / sp;
+  const int nwork = slices * 3 * nblk, grid = (nwork + 7) / 8 * 8;
+  k_conv_wgrad_seg<MT, NT, S><<<grid, 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout, L.Wout,
+                                                    L.Hin, L.Win, Nc, L.mode, sp, nwork,
+                                                    n->wpart, n->wpart + (size_t)slices * 9 * Mr * Nc);
+  return slices;
+}
+
+static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
+  const CnnLayer& L = n->L[l];
+  const int Mr = L.coutp, Nc = L.cinp, NB = std::min(Nc, 64);
+  if (Nc % NB) return 0;
+  // S (stage width 32 S pixels) so that about 256 staging blocks fill the workgroup
+  const int per_s = 4 * (Mr / 8) + 12 * (NB / 8);
+  const int S = per_s <= 64 ? 4 : (per_s <= 128 ? 2 : 1);
+  if (Mr == 32 && NB == 32 && S == 4) return launch_wgrad_seg<2, 2, 4>(n, l, B, st);
+  if (Mr == 32 && NB == 64 && S == 2) return launch_wgrad_seg<2, 4, 2>(n, l, B, st);
+  if (Mr == 64 && NB == 32 && S == 2) return launch_wgrad_seg<4, 2, 2>(n, l, B, st);
+  if (Mr == 64 && NB == 64 && S == 2) return launch_wgrad_seg<4, 4, 2>(n, l, B, st);
+  if (Mr == 128 && NB == 32 && S == 2) return launch_wgrad_seg<8, 2, 2>(n, l, B, st);
+  if (Mr == 128 && NB == 64 && S == 1) return launch_wgrad_seg<8, 4, 1>(n, l, B, st);
+  return 0;
 }
 
 // Backward pass from the gradient of the last layer's pre-activation in
@@ -1035,57 +1249,42 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
 static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
   for (int l = NL - 1; l >= 1; --l) {
     const CnnLayer& L = n->L[l];
-    const int npo = B * L.Hout * L.Wout;
-    // weight and bias gradients of layer l: about 256 pixel slices
-    const int per = wgrad_per(npo);
-    const int slices = (npo + per - 1) / per;
-    const bool rows = (L.mode == MAP_S1 || L.mode == MAP_UP) && L.Wout % 32 == 0 &&
-                      L.coutp == 32 && (L.cinp == 32 || L.cinp == 64);
-    int wslices = slices;
-    if (rows) {
-      // row segments of 32 output pixels, at most `slices` workgroups
-      const int nseg = B * L.Hout * (L.Wout / 32);
-      const int sp = (nseg + slices - 1) / slices;
-      wslices = (nseg + sp - 1) / sp;
-      if (L.cinp == 32)
-        k_conv_wgrad_rows<2, 2><<<wslices, 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout,
-                                                         L.Wout, L.Hin, L.Win, L.mode, sp,
-                                                         n->wpart);
-      else
-        k_conv_wgrad_rows<2, 4><<<wslices, 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout,
-                                                         L.Wout, L.Hin, L.Win, L.mode, sp,
-                                                         n->wpart);
-    } else {
-      k_conv_wgrad<<<dim3(slices, 9), 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout, L.Wout,
-                                                     L.Hin, L.Win, L.coutp, L.cinp, L.mode, per,
-                                                     n->wpart);
+    // weight and bias gradients of layer l
+    const int wslices = wgrad_seg(n, l, B, st);
+    if (wslices <= 0) {
+      dd_set_error("dd_cnn: no weight-gradient kernel for %d x %d channels", L.coutp, L.cinp);
+      return DD_EINVAL;
     }
-    const int tot = L.cout * L.cin * 9;
-    k_wgrad_reduce<<<(tot + 255) / 256, 256, 0, st>>>(n->wpart, wslices, L.coutp, L.cinp, L.cout,
-                                                      L.cin, n->grads + L.woff);
-    k_bias_grad<<<slices, 256, 0, st>>>(n->dz[l], npo, L.coutp, per, n->wpart);
-    k_bgrad_reduce<<<1, 256, 0, st>>>(n->wpart, slices, L.coutp, L.cout, n->grads + L.boff);
+    const int nent = 9 * L.coutp * L.cinp;
+    k_wgrad_reduce<<<(nent + 63) / 64, 256, 0, st>>>(n->wpart, wslices, L.coutp, L.cinp, L.cout,
+                                                     L.cin, n->grads + L.woff);
+    k_bgrad_reduce<<<(L.coutp + 15) / 16, 256, 0, st>>>(n->wpart + (size_t)wslices * nent,
+                                                         wslices, L.coutp, L.cout,
+                                                         n->grads + L.boff);
     // data gradient into the previous layer (masked by its ReLU)
     GemmArgs a{};
     a.src = n->dz[l];
-    a.W = n->wb[l];
+    a.W = L.up ? n->wu[l] : n->wb[l];
     a.mask = n->act[l - 1];
     a.out = n->dz[l - 1];
     a.B = B; a.Hq = L.Hin; a.Wq = L.Win;
     a.Hs = L.Hout; a.Ws = L.Wout; a.Hout = L.Hout; a.Wout = L.Wout;
-    a.Ksrc = L.coutp; a.M = L.cinp; a.mode = L.mode; a.entries = L.up ? 36 : 9;
-    gemm_dispatch(a, B * L.Hin * L.Win, true, st);
+    a.Ksrc = L.coutp; a.M = L.cinp; a.mode = L.mode; a.entries = L.up ? 16 : 9;
+    const dd_status rc = gemm_dispatch(a, B * L.Hin * L.Win, true, st);
+    if (rc != DD_OK) return rc;
   }
   {
     const CnnLayer& L = n->L[0];
     const int nt = L.cout * (9 * n->cin0 + 1);
     if (n->nx % 32 == 0 && L.coutp == 32 && 9 * n->cin0 + 1 <= 32) {
+      // about eight workgroups per CU, within the partial buffer
       const int nseg = B * n->ny * (n->nx / 32);
-      const int sp = (nseg + 255) / 256, slices = (nseg + sp - 1) / sp;
+      const int want = (int)std::min<size_t>((size_t)8 * n->ncu, n->wpart_elems / (32 * 32));
+      const int sp = (nseg + want - 1) / want, slices = (nseg + sp - 1) / sp;
       k_conv1_wgrad_rows<<<slices, 256, 0, st>>>(n->x0, n->dz[0], B, n->cin0, n->ny, n->nx, sp,
                                                  n->wpart);
-      k_conv1_rows_reduce<<<(nt + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
-                                                            n->grads + L.woff, n->grads + L.boff);
+      k_conv1_rows_reduce<<<64, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
+                                              n->grads + L.woff, n->grads + L.boff);
     } else {
       const int rows = B * n->ny, rows_per = std::max(1, (rows + 511) / 512);
       const int slices = (rows + rows_per - 1) / rows_per;
@@ -1106,7 +1305,7 @@ static dd_status backward(dd_cnn* n, const void* target, int B, float* loss, hip
   const int k = n->k;
   const CnnLayer& LL = n->L[NL - 1];
   const float scale = 2.0f / ((float)B * D * 2 * k);
-  const int nlb = (B * D + 255) / 256;
+  const int nlb = (int)(((long)B * D * (LL.coutp / 8) + 255) / 256);
   k_mse<<<nlb, 256, 0, st>>>(n->out, (const float2*)target, B, D, k, LL.coutp, scale,
                              n->dz[NL - 1], n->lpart);
   dd_status rc = backward_from_dz(n, B, st);
@@ -1143,10 +1342,8 @@ static dd_status predict(dd_cnn* n, const float* eps, const void* eim, int B, vo
   dd_status rc = check_batch(n, eps, eim, B, who);
   if (rc != DD_OK) return rc;
   if (!U) { dd_set_error("%s: U is NULL", who); return DD_EINVAL; }
-  rc = forward(n, eps, eim, B, st, n->biaspad);
+  rc = forward(n, eps, eim, B, st, n->biaspad, U);
   if (rc != DD_OK) return rc;
-  const int D = n->nx * n->ny;
-  k_to_fields<<<(B * D + 255) / 256, 256, 0, st>>>(n->out, B, D, n->k, (float2*)U);
   DD_HIP_CHECK(hipGetLastError());
   DD_HIP_CHECK(hipStreamSynchronize(st));
   return DD_OK;
@@ -1222,10 +1419,9 @@ static dd_status res_step(dd_cnn* n, const float* eps, const void* eim,
       return DD_EINVAL;
     }
   const size_t D = (size_t)n->nx * n->ny;
-  if (!n->rl_V) {
+  if (!n->rl_W) {
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-    chk(cnn_alloc(n, &n->rl_V, (size_t)n->maxB * n->k * D));
     chk(cnn_alloc(n, &n->rl_W, (size_t)n->maxB * n->k * D));
     chk(cnn_alloc(n, &n->rl_r, (size_t)n->maxB * D));
     chk(cnn_alloc(n, &n->rl_s, (size_t)n->maxB * D));
@@ -1234,12 +1430,11 @@ static dd_status res_step(dd_cnn* n, const float* eps, const void* eim,
       return e == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP;
     }
   }
-  rc = forward(n, eps, eim, B, st, n->biaspad);
+  rc = forward(n, eps, eim, B, st, n->biaspad);   // fields V in n->out
   if (rc != DD_OK) return rc;
-  k_to_fields<<<(unsigned)((B * D + 255) / 256), 256, 0, st>>>(n->out, B, (int)D, n->k, n->rl_V);
   DD_HIP_CHECK(hipGetLastError());
   std::vector<const void*> Vp(B);
-  for (int p = 0; p < B; ++p) Vp[p] = n->rl_V + (size_t)p * n->k * D;
+  for (int p = 0; p < B; ++p) Vp[p] = (const float2*)n->out + (size_t)p * n->k * D;
   std::vector<double> lv(B);
   rc = res_loss_core(ops, b, Vp.data(), B, n->k, n->rl_W, n->rl_r, n->rl_s, lv.data(),
                      n->dz[NL - 1], n->L[NL - 1].coutp, 1.0 / B, st);
@@ -1308,9 +1503,17 @@ extern "C" dd_status dd_cnn_debug_activation(const dd_cnn* n, int layer, int B, 
   }
   const CnnLayer& L = n->L[layer];
   const size_t pix = (size_t)B * L.Hout * L.Wout;
-  if (layer == NL - 1) {
+  if (layer == NL - 1) {   // n->out holds complex fields [B][k][D]: back to [pixel][2k]
     if (count != pix * L.cout) { dd_set_error("dd_cnn_debug_activation: count must be %zu", pix * L.cout); return DD_EINVAL; }
-    DD_HIP_CHECK(hipMemcpy(host, n->out, sizeof(float) * count, hipMemcpyDeviceToHost));
+    std::vector<float> f(count);
+    if (!n->last_fields) { dd_set_error("dd_cnn_debug_activation: no forward pass yet"); return DD_EINVAL; }
+    DD_HIP_CHECK(hipMemcpy(f.data(), n->last_fields, sizeof(float) * count, hipMemcpyDeviceToHost));
+    const int kf = n->k;
+    for (size_t p = 0; p < pix; ++p) {
+      const size_t b = p / D, e = p % D;
+      for (int j = 0; j < kf; ++j)
+        for (int c = 0; c < 2; ++c) host[p * 2 * kf + 2 * j + c] = f[((b * kf + j) * D + e) * 2 + c];
+    }
     return DD_OK;
   }
   if (count != pix * L.cout) { dd_set_error("dd_cnn_debug_activation: count must be %zu", pix * L.cout); return DD_EINVAL; }

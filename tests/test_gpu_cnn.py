@@ -74,13 +74,16 @@ def test_forward_full_size_sampled():
     assert _rel(U, ocnn.channels_to_fields(out)) < 3e-2
 
 
-@pytest.mark.parametrize("nx,ny", [(24, 16), (64, 32)])
-def test_gradients_match_oracle(nx, ny):
-    """24 x 16 takes the per-tap weight-gradient kernel everywhere; at 64 x 32
-    the full-resolution layers (6-8) take the row-segment kernel."""
+@pytest.mark.parametrize("nx,ny,k", [(24, 16, 10), (64, 32, 10), (40, 12, 20), (24, 16, 32)])
+def test_gradients_match_oracle(nx, ny, k):
+    """Layers 2-8 take the staged pixel-segment weight-gradient kernel: its
+    stages cross rows and images at 24 x 16 and 40 x 12 (ragged last stage),
+    and k = 20 / 32 give the last layer 48 / 64 padded output channels.
+    Layer 1 takes the row-segment GEMM at 64 x 32 (width a multiple of 32)
+    and the per-row-block kernel elsewhere."""
     import torch
     from paper_1902_00090_amd.cnn import flat_to_layers
-    B, k = 2, 10
+    B = 2
     net, op, eps, eps_d = _setup(nx, ny, B, k, seed=3)
     rng = np.random.default_rng(11)
     tgt = (rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny))) * 0.1
