@@ -657,6 +657,183 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_seg(const bf16* __restrict__
   }
 }
 
+// Weight gradients of the stride-1 and upsampling layers over row chunks:
+// the same GEMM as k_conv_wgrad_seg, but a stage is PX = 32 S pixels of one
+// output row (the last chunk of a row is ragged), so the three dx taps read
+// one staged input row at column shifts -1, 0, +1.  The row is staged once
+// (transposed, [channel][column], column = input column - x0 + 8; for the
+// upsampling layers the source row is expanded x2 while staging), and the
+// shifted operands are built from aligned 16-byte LDS reads by funnel shifts.
+// Per stage that moves PX + 16 (stride 1) or PX / 2 + 8 (upsampling) input
+// pixels instead of 3 PX.  A wave owns (row tile, column tile) units and
+// applies all three dx to each.  Work items, grid and partials are
+// k_conv_wgrad_seg's.
+template <int MT, int NT, int S, bool UP>
+__global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__ dz,
+                                                        const bf16* __restrict__ x, int B,
+                                                        int Hout, int Wout, int Hin, int Win,
+                                                        int Nc, int stages_per, int nwork,
+                                                        float* __restrict__ part,
+                                                        float* __restrict__ bpart) {
+  constexpr int Mr = 16 * MT, NB = 16 * NT, PX = 32 * S, LD = PX + 8;
+  constexpr int XC = PX + 16, LDX = XC + 8;          // staged columns x0 - 8 .. x0 + PX + 7
+  constexpr int ABLK = (PX / 8) * (Mr / 8);
+  constexpr int XG = UP ? (PX / 16 + 1) : (PX / 8 + 2);   // source groups of 8 pixels
+  constexpr int XBLK = XG * (NB / 8);
+  constexpr int NBLK = ABLK + XBLK, BPT = (NBLK + 255) / 256;
+  constexpr int NU = MT * NT, PER_WAVE = (NU + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16 As[Mr][LD];
+  __shared__ __attribute__((aligned(16))) bf16 Xs[NB][LDX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (w >= nwork) return;
+  const int nblk = Nc / NB;
+  const int dy = w % 3, n0 = ((w / 3) % nblk) * NB, slice = w / (3 * nblk);
+  const int nch = (Wout + PX - 1) / PX, nst = B * Hout * nch;
+  const int s0 = slice * stages_per, s1 = min(nst, s0 + stages_per);
+  bf16x8 reg[BPT][8];
+  auto load = [&](int sg) {
+    const int b = sg / (Hout * nch), rem = sg - b * Hout * nch, y = rem / nch;
+    const int x0 = (rem - y * nch) * PX;
+    const int uy = y + dy - 1;
+    const bool rowok = uy >= 0 && uy < Hout;
+    const int ys = UP ? (uy >> 1) : uy;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) reg[bi][i] = zero8();
+      if (blk < ABLK) {
+        const int pg = blk / (Mr / 8), cg = (blk % (Mr / 8)) * 8;
+        const bf16* src = dz + (((size_t)b * Hout + y) * Wout + x0) * Mr + cg;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (x0 + pg * 8 + i < Wout) reg[bi][i] = load8(src + (size_t)(pg * 8 + i) * Mr);
+      } else if (blk < NBLK && rowok) {
+        const int r = blk - ABLK, m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+        const int c0 = UP ? (x0 / 2 - 4 + 8 * m) : (x0 - 8 + 8 * m);   // first source column
+        const bf16* src = x + ((size_t)b * Hin + ys) * Win * Nc + n0 + cg;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (c0 + i >= 0 && c0 + i < Win) reg[bi][i] = load8(src + (size_t)(c0 + i) * Nc);
+      }
+    }
+  };
+  f32x4 acc[PER_WAVE][3];
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc[i][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int BT = (MT + 3) / 4;
+  const bool bias = (dy == 0 && n0 == 0);
+  f32x4 accb[BT];
+#pragma unroll
+  for (int i = 0; i < BT; ++i) accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.f;
+  const int kq = 8 * (lane >> 4);
+  if (s0 < s1) load(s0);
+  for (int sg = s0; sg < s1; ++sg) {
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      if (blk < ABLK) {
+        bf16* dst = &As[(blk % (Mr / 8)) * 8][(blk / (Mr / 8)) * 8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          bf16x8 t;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) t[i] = reg[bi][i][q];
+          *(bf16x8*)(dst + q * LD) = t;
+        }
+      } else if (blk < NBLK) {
+        const int r = blk - ABLK, m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (UP) {   // source pixel i fills columns 16 m + 2 i and 16 m + 2 i + 1
+            bf16x8 lo, hi;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              lo[2 * i] = lo[2 * i + 1] = reg[bi][i][q];
+              hi[2 * i] = hi[2 * i + 1] = reg[bi][i + 4][q];
+            }
+            *(bf16x8*)&Xs[cg + q][16 * m] = lo;
+            *(bf16x8*)&Xs[cg + q][16 * m + 8] = hi;
+          } else {
+            bf16x8 t;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) t[i] = reg[bi][i][q];
+            *(bf16x8*)&Xs[cg + q][8 * m] = t;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (sg + 1 < s1) load(sg + 1);
+#pragma unroll
+    for (int kk = 0; kk < S; ++kk) {
+#pragma unroll
+      for (int i = 0; i < PER_WAVE; ++i) {
+        const int u = wave + 4 * i;
+        if (u < NU) {
+          const int ti = u / NT, tj = u - ti * NT;
+          const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
+          const bf16* xr = &Xs[tj * 16 + (lane & 15)][kk * 32 + kq + 8];   // column of dx = 1
+          const u32x4 a4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr - 8));
+          const u32x4 b4 = __builtin_bit_cast(u32x4, *(const bf16x8*)xr);
+          const u32x4 c4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr + 8));
+          // columns shifted by one bf16: word j = high half of word j-1, low half of word j
+          const unsigned s0w = (a4[3] >> 16) | (b4[0] << 16), s1w = (b4[0] >> 16) | (b4[1] << 16);
+          const unsigned s2w = (b4[1] >> 16) | (b4[2] << 16), s3w = (b4[2] >> 16) | (b4[3] << 16);
+          const unsigned s4w = (b4[3] >> 16) | (c4[0] << 16);
+          const bf16x8 bl = __builtin_bit_cast(bf16x8, u32x4{s0w, s1w, s2w, s3w});   // dx = 0
+          const bf16x8 bm = __builtin_bit_cast(bf16x8, b4);                          // dx = 1
+          const bf16x8 br = __builtin_bit_cast(bf16x8, u32x4{s1w, s2w, s3w, s4w});   // dx = 2
+          acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[i][0], 0, 0, 0);
+          acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bm, acc[i][1], 0, 0, 0);
+          acc[i][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, br, acc[i][2], 0, 0, 0);
+        }
+      }
+      if (bias) {
+#pragma unroll
+        for (int i = 0; i < BT; ++i) {
+          const int ti = wave + 4 * i;
+          if (ti < MT) {
+            const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
+            accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb[i], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  if (bias) {
+#pragma unroll
+    for (int i = 0; i < BT; ++i) {
+      const int ti = wave + 4 * i;
+      if (ti < MT && (lane & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bpart[(size_t)slice * Mr + ti * 16 + 4 * (lane >> 4) + q] = accb[i][q];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i) {
+    const int u = wave + 4 * i;
+    if (u < NU) {
+      const int ti = u / NT, tj = u - ti * NT;
+      const int c = tj * 16 + (lane & 15);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float* out = part + (((size_t)slice * 9 + dy * 3 + d) * Mr) * Nc + n0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[i][d][q];
+      }
+    }
+  }
+}
+
 // Layer-1 weight and bias gradients as one GEMM over row segments of 32
 // pixels: dW[co][j] = sum_p dz[p][co] u[p][j], where u[p] is the pixel's
 // 9 C input values (plane-major, tap-minor, the [cout][cin][3][3] order of
@@ -1197,37 +1374,62 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
   return DD_OK;
 }
 
-// Weight- and bias-gradient partials of layer l >= 1 through
-// k_conv_wgrad_seg; returns the number of pixel slices written to n->wpart
-// (weights [slice][9][coutp][cinp], then bias [slice][coutp]), 0 (nothing
-// launched) for channel counts it has no instance for.
-template <int MT, int NT, int S>
-static int launch_wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
-  const CnnLayer& L = n->L[l];
-  const int Mr = 16 * MT, Nc = L.cinp, nblk = Nc / (16 * NT);
-  // resident workgroups per CU, queried once per instance
-  static int cap = 0;
-  if (cap == 0) {
-    int c = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_conv_wgrad_seg<MT, NT, S>, 256, 0) !=
-            hipSuccess || c < 1)
-      c = 1;
-    cap = c;
-  }
-  const int npix = B * L.Hout * L.Wout, nst = (npix + 32 * S - 1) / (32 * S);
-  // one round of resident workgroups, within the partial buffer (weights, then bias)
+// Work split of a weight-gradient kernel (k_conv_wgrad_seg, k_conv_wgrad_row)
+// over nst stages: one round of resident workgroups (cap per CU), within the
+// partial buffer (weights, then bias).
+struct WgradSplit {
+  int slices, stages_per, nwork, grid;
+};
+static WgradSplit wgrad_split(const dd_cnn* n, int cap, int Mr, int Nc, int NB, int nst) {
+  const int nblk = Nc / NB;
   int slices = std::max(1, cap * n->ncu / (3 * nblk));
   slices = (int)std::min<size_t>((size_t)slices, n->wpart_elems / ((size_t)9 * Mr * Nc + Mr));
   slices = std::max(1, std::min(slices, nst));
   const int sp = (nst + slices - 1) / slices;
   slices = (nst + sp - 1) / sp;
-  const int nwork = slices * 3 * nblk, grid = (nwork + 7) / 8 * 8;
-  k_conv_wgrad_seg<MT, NT, S><<<grid, 256, 0, st>>>(n->dz[l], n->act[l - 1], B, L.Hout, L.Wout,
-                                                    L.Hin, L.Win, Nc, L.mode, sp, nwork,
-                                                    n->wpart, n->wpart + (size_t)slices * 9 * Mr * Nc);
-  return slices;
+  const int nwork = slices * 3 * nblk;
+  return {slices, sp, nwork, (nwork + 7) / 8 * 8};
 }
 
+// resident workgroups per CU of a kernel (at least 1)
+template <typename K>
+static int occupancy(K kern) {
+  int c = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, kern, 256, 0) != hipSuccess || c < 1) c = 1;
+  return c;
+}
+
+template <int MT, int NT, int S>
+static int launch_wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
+  static const int cap = occupancy(k_conv_wgrad_seg<MT, NT, S>);
+  const CnnLayer& L = n->L[l];
+  const int Mr = 16 * MT, Nc = L.cinp;
+  const int nst = (B * L.Hout * L.Wout + 32 * S - 1) / (32 * S);
+  const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst);
+  k_conv_wgrad_seg<MT, NT, S><<<w.grid, 256, 0, st>>>(
+      n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, L.Hin, L.Win, Nc, L.mode, w.stages_per,
+      w.nwork, n->wpart, n->wpart + (size_t)w.slices * 9 * Mr * Nc);
+  return w.slices;
+}
+
+template <int MT, int NT, int S, bool UP>
+static int launch_wgrad_row(dd_cnn* n, int l, int B, hipStream_t st) {
+  static const int cap = occupancy(k_conv_wgrad_row<MT, NT, S, UP>);
+  const CnnLayer& L = n->L[l];
+  const int Mr = 16 * MT, Nc = L.cinp;
+  const int nst = B * L.Hout * ((L.Wout + 32 * S - 1) / (32 * S));
+  const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst);
+  k_conv_wgrad_row<MT, NT, S, UP><<<w.grid, 256, 0, st>>>(
+      n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, L.Hin, L.Win, Nc, w.stages_per, w.nwork,
+      n->wpart, n->wpart + (size_t)w.slices * 9 * Mr * Nc);
+  return w.slices;
+}
+
+// Weight- and bias-gradient partials of layer l >= 1: row chunks for the
+// stride-1 and upsampling layers, flattened pixel segments for the stride-2
+// ones.  Returns the number of pixel slices written to n->wpart (weights
+// [slice][9][coutp][cinp], then bias [slice][coutp]), 0 (nothing launched)
+// for channel counts without an instance.
 static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   const CnnLayer& L = n->L[l];
   const int Mr = L.coutp, Nc = L.cinp, NB = std::min(Nc, 64);
@@ -1235,12 +1437,23 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   // S (stage width 32 S pixels) so that about 256 staging blocks fill the workgroup
   const int per_s = 4 * (Mr / 8) + 12 * (NB / 8);
   const int S = per_s <= 64 ? 4 : (per_s <= 128 ? 2 : 1);
-  if (Mr == 32 && NB == 32 && S == 4) return launch_wgrad_seg<2, 2, 4>(n, l, B, st);
-  if (Mr == 32 && NB == 64 && S == 2) return launch_wgrad_seg<2, 4, 2>(n, l, B, st);
-  if (Mr == 64 && NB == 32 && S == 2) return launch_wgrad_seg<4, 2, 2>(n, l, B, st);
-  if (Mr == 64 && NB == 64 && S == 2) return launch_wgrad_seg<4, 4, 2>(n, l, B, st);
-  if (Mr == 128 && NB == 32 && S == 2) return launch_wgrad_seg<8, 2, 2>(n, l, B, st);
-  if (Mr == 128 && NB == 64 && S == 1) return launch_wgrad_seg<8, 4, 1>(n, l, B, st);
+#define WG_CASES(F)                                                  \
+  if (Mr == 32 && NB == 32 && S == 4) return F(2, 2, 4);             \
+  if (Mr == 32 && NB == 64 && S == 2) return F(2, 4, 2);             \
+  if (Mr == 64 && NB == 32 && S == 2) return F(4, 2, 2);             \
+  if (Mr == 64 && NB == 64 && S == 2) return F(4, 4, 2);             \
+  if (Mr == 128 && NB == 32 && S == 2) return F(8, 2, 2);            \
+  if (Mr == 128 && NB == 64 && S == 1) return F(8, 4, 1);
+#define WG_SEG(a, b, c) launch_wgrad_seg<a, b, c>(n, l, B, st)
+#define WG_ROW1(a, b, c) launch_wgrad_row<a, b, c, false>(n, l, B, st)
+#define WG_ROWU(a, b, c) launch_wgrad_row<a, b, c, true>(n, l, B, st)
+  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1) }
+  else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU) }
+  else { WG_CASES(WG_SEG) }
+#undef WG_CASES
+#undef WG_SEG
+#undef WG_ROW1
+#undef WG_ROWU
   return 0;
 }
 
