@@ -1130,6 +1130,7 @@ static dd_status pack_all(dd_cnn* n, hipStream_t st) {
     if (L.up)
       k_pack_up_weights<<<(16 * L.cinp * L.coutp + 255) / 256, 256, 0, st>>>(
           n->params + L.woff, L.cout, L.cin, L.coutp, L.cinp, n->wu[l]);
+    k_pad_bias<<<1, 256, 0, st>>>(n->params + L.boff, L.cout, L.coutp, n->biaspad + 256 * l);
   }
   DD_HIP_CHECK(hipGetLastError());
   return DD_OK;
@@ -1337,7 +1338,7 @@ static dd_status gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_
 
 // fields: destination of the complex output fields [B][k][D] (n->out if NULL)
 static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hipStream_t st,
-                         float* biaspad, void* fields = nullptr) {
+                         void* fields = nullptr) {
   const int D = n->nx * n->ny;
   if (n->cin0 == 3) {
     k_eim_scale_part<<<dim3(ES_SLICES, B), 256, 0, st>>>((const float2*)eim, D, n->espart);
@@ -1353,11 +1354,10 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
   }
   for (int l = 1; l < NL; ++l) {
     const CnnLayer& L = n->L[l];
-    k_pad_bias<<<1, 256, 0, st>>>(n->params + L.boff, L.cout, L.coutp, biaspad + 256 * l);
     GemmArgs a{};
     a.src = n->act[l - 1];
     a.W = n->wf[l];
-    a.bias = biaspad + 256 * l;
+    a.bias = n->biaspad + 256 * l;
     a.B = B; a.Hq = L.Hout; a.Wq = L.Wout;
     a.Hs = L.Hin; a.Ws = L.Win; a.Hout = L.Hout; a.Wout = L.Wout;
     a.Ksrc = L.cinp; a.M = L.coutp; a.mode = L.mode; a.entries = 9; a.relu = L.relu;
@@ -1555,7 +1555,7 @@ static dd_status predict(dd_cnn* n, const float* eps, const void* eim, int B, vo
   dd_status rc = check_batch(n, eps, eim, B, who);
   if (rc != DD_OK) return rc;
   if (!U) { dd_set_error("%s: U is NULL", who); return DD_EINVAL; }
-  rc = forward(n, eps, eim, B, st, n->biaspad, U);
+  rc = forward(n, eps, eim, B, st, U);
   if (rc != DD_OK) return rc;
   DD_HIP_CHECK(hipGetLastError());
   DD_HIP_CHECK(hipStreamSynchronize(st));
@@ -1582,7 +1582,7 @@ extern "C" dd_status dd_cnn_grad(dd_cnn* n, const float* eps, const void* eim, c
     dd_set_error("dd_cnn_grad: bad target or gradient size");
     return DD_EINVAL;
   }
-  rc = forward(n, eps, eim, B, st, n->biaspad);
+  rc = forward(n, eps, eim, B, st);
   if (rc != DD_OK) return rc;
   rc = backward(n, target, B, loss, st);
   if (rc != DD_OK) return rc;
@@ -1602,7 +1602,7 @@ extern "C" dd_status dd_cnn_train_step(dd_cnn* n, const float* eps, const void* 
     dd_set_error("dd_cnn_train_step: bad target or Adam parameters");
     return DD_EINVAL;
   }
-  rc = forward(n, eps, eim, B, st, n->biaspad);
+  rc = forward(n, eps, eim, B, st);
   if (rc != DD_OK) return rc;
   rc = backward(n, target, B, loss, st);
   if (rc != DD_OK) return rc;
@@ -1643,7 +1643,7 @@ static dd_status res_step(dd_cnn* n, const float* eps, const void* eim,
       return e == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP;
     }
   }
-  rc = forward(n, eps, eim, B, st, n->biaspad);   // fields V in n->out
+  rc = forward(n, eps, eim, B, st);   // fields V in n->out
   if (rc != DD_OK) return rc;
   DD_HIP_CHECK(hipGetLastError());
   std::vector<const void*> Vp(B);
