@@ -13,6 +13,7 @@ struct dd_solver {
   dd_solver_opts o{};
   int R = 1;          // field elements per thread
   int nchunks = 0;
+  int ncu = 1;        // compute units of the device
   std::vector<const fdfd_op*> ops;
   std::vector<ProbDesc> hdesc;
   std::vector<int> ksetup;  // augmenting columns given per problem
@@ -187,6 +188,13 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     blk += d.nblk;
   }
   s->nchunks = blk;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu > 0)
+      s->ncu = ncu;
+  }
   const size_t ib = inner_bytes(o.inner);
   const int NC = K + m + 1;
   const int NV = ((2 * NC + 31) / 32) * 32 + 32;
@@ -398,9 +406,13 @@ static void prof_collect(dd_solver* s) {
 template <typename T, int R>
 static void launch_step(dd_solver* s, int j, hipStream_t st) {
   const int g = s->nchunks, nb = s->nb;
+  // a launch of few chunks (one problem) leaves most CUs idle: split its dot
+  // products over up to four workgroups per chunk (groups of 16 vectors)
+  const int ngrp = (s->o.kmax + j + 1 + 15) / 16;
+  const dim3 gm(g, (g < s->ncu) ? std::min(4, ngrp) : 1);
   prof_mark(s, 0, st);
-  if (s->o.precond != DD_PRECOND_NONE) k_matvec_dot<T, R, true><<<g, DD_BLOCK, 0, st>>>(s->P, j);
-  else k_matvec_dot<T, R, false><<<g, DD_BLOCK, 0, st>>>(s->P, j);
+  if (s->o.precond != DD_PRECOND_NONE) k_matvec_dot<T, R, true><<<gm, DD_BLOCK, 0, st>>>(s->P, j);
+  else k_matvec_dot<T, R, false><<<gm, DD_BLOCK, 0, st>>>(s->P, j);
   prof_end(s, st);
   k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
   if (s->P.reorth_mode != 0) {

@@ -49,12 +49,16 @@ __device__ __forceinline__ double2 ddiv(double2 a, double2 b) {
 #define DD_LDSN (2 * (((DD_MAX_K + DD_MAX_M + 1) + 15) / 16) * 16 + 32)
 // An extra per-thread scalar (e.g. a squared norm) is summed alongside into
 // prow[2*round_up(n,16)].
+// With nvs > 1 the groups of 16 vectors are split over nvs workgroups of the
+// same chunk: this one (vs) takes groups vs, vs + nvs, ... and writes only
+// their entries; the extra scalar is written by vs = 0.
 template <typename T, int R>
 __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t Dp, int n,
                                            const c2<T> (&w)[R], int base,
-                                           T* __restrict__ prow, T* lds, T extra = T(0)) {
+                                           T* __restrict__ prow, T* lds, T extra = T(0),
+                                           int vs = 0, int nvs = 1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int v0 = 0; v0 < n; v0 += 16) {
+  for (int v0 = 16 * vs; v0 < n; v0 += 16 * nvs) {
     T acc[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) acc[i] = T(0);
@@ -80,7 +84,8 @@ __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t D
   if (lane == 0) lds[wave * DD_LDSN + nv] = extra;
   __syncthreads();
   for (int i = threadIdx.x; i <= nv; i += DD_BLOCK)
-    prow[i] = lds[i] + lds[DD_LDSN + i] + lds[2 * DD_LDSN + i] + lds[3 * DD_LDSN + i];
+    if (i == nv ? vs == 0 : (i / 32) % nvs == vs)
+      prow[i] = lds[i] + lds[DD_LDSN + i] + lds[2 * DD_LDSN + i] + lds[3 * DD_LDSN + i];
 }
 
 // FP64 sums over all of problem p's partial rows, added in chunk order (the
@@ -299,6 +304,9 @@ __global__ __launch_bounds__(DD_BLOCK) void k_start_dot(PlanDev P) {
 // the fly by hscale[j]) written to slot Q_{j+1}; partial dots [C Q_0..Q_j]^H w
 // and ||w||^2.
 // PC: the problem carries a diagonal preconditioner, w = P_L A P_R q_j.
+// grid.y > 1 splits the dot products of a chunk over grid.y workgroups (for
+// launches with few chunks); each recomputes the chunk's w, blockIdx.y = 0
+// stores it.
 template <typename T, int R, bool PC = false>
 __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
   const int chunk = blockIdx.x;
@@ -332,14 +340,14 @@ __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
       }
     }
     wv[r] = y;
-    w[e] = y;
+    if (blockIdx.y == 0) w[e] = y;
   }
   T w2 = T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) w2 += wv[r].x * wv[r].x + wv[r].y * wv[r].y;
   __shared__ T lds[4 * DD_LDSN];
   T* prow = (T*)P.partial + (size_t)chunk * P.NV;
-  block_dots<T, R>(B, Dp, n, wv, base, prow, lds, w2);
+  block_dots<T, R>(B, Dp, n, wv, base, prow, lds, w2, blockIdx.y, gridDim.y);
 }
 
 // One workgroup per problem: the dot products of the sweep before, as FP64
