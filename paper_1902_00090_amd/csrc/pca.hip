@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.h"
+#include "devbuf.h"
 #include "gram.h"
 
 #define DD_MAX_KPCA 64
@@ -309,15 +310,15 @@ dd_status gram_host(const float2* V, int k, int D, const double2* f, std::vector
                     hipStream_t stream) {
   const int K1 = k + 1;
   const int nslices = std::max(1, std::min(256, D / 4096));
-  double2* part = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&part, sizeof(double2) * nslices * K1 * K1));
+  DevBuf bpart;
+  DD_HIP_CHECK(hipMalloc(&bpart.p, sizeof(double2) * nslices * K1 * K1));
+  double2* part = bpart.as<double2>();
   DD_HIP_CHECK(hipMemsetAsync(part, 0, sizeof(double2) * nslices * K1 * K1, stream));
   k_small_gram<<<dim3(f ? K1 : k, nslices), 256, 0, stream>>>(V, k, D, f, f ? 1 : 0, nslices, part);
   std::vector<double2> hp((size_t)nslices * K1 * K1);
   DD_HIP_CHECK(hipMemcpyAsync(hp.data(), part, sizeof(double2) * hp.size(), hipMemcpyDeviceToHost,
                               stream));
   DD_HIP_CHECK(hipStreamSynchronize(stream));
-  DD_HIP_CHECK(hipFree(part));
   G.assign((size_t)K1 * K1, cd(0.0));
   for (int s = 0; s < nslices; ++s)
     for (int a = 0; a < K1; ++a)
@@ -337,17 +338,16 @@ static dd_status gram_rows(const float2* F, int S, int D, std::vector<cd>& G, hi
   const int ntiles = nta * (nta + 1) / 2;
   int nslices = std::max(1, std::min(256, 4096 / std::max(1, ntiles)));
   nslices = std::min(nslices, std::max(1, D / PE));
-  double2 *part = nullptr, *dG = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&part, sizeof(double2) * nslices * nta * nta * PT * PT));
-  DD_HIP_CHECK(hipMalloc((void**)&dG, sizeof(double2) * S * S));
+  DevBuf bpart, bG;
+  DD_HIP_CHECK(hipMalloc(&bpart.p, sizeof(double2) * nslices * nta * nta * PT * PT));
+  DD_HIP_CHECK(hipMalloc(&bG.p, sizeof(double2) * S * S));
+  double2 *part = bpart.as<double2>(), *dG = bG.as<double2>();
   k_pca_gram<<<dim3(nta, nta, nslices), 256, 0, stream>>>(F, S, D, nslices, part);
   k_pca_gram_reduce<<<dim3((S + 255) / 256, S), 256, 0, stream>>>(part, S, nta, nslices, dG);
   DD_HIP_CHECK(hipGetLastError());
   std::vector<double2> h((size_t)S * S);
   DD_HIP_CHECK(hipMemcpyAsync(h.data(), dG, sizeof(double2) * S * S, hipMemcpyDeviceToHost, stream));
   DD_HIP_CHECK(hipStreamSynchronize(stream));
-  DD_HIP_CHECK(hipFree(part));
-  DD_HIP_CHECK(hipFree(dG));
   G.resize((size_t)S * S);
   for (size_t i = 0; i < G.size(); ++i) G[i] = cd(h[i].x, h[i].y);
   return DD_OK;
@@ -392,17 +392,16 @@ extern "C" dd_status pca_build(const void* Sv, int M, int D, int k, void* Uv, do
   const int ntiles = nta * (nta + 1) / 2;
   int nslices = std::max(1, std::min(256, 4096 / std::max(1, ntiles)));
   nslices = std::min(nslices, std::max(1, D / PE));
-  double2 *part = nullptr, *G = nullptr, *coef = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&part, sizeof(double2) * nslices * nta * nta * PT * PT));
-  DD_HIP_CHECK(hipMalloc((void**)&G, sizeof(double2) * M * M));
+  DevBuf bpart, bG, bcoef, bT;
+  DD_HIP_CHECK(hipMalloc(&bpart.p, sizeof(double2) * nslices * nta * nta * PT * PT));
+  DD_HIP_CHECK(hipMalloc(&bG.p, sizeof(double2) * M * M));
+  double2 *part = bpart.as<double2>(), *G = bG.as<double2>();
   k_pca_gram<<<dim3(nta, nta, nslices), 256, 0, stream>>>(S, M, D, nslices, part);
   k_pca_gram_reduce<<<dim3((M + 255) / 256, M), 256, 0, stream>>>(part, M, nta, nslices, G);
   DD_HIP_CHECK(hipGetLastError());
   std::vector<cd> hG((size_t)M * M);
   DD_HIP_CHECK(hipMemcpyAsync(hG.data(), G, sizeof(double2) * M * M, hipMemcpyDeviceToHost, stream));
   DD_HIP_CHECK(hipStreamSynchronize(stream));
-  DD_HIP_CHECK(hipFree(part));
-  DD_HIP_CHECK(hipFree(G));
   for (const cd& v : hG)
     if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) {
       dd_set_error("pca_build: snapshots contain non-finite values");
@@ -426,12 +425,12 @@ extern "C" dd_status pca_build(const void* Sv, int M, int D, int k, void* Uv, do
       hc[(size_t)mrow * k + i] = make_double2(c.real(), c.imag());
     }
   }
-  DD_HIP_CHECK(hipMalloc((void**)&coef, sizeof(double2) * M * k));
+  DD_HIP_CHECK(hipMalloc(&bcoef.p, sizeof(double2) * M * k));
+  double2* coef = bcoef.as<double2>();
   DD_HIP_CHECK(hipMemcpyAsync(coef, hc.data(), sizeof(double2) * M * k, hipMemcpyHostToDevice, stream));
   k_pca_combine<<<dim3((D + 255) / 256, (k + 15) / 16), 256, 0, stream>>>(S, M, D, coef, k, U);
   DD_HIP_CHECK(hipGetLastError());
   DD_HIP_CHECK(hipStreamSynchronize(stream));
-  DD_HIP_CHECK(hipFree(coef));
   // one Cholesky QR pass restores orthonormality lost to FP32 storage
   std::vector<cd> Gu, L, T;
   dd_status rc = gram_host(U, k, D, nullptr, Gu, stream);
@@ -442,13 +441,12 @@ extern "C" dd_status pca_build(const void* Sv, int M, int D, int k, void* Uv, do
   }
   std::vector<double2> hT((size_t)k * k);
   for (size_t i = 0; i < hT.size(); ++i) hT[i] = make_double2(T[i].real(), T[i].imag());
-  double2* dT = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&dT, sizeof(double2) * k * k));
+  DD_HIP_CHECK(hipMalloc(&bT.p, sizeof(double2) * k * k));
+  double2* dT = bT.as<double2>();
   DD_HIP_CHECK(hipMemcpyAsync(dT, hT.data(), sizeof(double2) * k * k, hipMemcpyHostToDevice, stream));
   k_small_combine<<<(D + 255) / 256, 256, 0, stream>>>(U, k, D, dT);
   DD_HIP_CHECK(hipGetLastError());
   DD_HIP_CHECK(hipStreamSynchronize(stream));
-  DD_HIP_CHECK(hipFree(dT));
   return DD_OK;
 }
 
@@ -522,14 +520,14 @@ extern "C" dd_status local_pca_targets(const void* Fv, int S, int D, int window,
       }
     }
   }
-  double2* coef = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&coef, sizeof(double2) * hc.size()));
+  DevBuf bcoef;
+  DD_HIP_CHECK(hipMalloc(&bcoef.p, sizeof(double2) * hc.size()));
+  double2* coef = bcoef.as<double2>();
   DD_HIP_CHECK(hipMemcpyAsync(coef, hc.data(), sizeof(double2) * hc.size(), hipMemcpyHostToDevice, stream));
   k_local_combine<<<dim3((D + 255) / 256, S * ((k + 15) / 16)), 256, 0, stream>>>(F, S, D, coef, k,
                                                                                   (float2*)Tv);
   DD_HIP_CHECK(hipGetLastError());
   DD_HIP_CHECK(hipStreamSynchronize(stream));
-  DD_HIP_CHECK(hipFree(coef));
   return DD_OK;
 }
 

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "common.h"
+#include "devbuf.h"
 #include "gram.h"   // chol_inv
 #include "op.h"
 #include "resloss.h"
@@ -255,10 +256,11 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
     offR += (size_t)op->D;
     maxD = std::max(maxD, op->D);
   }
-  RlDesc* dd = nullptr;
-  double2* dc = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&dd, sizeof(RlDesc) * nb));
-  DD_HIP_CHECK(hipMalloc((void**)&dc, sizeof(double2) * 2 * (size_t)nb * k));
+  DevBuf bdd, bdc, bgp;
+  DD_HIP_CHECK(hipMalloc(&bdd.p, sizeof(RlDesc) * nb));
+  DD_HIP_CHECK(hipMalloc(&bdc.p, sizeof(double2) * 2 * (size_t)nb * k));
+  RlDesc* dd = (RlDesc*)bdd.p;
+  double2* dc = (double2*)bdc.p;
   for (int p = 0; p < nb; ++p) hd[p].c = dc + (size_t)p * k;
   DD_HIP_CHECK(hipMemcpyAsync(dd, hd.data(), sizeof(RlDesc) * nb, hipMemcpyHostToDevice, st));
   k_rl_apply<<<dim3((maxD + 255) / 256, k, nb), 256, 0, st>>>(dd);
@@ -269,9 +271,9 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
   int minD = maxD;
   for (const auto& d : hd) minD = std::min(minD, d.D);
   const int nslices = std::max(1, std::min({256, (2048 + nb - 1) / nb, minD / (8 * RL_GE)}));
-  double2* gp = nullptr;
   const size_t ngp = (size_t)nb * nslices * np;
-  DD_HIP_CHECK(hipMalloc((void**)&gp, sizeof(double2) * (ngp + (size_t)nb * np)));
+  DD_HIP_CHECK(hipMalloc(&bgp.p, sizeof(double2) * (ngp + (size_t)nb * np)));
+  double2* gp = (double2*)bgp.p;
   double2* gsum = gp + ngp;
   k_rl_gram<<<dim3(nslices, nb), 256, 0, st>>>(dd, k, nslices, gp);
   k_rl_gram_reduce<<<dim3((np + 255) / 256, nb), 256, 0, st>>>(gp, np, nslices, gsum);
@@ -279,7 +281,6 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
   std::vector<double2> hg((size_t)nb * np);
   DD_HIP_CHECK(hipMemcpyAsync(hg.data(), gsum, sizeof(double2) * hg.size(), hipMemcpyDeviceToHost, st));
   DD_HIP_CHECK(hipStreamSynchronize(st));
-  DD_HIP_CHECK(hipFree(gp));
   for (int p = 0; p < nb; ++p) {
     std::vector<cd> G((size_t)K1 * K1, cd(0.0)), c;
     for (int a = 0, q = 0; a < K1; ++a)
@@ -306,8 +307,6 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
     DD_HIP_CHECK(hipGetLastError());
   }
   DD_HIP_CHECK(hipStreamSynchronize(st));
-  DD_HIP_CHECK(hipFree(dd));
-  DD_HIP_CHECK(hipFree(dc));
   return DD_OK;
 }
 
@@ -326,10 +325,8 @@ extern "C" dd_status res_loss_batched(const fdfd_op* const* ops, const void* con
     }
     tot += (size_t)ops[p]->D;
   }
-  float2* Wb = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&Wb, sizeof(float2) * tot * k));
-  dd_status rc = res_loss_core(ops, b, V, nb, k, Wb, nullptr, nullptr, out, nullptr, 0, 0.0,
-                               stream);
-  (void)hipFree(Wb);
-  return rc;
+  DevBuf wb;
+  DD_HIP_CHECK(hipMalloc(&wb.p, sizeof(float2) * tot * k));
+  return res_loss_core(ops, b, V, nb, k, (float2*)wb.p, nullptr, nullptr, out, nullptr, 0, 0.0,
+                       stream);
 }
