@@ -38,6 +38,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 #define NL 8
 #define CNN_EPS_LO 2.085f
@@ -364,39 +365,76 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int kq = 8 * (lane >> 4);
+  // weight operand of tap t of the chunk at c0 (rows i * 16 + lane % 16)
+  auto wload = [&](int t, int c0, bf16x8 (&av)[MT]) {
+    const bf16* wt = a.W + (size_t)(BWD ? 8 - t : t) * a.M * a.Ksrc + c0 + kq;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
+  };
+  constexpr int NSTG = (CT_PH * CT_PW * 4 + 255) / 256;   // staging loads per thread
   for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
-    for (int u = threadIdx.x; u < CT_PH * CT_PW * 4; u += 256) {
+    // all of this thread's patch loads are issued before the first LDS store,
+    // and tap 0's weights are in flight meanwhile
+    bf16x8 wcur[MT], wnext[MT];
+    wload(0, c0, wcur);
+    u32x4 sv[NSTG];
+#pragma unroll
+    for (int it = 0; it < NSTG; ++it) {
+      const int u = threadIdx.x + 256 * it;
       const int pix = u >> 2, q = u & 3;
       const int py = pix / CT_PW, px = pix - py * CT_PW;
       const int uy = y0 + py - 1, ux = x0 + px - 1;   // conv-input grid (= output grid)
-      u32x4 v = u32x4{0u, 0u, 0u, 0u};
-      if (uy >= 0 && uy < Hq && ux >= 0 && ux < Wq) {
+      sv[it] = u32x4{0u, 0u, 0u, 0u};
+      if (u < CT_PH * CT_PW * 4 && uy >= 0 && uy < Hq && ux >= 0 && ux < Wq) {
         const int sy = up ? (uy >> 1) : uy, sx = up ? (ux >> 1) : ux;
-        v = *(const u32x4*)(a.src + ((size_t)(b * a.Hs + sy) * a.Ws + sx) * a.Ksrc + c0 + 8 * q);
+        sv[it] = *(const u32x4*)(a.src + ((size_t)(b * a.Hs + sy) * a.Ws + sx) * a.Ksrc + c0 + 8 * q);
       }
-      *(u32x4*)(patch + pix * CT_PS + 8 * q) = v;
+    }
+#pragma unroll
+    for (int it = 0; it < NSTG; ++it) {
+      const int u = threadIdx.x + 256 * it;
+      if (u < CT_PH * CT_PW * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
     }
     __syncthreads();
+    // taps: the next tap's weights are loaded while this tap's MFMAs run
 #pragma unroll 1
     for (int t = 0; t < 9; ++t) {
+      if (t + 1 < 9) wload(t + 1, c0, wnext);
       const int dy = t / 3, dx = t - 3 * (t / 3);
       bf16x8 bv[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         bv[j] = *(const bf16x8*)(patch + ((wave + dy) * CT_PW + 16 * j + (lane & 15) + dx) * CT_PS + kq);
-      const bf16* wt = a.W + (size_t)(BWD ? 8 - t : t) * a.M * a.Ksrc + c0 + kq;
 #pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        const bf16x8 av = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
+      for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], bv[j], acc[i][j], 0, 0, 0);
+      if (t + 1 < 9) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i) wcur[i] = wnext[i];
       }
     }
     __syncthreads();
   }
   const int y = y0 + wave;
   if (y >= Hq) return;
+  // epilogue operands (bias, or the ReLU mask of the layer input) are all
+  // loaded before any result is stored
+  float4 bias4[MT];
+  u32x2 mk[MT][4];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    const int r0 = i * 16 + 4 * (lane >> 4);
+    if (!BWD) bias4[i] = *(const float4*)(a.bias + r0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = x0 + 16 * j + (lane & 15);
+      mk[i][j] = u32x2{0u, 0u};
+      if (BWD && x < Wq)
+        mk[i][j] = *(const u32x2*)(a.mask + (((size_t)b * Hq + y) * Wq + x) * a.M + r0);
+    }
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int x = x0 + 16 * j + (lane & 15);
@@ -406,12 +444,15 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
     for (int i = 0; i < MT; ++i) {
       const int r0 = i * 16 + 4 * (lane >> 4);
       float v[4];
+      if (BWD) {
+        const bf16x4 m4 = __builtin_bit_cast(bf16x4, mk[i][j]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (BWD) {
-          v[q] = (bf2f(a.mask[p * a.M + r0 + q]) > 0.f) ? acc[i][j][q] : 0.f;
-        } else {
-          v[q] = acc[i][j][q] + a.bias[r0 + q];
+        for (int q = 0; q < 4; ++q) v[q] = ((float)m4[q] > 0.f) ? acc[i][j][q] : 0.f;
+      } else {
+        const float bq[4] = {bias4[i].x, bias4[i].y, bias4[i].z, bias4[i].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          v[q] = acc[i][j][q] + bq[q];
           if (a.relu) v[q] = fmaxf(v[q], 0.f);
         }
       }
