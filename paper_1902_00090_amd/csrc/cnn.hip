@@ -193,36 +193,56 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
     if (p >= npix) pb[j] = -1;
   }
   const int kq = 8 * (lane >> 4);
-  for (int e = 0; e < a.entries; ++e) {
-    const bf16* srcp[NT];
-    int tap = e;
+  // source rows of entry e for this lane's pixels (NULL: zero padding)
+  auto sources = [&](int e, const bf16* (&sp)[NT]) {
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-      srcp[j] = nullptr;
+      sp[j] = nullptr;
       if (pb[j] < 0) continue;
-      int sy, sx;
-      bool ok;
-      if (!BWD) {
-        ok = fwd_src(a.mode, py[j], px[j], e / 3, e % 3, a.Hs, a.Ws, a.Hout, a.Wout, sy, sx);
-      } else {
-        ok = bwd_src(a.mode, e, py[j], px[j], a.Hout, a.Wout, sy, sx, tap);
-      }
-      if (ok) srcp[j] = a.src + ((size_t)(pb[j] * a.Hs + sy) * a.Ws + sx) * a.Ksrc;
+      int sy, sx, tp;
+      const bool ok = BWD ? bwd_src(a.mode, e, py[j], px[j], a.Hout, a.Wout, sy, sx, tp)
+                          : fwd_src(a.mode, py[j], px[j], e / 3, e % 3, a.Hs, a.Ws, a.Hout,
+                                    a.Wout, sy, sx);
+      if (ok) sp[j] = a.src + ((size_t)(pb[j] * a.Hs + sy) * a.Ws + sx) * a.Ksrc;
     }
-    if (BWD) tap = e;   // same for every lane (bwd_src)
-    const bf16* wt = a.W + (size_t)tap * a.M * a.Ksrc;
-    for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
-      bf16x8 bv[NT];
+  };
+  // operands of (entry e, channels c0..c0+31); the weight tap is e (bwd_src)
+  auto operands = [&](int e, int c0, const bf16* const (&sp)[NT], bf16x8 (&bv)[NT],
+                      bf16x8 (&av)[MT]) {
 #pragma unroll
-      for (int j = 0; j < NT; ++j) bv[j] = srcp[j] ? load8(srcp[j] + c0 + kq) : zero8();
+    for (int j = 0; j < NT; ++j) bv[j] = sp[j] ? load8(sp[j] + c0 + kq) : zero8();
+    const bf16* wt = a.W + (size_t)e * a.M * a.Ksrc + c0 + kq;
 #pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        const bf16x8 av = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc + c0 + kq);
-#pragma unroll
-        for (int j = 0; j < NT; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
-      }
+    for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
+  };
+  // (entry, 32-channel chunk) iterations, the next one's loads in flight
+  // during the current one's MFMAs
+  const int nch = a.Ksrc / 32, niter = a.entries * nch;
+  const bf16* sp[NT];
+  bf16x8 bv[NT], av[MT];
+  sources(0, sp);
+  operands(0, 0, sp, bv, av);
+  int e = 0, c = 0;
+  for (int it = 0; it < niter; ++it) {
+    int en = e, cn = c + 1;
+    if (cn == nch) { cn = 0; ++en; }
+    bf16x8 bvn[NT], avn[MT];
+    if (it + 1 < niter) {
+      if (en != e) sources(en, sp);
+      operands(en, cn * 32, sp, bvn, avn);
     }
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    if (it + 1 < niter) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) bv[j] = bvn[j];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) av[i] = avn[i];
+    }
+    e = en; c = cn;
   }
   // epilogue: lane holds channels r0..r0+3 of pixel column (lane & 15)
 #pragma unroll
@@ -289,33 +309,39 @@ __global__ __launch_bounds__(256) void k_bwd_s2(GemmArgs a) {
   const int kq = 8 * (lane >> 4);
   const int dy0 = (y & 1) ? 0 : 1, ndy = (y & 1) ? 2 : 1;
   const int dx0 = par ? 0 : 1, ndx = par ? 2 : 1;
-  for (int iy = 0; iy < ndy; ++iy) {
-    const int dy = dy0 + 2 * iy, ty = y + 1 - dy;
-    if (ty < 0 || (ty >> 1) >= a.Hs) continue;
-    const int py = ty >> 1;
-    for (int ix = 0; ix < ndx; ++ix) {
-      const int dx = dx0 + 2 * ix, tap = 3 * dy + dx;
-      const bf16* srcp[NT];
+  // (tap, 32-channel chunk) iterations over this wave's 1, 2 or 4 taps, the
+  // next one's loads in flight during the current one's MFMAs
+  auto operands = [&](int tt, int c0, bf16x8 (&bv)[NT], bf16x8 (&av)[MT]) {
+    const int dy = dy0 + 2 * (tt / ndx), dx = dx0 + 2 * (tt % ndx), ty = y + 1 - dy;
+    const bool rowok = ty >= 0 && (ty >> 1) < a.Hs;
 #pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const int tx = xs[j] + 1 - dx;
-        srcp[j] = (xs[j] >= 0 && tx >= 0 && (tx >> 1) < a.Ws)
-                      ? a.src + ((size_t)(b * a.Hs + py) * a.Ws + (tx >> 1)) * a.Ksrc
-                      : nullptr;
-      }
-      const bf16* wt = a.W + (size_t)tap * a.M * a.Ksrc;
-      for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
-        bf16x8 bv[NT];
+    for (int j = 0; j < NT; ++j) {
+      const int tx = xs[j] + 1 - dx;
+      bv[j] = (rowok && xs[j] >= 0 && tx >= 0 && (tx >> 1) < a.Ws)
+                  ? load8(a.src + ((size_t)(b * a.Hs + (ty >> 1)) * a.Ws + (tx >> 1)) * a.Ksrc +
+                          c0 + kq)
+                  : zero8();
+    }
+    const bf16* wt = a.W + (size_t)(3 * dy + dx) * a.M * a.Ksrc + c0 + kq;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) bv[j] = srcp[j] ? load8(srcp[j] + c0 + kq) : zero8();
+    for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
+  };
+  const int nch = a.Ksrc / 32, niter = ndy * ndx * nch;
+  bf16x8 bv[NT], av[MT];
+  operands(0, 0, bv, av);
+  for (int it = 0; it < niter; ++it) {
+    bf16x8 bvn[NT], avn[MT];
+    if (it + 1 < niter) operands((it + 1) / nch, ((it + 1) % nch) * 32, bvn, avn);
 #pragma unroll
-        for (int i = 0; i < MT; ++i) {
-          const bf16x8 av = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc + c0 + kq);
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
-          for (int j = 0; j < NT; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
-        }
-      }
+      for (int j = 0; j < NT; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    if (it + 1 < niter) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) bv[j] = bvn[j];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) av[i] = avn[i];
     }
   }
 #pragma unroll
