@@ -1501,16 +1501,20 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   const CnnLayer& L = n->L[l];
   const int Mr = L.coutp, Nc = L.cinp, NB = std::min(Nc, 64);
   if (Nc % NB) return 0;
-  // S (stage width 32 S pixels) so that about 256 staging blocks fill the workgroup
-  const int per_s = 4 * (Mr / 8) + 12 * (NB / 8);
-  const int S = per_s <= 64 ? 4 : (per_s <= 128 ? 2 : 1);
-#define WG_CASES(F)                                                  \
-  if (Mr == 32 && NB == 32 && S == 4) return F(2, 2, 4);             \
-  if (Mr == 32 && NB == 64 && S == 2) return F(2, 4, 2);             \
-  if (Mr == 64 && NB == 32 && S == 2) return F(4, 2, 2);             \
-  if (Mr == 64 && NB == 64 && S == 2) return F(4, 4, 2);             \
-  if (Mr == 128 && NB == 32 && S == 2) return F(8, 2, 2);            \
-  if (Mr == 128 && NB == 64 && S == 1) return F(8, 4, 1);
+  // S (stage width 32 S pixels, 1, 2 or 4): the largest whose 8 x 8 staging
+  // blocks (dz, then the input pixels a stage needs) fit one per thread
+  auto blocks = [&](int S) {
+    const int xg = (L.mode == MAP_S1) ? 4 * S + 2 : (L.mode == MAP_UP) ? 2 * S + 1 : 12 * S;
+    return 4 * S * (Mr / 8) + xg * (NB / 8);
+  };
+  const int S = blocks(4) <= 256 ? 4 : (blocks(2) <= 256 ? 2 : 1);
+#define WG_CASES(F)                                                    \
+  if (Mr == 32 && NB == 32) return S == 4 ? F(2, 2, 4) : 0;            \
+  if (Mr == 32 && NB == 64) return S == 4 ? F(2, 4, 4) : F(2, 4, 2);   \
+  if (Mr == 64 && NB == 32) return S == 4 ? F(4, 2, 4) : F(4, 2, 2);   \
+  if (Mr == 64 && NB == 64) return S == 4 ? F(4, 4, 4) : F(4, 4, 2);   \
+  if (Mr == 128 && NB == 32) return S == 2 ? F(8, 2, 2) : 0;           \
+  if (Mr == 128 && NB == 64) return S == 2 ? F(8, 4, 2) : F(8, 4, 1);
 #define WG_SEG(a, b, c) launch_wgrad_seg<a, b, c>(n, l, B, st)
 #define WG_ROW1(a, b, c) launch_wgrad_row<a, b, c, false>(n, l, B, st)
 #define WG_ROWU(a, b, c) launch_wgrad_row<a, b, c, true>(n, l, B, st)
