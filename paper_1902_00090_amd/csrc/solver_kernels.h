@@ -552,22 +552,31 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
     double2* Hraw = P.Hraw + ((size_t)p * m + j) * (m + 1);
     double2* Hc = P.H + ((size_t)p * m + j) * (m + 1);
     double2* Bc = P.Bc + ((size_t)p * m + j) * P.kmax;
+    double2* hcol = col + k;
+    // the previous rotations, staged by all threads for thread 0's serial pass
+    __shared__ double cs_l[DD_MAX_M];
+    __shared__ double2 sn_l[DD_MAX_M];
+    for (int i = t; i < j; i += DD_BLOCK) {
+      cs_l[i] = P.cs[(size_t)p * m + i];
+      sn_l[i] = P.sn[(size_t)p * m + i];
+    }
     for (int v = t; v < k; v += DD_BLOCK) Bc[v] = col[v];
     for (int i = t; i <= j; i += DD_BLOCK) Hraw[i] = col[k + i];
+    __syncthreads();
     if (t == 0) {
       Hraw[j + 1] = make_double2(nrm, 0.0);
-      double2* hcol = col + k;
-      const double* cs = P.cs + (size_t)p * m;
-      const double2* sn = P.sn + (size_t)p * m;
+      // apply rotations 0..j-1 to the new column; the entry being rotated into
+      // the next position stays in registers
+      double2 cur = hcol[0];
       for (int i = 0; i < j; ++i) {
-        const double2 a = hcol[i], b = hcol[i + 1];
-        const double c = cs[i];
-        const double2 s = sn[i];
-        hcol[i] = dadd(make_double2(c * a.x, c * a.y), dmul(s, b));
-        hcol[i + 1] = dsub(make_double2(c * b.x, c * b.y), dmulc(s, a));
+        const double2 b = hcol[i + 1];
+        const double c = cs_l[i];
+        const double2 s = sn_l[i];
+        hcol[i] = dadd(make_double2(c * cur.x, c * cur.y), dmul(s, b));
+        cur = dsub(make_double2(c * b.x, c * b.y), dmulc(s, cur));
       }
       // new rotation zeroing the subdiagonal entry nrm
-      const double2 a = hcol[j];
+      const double2 a = cur;
       const double aa = sqrt(a.x * a.x + a.y * a.y);
       double c;
       double2 s, rr;
@@ -583,7 +592,6 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
       hcol[j] = rr;
       P.cs[(size_t)p * m + j] = c;
       P.sn[(size_t)p * m + j] = s;
-      for (int i = 0; i <= j; ++i) Hc[i] = hcol[i];
       Hc[j + 1] = make_double2(0.0, 0.0);
       double2* g = P.g + (size_t)p * (m + 1);
       const double2 gj = g[j];
@@ -608,6 +616,8 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
         nfin = j + 1;
       }
     }
+    __syncthreads();
+    for (int i = t; i <= j; i += DD_BLOCK) Hc[i] = hcol[i];   // the rotated column
   }
   __syncthreads();
   if (fin) finish_cycle(P, p, k, nfin);
