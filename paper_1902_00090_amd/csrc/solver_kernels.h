@@ -524,17 +524,32 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
   const int k = d.k;
   const int n = (mode == MODE_START) ? k : k + j + 1;
   const int m = P.m;
+  const int t = threadIdx.x;
+  double* sd = P.stD + p * SD_ND;
+  // thread 0's scalar state for an Arnoldi step, loaded before the reduction
+  // so that its latency overlaps it (only thread 0 writes these below)
+  double2 gj = make_double2(0.0, 0.0);
+  int it0 = 0, nre0 = 0;
+  double nsum0 = 0.0, nsum20 = 0.0, bn = 0.0, ctl_tol = 0.0, ctl_maxit = 0.0;
+  if (t == 0 && mode != MODE_START) {
+    gj = P.g[(size_t)p * (m + 1) + j];
+    it0 = st[ST_ITERS];
+    nre0 = st[ST_NREORTH];
+    nsum0 = sd[SD_NSUM];
+    nsum20 = sd[SD_NSUM2];
+    bn = sd[SD_PBNORM];
+    ctl_tol = P.ctl[0];
+    ctl_maxit = P.ctl[1];
+  }
   __shared__ double red[1];
   reduce_rows<PT>(P, d.blk0, d.nblk, 1, red);
   __shared__ double2 col[DD_MAX_K + DD_MAX_M + 2];
   __shared__ int fin, nfin;
-  const int t = threadIdx.x;
   const double2* cA = P.coefA + (size_t)p * P.NC;
   const double2* cB = P.coefB + (size_t)p * P.NC;
   for (int v = t; v < n; v += DD_BLOCK) col[v] = cgs2 ? dadd(cA[v], cB[v]) : cA[v];
   if (t == 0) fin = 0;
   __syncthreads();
-  double* sd = P.stD + p * SD_ND;
   const double nrm = sqrt(red[0]);
   if (mode == MODE_START) {
     const double rho = sd[SD_PRHO];
@@ -594,23 +609,22 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
       P.sn[(size_t)p * m + j] = s;
       Hc[j + 1] = make_double2(0.0, 0.0);
       double2* g = P.g + (size_t)p * (m + 1);
-      const double2 gj = g[j];
-      g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+      const double2 gn = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+      g[j + 1] = gn;
       g[j] = make_double2(c * gj.x, c * gj.y);
       P.hscale[(size_t)p * (m + 1) + j + 1] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
-      const int it = st[ST_ITERS] + 1;
+      const int it = it0 + 1;
       st[ST_ITERS] = it;
       if (cgs2) {
-        st[ST_NREORTH] += 1;
-        sd[SD_NSUM2] += (double)n;
+        st[ST_NREORTH] = nre0 + 1;
+        sd[SD_NSUM2] = nsum20 + (double)n;
       }
-      sd[SD_NSUM] += (double)n;
+      sd[SD_NSUM] = nsum0 + (double)n;
       st[ST_J] = j + 1;
-      const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
-      const double bn = sd[SD_PBNORM];
+      const double est = sqrt(gn.x * gn.x + gn.y * gn.y);
       sd[SD_EST] = est / bn;
       if (it <= P.hist_cap) P.hist[(size_t)p * P.hist_cap + it - 1] = est / bn;
-      if (est <= P.ctl[0] * bn || it >= (int)P.ctl[1] || !(nrm > 0.0) || !isfinite(nrm) ||
+      if (est <= ctl_tol * bn || it >= (int)ctl_maxit || !(nrm > 0.0) || !isfinite(nrm) ||
           j + 1 == m) {
         fin = 1;
         nfin = j + 1;
