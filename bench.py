@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc passes (FETCH_SIZE x2.000, WRITE_SIZE x1.000 after
 # calibration on a 1 GiB copy) over this workload (64 problems, k = 20); valid
 # only for the kernel sources they were taken with (see profiles/).
-MEASURED_TRAFFIC = {"bytes_per_launch": {"k_update_norm": 3.172e9, "k_matvec_dot": 3.190e9},
-                    "sources_sha256_16": "f816ca34ce8cb877"}
+MEASURED_TRAFFIC = {"bytes_per_launch": {"k_update_norm": 3.172e9, "k_matvec_dot": 3.189e9},
+                    "sources_sha256_16": "9f9ee175871076d2"}
 
 
 def kernel_sources_hash():
