@@ -494,6 +494,103 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
   }
 }
 
+// Forward pass of the stride-2 layers, LDS-tiled: a workgroup computes a
+// 4 x 32 tile of output pixels of one image for all M = 16 MT output channels.
+// Per 32 input channels it stages the 9 x 66 input patch the tile reads
+// (rows 2 y0 - 1 .. 2 y0 + 7, columns 2 x0 - 1 .. 2 x0 + 64, zero padding
+// resolved while staging) and applies the nine taps from LDS: output pixel
+// (y, x) reads patch pixel (2 (y - y0) + dy, 2 (x - x0) + dx).  Wave w owns
+// output row y0 + w (two pixel tiles of 16).  Loads are issued as in
+// k_conv_tile; operand layouts are k_conv_gemm's.
+#define CS_TH 4
+#define CS_TW 32
+#define CS_PH (2 * CS_TH + 1)
+#define CS_PW (2 * CS_TW + 2)
+template <int MT>
+__global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 patch[CS_PH * CS_PW * CT_PS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * CS_TW, y0 = blockIdx.y * CS_TH, b = blockIdx.z;
+  const int Hq = a.Hq, Wq = a.Wq;
+  f32x4 acc[MT][2];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kq = 8 * (lane >> 4);
+  auto wload = [&](int t, int c0, bf16x8 (&av)[MT]) {
+    const bf16* wt = a.W + (size_t)t * a.M * a.Ksrc + c0 + kq;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
+  };
+  constexpr int NSTG = (CS_PH * CS_PW * 4 + 255) / 256;
+  for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
+    bf16x8 wcur[MT], wnext[MT];
+    wload(0, c0, wcur);
+    u32x4 sv[NSTG];
+#pragma unroll
+    for (int it = 0; it < NSTG; ++it) {
+      const int u = threadIdx.x + 256 * it;
+      const int pix = u >> 2, q = u & 3;
+      const int py = pix / CS_PW, px = pix - py * CS_PW;
+      const int sy = 2 * y0 + py - 1, sx = 2 * x0 + px - 1;   // layer-input grid
+      sv[it] = u32x4{0u, 0u, 0u, 0u};
+      if (u < CS_PH * CS_PW * 4 && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws)
+        sv[it] = *(const u32x4*)(a.src + ((size_t)(b * a.Hs + sy) * a.Ws + sx) * a.Ksrc + c0 + 8 * q);
+    }
+#pragma unroll
+    for (int it = 0; it < NSTG; ++it) {
+      const int u = threadIdx.x + 256 * it;
+      if (u < CS_PH * CS_PW * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+      if (t + 1 < 9) wload(t + 1, c0, wnext);
+      const int dy = t / 3, dx = t - 3 * (t / 3);
+      bf16x8 bv[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        bv[j] = *(const bf16x8*)(patch + ((2 * wave + dy) * CS_PW + 2 * (16 * j + (lane & 15)) + dx) *
+                                             CT_PS + kq);
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], bv[j], acc[i][j], 0, 0, 0);
+      if (t + 1 < 9) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i) wcur[i] = wnext[i];
+      }
+    }
+    __syncthreads();
+  }
+  const int y = y0 + wave;
+  if (y >= Hq) return;
+  float4 bias4[MT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) bias4[i] = *(const float4*)(a.bias + i * 16 + 4 * (lane >> 4));
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int x = x0 + 16 * j + (lane & 15);
+    if (x >= Wq) continue;
+    const size_t p = ((size_t)b * Hq + y) * Wq + x;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      const int r0 = i * 16 + 4 * (lane >> 4);
+      const float bq[4] = {bias4[i].x, bias4[i].y, bias4[i].z, bias4[i].w};
+      bf16 h[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float v = acc[i][j][q] + bq[q];
+        if (a.relu) v = fmaxf(v, 0.f);
+        h[q] = (bf16)v;
+      }
+      *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
+    }
+  }
+}
+
 // ------------------------------------------------------------- layer 1 ----
 // Cin = 1 or 3 input planes: direct FP32 arithmetic (9 taps per plane), one
 // thread per pixel for all output channels (the weights are then uniform
@@ -1371,6 +1468,15 @@ static dd_status gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_
       case 2: k_conv_tile<2, true><<<grid, 256, 0, st>>>(a); break;
       case 4: k_conv_tile<4, true><<<grid, 256, 0, st>>>(a); break;
       case 8: k_conv_tile<8, true><<<grid, 256, 0, st>>>(a); break;
+    }
+    return DD_OK;
+  }
+  if (!bwd && a.mode == MAP_S2 && !a.outf) {
+    const dim3 grid((a.Wq + CS_TW - 1) / CS_TW, (a.Hq + CS_TH - 1) / CS_TH, a.B);
+    switch (MT) {
+      case 2: k_conv_tile_s2<2><<<grid, 256, 0, st>>>(a); break;
+      case 4: k_conv_tile_s2<4><<<grid, 256, 0, st>>>(a); break;
+      case 8: k_conv_tile_s2<8><<<grid, 256, 0, st>>>(a); break;
     }
     return DD_OK;
   }

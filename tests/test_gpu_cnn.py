@@ -50,7 +50,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("nx,ny,B", [(24, 16, 2), (40, 12, 3)])
+@pytest.mark.parametrize("nx,ny,B", [(24, 16, 2), (40, 12, 3), (8, 8, 1)])
 def test_forward_matches_oracle(nx, ny, B):
     k = 10
     net, op, eps, eps_d = _setup(nx, ny, B, k, seed=nx)
@@ -74,16 +74,22 @@ def test_forward_full_size_sampled():
     assert _rel(U, ocnn.channels_to_fields(out)) < 3e-2
 
 
-@pytest.mark.parametrize("nx,ny,k", [(24, 16, 10), (64, 32, 10), (40, 12, 20), (24, 16, 32)])
+@pytest.mark.parametrize("nx,ny,k", [(24, 16, 10), (64, 32, 10), (40, 12, 20), (24, 16, 32),
+                                     (8, 8, 10)])
 def test_gradients_match_oracle(nx, ny, k):
-    """Layers 2-8 take the staged pixel-segment weight-gradient kernel: its
-    stages cross rows and images at 24 x 16 and 40 x 12 (ragged last stage),
-    and k = 20 / 32 give the last layer 48 / 64 padded output channels.
-    Layer 1 takes the row-segment GEMM at 64 x 32 (width a multiple of 32)
-    and the per-row-block kernel elsewhere."""
+    """Weight gradients: row chunks for the stride-1 and upsampling layers
+    (one ragged chunk per row at these widths), flattened pixel stages for the
+    stride-2 layers (crossing rows and images, ragged at the end).  k = 20 / 32
+    give the last layer 40 / 64 real channels (padded to 64).  8 x 8 shrinks
+    the stride-2 layers to 4 x 4 and 2 x 2 outputs; there a weight gradient
+    sums so few products that the bf16 rounding of single activations and
+    ReLU decisions shows (7% norm-wise at batch 2, 2.7% at batch 8, 1.3% at
+    batch 32), so that case runs at batch 8.  Layer 1 takes the row-segment
+    GEMM at 64 x 32 (width a multiple of 32) and the per-row-block kernel
+    elsewhere."""
     import torch
     from paper_1902_00090_amd.cnn import flat_to_layers
-    B = 2
+    B = 8 if nx * ny <= 64 else 2
     net, op, eps, eps_d = _setup(nx, ny, B, k, seed=3)
     rng = np.random.default_rng(11)
     tgt = (rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny))) * 0.1
