@@ -280,86 +280,6 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
   }
 }
 
-// Backward data of the stride-2 layers.  A layer-input pixel (y, x) receives
-// dz only through the taps with y + 1 - dy and x + 1 - dx even: one tap per
-// dimension at even y (x), two at odd.  A wave takes NT tiles of 16 pixels of
-// one row and one column parity (x = 2 xh + par), so its tap set is uniform
-// and only those 1, 2 or 4 taps are applied (instead of all nine with most
-// gathers masked).  Layouts, weights and the ReLU mask are k_conv_gemm's.
-template <int MT, int NT>
-__global__ __launch_bounds__(256) void k_bwd_s2(GemmArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int Wh = (a.Wq + 1) / 2, ngr = ((Wh + 15) / 16 + NT - 1) / NT;   // x-tiles per parity
-  const int nitems = a.B * a.Hq * 2 * ngr;
-  const int item = blockIdx.x * 4 + wave;
-  if (item >= nitems) return;   // no barriers below
-  const int g = item % ngr, par = (item / ngr) & 1, row = item / (2 * ngr);
-  const int y = row % a.Hq, b = row / a.Hq;
-  int xs[NT];
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const int xh = (g * NT + j) * 16 + (lane & 15);
-    xs[j] = (2 * xh + par < a.Wq) ? 2 * xh + par : -1;
-  }
-  f32x4 acc[MT][NT];
-#pragma unroll
-  for (int i = 0; i < MT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int kq = 8 * (lane >> 4);
-  const int dy0 = (y & 1) ? 0 : 1, ndy = (y & 1) ? 2 : 1;
-  const int dx0 = par ? 0 : 1, ndx = par ? 2 : 1;
-  // (tap, 32-channel chunk) iterations over this wave's 1, 2 or 4 taps, the
-  // next one's loads in flight during the current one's MFMAs
-  auto operands = [&](int tt, int c0, bf16x8 (&bv)[NT], bf16x8 (&av)[MT]) {
-    const int dy = dy0 + 2 * (tt / ndx), dx = dx0 + 2 * (tt % ndx), ty = y + 1 - dy;
-    const bool rowok = ty >= 0 && (ty >> 1) < a.Hs;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int tx = xs[j] + 1 - dx;
-      bv[j] = (rowok && xs[j] >= 0 && tx >= 0 && (tx >> 1) < a.Ws)
-                  ? load8(a.src + ((size_t)(b * a.Hs + (ty >> 1)) * a.Ws + (tx >> 1)) * a.Ksrc +
-                          c0 + kq)
-                  : zero8();
-    }
-    const bf16* wt = a.W + (size_t)(3 * dy + dx) * a.M * a.Ksrc + c0 + kq;
-#pragma unroll
-    for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
-  };
-  const int nch = a.Ksrc / 32, niter = ndy * ndx * nch;
-  bf16x8 bv[NT], av[MT];
-  operands(0, 0, bv, av);
-  for (int it = 0; it < niter; ++it) {
-    bf16x8 bvn[NT], avn[MT];
-    if (it + 1 < niter) operands((it + 1) / nch, ((it + 1) % nch) * 32, bvn, avn);
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-      for (int j = 0; j < NT; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-    if (it + 1 < niter) {
-#pragma unroll
-      for (int j = 0; j < NT; ++j) bv[j] = bvn[j];
-#pragma unroll
-      for (int i = 0; i < MT; ++i) av[i] = avn[i];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    if (xs[j] < 0) continue;
-    const size_t p = ((size_t)b * a.Hq + y) * a.Wq + xs[j];
-#pragma unroll
-    for (int i = 0; i < MT; ++i) {
-      const int r0 = i * 16 + 4 * (lane >> 4);
-      const bf16* mk = a.mask + p * a.M + r0;
-      bf16 h[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) h[q] = (bf16)((bf2f(mk[q]) > 0.f) ? acc[i][j][q] : 0.f);
-      *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
-    }
-  }
-}
-
 // ---------------------------------------- LDS-tiled forward convolution ----
 // Forward pass of the stride-1 layers, plain (MAP_S1) or after a x2 nearest
 // upsample (MAP_UP), and (BWD) the backward-data pass of the plain stride-1
@@ -586,6 +506,121 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
         if (a.relu) v = fmaxf(v, 0.f);
         h[q] = (bf16)v;
       }
+      *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
+    }
+  }
+}
+
+// Backward data of the stride-2 layers, LDS-tiled: a workgroup computes a
+// 4 x 64 tile of layer-input pixels (all M = 16 MT channels) from the 3 x 33
+// dz pixels it reads (rows y0/2 .. y0/2 + 2, columns x0/2 .. x0/2 + 32),
+// staged in LDS per 32 dz channels.  Wave w owns input row y = y0 + w and four
+// pixel tiles of 16: even columns x0 + 2 i (tiles 0, 1) and odd columns
+// x0 + 2 i + 1 (tiles 2, 3).  Tap (dy, dx) reaches row y only when
+// y + 1 - dy is even (one dy at even y, two at odd) and a column only when
+// x + 1 - dx is even (dx = 1 for the even tiles, 0 and 2 for the odd ones), so
+// each wave applies 3 or 6 taps to two tiles each.  The next tap's weights
+// are loaded during the current tap's MFMAs.  Weights are the backward-data
+// copy [tap][cinp][coutp]; the epilogue masks by the ReLU of the layer input.
+#define BS_TH 4
+#define BS_TW 64
+#define BS_PR 3
+#define BS_PC 34
+template <int MT>
+__global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 patch[BS_PR * BS_PC * CT_PS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * BS_TW, y0 = blockIdx.y * BS_TH, b = blockIdx.z;
+  const int Hq = a.Hq, Wq = a.Wq, py0 = y0 / 2, px0 = x0 / 2;
+  const int y = y0 + wave;
+  f32x4 acc[MT][4];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kq = 8 * (lane >> 4);
+  const int dy0 = (y & 1) ? 0 : 1, ntap = (y & 1) ? 6 : 3;   // taps (dy0 + 2 (i / 3), i % 3)
+  auto wload = [&](int i, int c0, bf16x8 (&av)[MT]) {
+    const int tap = 3 * (dy0 + 2 * (i / 3)) + i % 3;
+    const bf16* wt = a.W + (size_t)tap * a.M * a.Ksrc + c0 + kq;
+#pragma unroll
+    for (int r = 0; r < MT; ++r) av[r] = load8(wt + (size_t)(r * 16 + (lane & 15)) * a.Ksrc);
+  };
+  constexpr int NSTG = (BS_PR * BS_PC * 4 + 255) / 256;
+  for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
+    bf16x8 wcur[MT], wnext[MT];
+    wload(0, c0, wcur);
+    u32x4 sv[NSTG];
+#pragma unroll
+    for (int it = 0; it < NSTG; ++it) {
+      const int u = threadIdx.x + 256 * it;
+      const int pix = u >> 2, q = u & 3;
+      const int pr = pix / BS_PC, pc = pix - pr * BS_PC;
+      const int sy = py0 + pr, sx = px0 + pc;   // dz grid
+      sv[it] = u32x4{0u, 0u, 0u, 0u};
+      if (u < BS_PR * BS_PC * 4 && sy < a.Hs && sx < a.Ws)
+        sv[it] = *(const u32x4*)(a.src + ((size_t)(b * a.Hs + sy) * a.Ws + sx) * a.Ksrc + c0 + 8 * q);
+    }
+#pragma unroll
+    for (int it = 0; it < NSTG; ++it) {
+      const int u = threadIdx.x + 256 * it;
+      if (u < BS_PR * BS_PC * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int i = 0; i < ntap; ++i) {
+      if (i + 1 < ntap) wload(i + 1, c0, wnext);
+      const int dy = dy0 + 2 * (i / 3), dx = i % 3;
+      const int pr = (y + 1 - dy) / 2 - py0;                 // 0..2
+      const int j0 = (dx == 1) ? 0 : 2;                      // even tiles take dx = 1
+      const int coff = (dx == 0) ? 1 : 0;                    // odd x, dx = 0: one column on
+      bf16x8 bv[2];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int c = 16 * jj + (lane & 15) + coff;
+        bv[jj] = *(const bf16x8*)(patch + (pr * BS_PC + c) * CT_PS + kq);
+      }
+#pragma unroll
+      for (int r = 0; r < MT; ++r) {
+        if (j0 == 0) {
+          acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[0], acc[r][0], 0, 0, 0);
+          acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[1], acc[r][1], 0, 0, 0);
+        } else {
+          acc[r][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[0], acc[r][2], 0, 0, 0);
+          acc[r][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[1], acc[r][3], 0, 0, 0);
+        }
+      }
+      if (i + 1 < ntap) {
+#pragma unroll
+        for (int r = 0; r < MT; ++r) wcur[r] = wnext[r];
+      }
+    }
+    __syncthreads();
+  }
+  if (y >= Hq) return;
+  u32x2 mk[MT][4];
+#pragma unroll
+  for (int r = 0; r < MT; ++r)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = x0 + 2 * (16 * (j & 1) + (lane & 15)) + (j >> 1);
+      mk[r][j] = u32x2{0u, 0u};
+      if (x < Wq)
+        mk[r][j] = *(const u32x2*)(a.mask + (((size_t)b * Hq + y) * Wq + x) * a.M + r * 16 +
+                                   4 * (lane >> 4));
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int x = x0 + 2 * (16 * (j & 1) + (lane & 15)) + (j >> 1);
+    if (x >= Wq) continue;
+    const size_t p = ((size_t)b * Hq + y) * Wq + x;
+#pragma unroll
+    for (int r = 0; r < MT; ++r) {
+      const int r0 = r * 16 + 4 * (lane >> 4);
+      const bf16x4 m4 = __builtin_bit_cast(bf16x4, mk[r][j]);
+      bf16 h[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = (bf16)(((float)m4[q] > 0.f) ? acc[r][j][q] : 0.f);
       *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
     }
   }
@@ -1481,15 +1516,11 @@ static dd_status gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_
     return DD_OK;
   }
   if (bwd && a.mode == MAP_S2) {
-    // wave items: (image, row, column parity, group of NT x-tiles of 16)
-    auto items = [&](int NT) {
-      const int ntile = ((a.Wq + 1) / 2 + 15) / 16;
-      return a.B * a.Hq * 2 * ((ntile + NT - 1) / NT);
-    };
+    const dim3 grid((a.Wq + BS_TW - 1) / BS_TW, (a.Hq + BS_TH - 1) / BS_TH, a.B);
     switch (MT) {
-      case 2: k_bwd_s2<2, 8><<<(items(8) + 3) / 4, 256, 0, st>>>(a); break;
-      case 4: k_bwd_s2<4, 4><<<(items(4) + 3) / 4, 256, 0, st>>>(a); break;
-      case 8: k_bwd_s2<8, 2><<<(items(2) + 3) / 4, 256, 0, st>>>(a); break;
+      case 2: k_bwd_s2_tile<2><<<grid, 256, 0, st>>>(a); break;
+      case 4: k_bwd_s2_tile<4><<<grid, 256, 0, st>>>(a); break;
+      case 8: k_bwd_s2_tile<8><<<grid, 256, 0, st>>>(a); break;
     }
     return DD_OK;
   }
