@@ -108,40 +108,17 @@ __device__ __forceinline__ bool fwd_src(int mode, int y, int x, int dy, int dx, 
   }
 }
 
-// Backward-data gather: for layer-input pixel (y, x) and entry e, the layer-
-// output pixel whose gradient reaches it through weight tap `tap`.
-//  * stride 1 and 2: tap e (one of the nine);
-//  * upsampled layers: the gradient of the x2 nearest upsample sums the four
-//    upsampled positions (2y + sy, 2x + sx), each seen by nine taps; grouped by
-//    the dz offset (oy, ox) = (sy - dy + 1, sx - dx + 1) in -1..2 these are 16
-//    entries e = 4 (oy + 1) + (ox + 1) reading dz at (2y + oy, 2x + ox) with an
-//    effective weight summed over the taps of that offset (k_pack_up_weights).
-__device__ __forceinline__ bool bwd_src(int mode, int e, int y, int x, int Hout, int Wout,
-                                        int& py, int& px, int& tap) {
-  if (mode == MAP_UP) {
-    tap = e;
-    py = 2 * y + e / 4 - 1; px = 2 * x + e % 4 - 1;
-    return py >= 0 && py < Hout && px >= 0 && px < Wout;
-  }
-  tap = e;
-  const int dy = tap / 3, dx = tap % 3;
-  if (mode == MAP_S1) {
-    py = y - dy + 1; px = x - dx + 1;
-    return py >= 0 && py < Hout && px >= 0 && px < Wout;
-  }
-  const int ty = y - dy + 1, tx = x - dx + 1;   // MAP_S2
-  if (ty < 0 || tx < 0 || (ty & 1) || (tx & 1)) return false;
-  py = ty >> 1; px = tx >> 1;
-  return py < Hout && px < Wout;
-}
-
-// ------------------------------------------------- implicit GEMM (MFMA) ----
-// Forward (BWD = false): out[p][r] = act(bias[r] + sum_{tap,c} Wf[tap][r][c] *
+// ------------------------------------------ convolutions as MFMA GEMMs ----
+// Forward: out[p][r] = act(bias[r] + sum_{tap,c} Wf[tap][r][c] *
 //   src[map(p, tap)][c]), p over output pixels, r < M = coutp.
-// Backward data (BWD = true): dzprev[q][r] = mask(q, r) * sum_{e,c} Wb[tap][r][c]
-//   * dz[gather(q, e)][c], q over layer-input pixels, r < M = cinp, mask = the
+// Backward data: dzprev[q][r] = mask(q, r) * sum_{tap,c} Wb[tap][r][c] *
+//   dz[gather(q, tap)][c], q over layer-input pixels, r < M = cinp, mask = the
 //   ReLU mask of the previous layer's output (the layer input).
-// MT = M / 16 row tiles per wave, NT pixel tiles of 16 per wave, 4 waves.
+// Operands of v_mfma_f32_16x16x32_bf16: A = 16 rows (result channels) x 32
+// source channels of one tap's weights, B = 32 source channels x 16 pixels;
+// lane l holds row / pixel l % 16 and channels 8 (l / 16) .. 8 (l / 16) + 7
+// (16-byte reads of NHWC data); the accumulator holds rows 4 (l / 16) .. + 3
+// of pixel l % 16.  MT = M / 16 row tiles.
 struct GemmArgs {
   const bf16* src;       // forward: layer input; backward: dz of this layer
   const bf16* W;         // Wf or Wb
@@ -152,10 +129,9 @@ struct GemmArgs {
   int nreal;             // real channels of the final layer (2 k)
   int B, Hq, Wq;         // grid of the result pixels
   int Hs, Ws;            // grid of the source pixels
-  int Hout, Wout;        // layer output grid (for the map functions)
   int Ksrc;              // channels of the source (multiple of 32)
   int M;                 // result channels (= 16 MT)
-  int mode, entries, relu;
+  int mode, relu;
 };
 
 // Final-layer epilogue: channels r0..r0+3 of pixel e of image b are (Re, Im)
@@ -171,115 +147,6 @@ __device__ __forceinline__ void store_fields(float* outf, int kf, int D, int b, 
   }
 }
 
-template <int MT, int NT, bool BWD>
-__global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int npix = a.B * a.Hq * a.Wq;
-  const int pbase = (blockIdx.x * 4 + wave) * NT * 16;
-  f32x4 acc[MT][NT];
-#pragma unroll
-  for (int i = 0; i < MT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int pb[NT], py[NT], px[NT];
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const int p = pbase + j * 16 + (lane & 15);
-    const int pc = min(p, npix - 1);
-    pb[j] = pc / (a.Hq * a.Wq);
-    const int rem = pc - pb[j] * a.Hq * a.Wq;
-    py[j] = rem / a.Wq;
-    px[j] = rem - py[j] * a.Wq;
-    if (p >= npix) pb[j] = -1;
-  }
-  const int kq = 8 * (lane >> 4);
-  // source rows of entry e for this lane's pixels (NULL: zero padding)
-  auto sources = [&](int e, const bf16* (&sp)[NT]) {
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      sp[j] = nullptr;
-      if (pb[j] < 0) continue;
-      int sy, sx, tp;
-      const bool ok = BWD ? bwd_src(a.mode, e, py[j], px[j], a.Hout, a.Wout, sy, sx, tp)
-                          : fwd_src(a.mode, py[j], px[j], e / 3, e % 3, a.Hs, a.Ws, a.Hout,
-                                    a.Wout, sy, sx);
-      if (ok) sp[j] = a.src + ((size_t)(pb[j] * a.Hs + sy) * a.Ws + sx) * a.Ksrc;
-    }
-  };
-  // operands of (entry e, channels c0..c0+31); the weight tap is e (bwd_src)
-  auto operands = [&](int e, int c0, const bf16* const (&sp)[NT], bf16x8 (&bv)[NT],
-                      bf16x8 (&av)[MT]) {
-#pragma unroll
-    for (int j = 0; j < NT; ++j) bv[j] = sp[j] ? load8(sp[j] + c0 + kq) : zero8();
-    const bf16* wt = a.W + (size_t)e * a.M * a.Ksrc + c0 + kq;
-#pragma unroll
-    for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
-  };
-  // (entry, 32-channel chunk) iterations, the next one's loads in flight
-  // during the current one's MFMAs
-  const int nch = a.Ksrc / 32, niter = a.entries * nch;
-  const bf16* sp[NT];
-  bf16x8 bv[NT], av[MT];
-  sources(0, sp);
-  operands(0, 0, sp, bv, av);
-  int e = 0, c = 0;
-  for (int it = 0; it < niter; ++it) {
-    int en = e, cn = c + 1;
-    if (cn == nch) { cn = 0; ++en; }
-    bf16x8 bvn[NT], avn[MT];
-    if (it + 1 < niter) {
-      if (en != e) sources(en, sp);
-      operands(en, cn * 32, sp, bvn, avn);
-    }
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-      for (int j = 0; j < NT; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-    if (it + 1 < niter) {
-#pragma unroll
-      for (int j = 0; j < NT; ++j) bv[j] = bvn[j];
-#pragma unroll
-      for (int i = 0; i < MT; ++i) av[i] = avn[i];
-    }
-    e = en; c = cn;
-  }
-  // epilogue: lane holds channels r0..r0+3 of pixel column (lane & 15)
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const int p = pbase + j * 16 + (lane & 15);
-    if (p >= npix) continue;
-#pragma unroll
-    for (int i = 0; i < MT; ++i) {
-      const int r0 = i * 16 + 4 * (lane >> 4);
-      float v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        v[q] = acc[i][j][q];
-        if (!BWD) {
-          v[q] += a.bias[r0 + q];
-          if (a.relu) v[q] = fmaxf(v[q], 0.f);
-        }
-      }
-      if (BWD) {
-        const bf16* mk = a.mask + (size_t)p * a.M + r0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (!(bf2f(mk[q]) > 0.f)) v[q] = 0.f;
-      }
-      if (a.outf) {
-        const int D = a.Hq * a.Wq, b = p / D;
-        store_fields(a.outf, a.nreal / 2, D, b, p - b * D, r0, v);
-      } else {
-        bf16 h[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) h[q] = (bf16)v[q];
-        *(u32x2*)(a.out + (size_t)p * a.M + r0) = __builtin_bit_cast(u32x2, h);
-      }
-    }
-  }
-}
-
 // ---------------------------------------- LDS-tiled forward convolution ----
 // Forward pass of the stride-1 layers, plain (MAP_S1) or after a x2 nearest
 // upsample (MAP_UP), and (BWD) the backward-data pass of the plain stride-1
@@ -291,8 +158,8 @@ __global__ __launch_bounds__(256) void k_conv_gemm(GemmArgs a) {
 // resolved while staging) is written once to LDS and read there by all nine
 // taps, so each source value is fetched from memory once instead of nine
 // times.  Wave w owns output row w of the tile (four pixel tiles of 16).  The
-// weights come from the L2-resident packed copy.  Operand layouts are those of
-// k_conv_gemm.
+// weights come from the L2-resident packed copy.  Operand layouts are those
+// described at GemmArgs.
 #define CT_TH 4
 #define CT_TW 64
 #define CT_PH (CT_TH + 2)
@@ -414,21 +281,25 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
   }
 }
 
-// Forward pass of the stride-2 layers, LDS-tiled: a workgroup computes a
-// 4 x 32 tile of output pixels of one image for all M = 16 MT output channels.
-// Per 32 input channels it stages the 9 x 66 input patch the tile reads
-// (rows 2 y0 - 1 .. 2 y0 + 7, columns 2 x0 - 1 .. 2 x0 + 64, zero padding
-// resolved while staging) and applies the nine taps from LDS: output pixel
-// (y, x) reads patch pixel (2 (y - y0) + dy, 2 (x - x0) + dx).  Wave w owns
-// output row y0 + w (two pixel tiles of 16).  Loads are issued as in
-// k_conv_tile; operand layouts are k_conv_gemm's.
+// Stride-2 reads from LDS, for two passes of the same form: output pixel
+// (y, x) of a 4 x 32 tile sums taps (ty, tx) over a KS x KS window of the
+// source at (2 y - 1 + ty, 2 x - 1 + tx), weight tap KS ty + tx:
+//  * KS = 3, forward of the stride-2 layers: source = layer input, weights Wf,
+//    bias and ReLU epilogue;
+//  * KS = 4, backward data of the upsampling layers (BWD): source = dz on the
+//    upsampled grid, the 16 effective weights of k_pack_up_weights, ReLU-mask
+//    epilogue.
+// A workgroup stages the (2 CS_TH + KS - 2) x (2 CS_TW + KS - 2) source patch of
+// its tile in LDS per 32 source channels (zero padding resolved while staging)
+// and applies the taps from there; wave w owns output row y0 + w (two pixel
+// tiles of 16).  Loads are issued as in k_conv_tile; operand layouts are
+// those described at GemmArgs.
 #define CS_TH 4
 #define CS_TW 32
-#define CS_PH (2 * CS_TH + 1)
-#define CS_PW (2 * CS_TW + 2)
-template <int MT>
+template <int MT, int KS, bool BWD>
 __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
-  __shared__ __attribute__((aligned(16))) bf16 patch[CS_PH * CS_PW * CT_PS];
+  constexpr int PH = 2 * CS_TH + KS - 2, PW = 2 * CS_TW + KS - 2, NTAP = KS * KS;
+  __shared__ __attribute__((aligned(16))) bf16 patch[PH * PW * CT_PS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x0 = blockIdx.x * CS_TW, y0 = blockIdx.y * CS_TH, b = blockIdx.z;
   const int Hq = a.Hq, Wq = a.Wq;
@@ -443,7 +314,7 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
   };
-  constexpr int NSTG = (CS_PH * CS_PW * 4 + 255) / 256;
+  constexpr int NSTG = (PH * PW * 4 + 255) / 256;
   for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
     bf16x8 wcur[MT], wnext[MT];
     wload(0, c0, wcur);
@@ -452,33 +323,33 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
     for (int it = 0; it < NSTG; ++it) {
       const int u = threadIdx.x + 256 * it;
       const int pix = u >> 2, q = u & 3;
-      const int py = pix / CS_PW, px = pix - py * CS_PW;
-      const int sy = 2 * y0 + py - 1, sx = 2 * x0 + px - 1;   // layer-input grid
+      const int py = pix / PW, px = pix - py * PW;
+      const int sy = 2 * y0 + py - 1, sx = 2 * x0 + px - 1;   // source grid
       sv[it] = u32x4{0u, 0u, 0u, 0u};
-      if (u < CS_PH * CS_PW * 4 && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws)
+      if (u < PH * PW * 4 && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws)
         sv[it] = *(const u32x4*)(a.src + ((size_t)(b * a.Hs + sy) * a.Ws + sx) * a.Ksrc + c0 + 8 * q);
     }
 #pragma unroll
     for (int it = 0; it < NSTG; ++it) {
       const int u = threadIdx.x + 256 * it;
-      if (u < CS_PH * CS_PW * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
+      if (u < PH * PW * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
     }
     __syncthreads();
 #pragma unroll 1
-    for (int t = 0; t < 9; ++t) {
-      if (t + 1 < 9) wload(t + 1, c0, wnext);
-      const int dy = t / 3, dx = t - 3 * (t / 3);
+    for (int t = 0; t < NTAP; ++t) {
+      if (t + 1 < NTAP) wload(t + 1, c0, wnext);
+      const int ty = t / KS, tx = t - KS * (t / KS);
       bf16x8 bv[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        bv[j] = *(const bf16x8*)(patch + ((2 * wave + dy) * CS_PW + 2 * (16 * j + (lane & 15)) + dx) *
+        bv[j] = *(const bf16x8*)(patch + ((2 * wave + ty) * PW + 2 * (16 * j + (lane & 15)) + tx) *
                                              CT_PS + kq);
 #pragma unroll
       for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], bv[j], acc[i][j], 0, 0, 0);
-      if (t + 1 < 9) {
+      if (t + 1 < NTAP) {
 #pragma unroll
         for (int i = 0; i < MT; ++i) wcur[i] = wnext[i];
       }
@@ -488,8 +359,19 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
   const int y = y0 + wave;
   if (y >= Hq) return;
   float4 bias4[MT];
+  u32x2 mk[MT][2];
 #pragma unroll
-  for (int i = 0; i < MT; ++i) bias4[i] = *(const float4*)(a.bias + i * 16 + 4 * (lane >> 4));
+  for (int i = 0; i < MT; ++i) {
+    const int r0 = i * 16 + 4 * (lane >> 4);
+    if (!BWD) bias4[i] = *(const float4*)(a.bias + r0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int x = x0 + 16 * j + (lane & 15);
+      mk[i][j] = u32x2{0u, 0u};
+      if (BWD && x < Wq)
+        mk[i][j] = *(const u32x2*)(a.mask + (((size_t)b * Hq + y) * Wq + x) * a.M + r0);
+    }
+  }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int x = x0 + 16 * j + (lane & 15);
@@ -498,13 +380,19 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
       const int r0 = i * 16 + 4 * (lane >> 4);
-      const float bq[4] = {bias4[i].x, bias4[i].y, bias4[i].z, bias4[i].w};
       bf16 h[4];
+      if (BWD) {
+        const bf16x4 m4 = __builtin_bit_cast(bf16x4, mk[i][j]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float v = acc[i][j][q] + bq[q];
-        if (a.relu) v = fmaxf(v, 0.f);
-        h[q] = (bf16)v;
+        for (int q = 0; q < 4; ++q) h[q] = (bf16)(((float)m4[q] > 0.f) ? acc[i][j][q] : 0.f);
+      } else {
+        const float bq[4] = {bias4[i].x, bias4[i].y, bias4[i].z, bias4[i].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v = acc[i][j][q] + bq[q];
+          if (a.relu) v = fmaxf(v, 0.f);
+          h[q] = (bf16)v;
+        }
       }
       *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
     }
@@ -1265,7 +1153,7 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Effective backward-data weights of an upsampled layer (bwd_src):
+// Effective backward-data weights of an upsampled layer (k_conv_tile_s2):
 // wu[e][ci][co] = sum of w[co][ci][dy][dx] over the taps whose dz offset is
 // (oy, ox) = (e / 4 - 1, e % 4 - 1), i.e. sy = oy + dy - 1 and sx = ox + dx - 1
 // in {0, 1}; FP32 sums rounded once to bf16.
@@ -1476,13 +1364,7 @@ extern "C" dd_status dd_cnn_set_params(dd_cnn* n, const float* host, size_t coun
   return DD_OK;
 }
 
-template <int MT, int NT, bool BWD>
-static void launch_gemm(const GemmArgs& a, int npix, hipStream_t st) {
-  const int per_block = 4 * NT * 16;
-  k_conv_gemm<MT, NT, BWD><<<(npix + per_block - 1) / per_block, 256, 0, st>>>(a);
-}
-
-static dd_status gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_t st) {
+static dd_status gemm_dispatch(const GemmArgs& a, bool bwd, hipStream_t st) {
   const int MT = a.M / 16;
   if ((MT != 2 && MT != 4 && MT != 8) || a.M % 16 || a.Ksrc % 32) {
     dd_set_error("dd_cnn: no convolution kernel for %d result / %d source channels", a.M, a.Ksrc);
@@ -1506,12 +1388,20 @@ static dd_status gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_
     }
     return DD_OK;
   }
-  if (!bwd && a.mode == MAP_S2 && !a.outf) {
+  if ((!bwd && a.mode == MAP_S2 && !a.outf) || (bwd && a.mode == MAP_UP)) {
     const dim3 grid((a.Wq + CS_TW - 1) / CS_TW, (a.Hq + CS_TH - 1) / CS_TH, a.B);
-    switch (MT) {
-      case 2: k_conv_tile_s2<2><<<grid, 256, 0, st>>>(a); break;
-      case 4: k_conv_tile_s2<4><<<grid, 256, 0, st>>>(a); break;
-      case 8: k_conv_tile_s2<8><<<grid, 256, 0, st>>>(a); break;
+    if (!bwd) {
+      switch (MT) {
+        case 2: k_conv_tile_s2<2, 3, false><<<grid, 256, 0, st>>>(a); break;
+        case 4: k_conv_tile_s2<4, 3, false><<<grid, 256, 0, st>>>(a); break;
+        case 8: k_conv_tile_s2<8, 3, false><<<grid, 256, 0, st>>>(a); break;
+      }
+    } else {
+      switch (MT) {
+        case 2: k_conv_tile_s2<2, 4, true><<<grid, 256, 0, st>>>(a); break;
+        case 4: k_conv_tile_s2<4, 4, true><<<grid, 256, 0, st>>>(a); break;
+        case 8: k_conv_tile_s2<8, 4, true><<<grid, 256, 0, st>>>(a); break;
+      }
     }
     return DD_OK;
   }
@@ -1524,20 +1414,8 @@ static dd_status gemm_dispatch(const GemmArgs& a, int npix, bool bwd, hipStream_
     }
     return DD_OK;
   }
-  if (!bwd) {
-    switch (MT) {
-      case 2: launch_gemm<2, 8, false>(a, npix, st); break;
-      case 4: launch_gemm<4, 4, false>(a, npix, st); break;
-      case 8: launch_gemm<8, 2, false>(a, npix, st); break;
-    }
-  } else {
-    switch (MT) {
-      case 2: launch_gemm<2, 8, true>(a, npix, st); break;
-      case 4: launch_gemm<4, 4, true>(a, npix, st); break;
-      case 8: launch_gemm<8, 2, true>(a, npix, st); break;
-    }
-  }
-  return DD_OK;
+  dd_set_error("dd_cnn: no convolution kernel for this layer map");
+  return DD_EINVAL;
 }
 
 // fields: destination of the complex output fields [B][k][D] (n->out if NULL)
@@ -1563,15 +1441,15 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
     a.W = n->wf[l];
     a.bias = n->biaspad + 256 * l;
     a.B = B; a.Hq = L.Hout; a.Wq = L.Wout;
-    a.Hs = L.Hin; a.Ws = L.Win; a.Hout = L.Hout; a.Wout = L.Wout;
-    a.Ksrc = L.cinp; a.M = L.coutp; a.mode = L.mode; a.entries = 9; a.relu = L.relu;
+    a.Hs = L.Hin; a.Ws = L.Win;
+    a.Ksrc = L.cinp; a.M = L.coutp; a.mode = L.mode; a.relu = L.relu;
     if (l == NL - 1) {
       a.outf = fields ? (float*)fields : n->out;
       a.nreal = L.cout;
       n->last_fields = a.outf;
     }
     else a.out = n->act[l];
-    const dd_status rc = gemm_dispatch(a, B * L.Hout * L.Wout, false, st);
+    const dd_status rc = gemm_dispatch(a, false, st);
     if (rc != DD_OK) return rc;
   }
   DD_HIP_CHECK(hipGetLastError());
@@ -1689,9 +1567,9 @@ static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
     a.mask = n->act[l - 1];
     a.out = n->dz[l - 1];
     a.B = B; a.Hq = L.Hin; a.Wq = L.Win;
-    a.Hs = L.Hout; a.Ws = L.Wout; a.Hout = L.Hout; a.Wout = L.Wout;
-    a.Ksrc = L.coutp; a.M = L.cinp; a.mode = L.mode; a.entries = L.up ? 16 : 9;
-    const dd_status rc = gemm_dispatch(a, B * L.Hin * L.Win, true, st);
+    a.Hs = L.Hout; a.Ws = L.Wout;
+    a.Ksrc = L.coutp; a.M = L.cinp; a.mode = L.mode;
+    const dd_status rc = gemm_dispatch(a, true, st);
     if (rc != DD_OK) return rc;
   }
   {
