@@ -140,6 +140,7 @@ __device__ __forceinline__ void rl_pair(int q, int K1, int& a, int& b) {
   b = a + q;
 }
 
+template <int NI>   // staging values per thread: ceil((k + 1) RL_GE / 256) <= NI
 __global__ __launch_bounds__(256) void k_rl_gram(const RlDesc* __restrict__ desc, int k, int nslices,
                                                  double2* __restrict__ part) {
   __shared__ double2 xs[RL_GE * RL_LD];
@@ -148,35 +149,53 @@ __global__ __launch_bounds__(256) void k_rl_gram(const RlDesc* __restrict__ desc
   const RlDesc d = desc[p];
   const int per = ((d.D + nslices - 1) / nslices + RL_GE - 1) / RL_GE * RL_GE;
   const int e0 = slice * per, e1 = min(d.D, e0 + per);
+  // with few pairs (np <= 128) tpp threads share a pair, each taking every
+  // tpp-th element of a chunk; otherwise a thread owns pairs t, t + 256, ...
+  const int tpp = (np <= 128) ? min(8, 256 / np) : 1;
+  const int sub = t % tpp, t0 = t / tpp, npt = (tpp > 1) ? np : 256;   // pairs t0 + q npt
   int pa[RL_MAXP], pb[RL_MAXP];
   double sx[RL_MAXP], sy[RL_MAXP];
 #pragma unroll
   for (int q = 0; q < RL_MAXP; ++q) {
     pa[q] = pb[q] = 0;
-    if (q * 256 + t < np) rl_pair(q * 256 + t, K1, pa[q], pb[q]);
+    if (q * npt + t0 < np && (tpp == 1 || q == 0)) rl_pair(q * npt + t0, K1, pa[q], pb[q]);
     sx[q] = sy[q] = 0.0;
   }
-  for (int c0 = e0; c0 < e1; c0 += RL_GE) {
-    __syncthreads();
-    for (int i = t; i < K1 * RL_GE; i += 256) {
+  const int nq = (tpp > 1) ? 1 : RL_MAXP;
+  // this thread's staging values of the chunk at c0 (items t, t + 256, ...),
+  // loaded one chunk ahead of their use
+  double2 xv[NI];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = t + 256 * j;
       const int v = i / RL_GE, el = i - v * RL_GE, e = c0 + el;
-      double2 x = make_double2(0.0, 0.0);
-      if (e < e1) {
+      xv[j] = make_double2(0.0, 0.0);
+      if (i < K1 * RL_GE && e < e1) {
         if (v < k) {
           const float2 w = d.W[(size_t)v * d.D + e];
-          x = make_double2(w.x, w.y);
+          xv[j] = make_double2(w.x, w.y);
         } else {
-          x = d.b[e];
+          xv[j] = d.b[e];
         }
       }
-      xs[el * RL_LD + v] = x;
     }
+  };
+  if (e0 < e1) load(e0);
+  for (int c0 = e0; c0 < e1; c0 += RL_GE) {
     __syncthreads();
 #pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = t + 256 * j;
+      if (i < K1 * RL_GE) xs[(i % RL_GE) * RL_LD + i / RL_GE] = xv[j];
+    }
+    __syncthreads();
+    if (c0 + RL_GE < e1) load(c0 + RL_GE);
+#pragma unroll
     for (int q = 0; q < RL_MAXP; ++q) {
-      if (q * 256 + t < np) {
+      if (q < nq && q * npt + t0 < np) {
         double ax = 0.0, ay = 0.0;
-        for (int el = 0; el < RL_GE; ++el) {
+        for (int el = sub; el < RL_GE; el += tpp) {
           const double2 xa = xs[el * RL_LD + pa[q]], xb = xs[el * RL_LD + pb[q]];
           ax += xa.x * xb.x + xa.y * xb.y;
           ay += xa.x * xb.y - xa.y * xb.x;
@@ -185,6 +204,20 @@ __global__ __launch_bounds__(256) void k_rl_gram(const RlDesc* __restrict__ desc
         sy[q] += ay;
       }
     }
+  }
+  if (tpp > 1) {   // add the tpp partial sums of a pair in sub order
+    __syncthreads();
+    xs[t] = make_double2(sx[0], sy[0]);
+    __syncthreads();
+    if (sub == 0 && t0 < np) {
+      double tx = 0.0, ty = 0.0;
+      for (int j = 0; j < tpp; ++j) {
+        tx += xs[t + j].x;
+        ty += xs[t + j].y;
+      }
+      part[((size_t)p * nslices + slice) * np + t0] = make_double2(tx, ty);
+    }
+    return;
   }
 #pragma unroll
   for (int q = 0; q < RL_MAXP; ++q)
@@ -275,7 +308,10 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
   DD_HIP_CHECK(hipMalloc(&bgp.p, sizeof(double2) * (ngp + (size_t)nb * np)));
   double2* gp = (double2*)bgp.p;
   double2* gsum = gp + ngp;
-  k_rl_gram<<<dim3(nslices, nb), 256, 0, st>>>(dd, k, nslices, gp);
+  if (K1 * RL_GE <= 2 * 256)
+    k_rl_gram<2><<<dim3(nslices, nb), 256, 0, st>>>(dd, k, nslices, gp);
+  else
+    k_rl_gram<(RL_LD * RL_GE + 255) / 256><<<dim3(nslices, nb), 256, 0, st>>>(dd, k, nslices, gp);
   k_rl_gram_reduce<<<dim3((np + 255) / 256, nb), 256, 0, st>>>(gp, np, nslices, gsum);
   DD_HIP_CHECK(hipGetLastError());
   std::vector<double2> hg((size_t)nb * np);
