@@ -165,9 +165,12 @@ __device__ __forceinline__ void store_fields(float* outf, int kf, int D, int b, 
 #define CT_PH (CT_TH + 2)
 #define CT_PW (CT_TW + 2)
 #define CT_PS 40   // bf16 per staged pixel: 32 channels + 8 of padding (80-byte stride)
-template <int MT, bool BWD = false>
+template <int MT, bool BWD = false, bool WL = false>
 __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) bf16 patch[CT_PH * CT_PW * CT_PS];
+  // WL: the chunk's weights of all nine taps are staged in LDS with the patch
+  // ([tap][row][40], 80-byte rows), so the tap loop waits on no global load
+  __shared__ __attribute__((aligned(16))) bf16 wl[WL ? 9 * 16 * MT * CT_PS : 8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x0 = blockIdx.x * CT_TW, y0 = blockIdx.y * CT_TH, b = blockIdx.z;
   const int Hq = a.Hq, Wq = a.Wq;
@@ -185,11 +188,25 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
     for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
   };
   constexpr int NSTG = (CT_PH * CT_PW * 4 + 255) / 256;   // staging loads per thread
+  constexpr int NWI = 9 * 16 * MT * 4, NWS = WL ? (NWI + 255) / 256 : 1;   // weight items
   for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
     // all of this thread's patch loads are issued before the first LDS store,
     // and tap 0's weights are in flight meanwhile
     bf16x8 wcur[MT], wnext[MT];
-    wload(0, c0, wcur);
+    u32x4 wv[NWS];
+    if (WL) {
+#pragma unroll
+      for (int it = 0; it < NWS; ++it) {
+        const int u = threadIdx.x + 256 * it;   // (tap, row, quarter)
+        const int tq = u / (16 * MT * 4), rem = u - tq * 16 * MT * 4;
+        wv[it] = u32x4{0u, 0u, 0u, 0u};
+        if (u < NWI)
+          wv[it] = *(const u32x4*)(a.W + ((size_t)(BWD ? 8 - tq : tq) * a.M + (rem >> 2)) * a.Ksrc +
+                                   c0 + 8 * (rem & 3));
+      }
+    } else {
+      wload(0, c0, wcur);
+    }
     u32x4 sv[NSTG];
 #pragma unroll
     for (int it = 0; it < NSTG; ++it) {
@@ -208,11 +225,24 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
       const int u = threadIdx.x + 256 * it;
       if (u < CT_PH * CT_PW * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
     }
+    if (WL) {
+#pragma unroll
+      for (int it = 0; it < NWS; ++it) {
+        const int u = threadIdx.x + 256 * it;
+        if (u < NWI) *(u32x4*)(wl + (u >> 2) * CT_PS + 8 * (u & 3)) = wv[it];
+      }
+    }
     __syncthreads();
     // taps: the next tap's weights are loaded while this tap's MFMAs run
 #pragma unroll 1
     for (int t = 0; t < 9; ++t) {
-      if (t + 1 < 9) wload(t + 1, c0, wnext);
+      if (WL) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+          wcur[i] = *(const bf16x8*)(wl + ((t * 16 * MT) + i * 16 + (lane & 15)) * CT_PS + kq);
+      } else if (t + 1 < 9) {
+        wload(t + 1, c0, wnext);
+      }
       const int dy = t / 3, dx = t - 3 * (t / 3);
       bf16x8 bv[4];
 #pragma unroll
@@ -223,7 +253,7 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], bv[j], acc[i][j], 0, 0, 0);
-      if (t + 1 < 9) {
+      if (!WL && t + 1 < 9) {
 #pragma unroll
         for (int i = 0; i < MT; ++i) wcur[i] = wnext[i];
       }
@@ -1370,21 +1400,42 @@ static dd_status gemm_dispatch(const GemmArgs& a, bool bwd, hipStream_t st) {
     dd_set_error("dd_cnn: no convolution kernel for %d result / %d source channels", a.M, a.Ksrc);
     return DD_EINVAL;
   }
+  // several 32-channel chunks: weights staged in LDS (fewer resident
+  // workgroups, no global loads in the tap loop); one chunk: weights from L2
+  const bool wl = a.Ksrc > 32;
   if (!bwd && (a.mode == MAP_S1 || a.mode == MAP_UP)) {
     const dim3 grid((a.Wq + CT_TW - 1) / CT_TW, (a.Hq + CT_TH - 1) / CT_TH, a.B);
     switch (MT) {
-      case 2: k_conv_tile<2><<<grid, 256, 0, st>>>(a); break;
-      case 4: k_conv_tile<4><<<grid, 256, 0, st>>>(a); break;
-      case 8: k_conv_tile<8><<<grid, 256, 0, st>>>(a); break;
+      case 2:
+        if (wl) k_conv_tile<2, false, true><<<grid, 256, 0, st>>>(a);
+        else k_conv_tile<2><<<grid, 256, 0, st>>>(a);
+        break;
+      case 4:
+        if (wl) k_conv_tile<4, false, true><<<grid, 256, 0, st>>>(a);
+        else k_conv_tile<4><<<grid, 256, 0, st>>>(a);
+        break;
+      case 8:
+        if (wl) k_conv_tile<8, false, true><<<grid, 256, 0, st>>>(a);
+        else k_conv_tile<8><<<grid, 256, 0, st>>>(a);
+        break;
     }
     return DD_OK;
   }
   if (bwd && a.mode == MAP_S1) {
     const dim3 grid((a.Wq + CT_TW - 1) / CT_TW, (a.Hq + CT_TH - 1) / CT_TH, a.B);
     switch (MT) {
-      case 2: k_conv_tile<2, true><<<grid, 256, 0, st>>>(a); break;
-      case 4: k_conv_tile<4, true><<<grid, 256, 0, st>>>(a); break;
-      case 8: k_conv_tile<8, true><<<grid, 256, 0, st>>>(a); break;
+      case 2:
+        if (wl) k_conv_tile<2, true, true><<<grid, 256, 0, st>>>(a);
+        else k_conv_tile<2, true><<<grid, 256, 0, st>>>(a);
+        break;
+      case 4:
+        if (wl) k_conv_tile<4, true, true><<<grid, 256, 0, st>>>(a);
+        else k_conv_tile<4, true><<<grid, 256, 0, st>>>(a);
+        break;
+      case 8:
+        if (wl) k_conv_tile<8, true, true><<<grid, 256, 0, st>>>(a);
+        else k_conv_tile<8, true><<<grid, 256, 0, st>>>(a);
+        break;
     }
     return DD_OK;
   }
