@@ -322,14 +322,16 @@ __global__ __launch_bounds__(256) void k_conv_tile(GemmArgs a) {
 // A workgroup stages the (2 CS_TH + KS - 2) x (2 CS_TW + KS - 2) source patch of
 // its tile in LDS per 32 source channels (zero padding resolved while staging)
 // and applies the taps from there; wave w owns output row y0 + w (two pixel
-// tiles of 16).  Loads are issued as in k_conv_tile; operand layouts are
-// those described at GemmArgs.
+// tiles of 16).  Loads are issued as in k_conv_tile, and WL stages the
+// weights in LDS as there; operand layouts are those described at GemmArgs.
 #define CS_TH 4
 #define CS_TW 32
-template <int MT, int KS, bool BWD>
+template <int MT, int KS, bool BWD, bool WL = false>
 __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
   constexpr int PH = 2 * CS_TH + KS - 2, PW = 2 * CS_TW + KS - 2, NTAP = KS * KS;
   __shared__ __attribute__((aligned(16))) bf16 patch[PH * PW * CT_PS];
+  // WL: the chunk's weights of every tap, staged with the patch ([tap][row][40])
+  __shared__ __attribute__((aligned(16))) bf16 wl[WL ? NTAP * 16 * MT * CT_PS : 8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x0 = blockIdx.x * CS_TW, y0 = blockIdx.y * CS_TH, b = blockIdx.z;
   const int Hq = a.Hq, Wq = a.Wq;
@@ -345,9 +347,22 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
     for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
   };
   constexpr int NSTG = (PH * PW * 4 + 255) / 256;
+  constexpr int NWI = WL ? NTAP * 16 * MT * 4 : 0, NWS = (NWI + 255) / 256;
   for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
     bf16x8 wcur[MT], wnext[MT];
-    wload(0, c0, wcur);
+    u32x4 wv[NWS > 0 ? NWS : 1];
+    if (WL) {
+#pragma unroll
+      for (int it = 0; it < NWS; ++it) {
+        const int u = threadIdx.x + 256 * it;   // (tap, row, quarter)
+        const int tq = u / (16 * MT * 4), rem = u - tq * 16 * MT * 4;
+        wv[it] = u32x4{0u, 0u, 0u, 0u};
+        if (u < NWI)
+          wv[it] = *(const u32x4*)(a.W + ((size_t)tq * a.M + (rem >> 2)) * a.Ksrc + c0 + 8 * (rem & 3));
+      }
+    } else {
+      wload(0, c0, wcur);
+    }
     u32x4 sv[NSTG];
 #pragma unroll
     for (int it = 0; it < NSTG; ++it) {
@@ -364,10 +379,23 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
       const int u = threadIdx.x + 256 * it;
       if (u < PH * PW * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
     }
+    if (WL) {
+#pragma unroll
+      for (int it = 0; it < NWS; ++it) {
+        const int u = threadIdx.x + 256 * it;
+        if (u < NWI) *(u32x4*)(wl + (u >> 2) * CT_PS + 8 * (u & 3)) = wv[it];
+      }
+    }
     __syncthreads();
 #pragma unroll 1
     for (int t = 0; t < NTAP; ++t) {
-      if (t + 1 < NTAP) wload(t + 1, c0, wnext);
+      if (WL) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+          wcur[i] = *(const bf16x8*)(wl + (t * 16 * MT + i * 16 + (lane & 15)) * CT_PS + kq);
+      } else if (t + 1 < NTAP) {
+        wload(t + 1, c0, wnext);
+      }
       const int ty = t / KS, tx = t - KS * (t / KS);
       bf16x8 bv[2];
 #pragma unroll
@@ -379,7 +407,7 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], bv[j], acc[i][j], 0, 0, 0);
-      if (t + 1 < NTAP) {
+      if (!WL && t + 1 < NTAP) {
 #pragma unroll
         for (int i = 0; i < MT; ++i) wcur[i] = wnext[i];
       }
@@ -437,9 +465,9 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
 // x0 + 2 i + 1 (tiles 2, 3).  Tap (dy, dx) reaches row y only when
 // y + 1 - dy is even (one dy at even y, two at odd) and a column only when
 // x + 1 - dx is even (dx = 1 for the even tiles, 0 and 2 for the odd ones), so
-// each wave applies 3 or 6 taps to two tiles each.  The next tap's weights
-// are loaded during the current tap's MFMAs.  Weights are the backward-data
-// copy [tap][cinp][coutp]; the epilogue masks by the ReLU of the layer input.
+// each wave applies 3 or 6 taps to two tiles each.  The weights of all nine
+// taps (backward-data copy [tap][cinp][coutp]) are staged in LDS with the
+// patch; the epilogue masks by the ReLU of the layer input.
 #define BS_TH 4
 #define BS_TW 64
 #define BS_PR 3
@@ -447,6 +475,8 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
 template <int MT>
 __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) bf16 patch[BS_PR * BS_PC * CT_PS];
+  // the chunk's weights of all nine taps, staged with the patch ([tap][row][40])
+  __shared__ __attribute__((aligned(16))) bf16 wl[9 * 16 * MT * CT_PS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x0 = blockIdx.x * BS_TW, y0 = blockIdx.y * BS_TH, b = blockIdx.z;
   const int Hq = a.Hq, Wq = a.Wq, py0 = y0 / 2, px0 = x0 / 2;
@@ -458,16 +488,19 @@ __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int kq = 8 * (lane >> 4);
   const int dy0 = (y & 1) ? 0 : 1, ntap = (y & 1) ? 6 : 3;   // taps (dy0 + 2 (i / 3), i % 3)
-  auto wload = [&](int i, int c0, bf16x8 (&av)[MT]) {
-    const int tap = 3 * (dy0 + 2 * (i / 3)) + i % 3;
-    const bf16* wt = a.W + (size_t)tap * a.M * a.Ksrc + c0 + kq;
-#pragma unroll
-    for (int r = 0; r < MT; ++r) av[r] = load8(wt + (size_t)(r * 16 + (lane & 15)) * a.Ksrc);
-  };
   constexpr int NSTG = (BS_PR * BS_PC * 4 + 255) / 256;
+  constexpr int NWI = 9 * 16 * MT * 4, NWS = (NWI + 255) / 256;   // weight items
   for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
-    bf16x8 wcur[MT], wnext[MT];
-    wload(0, c0, wcur);
+    bf16x8 wcur[MT];
+    u32x4 wv[NWS];
+#pragma unroll
+    for (int it = 0; it < NWS; ++it) {
+      const int u = threadIdx.x + 256 * it;   // (tap, row, quarter)
+      const int tq = u / (16 * MT * 4), rem = u - tq * 16 * MT * 4;
+      wv[it] = u32x4{0u, 0u, 0u, 0u};
+      if (u < NWI)
+        wv[it] = *(const u32x4*)(a.W + ((size_t)tq * a.M + (rem >> 2)) * a.Ksrc + c0 + 8 * (rem & 3));
+    }
     u32x4 sv[NSTG];
 #pragma unroll
     for (int it = 0; it < NSTG; ++it) {
@@ -484,11 +517,18 @@ __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
       const int u = threadIdx.x + 256 * it;
       if (u < BS_PR * BS_PC * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
     }
+#pragma unroll
+    for (int it = 0; it < NWS; ++it) {
+      const int u = threadIdx.x + 256 * it;
+      if (u < NWI) *(u32x4*)(wl + (u >> 2) * CT_PS + 8 * (u & 3)) = wv[it];
+    }
     __syncthreads();
 #pragma unroll 1
     for (int i = 0; i < ntap; ++i) {
-      if (i + 1 < ntap) wload(i + 1, c0, wnext);
       const int dy = dy0 + 2 * (i / 3), dx = i % 3;
+#pragma unroll
+      for (int r = 0; r < MT; ++r)
+        wcur[r] = *(const bf16x8*)(wl + ((3 * dy + dx) * 16 * MT + r * 16 + (lane & 15)) * CT_PS + kq);
       const int pr = (y + 1 - dy) / 2 - py0;                 // 0..2
       const int j0 = (dx == 1) ? 0 : 2;                      // even tiles take dx = 1
       const int coff = (dx == 0) ? 1 : 0;                    // odd x, dx = 0: one column on
@@ -507,10 +547,6 @@ __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
           acc[r][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[0], acc[r][2], 0, 0, 0);
           acc[r][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[1], acc[r][3], 0, 0, 0);
         }
-      }
-      if (i + 1 < ntap) {
-#pragma unroll
-        for (int r = 0; r < MT; ++r) wcur[r] = wnext[r];
       }
     }
     __syncthreads();
@@ -1445,7 +1481,10 @@ static dd_status gemm_dispatch(const GemmArgs& a, bool bwd, hipStream_t st) {
       switch (MT) {
         case 2: k_conv_tile_s2<2, 3, false><<<grid, 256, 0, st>>>(a); break;
         case 4: k_conv_tile_s2<4, 3, false><<<grid, 256, 0, st>>>(a); break;
-        case 8: k_conv_tile_s2<8, 3, false><<<grid, 256, 0, st>>>(a); break;
+        case 8:
+          if (a.Ksrc > 32) k_conv_tile_s2<8, 3, false, true><<<grid, 256, 0, st>>>(a);
+          else k_conv_tile_s2<8, 3, false><<<grid, 256, 0, st>>>(a);
+          break;
       }
     } else {
       switch (MT) {
