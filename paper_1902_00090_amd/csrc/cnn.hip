@@ -581,41 +581,91 @@ __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
 }
 
 // ------------------------------------------------------------- layer 1 ----
-// Cin = 1 or 3 input planes: direct FP32 arithmetic (9 taps per plane), one
-// thread per pixel for all output channels (the weights are then uniform
-// across the wave and come through the scalar cache); 16-byte stores of 8
-// channels.  x0 is planar [B][C][H][W].
+// Cin = 1 or 3 input planes, 32 output channels, FP32 throughout on the
+// matrix cores: per 16 output pixels the product W[32][9C] . X[9C][16] runs as
+// FP32 16x16x4 MFMAs over K = 9C padded to a multiple of 4 (k = 9 c + tap,
+// padded rows zero).  Lane l supplies weight row l % 16 / k-slot l / 16 and
+// the input of pixel l % 16 at k-slot l / 16; its accumulators hold output
+// channels 4 (l / 16) + q of pixel l % 16.  A wave takes C1_NT tiles of 16
+// consecutive pixels (row-major over [B][H][W]) and issues every input load
+// before its first MFMA; 8-byte bf16 stores of 4 channels.  x0 is planar
+// [B][C][H][W], w is [32][C][9].
+#define C1_NT 8
+template <int C>
 __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
                                                    const float* __restrict__ w,
-                                                   const float* __restrict__ bias, int B, int C,
-                                                   int H, int W, int coutp,
-                                                   bf16* __restrict__ out) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= B * H * W) return;
-  const int b = p / (H * W), rem = p - b * H * W, y = rem / W, x = rem - (rem / W) * W;
-  float xin[3][9];
+                                                   const float* __restrict__ bias, int B, int H,
+                                                   int W, bf16* __restrict__ out) {
+  constexpr int KS = (9 * C + 3) / 4;   // k-steps of 4
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ks = lane >> 4, col = lane & 15;
+  const int total = B * H * W;
+  float av[2][KS];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + ks;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int ys = y + t / 3 - 1, xs = x + t % 3 - 1;
-      xin[c][t] = (c < C && ys >= 0 && ys < H && xs >= 0 && xs < W)
-                      ? x0[(((size_t)b * C + c) * H + ys) * W + xs] : 0.f;
+    for (int i = 0; i < 2; ++i) av[i][s] = (k < 9 * C) ? w[(16 * i + col) * 9 * C + k] : 0.f;
+  }
+  // per k-slot: plane offset and tap shift, the same for every pixel tile
+  const int HW = H * W;
+  int koff[KS], kdy[KS], kdx[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + ks, c = k / 9, t = k - 9 * c;
+    kdy[s] = (k < 9 * C) ? t / 3 - 1 : -H;   // padded k-slots fall outside every row
+    kdx[s] = t % 3 - 1;
+    koff[s] = c * HW + kdy[s] * W + kdx[s];
+  }
+  const int base = (blockIdx.x * 4 + wave) * 16 * C1_NT;
+  float bv[C1_NT][KS];
+  // (b, y, x) of this lane's pixel, advanced by 16 pixels per tile
+  int b = (unsigned)(base + col) / (unsigned)HW, x = base + col - b * HW;
+  int y = (unsigned)x / (unsigned)W;
+  x -= y * W;
+#pragma unroll
+  for (int j = 0; j < C1_NT; ++j) {
+    const int p = base + 16 * j + col;
+    if (j > 0) {
+      x += 16;
+      while (x >= W) {
+        x -= W;
+        if (++y == H) { y = 0; ++b; }
+      }
     }
-  for (int co = 0; co < coutp; co += 8) {
-    bf16x8 h;
+    const int pb = p + b * (C - 1) * HW;   // element (b, 0, y, x) of the planar input
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      float s = bias[co + q];
-      const float* wr = w + (size_t)(co + q) * C * 9;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        if (c < C)
-#pragma unroll
-          for (int t = 0; t < 9; ++t) s += wr[c * 9 + t] * xin[c][t];
-      h[q] = (bf16)fmaxf(s, 0.f);
+    for (int s = 0; s < KS; ++s) {
+      // out-of-range taps read element 0 and are zeroed after the load, so
+      // every load is issued unconditionally
+      const bool ok = (p < total) & ((unsigned)(y + kdy[s]) < (unsigned)H) &
+                      ((unsigned)(x + kdx[s]) < (unsigned)W);
+      const float v = x0[ok ? (unsigned)(pb + koff[s]) : 0u];
+      bv[j][s] = ok ? v : 0.f;
     }
-    *(u32x4*)(out + (size_t)p * coutp + co) = __builtin_bit_cast(u32x4, h);
+  }
+  float bq[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bq[i][q] = bias[16 * i + 4 * ks + q];
+#pragma unroll
+  for (int j = 0; j < C1_NT; ++j) {
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i], 0, 0, 0);
+    const int p = base + 16 * j + col;
+    if (p >= total) continue;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      bf16 h[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = (bf16)fmaxf(acc[i][q] + bq[i][q], 0.f);
+      *(u32x2*)(out + (size_t)p * 32 + 16 * i + 4 * ks) = __builtin_bit_cast(u32x2, h);
+    }
   }
 }
 
@@ -1520,9 +1570,13 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
                                                  n->x0);
   {
     const CnnLayer& L = n->L[0];
-    k_conv1_fwd<<<(B * D + 255) / 256, 256, 0, st>>>(n->x0, n->params + L.woff,
-                                                      n->params + L.boff, B, n->cin0, n->ny,
-                                                      n->nx, L.coutp, n->act[0]);
+    const dim3 grid((B * D + 64 * C1_NT - 1) / (64 * C1_NT));
+    if (n->cin0 == 3)
+      k_conv1_fwd<3><<<grid, 256, 0, st>>>(n->x0, n->params + L.woff, n->params + L.boff, B,
+                                           n->ny, n->nx, n->act[0]);
+    else
+      k_conv1_fwd<1><<<grid, 256, 0, st>>>(n->x0, n->params + L.woff, n->params + L.boff, B,
+                                           n->ny, n->nx, n->act[0]);
   }
   for (int l = 1; l < NL; ++l) {
     const CnnLayer& L = n->L[l];
