@@ -669,40 +669,6 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
   }
 }
 
-// Layer-1 weight gradient partials: thread (co, j) with j = 9 ci + tap (j = 9C
-// is the bias) sums over the rows [r0, r1) of the batch (row = one image row),
-// walking x without divisions.  Block size: cout (9C + 1) rounded up to 64.
-__global__ __launch_bounds__(1024) void k_conv1_wgrad(const float* __restrict__ x0,
-                                                      const bf16* __restrict__ dz, int B, int C,
-                                                      int H, int W, int cout, int coutp,
-                                                      int rows_per, float* __restrict__ part) {
-  const int t = threadIdx.x, J = 9 * C + 1;
-  const int r0 = blockIdx.x * rows_per, r1 = min(B * H, r0 + rows_per);
-  if (t >= cout * J) return;
-  const int co = t / J, j = t % J;
-  const bool isb = (j == 9 * C);
-  const int ci = isb ? 0 : j / 9, tap = isb ? 0 : j % 9;
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  float s = 0.f;
-  for (int row = r0; row < r1; ++row) {
-    const int b = row / H, y = row - b * H;
-    const int ys = y + dy;
-    const bool rowok = isb || (ys >= 0 && ys < H);
-    if (!rowok) continue;
-    const float* xr = x0 + (((size_t)b * C + ci) * H + (isb ? 0 : ys)) * W;
-    const bf16* g = dz + (size_t)row * W * coutp + co;
-    for (int x = 0; x < W; ++x) {
-      float xv = 1.f;
-      if (!isb) {
-        const int xs = x + dx;
-        xv = (xs >= 0 && xs < W) ? xr[xs] : 0.f;
-      }
-      s += bf2f(g[(size_t)x * coutp]) * xv;
-    }
-  }
-  part[(size_t)blockIdx.x * cout * J + t] = s;
-}
-
 // --------------------------------------------------- weight gradients ----
 // Weight gradients of a 3x3 layer of any map (stride 1, stride 2, upsampling)
 // as GEMMs over stages of 32 S consecutive output pixels (flattened b, y, x
@@ -1037,56 +1003,96 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
   }
 }
 
-// Layer-1 weight and bias gradients as one GEMM over row segments of 32
-// pixels: dW[co][j] = sum_p dz[p][co] u[p][j], where u[p] is the pixel's
-// 9 C input values (plane-major, tap-minor, the [cout][cin][3][3] order of
-// the weights), then 1 for the bias, then zeros up to 32 columns.  dz and u
-// are staged transposed in LDS (u rounded to bf16), one MFMA tile per wave and
-// segment, FP32 accumulation.  Needs W % 32 == 0, coutp == 32 and 9 C + 1 <= 32.
-// Partials [slice][32][32].
-__global__ __launch_bounds__(256) void k_conv1_wgrad_rows(const float* __restrict__ x0,
-                                                          const bf16* __restrict__ dz, int B,
-                                                          int C, int H, int W, int segs_per,
-                                                          float* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) bf16 As[32][40];
-  __shared__ __attribute__((aligned(16))) bf16 Us[32][40];
+// Layer-1 weight and bias gradients on FP32 matrix cores: dW[co][j] =
+// sum_p dz[p][co] u[p][j], where u[p] is the pixel's 9 C input values
+// (plane-major, tap-minor: the [cout][cin][3][3] order of the weights), then 1
+// for the bias, then zeros.  Per 4 pixels, 16x16x4 FP32 MFMAs take
+// A[r][px] = dz[px][2 r + i] (row r of tile i is channel 2 r + i, so a lane's
+// two channels are one 4-byte load) and B[px][jj] = u[px][16 jt + jj].  A
+// workgroup owns the contiguous pixel range [p0, p0 + pix_per); per
+// iteration it takes 16 pixels, pixel p0 + 16 it + 4 w + px for wave w, and
+// C1W_U iterations' loads are issued before their MFMAs.  The four waves are
+// summed in LDS; partials [slice][32][32] (column 9 C = bias).
+#define C1W_U 4
+template <int C>
+__global__ __launch_bounds__(256) void k_conv1_wgrad(const float* __restrict__ x0,
+                                                     const bf16* __restrict__ dz, int B, int H,
+                                                     int W, int pix_per,
+                                                     float* __restrict__ part) {
+  constexpr int J = 9 * C, NJT = (J + 16) / 16;   // column tiles holding J + 1 columns
+  __shared__ float red[4][32 * 32];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int W32 = W / 32, nseg = B * H * W32;
-  const int s0 = blockIdx.x * segs_per, s1 = min(nseg, s0 + segs_per);
-  const int ti = wave >> 1, tj = wave & 1;   // the four 16 x 16 tiles of the 32 x 32 result
-  const int J = 9 * C;
-  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int kq = 8 * (lane >> 4);
-  for (int sg = s0; sg < s1; ++sg) {
-    const int b = sg / (H * W32), rem = sg - b * H * W32;
-    const int y = rem / W32, xb = (rem - y * W32) * 32;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 32 * 4; idx += 256) {
-      const int pp = idx >> 2, cg = (idx & 3) * 8;
-      const bf16x8 v = load8(dz + (((size_t)b * H + y) * W + xb + pp) * 32 + cg);
+  const int g = lane >> 4, col = lane & 15;
+  const int HW = H * W, total = B * HW;
+  const int p0 = blockIdx.x * pix_per, p1 = min(total, p0 + pix_per);
+  int koff[NJT], kdy[NJT], kdx[NJT];
+  bool kone[NJT];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) As[cg + q][pp] = v[q];
-    }
-    for (int idx = threadIdx.x; idx < 32 * 32; idx += 256) {
-      const int j = idx >> 5, k = idx & 31;   // consecutive threads: consecutive pixels
-      float v = 0.f;
-      if (j < J) {
-        const int ci = j / 9, t = j - 9 * ci;
-        const int ys = y + t / 3 - 1, xs = xb + k + t % 3 - 1;
-        if (ys >= 0 && ys < H && xs >= 0 && xs < W) v = x0[(((size_t)b * C + ci) * H + ys) * W + xs];
-      } else if (j == J) {
-        v = 1.f;
-      }
-      Us[j][k] = (bf16)v;
-    }
-    __syncthreads();
-    const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kq];
-    const bf16x8 bv = *(const bf16x8*)&Us[tj * 16 + (lane & 15)][kq];
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  for (int jt = 0; jt < NJT; ++jt) {
+    const int j = 16 * jt + col, c = j / 9, t = j - 9 * c;
+    kone[jt] = (j == J);
+    kdy[jt] = (j < J) ? t / 3 - 1 : -H;   // bias and padding columns read no input
+    kdx[jt] = t % 3 - 1;
+    koff[jt] = c * HW + kdy[jt] * W + kdx[jt];
   }
-  float* out = part + (size_t)blockIdx.x * 32 * 32;
+  // (b, y, x) of this lane's pixel, advanced by 16 pixels per iteration
+  int p = p0 + 4 * wave + g;
+  int b = (unsigned)p / (unsigned)HW, x = p - b * HW;
+  int y = (unsigned)x / (unsigned)W;
+  x -= y * W;
+  f32x4 acc[2][NJT];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) out[(ti * 16 + 4 * (lane >> 4) + q) * 32 + tj * 16 + (lane & 15)] = acc[q];
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jt = 0; jt < NJT; ++jt) acc[i][jt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int it0 = 0; p0 + 16 * it0 < p1; it0 += C1W_U) {
+    uint32_t dv[C1W_U];
+    float uv[C1W_U][NJT];
+#pragma unroll
+    for (int u = 0; u < C1W_U; ++u) {
+      const bool pv = p < p1;
+      // out-of-range reads go to element 0 / pixel p0 and are zeroed after
+      const uint32_t d = *(const uint32_t*)(dz + (size_t)(pv ? p : p0) * 32 + 2 * col);
+      dv[u] = pv ? d : 0u;
+      const int pb = p + b * (C - 1) * HW;   // element (b, 0, y, x) of the planar input
+#pragma unroll
+      for (int jt = 0; jt < NJT; ++jt) {
+        const bool ok = pv & ((unsigned)(y + kdy[jt]) < (unsigned)H) &
+                        ((unsigned)(x + kdx[jt]) < (unsigned)W);
+        const float v = x0[ok ? (unsigned)(pb + koff[jt]) : 0u];
+        uv[u][jt] = ok ? v : ((pv & kone[jt]) ? 1.f : 0.f);
+      }
+      p += 16;
+      x += 16;
+      while (x >= W) {
+        x -= W;
+        if (++y == H) { y = 0; ++b; }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < C1W_U; ++u) {
+      const float a0 = __uint_as_float(dv[u] << 16), a1 = __uint_as_float(dv[u] & 0xffff0000u);
+#pragma unroll
+      for (int jt = 0; jt < NJT; ++jt) {
+        acc[0][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, uv[u][jt], acc[0][jt], 0, 0, 0);
+        acc[1][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, uv[u][jt], acc[1][jt], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds rows 4 g + q (channel 2 (4 g + q) + i) of column 16 jt + col
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float* r = &red[wave][(2 * (4 * g + q) + i) * 32 + col];
+#pragma unroll
+      for (int jt = 0; jt < NJT; ++jt) r[16 * jt] = acc[i][jt][q];
+      if (NJT == 1) r[16] = 0.f;
+    }
+  __syncthreads();
+  float* out = part + (size_t)blockIdx.x * 32 * 32;
+  for (int e = threadIdx.x; e < 32 * 32; e += 256)
+    out[e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
 // Sum over slices of [slice][nent] partials for 16 consecutive entries per
@@ -1105,7 +1111,7 @@ __device__ __forceinline__ float slice_sum16(const float* __restrict__ part, int
   return t;
 }
 
-// Sum the [slice][32][32] partials of k_conv1_wgrad_rows (16 entries per block).
+// Sum the [slice][32][32] partials of k_conv1_wgrad (16 entries per block).
 __global__ __launch_bounds__(256) void k_conv1_rows_reduce(const float* __restrict__ part,
                                                            int nslices, int cout, int C,
                                                            float* __restrict__ gw,
@@ -1148,17 +1154,6 @@ __global__ __launch_bounds__(256) void k_bgrad_reduce(const float* __restrict__ 
   const int r = blockIdx.x * 16 + (threadIdx.x & 15);
   const float s = slice_sum16(part, nslices, Mr, r, red);
   if ((threadIdx.x >> 4) == 0 && r < cout) g[r] = s;
-}
-__global__ void k_conv1_reduce(const float* __restrict__ part, int nslices, int cout, int C,
-                               float* __restrict__ gw, float* __restrict__ gb) {
-  const int J = 9 * C + 1;
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= cout * J) return;
-  float s = 0.f;
-  for (int sl = 0; sl < nslices; ++sl) s += part[(size_t)sl * cout * J + t];
-  const int co = t / J, j = t % J;
-  if (j < 9 * C) gw[(size_t)co * 9 * C + j] = s;   // [cout][cin][3][3]
-  else gb[co] = s;
 }
 
 // ------------------------------------------------ input, loss, output ----
@@ -1411,14 +1406,13 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_
     chk(cnn_alloc(n, &n->dz[l], pix * L.coutp));
     // gradient partials: k_conv_wgrad_seg runs at most 8 workgroups per CU
     // (256 threads each) over 3 dy and the 64-channel blocks; layer 1 uses
-    // [slice][32][32] (at most 8 slices per CU) or its per-row-block fallback
+    // [slice][32][32] (at most 8 slices per CU)
     if (l > 0) {
       const size_t nblk = (size_t)std::max(1, L.cinp / 64);
       const size_t sl = std::max<size_t>(1, (size_t)8 * n->ncu / (3 * nblk));
       wp = std::max(wp, sl * ((size_t)9 * L.coutp * L.cinp + L.coutp));
     } else {
       wp = std::max(wp, (size_t)8 * n->ncu * 32 * 32);
-      wp = std::max(wp, (size_t)512 * L.cout * (9 * L.cin + 1));
     }
   }
   n->wpart_elems = wp;
@@ -1718,25 +1712,21 @@ static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
   }
   {
     const CnnLayer& L = n->L[0];
-    const int nt = L.cout * (9 * n->cin0 + 1);
-    if (n->nx % 32 == 0 && L.coutp == 32 && 9 * n->cin0 + 1 <= 32) {
-      // about eight workgroups per CU, within the partial buffer
-      const int nseg = B * n->ny * (n->nx / 32);
-      const int want = (int)std::min<size_t>((size_t)8 * n->ncu, n->wpart_elems / (32 * 32));
-      const int sp = (nseg + want - 1) / want, slices = (nseg + sp - 1) / sp;
-      k_conv1_wgrad_rows<<<slices, 256, 0, st>>>(n->x0, n->dz[0], B, n->cin0, n->ny, n->nx, sp,
-                                                 n->wpart);
-      k_conv1_rows_reduce<<<64, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
-                                              n->grads + L.woff, n->grads + L.boff);
-    } else {
-      const int rows = B * n->ny, rows_per = std::max(1, (rows + 511) / 512);
-      const int slices = (rows + rows_per - 1) / rows_per;
-      k_conv1_wgrad<<<slices, (nt + 63) / 64 * 64, 0, st>>>(n->x0, n->dz[0], B, n->cin0, n->ny,
-                                                            n->nx, L.cout, L.coutp, rows_per,
-                                                            n->wpart);
-      k_conv1_reduce<<<(nt + 255) / 256, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
-                                                       n->grads + L.woff, n->grads + L.boff);
-    }
+    // about eight workgroups per CU, within the partial buffer; each takes a
+    // multiple of 16 C1W_U pixels
+    const int total = B * n->nx * n->ny;
+    const int want = (int)std::min<size_t>((size_t)8 * n->ncu, n->wpart_elems / (32 * 32));
+    const int step = 16 * C1W_U;
+    const int pp = (total + want - 1) / want, pix_per = (pp + step - 1) / step * step;
+    const int slices = (total + pix_per - 1) / pix_per;
+    if (n->cin0 == 3)
+      k_conv1_wgrad<3><<<slices, 256, 0, st>>>(n->x0, n->dz[0], B, n->ny, n->nx, pix_per,
+                                               n->wpart);
+    else
+      k_conv1_wgrad<1><<<slices, 256, 0, st>>>(n->x0, n->dz[0], B, n->ny, n->nx, pix_per,
+                                               n->wpart);
+    k_conv1_rows_reduce<<<64, 256, 0, st>>>(n->wpart, slices, L.cout, n->cin0,
+                                            n->grads + L.woff, n->grads + L.boff);
   }
   DD_HIP_CHECK(hipGetLastError());
   return DD_OK;

@@ -84,9 +84,8 @@ def test_gradients_match_oracle(nx, ny, k):
     the stride-2 layers to 4 x 4 and 2 x 2 outputs; there a weight gradient
     sums so few products that the bf16 rounding of single activations and
     ReLU decisions shows (7% norm-wise at batch 2, 2.7% at batch 8, 1.3% at
-    batch 32), so that case runs at batch 8.  Layer 1 takes the row-segment
-    GEMM at 64 x 32 (width a multiple of 32) and the per-row-block kernel
-    elsewhere."""
+    batch 32), so that case runs at batch 8.  Layer 1's gradient runs over
+    flattened pixel ranges, crossing rows and images at every width here."""
     import torch
     from paper_1902_00090_amd.cnn import flat_to_layers
     B = 8 if nx * ny <= 64 else 2
