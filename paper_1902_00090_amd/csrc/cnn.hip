@@ -724,17 +724,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_seg(const bf16* __restrict__
       int b = p / HW, rem = p - b * HW, y = rem / Wout, xx = rem - y * Wout;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        bf16x8 v = zero8();
-        if (blk < NBLK && p < npix) {
-          if (isA) {
-            v = load8(dz + (size_t)p * Mr + cg);
-          } else {
-            int ys, xs;
-            if (fwd_src(mode, y, xx, dy, dx, Hin, Win, Hout, Wout, ys, xs))
-              v = load8(x + ((size_t)(b * Hin + ys) * Win + xs) * Nc + n0 + cg);
-          }
-        }
-        reg[bi][i] = v;
+        // out-of-range reads go to dz[0] and are zeroed after the load, so
+        // every load is issued unconditionally
+        int ys = 0, xs = 0;
+        const bool src_ok = isA || fwd_src(mode, y, xx, dy, dx, Hin, Win, Hout, Wout, ys, xs);
+        const bool ok = blk < NBLK && p < npix && src_ok;
+        const bf16* ptr = !ok ? dz
+                          : isA ? dz + (size_t)p * Mr + cg
+                                : x + ((size_t)(b * Hin + ys) * Win + xs) * Nc + n0 + cg;
+        const bf16x8 v = load8(ptr);
+        reg[bi][i] = ok ? v : zero8();
         ++p;
         if (++xx == Wout) { xx = 0; if (++y == Hout) { y = 0; ++b; } }
       }
@@ -1712,10 +1711,10 @@ static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
   }
   {
     const CnnLayer& L = n->L[0];
-    // about eight workgroups per CU, within the partial buffer; each takes a
-    // multiple of 16 C1W_U pixels
+    // about four workgroups per CU (fewer partials to sum), within the
+    // partial buffer; each takes a multiple of 16 C1W_U pixels
     const int total = B * n->nx * n->ny;
-    const int want = (int)std::min<size_t>((size_t)8 * n->ncu, n->wpart_elems / (32 * 32));
+    const int want = (int)std::min<size_t>((size_t)4 * n->ncu, n->wpart_elems / (32 * 32));
     const int step = 16 * C1W_U;
     const int pp = (total + want - 1) / want, pix_per = (pp + step - 1) / step * step;
     const int slices = (total + pix_per - 1) / pix_per;
