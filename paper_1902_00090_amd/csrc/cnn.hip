@@ -1654,29 +1654,34 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   const int Mr = L.coutp, Nc = L.cinp, NB = std::min(Nc, 64);
   if (Nc % NB) return 0;
   // S (stage width 32 S pixels, 1, 2 or 4): the largest whose 8 x 8 staging
-  // blocks (dz, then the input pixels a stage needs) fit one per thread
+  // blocks (dz, then the input pixels a stage needs) fit one per thread; 8
+  // for the upsampling row-chunk kernel with 32 output channels (measured
+  // faster there, slower for the stride-1 ones)
   auto blocks = [&](int S) {
     const int xg = (L.mode == MAP_S1) ? 4 * S + 2 : (L.mode == MAP_UP) ? 2 * S + 1 : 12 * S;
     return 4 * S * (Mr / 8) + xg * (NB / 8);
   };
-  const int S = blocks(4) <= 256 ? 4 : (blocks(2) <= 256 ? 2 : 1);
-#define WG_CASES(F)                                                    \
-  if (Mr == 32 && NB == 32) return S == 4 ? F(2, 2, 4) : 0;            \
-  if (Mr == 32 && NB == 64) return S == 4 ? F(2, 4, 4) : F(2, 4, 2);   \
-  if (Mr == 64 && NB == 32) return S == 4 ? F(4, 2, 4) : F(4, 2, 2);   \
-  if (Mr == 64 && NB == 64) return S == 4 ? F(4, 4, 4) : F(4, 4, 2);   \
-  if (Mr == 128 && NB == 32) return S == 2 ? F(8, 2, 2) : 0;           \
+  const int S = (Mr == 32 && L.mode == MAP_UP) ? 8
+                : blocks(4) <= 256 ? 4 : (blocks(2) <= 256 ? 2 : 1);
+#define WG_CASES(F, F8)                                                              \
+  if (Mr == 32 && NB == 32) return S == 8 ? F8(2, 2, 8) : S == 4 ? F(2, 2, 4) : 0;   \
+  if (Mr == 32 && NB == 64) return S == 8 ? F8(2, 4, 8) : S == 4 ? F(2, 4, 4) : F(2, 4, 2); \
+  if (Mr == 64 && NB == 32) return S == 4 ? F(4, 2, 4) : F(4, 2, 2);                 \
+  if (Mr == 64 && NB == 64) return S == 4 ? F(4, 4, 4) : F(4, 4, 2);                 \
+  if (Mr == 128 && NB == 32) return S == 2 ? F(8, 2, 2) : 0;                         \
   if (Mr == 128 && NB == 64) return S == 2 ? F(8, 4, 2) : F(8, 4, 1);
 #define WG_SEG(a, b, c) launch_wgrad_seg<a, b, c>(n, l, B, st)
 #define WG_ROW1(a, b, c) launch_wgrad_row<a, b, c, false>(n, l, B, st)
 #define WG_ROWU(a, b, c) launch_wgrad_row<a, b, c, true>(n, l, B, st)
-  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1) }
-  else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU) }
-  else { WG_CASES(WG_SEG) }
+#define WG_NONE(a, b, c) 0
+  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_NONE) }
+  else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU, WG_ROWU) }
+  else { WG_CASES(WG_SEG, WG_NONE) }
 #undef WG_CASES
 #undef WG_SEG
 #undef WG_ROW1
 #undef WG_ROWU
+#undef WG_NONE
   return 0;
 }
 
