@@ -47,12 +47,34 @@ struct RlDesc {
   const double2* c;     // [k] minimiser
 };
 
-__global__ __launch_bounds__(256) void k_rl_apply(const RlDesc* __restrict__ desc) {
-  const RlDesc d = desc[blockIdx.z];
-  const int e = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+// W_j = A V_j for all k vectors: a thread takes one cell of every vector, so
+// the neighbour indices, the stencil coefficients and omega^2 eps are formed
+// once per cell (the arithmetic is the operator's stencil, term for term).
+__global__ __launch_bounds__(256) void k_rl_apply(const RlDesc* __restrict__ desc, int k) {
+  const RlDesc d = desc[blockIdx.y];
+  const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= d.D) return;
-  d.W[(size_t)j * d.D + e] =
-      stencil_point<float, float>(d.V + (size_t)j * d.D, e, d.nx, d.ny, d.cf, d.eps, d.omega2);
+  const int nx = d.nx, ny = d.ny;
+  const int iy = e / nx, ix = e - iy * nx;
+  const int ew = (ix == 0) ? e + nx - 1 : e - 1;
+  const int ee = (ix == nx - 1) ? e - nx + 1 : e + 1;
+  const int es = (iy == 0) ? e + (ny - 1) * nx : e - nx;
+  const int en = (iy == ny - 1) ? e - (ny - 1) * nx : e + nx;
+  const float2 cxm = d.cf[ix], cxp = d.cf[nx + ix], cym = d.cf[2 * nx + iy],
+               cyp = d.cf[2 * nx + ny + iy];
+  const float de = d.omega2 * d.eps[e];
+#pragma unroll 2
+  for (int j = 0; j < k; ++j) {
+    const float2* x = d.V + (size_t)j * d.D;
+    const float2 c = x[e], w = x[ew], ea = x[ee], s = x[es], n = x[en];
+    float2 r = cmul(cxm, csub(c, w));
+    r = csub(r, cmul(cxp, csub(ea, c)));
+    r = cadd(r, cmul(cym, csub(c, s)));
+    r = csub(r, cmul(cyp, csub(n, c)));
+    r.x -= de * c.x;
+    r.y -= de * c.y;
+    d.W[(size_t)j * d.D + e] = r;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_rl_resid(const RlDesc* __restrict__ desc, int k) {
@@ -296,7 +318,7 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
   double2* dc = (double2*)bdc.p;
   for (int p = 0; p < nb; ++p) hd[p].c = dc + (size_t)p * k;
   DD_HIP_CHECK(hipMemcpyAsync(dd, hd.data(), sizeof(RlDesc) * nb, hipMemcpyHostToDevice, st));
-  k_rl_apply<<<dim3((maxD + 255) / 256, k, nb), 256, 0, st>>>(dd);
+  k_rl_apply<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k);
   DD_HIP_CHECK(hipGetLastError());
   std::vector<double2> hc((size_t)2 * nb * k, make_double2(0.0, 0.0));
   // Gram matrices of [W b], all problems in one launch

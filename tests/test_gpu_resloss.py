@@ -18,10 +18,12 @@ def _ops_b(insts):
     return ops, bs
 
 
-@pytest.mark.parametrize("k", [5, 20])
+@pytest.mark.parametrize("k", [5, 10, 20])
 def test_res_loss_batched_matches_oracle(k):
-    """k = 5: few Gram pairs, several threads per pair; k = 20: 231 pairs, one
-    thread per pair and more staging values per thread."""
+    """k = 5: few Gram pairs, several threads per pair; k = 10: the CNN's
+    subspace size (66 pairs); k = 20: 231 pairs, one thread per pair and more
+    staging values per thread.  The grids are of three sizes, so the element
+    slices end ragged."""
     import torch
     from paper_1902_00090_amd import res_loss_batched
     insts = [W.grating(1000, nx=96, ny=48), W.grating(1001),
