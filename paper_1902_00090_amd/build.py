@@ -19,7 +19,7 @@ OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["op.hip", "solver.hip", "pca.hip", "cnn.hip", "eim.hip", "resloss.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
+    "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wextra",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,

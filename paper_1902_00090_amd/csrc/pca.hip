@@ -466,10 +466,11 @@ __global__ __launch_bounds__(256) void k_local_combine(const float2* __restrict_
     const float2 f = F[(size_t)m * D + e];
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
-      if (o0 + o >= k) break;
-      const double2 c = coef[((size_t)s * S + m) * k + o0 + o];
-      acc[o].x += c.x * f.x - c.y * f.y;
-      acc[o].y += c.x * f.y + c.y * f.x;
+      if (o0 + o < k) {
+        const double2 c = coef[((size_t)s * S + m) * k + o0 + o];
+        acc[o].x += c.x * f.x - c.y * f.y;
+        acc[o].y += c.x * f.y + c.y * f.x;
+      }
     }
   }
   for (int o = 0; o < 16 && o0 + o < k; ++o)
