@@ -836,7 +836,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_seg(const bf16* __restrict__
 // pixels instead of 3 PX.  A wave owns (row tile, column tile) units and
 // applies all three dx to each.  Work items, grid and partials are
 // k_conv_wgrad_seg's.
-template <int MT, int NT, int S, bool UP>
+template <int MT, int NT, int S, bool UP, int ND = 1>
 __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__ dz,
                                                         const bf16* __restrict__ x, int B,
                                                         int Hout, int Wout, int Hin, int Win,
@@ -848,24 +848,24 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
   constexpr int ABLK = (PX / 8) * (Mr / 8);
   constexpr int XG = UP ? (PX / 16 + 1) : (PX / 8 + 2);   // source groups of 8 pixels
   constexpr int XBLK = XG * (NB / 8);
-  constexpr int NBLK = ABLK + XBLK, BPT = (NBLK + 255) / 256;
+  constexpr int NBLK = ABLK + ND * XBLK, BPT = (NBLK + 255) / 256;
   constexpr int NU = MT * NT, PER_WAVE = (NU + 3) / 4;
   __shared__ __attribute__((aligned(16))) bf16 As[Mr][LD];
-  __shared__ __attribute__((aligned(16))) bf16 Xs[NB][LDX];
+  __shared__ __attribute__((aligned(16))) bf16 Xs[ND][NB][LDX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int w = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   if (w >= nwork) return;
   const int nblk = Nc / NB;
-  const int dy = w % 3, n0 = ((w / 3) % nblk) * NB, slice = w / (3 * nblk);
+  // ND = 3: one item takes all three dy (first dy0 = 0) and stages dz once
+  const int dy0 = (ND == 3) ? 0 : w % 3;
+  const int n0 = ((ND == 3) ? w % nblk : (w / 3) % nblk) * NB;
+  const int slice = (ND == 3) ? w / nblk : w / (3 * nblk);
   const int nch = (Wout + PX - 1) / PX, nst = B * Hout * nch;
   const int s0 = slice * stages_per, s1 = min(nst, s0 + stages_per);
   bf16x8 reg[BPT][8];
   auto load = [&](int sg) {
     const int b = sg / (Hout * nch), rem = sg - b * Hout * nch, y = rem / nch;
     const int x0 = (rem - y * nch) * PX;
-    const int uy = y + dy - 1;
-    const bool rowok = uy >= 0 && uy < Hout;
-    const int ys = UP ? (uy >> 1) : uy;
 #pragma unroll
     for (int bi = 0; bi < BPT; ++bi) {
       const int blk = threadIdx.x + 256 * bi;
@@ -877,23 +877,28 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
 #pragma unroll
         for (int i = 0; i < 8; ++i)
           if (x0 + pg * 8 + i < Wout) reg[bi][i] = load8(src + (size_t)(pg * 8 + i) * Mr);
-      } else if (blk < NBLK && rowok) {
-        const int r = blk - ABLK, m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
-        const int c0 = UP ? (x0 / 2 - 4 + 8 * m) : (x0 - 8 + 8 * m);   // first source column
-        const bf16* src = x + ((size_t)b * Hin + ys) * Win * Nc + n0 + cg;
+      } else if (blk < NBLK) {
+        const int rd = (blk - ABLK) / XBLK, r = blk - ABLK - rd * XBLK;   // dy row, item
+        const int uy = y + dy0 + rd - 1;
+        if (uy >= 0 && uy < Hout) {
+          const int ys = UP ? (uy >> 1) : uy;
+          const int m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+          const int c0 = UP ? (x0 / 2 - 4 + 8 * m) : (x0 - 8 + 8 * m);   // first source column
+          const bf16* src = x + ((size_t)b * Hin + ys) * Win * Nc + n0 + cg;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (c0 + i >= 0 && c0 + i < Win) reg[bi][i] = load8(src + (size_t)(c0 + i) * Nc);
+          for (int i = 0; i < 8; ++i)
+            if (c0 + i >= 0 && c0 + i < Win) reg[bi][i] = load8(src + (size_t)(c0 + i) * Nc);
+        }
       }
     }
   };
-  f32x4 acc[PER_WAVE][3];
+  f32x4 acc[PER_WAVE][3 * ND];   // [unit][row (dy - dy0) * 3 + dx]
 #pragma unroll
   for (int i = 0; i < PER_WAVE; ++i)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) acc[i][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < 3 * ND; ++d) acc[i][d] = f32x4{0.f, 0.f, 0.f, 0.f};
   constexpr int BT = (MT + 3) / 4;
-  const bool bias = (dy == 0 && n0 == 0);
+  const bool bias = (dy0 == 0 && n0 == 0);
   f32x4 accb[BT];
 #pragma unroll
   for (int i = 0; i < BT; ++i) accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -917,7 +922,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
           *(bf16x8*)(dst + q * LD) = t;
         }
       } else if (blk < NBLK) {
-        const int r = blk - ABLK, m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+        const int rd = (blk - ABLK) / XBLK, r = blk - ABLK - rd * XBLK;
+        const int m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+        bf16 (*Xr)[LDX] = Xs[rd];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           if (UP) {   // source pixel i fills columns 16 m + 2 i and 16 m + 2 i + 1
@@ -927,13 +934,13 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
               lo[2 * i] = lo[2 * i + 1] = reg[bi][i][q];
               hi[2 * i] = hi[2 * i + 1] = reg[bi][i + 4][q];
             }
-            *(bf16x8*)&Xs[cg + q][16 * m] = lo;
-            *(bf16x8*)&Xs[cg + q][16 * m + 8] = hi;
+            *(bf16x8*)&Xr[cg + q][16 * m] = lo;
+            *(bf16x8*)&Xr[cg + q][16 * m + 8] = hi;
           } else {
             bf16x8 t;
 #pragma unroll
             for (int i = 0; i < 8; ++i) t[i] = reg[bi][i][q];
-            *(bf16x8*)&Xs[cg + q][8 * m] = t;
+            *(bf16x8*)&Xr[cg + q][8 * m] = t;
           }
         }
       }
@@ -948,20 +955,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
         if (u < NU) {
           const int ti = u / NT, tj = u - ti * NT;
           const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
-          const bf16* xr = &Xs[tj * 16 + (lane & 15)][kk * 32 + kq + 8];   // column of dx = 1
-          const u32x4 a4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr - 8));
-          const u32x4 b4 = __builtin_bit_cast(u32x4, *(const bf16x8*)xr);
-          const u32x4 c4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr + 8));
-          // columns shifted by one bf16: word j = high half of word j-1, low half of word j
-          const unsigned s0w = (a4[3] >> 16) | (b4[0] << 16), s1w = (b4[0] >> 16) | (b4[1] << 16);
-          const unsigned s2w = (b4[1] >> 16) | (b4[2] << 16), s3w = (b4[2] >> 16) | (b4[3] << 16);
-          const unsigned s4w = (b4[3] >> 16) | (c4[0] << 16);
-          const bf16x8 bl = __builtin_bit_cast(bf16x8, u32x4{s0w, s1w, s2w, s3w});   // dx = 0
-          const bf16x8 bm = __builtin_bit_cast(bf16x8, b4);                          // dx = 1
-          const bf16x8 br = __builtin_bit_cast(bf16x8, u32x4{s1w, s2w, s3w, s4w});   // dx = 2
-          acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[i][0], 0, 0, 0);
-          acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bm, acc[i][1], 0, 0, 0);
-          acc[i][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, br, acc[i][2], 0, 0, 0);
+#pragma unroll
+          for (int rd = 0; rd < ND; ++rd) {
+            const bf16* xr = &Xs[rd][tj * 16 + (lane & 15)][kk * 32 + kq + 8];   // column of dx = 1
+            const u32x4 a4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr - 8));
+            const u32x4 b4 = __builtin_bit_cast(u32x4, *(const bf16x8*)xr);
+            const u32x4 c4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr + 8));
+            // columns shifted by one bf16: word j = high half of word j-1, low half of word j
+            const unsigned s0w = (a4[3] >> 16) | (b4[0] << 16), s1w = (b4[0] >> 16) | (b4[1] << 16);
+            const unsigned s2w = (b4[1] >> 16) | (b4[2] << 16), s3w = (b4[2] >> 16) | (b4[3] << 16);
+            const unsigned s4w = (b4[3] >> 16) | (c4[0] << 16);
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, u32x4{s0w, s1w, s2w, s3w});   // dx = 0
+            const bf16x8 bm = __builtin_bit_cast(bf16x8, b4);                          // dx = 1
+            const bf16x8 br = __builtin_bit_cast(bf16x8, u32x4{s1w, s2w, s3w, s4w});   // dx = 2
+            acc[i][3 * rd] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[i][3 * rd], 0, 0, 0);
+            acc[i][3 * rd + 1] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bm, acc[i][3 * rd + 1], 0, 0, 0);
+            acc[i][3 * rd + 2] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, br, acc[i][3 * rd + 2], 0, 0, 0);
+          }
         }
       }
       if (bias) {
@@ -993,8 +1005,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
       const int ti = u / NT, tj = u - ti * NT;
       const int c = tj * 16 + (lane & 15);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        float* out = part + (((size_t)slice * 9 + dy * 3 + d) * Mr) * Nc + n0;
+      for (int d = 0; d < 3 * ND; ++d) {   // tap (dy0 + d / 3) * 3 + d % 3 = 3 dy0 + d
+        float* out = part + (((size_t)slice * 9 + dy0 * 3 + d) * Mr) * Nc + n0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[i][d][q];
       }
@@ -1100,8 +1112,18 @@ __device__ __forceinline__ float slice_sum16(const float* __restrict__ part, int
                                              int ent, float (*red)[16]) {
   const int j = threadIdx.x & 15, grp = threadIdx.x >> 4;
   float s = 0.f;
-  if (ent < nent)
-    for (int sl = grp; sl < nslices; sl += 16) s += part[(size_t)sl * nent + ent];
+  if (ent < nent) {
+    // slices grp, grp + 16, ... added in order; eight loads in flight at a time
+    int sl = grp;
+    for (; sl + 112 < nslices; sl += 128) {
+      float a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = part[(size_t)(sl + 16 * q) * nent + ent];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += a[q];
+    }
+    for (; sl < nslices; sl += 16) s += part[(size_t)sl * nent + ent];
+  }
   red[grp][j] = s;
   __syncthreads();
   float t = 0.f;
@@ -1137,8 +1159,18 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
   const int j = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int ent = blockIdx.x * 64 + j, nent = 9 * Mr * Nc;
   float s = 0.f;
-  if (ent < nent)
-    for (int sl = grp; sl < nslices; sl += 4) s += part[(size_t)sl * nent + ent];
+  if (ent < nent) {
+    // slices grp, grp + 4, ... added in order; eight loads in flight at a time
+    int sl = grp;
+    for (; sl + 28 < nslices; sl += 32) {
+      float a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = part[(size_t)(sl + 4 * q) * nent + ent];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += a[q];
+    }
+    for (; sl < nslices; sl += 4) s += part[(size_t)sl * nent + ent];
+  }
   red[grp][j] = s;
   __syncthreads();
   if (grp == 0 && ent < nent) {
@@ -1599,14 +1631,16 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
 struct WgradSplit {
   int slices, stages_per, nwork, grid;
 };
-static WgradSplit wgrad_split(const dd_cnn* n, int cap, int Mr, int Nc, int NB, int nst) {
+// dsplit: work items per (slice, channel block), 3 (one per dy) or 1.
+static WgradSplit wgrad_split(const dd_cnn* n, int cap, int Mr, int Nc, int NB, int nst,
+                              int dsplit = 3) {
   const int nblk = Nc / NB;
-  int slices = std::max(1, cap * n->ncu / (3 * nblk));
+  int slices = std::max(1, cap * n->ncu / (dsplit * nblk));
   slices = (int)std::min<size_t>((size_t)slices, n->wpart_elems / ((size_t)9 * Mr * Nc + Mr));
   slices = std::max(1, std::min(slices, nst));
   const int sp = (nst + slices - 1) / slices;
   slices = (nst + sp - 1) / sp;
-  const int nwork = slices * 3 * nblk;
+  const int nwork = slices * dsplit * nblk;
   return {slices, sp, nwork, (nwork + 7) / 8 * 8};
 }
 
@@ -1631,14 +1665,14 @@ static int launch_wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   return w.slices;
 }
 
-template <int MT, int NT, int S, bool UP>
+template <int MT, int NT, int S, bool UP, int ND = 1>
 static int launch_wgrad_row(dd_cnn* n, int l, int B, hipStream_t st) {
-  static const int cap = occupancy(k_conv_wgrad_row<MT, NT, S, UP>);
+  static const int cap = occupancy(k_conv_wgrad_row<MT, NT, S, UP, ND>);
   const CnnLayer& L = n->L[l];
   const int Mr = 16 * MT, Nc = L.cinp;
   const int nst = B * L.Hout * ((L.Wout + 32 * S - 1) / (32 * S));
-  const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst);
-  k_conv_wgrad_row<MT, NT, S, UP><<<w.grid, 256, 0, st>>>(
+  const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst, ND == 3 ? 1 : 3);
+  k_conv_wgrad_row<MT, NT, S, UP, ND><<<w.grid, 256, 0, st>>>(
       n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, L.Hin, L.Win, Nc, w.stages_per, w.nwork,
       n->wpart, n->wpart + (size_t)w.slices * 9 * Mr * Nc);
   return w.slices;
@@ -1654,34 +1688,35 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   const int Mr = L.coutp, Nc = L.cinp, NB = std::min(Nc, 64);
   if (Nc % NB) return 0;
   // S (stage width 32 S pixels, 1, 2 or 4): the largest whose 8 x 8 staging
-  // blocks (dz, then the input pixels a stage needs) fit one per thread; 8
-  // for the upsampling row-chunk kernel with 32 output channels (measured
-  // faster there, slower for the stride-1 ones)
+  // blocks (dz, then the input pixels a stage needs) fit one per thread.
+  // The row-chunk kernels with 32 output channels take all three dy per work
+  // item (ND = 3: dz staged once for the three input rows).
   auto blocks = [&](int S) {
     const int xg = (L.mode == MAP_S1) ? 4 * S + 2 : (L.mode == MAP_UP) ? 2 * S + 1 : 12 * S;
     return 4 * S * (Mr / 8) + xg * (NB / 8);
   };
-  const int S = (Mr == 32 && L.mode == MAP_UP) ? 8
-                : blocks(4) <= 256 ? 4 : (blocks(2) <= 256 ? 2 : 1);
-#define WG_CASES(F, F8)                                                              \
-  if (Mr == 32 && NB == 32) return S == 8 ? F8(2, 2, 8) : S == 4 ? F(2, 2, 4) : 0;   \
-  if (Mr == 32 && NB == 64) return S == 8 ? F8(2, 4, 8) : S == 4 ? F(2, 4, 4) : F(2, 4, 2); \
-  if (Mr == 64 && NB == 32) return S == 4 ? F(4, 2, 4) : F(4, 2, 2);                 \
-  if (Mr == 64 && NB == 64) return S == 4 ? F(4, 4, 4) : F(4, 4, 2);                 \
-  if (Mr == 128 && NB == 32) return S == 2 ? F(8, 2, 2) : 0;                         \
+  const int S = blocks(4) <= 256 ? 4 : (blocks(2) <= 256 ? 2 : 1);
+#define WG_CASES(F, F3)                                                    \
+  if (Mr == 32 && NB == 32) return S == 4 ? F3(2, 2, 4) : 0;           \
+  if (Mr == 32 && NB == 64) return S == 4 ? F3(2, 4, 4) : F(2, 4, 2);  \
+  if (Mr == 64 && NB == 32) return S == 4 ? F(4, 2, 4) : F(4, 2, 2);   \
+  if (Mr == 64 && NB == 64) return S == 4 ? F(4, 4, 4) : F(4, 4, 2);   \
+  if (Mr == 128 && NB == 32) return S == 2 ? F(8, 2, 2) : 0;           \
   if (Mr == 128 && NB == 64) return S == 2 ? F(8, 4, 2) : F(8, 4, 1);
 #define WG_SEG(a, b, c) launch_wgrad_seg<a, b, c>(n, l, B, st)
 #define WG_ROW1(a, b, c) launch_wgrad_row<a, b, c, false>(n, l, B, st)
 #define WG_ROWU(a, b, c) launch_wgrad_row<a, b, c, true>(n, l, B, st)
-#define WG_NONE(a, b, c) 0
-  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_NONE) }
-  else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU, WG_ROWU) }
-  else { WG_CASES(WG_SEG, WG_NONE) }
+#define WG_ROW3(a, b, c) launch_wgrad_row<a, b, c, false, 3>(n, l, B, st)
+#define WG_ROWU3(a, b, c) launch_wgrad_row<a, b, c, true, 3>(n, l, B, st)
+  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_ROW3) }
+  else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU, WG_ROWU3) }
+  else { WG_CASES(WG_SEG, WG_SEG) }
 #undef WG_CASES
 #undef WG_SEG
 #undef WG_ROW1
 #undef WG_ROWU
-#undef WG_NONE
+#undef WG_ROW3
+#undef WG_ROWU3
   return 0;
 }
 
