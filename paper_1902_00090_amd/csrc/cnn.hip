@@ -330,8 +330,11 @@ template <int MT, int KS, bool BWD, bool WL = false>
 __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
   constexpr int PH = 2 * CS_TH + KS - 2, PW = 2 * CS_TW + KS - 2, NTAP = KS * KS;
   __shared__ __attribute__((aligned(16))) bf16 patch[PH * PW * CT_PS];
-  // WL: the chunk's weights of every tap, staged with the patch ([tap][row][40])
-  __shared__ __attribute__((aligned(16))) bf16 wl[WL ? NTAP * 16 * MT * CT_PS : 8];
+  // WL: the chunk's weights, staged with the patch ([tap][row][40]) in groups
+  // of NTW taps (all nine for KS = 3; two groups of eight for the 16 taps of
+  // KS = 4, whose weights would not fit LDS at once)
+  constexpr int NTW = WL ? (NTAP > 9 ? NTAP / 2 : NTAP) : 1;
+  __shared__ __attribute__((aligned(16))) bf16 wl[WL ? NTW * 16 * MT * CT_PS : 8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x0 = blockIdx.x * CS_TW, y0 = blockIdx.y * CS_TH, b = blockIdx.z;
   const int Hq = a.Hq, Wq = a.Wq;
@@ -347,19 +350,31 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
     for (int i = 0; i < MT; ++i) av[i] = load8(wt + (size_t)(i * 16 + (lane & 15)) * a.Ksrc);
   };
   constexpr int NSTG = (PH * PW * 4 + 255) / 256;
-  constexpr int NWI = WL ? NTAP * 16 * MT * 4 : 0, NWS = (NWI + 255) / 256;
+  constexpr int NWI = WL ? NTW * 16 * MT * 4 : 0, NWS = (NWI + 255) / 256;
+  u32x4 wv[NWS > 0 ? NWS : 1];
+  // weights of taps g0 .. g0 + NTW - 1 of chunk c0 into registers, then LDS
+  auto wfetch = [&](int g0, int c0) {
+#pragma unroll
+    for (int it = 0; it < NWS; ++it) {
+      const int u = threadIdx.x + 256 * it;   // (tap, row, quarter)
+      const int tq = u / (16 * MT * 4), rem = u - tq * 16 * MT * 4;
+      wv[it] = u32x4{0u, 0u, 0u, 0u};
+      if (u < NWI)
+        wv[it] = *(const u32x4*)(a.W + ((size_t)(g0 + tq) * a.M + (rem >> 2)) * a.Ksrc + c0 +
+                                 8 * (rem & 3));
+    }
+  };
+  auto wstore = [&]() {
+#pragma unroll
+    for (int it = 0; it < NWS; ++it) {
+      const int u = threadIdx.x + 256 * it;
+      if (u < NWI) *(u32x4*)(wl + (u >> 2) * CT_PS + 8 * (u & 3)) = wv[it];
+    }
+  };
   for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
     bf16x8 wcur[MT], wnext[MT];
-    u32x4 wv[NWS > 0 ? NWS : 1];
     if (WL) {
-#pragma unroll
-      for (int it = 0; it < NWS; ++it) {
-        const int u = threadIdx.x + 256 * it;   // (tap, row, quarter)
-        const int tq = u / (16 * MT * 4), rem = u - tq * 16 * MT * 4;
-        wv[it] = u32x4{0u, 0u, 0u, 0u};
-        if (u < NWI)
-          wv[it] = *(const u32x4*)(a.W + ((size_t)tq * a.M + (rem >> 2)) * a.Ksrc + c0 + 8 * (rem & 3));
-      }
+      wfetch(0, c0);
     } else {
       wload(0, c0, wcur);
     }
@@ -379,20 +394,20 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
       const int u = threadIdx.x + 256 * it;
       if (u < PH * PW * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
     }
-    if (WL) {
-#pragma unroll
-      for (int it = 0; it < NWS; ++it) {
-        const int u = threadIdx.x + 256 * it;
-        if (u < NWI) *(u32x4*)(wl + (u >> 2) * CT_PS + 8 * (u & 3)) = wv[it];
-      }
-    }
+    if (WL) wstore();
     __syncthreads();
 #pragma unroll 1
     for (int t = 0; t < NTAP; ++t) {
       if (WL) {
+        if (t > 0 && t % NTW == 0) {   // next tap group (only for NTW < NTAP)
+          __syncthreads();
+          wfetch(t, c0);
+          wstore();
+          __syncthreads();
+        }
 #pragma unroll
         for (int i = 0; i < MT; ++i)
-          wcur[i] = *(const bf16x8*)(wl + (t * 16 * MT + i * 16 + (lane & 15)) * CT_PS + kq);
+          wcur[i] = *(const bf16x8*)(wl + ((t % NTW) * 16 * MT + i * 16 + (lane & 15)) * CT_PS + kq);
       } else if (t + 1 < NTAP) {
         wload(t + 1, c0, wnext);
       }
@@ -1565,7 +1580,10 @@ static dd_status gemm_dispatch(const GemmArgs& a, bool bwd, hipStream_t st) {
       switch (MT) {
         case 2: k_conv_tile_s2<2, 4, true><<<grid, 256, 0, st>>>(a); break;
         case 4: k_conv_tile_s2<4, 4, true><<<grid, 256, 0, st>>>(a); break;
-        case 8: k_conv_tile_s2<8, 4, true><<<grid, 256, 0, st>>>(a); break;
+        case 8:
+          if (a.Ksrc > 32) k_conv_tile_s2<8, 4, true, true><<<grid, 256, 0, st>>>(a);
+          else k_conv_tile_s2<8, 4, true><<<grid, 256, 0, st>>>(a);
+          break;
       }
     }
     return DD_OK;
