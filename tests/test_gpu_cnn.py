@@ -128,8 +128,8 @@ def test_adam_step_and_training_reduces_loss():
 def test_three_channel_forward_and_gradients_match_oracle(nx, ny):
     """Permittivity plus effective-index field (the paper's CNN input): the
     input planes, every layer, the output and all gradients against the
-    oracle at identical weights (64 x 32 takes the row-segment weight-gradient
-    kernels of layers 1 and 6-8)."""
+    oracle at identical weights (64 x 32: two full 128-pixel row chunks per
+    row in the weight gradients of layers 6-8)."""
     import torch
     from paper_1902_00090_amd.cnn import flat_to_layers
     B, k = 3, 4
@@ -146,6 +146,32 @@ def test_three_channel_forward_and_gradients_match_oracle(nx, ny):
         assert _rel(a_gpu.transpose(0, 3, 1, 2), a_ref) < 3e-2, li
     assert _rel(U, ocnn.channels_to_fields(out)) < 3e-2
     rng = np.random.default_rng(12)
+    tgt = ((rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny)))
+           * 0.1).astype(np.complex64)
+    loss, g = net.grad(eps_d, torch.tensor(tgt, device="cuda"), eim=eim_d)
+    lo, dout = ocnn.mse(out, ocnn.fields_to_channels(tgt.astype(np.complex128), ny, nx))
+    go = ocnn.backward(op, cache, dout, k)
+    assert abs(loss - lo) < 1e-2 * lo
+    gg = flat_to_layers(g.astype(np.float64), net.layers())
+    for li in range(8):
+        assert _rel(gg[li][0], go[li][0]) < 6e-2, ("w", li, _rel(gg[li][0], go[li][0]))
+        assert _rel(gg[li][1], go[li][1]) < 6e-2, ("b", li, _rel(gg[li][1], go[li][1]))
+
+
+def test_full_size_three_planes_forward_and_gradients():
+    """The benchmark's network at its grid: 480 x 240, permittivity plus
+    effective-index field, k = 10, two images.  Every kernel runs at the
+    shapes the benchmark times (LDS-staged weights, the FP32-MFMA layer 1, the
+    three-dy weight gradients and the two tap groups of the upsampling
+    backward); output and all gradients against the oracle."""
+    import torch
+    from paper_1902_00090_amd.cnn import flat_to_layers
+    nx, ny, B, k = 480, 240, 2, 10
+    net, op, eps, eps_d, eim, eim_d = _setup(nx, ny, B, k, seed=21, in_ch=3)
+    U = net.predict(eps_d, eim=eim_d).cpu().numpy()
+    out, cache = ocnn.forward(op, eps.astype(np.float64), k, eim=eim.astype(np.complex128))
+    assert _rel(U, ocnn.channels_to_fields(out)) < 3e-2
+    rng = np.random.default_rng(22)
     tgt = ((rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny)))
            * 0.1).astype(np.complex64)
     loss, g = net.grad(eps_d, torch.tensor(tgt, device="cuda"), eim=eim_d)
