@@ -316,7 +316,8 @@ dd_status eim_field(const fdfd_op* const* ops, int nb, const void* const* b, voi
  * image (the architecture figure of the paper is not available; the layer
  * list is fixed by dd_cnn_layer_info).  Activations are bf16 in NHWC
  * layout, products accumulate in FP32 on the matrix cores, master weights
- * and Adam moments are FP32.  The 2k output channels are read as k complex
+ * and Adam moments are FP32.  The first layer (input planes to 32 channels)
+ * and its weight gradient run in FP32 throughout.  The 2k output channels are read as k complex
  * fields (channel 2j = real part, 2j+1 = imaginary part of v_j).
  */
 
