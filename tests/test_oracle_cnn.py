@@ -132,3 +132,40 @@ def test_effective_index_input_planes():
     np.testing.assert_allclose(np.mean(x[0, 1] ** 2 + x[0, 2] ** 2), 1.0, rtol=1e-12)
     assert np.all(x[1, 1:] == 0.0)
     np.testing.assert_allclose(x[:, 0], cnn.normalise(eps), rtol=0)
+
+
+@pytest.mark.parametrize("b1,b2", [(0.9, 0.999), (0.5, 0.7)])
+def test_adam_constant_gradient_every_step(b1, b2):
+    """With a constant gradient g and zero initial moments the bias-corrected
+    moments are exactly m^ = g and v^ = g^2 at every step t (the corrections
+    1 - b^t cancel the geometric sums), so p_t = p_0 - t lr g / (|g| + eps).
+    A wrong correction exponent (b instead of b^t) breaks this from t = 2 on."""
+    g0 = np.array([0.5, -4.0, 1e-3, 2.5])
+    p0 = np.array([1.0, -2.0, 3.0, 0.0])
+    p = [[p0.copy()]]
+    st = {}
+    lr, eps = 0.01, 1e-8
+    for t in range(1, 13):
+        cnn.adam_step(p, [[g0.copy()]], st, lr=lr, b1=b1, b2=b2, eps=eps)
+        np.testing.assert_allclose(p[0][0], p0 - t * lr * g0 / (np.abs(g0) + eps),
+                                   rtol=1e-12, atol=1e-15)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """Gradients g, -g, g, -g, ...: the first moment is a geometric sum with
+    ratio -b1, m_t = (1 - b1) g sum_{i<t} (-b1)^i (-1)^(t-1) ... in closed form
+    m_t = (1-b1)/(1+b1) (1 - (-b1)^t) g (-1)^(t-1), while v_t = (1 - b2^t) g^2.
+    Hence the step at t is lr * (1-b1)/(1+b1) * (1 - (-b1)^t)/(1 - b1^t)
+    * (-1)^(t-1) g / (|g| + eps); this separates the first and second moments
+    and both bias corrections."""
+    b1, b2, lr, eps = 0.9, 0.999, 0.1, 0.0
+    g0 = np.array([0.3, -1.7, 4.0])
+    p = [[np.zeros(3)]]
+    st = {}
+    ref = np.zeros(3)
+    for t in range(1, 9):
+        sgn = (-1.0) ** (t - 1)
+        cnn.adam_step(p, [[sgn * g0]], st, lr=lr, b1=b1, b2=b2, eps=eps)
+        mh = (1 - b1) / (1 + b1) * (1 - (-b1) ** t) / (1 - b1 ** t) * sgn
+        ref = ref - lr * mh * g0 / np.abs(g0)
+        np.testing.assert_allclose(p[0][0], ref, rtol=1e-12)

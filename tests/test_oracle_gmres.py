@@ -134,3 +134,51 @@ def test_augmentation_cuts_first_iteration_residual():
     _, ip = gmres.gmres(A, inst.b, restart=30, tol=1e-8, maxit=500)
     assert ia["history"][0] < 1e-2 < ip["history"][0]
     assert ia["iters"] < ip["iters"]
+
+
+def test_restarted_augmented_converges_to_dense_solution():
+    """Many restarted cycles (restart far shorter than the iteration count,
+    k > 0): the oracle must reach the tolerance, report it truthfully, and
+    land on the dense LU solution (every cycle after the first starts from
+    x != 0 with the right-hand side [C^H r; Q^H r] of eq:final_lsq)."""
+    inst = tiny(10, 14, 12)
+    A = fdfd.assemble_instance(inst)
+    V = W.random_complex(np.random.default_rng(6), (inst.D, 4))
+    x, info = gmres_aug.gmres_aug(A, inst.b, V, restart=6, tol=1e-10, maxit=20000)
+    assert info["cycles"] >= 5 and info["iters"] > 6
+    assert info["converged"]
+    rr = np.linalg.norm(inst.b - A @ x) / np.linalg.norm(inst.b)
+    assert rr <= 1e-10 and abs(rr - info["rel_res"]) <= 1e-12
+    xs = direct.dense_solve(A, inst.b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
+
+
+@pytest.mark.parametrize("i", [1, 2, 3])
+def test_augmented_cycle_from_nonzero_start(i):
+    """A cycle started from x0 != 0 minimises over x0 + range(V) + K_i(P A, P r0),
+    r0 = b - A x0: it equals x0 plus the brute-force minimiser of the shifted
+    system A e = r0 over explicit bases."""
+    inst = tiny(11)
+    A = fdfd.assemble_instance(inst)
+    rng = np.random.default_rng(7)
+    V = W.random_complex(rng, (inst.D, 3))
+    x0 = W.random_complex(rng, inst.D)
+    x, _ = gmres_aug.gmres_aug(A, inst.b, V, x0=x0, tol=0.0, maxit=i)
+    xb = x0 + gmres_aug.augmented_bruteforce(A, inst.b - A @ x0, V, i)
+    np.testing.assert_allclose(x, xb, atol=1e-9 * np.abs(xb).max())
+
+
+@pytest.mark.parametrize("m,i", [(2, 1), (3, 2), (3, 3)])
+def test_second_cycle_is_minimiser_from_first_cycle_iterate(m, i):
+    """Restarted cycles: after a first cycle of m steps (iterate x1, the
+    minimiser over range(V) + K_m), the next i <= m steps give x1 plus the
+    minimiser over range(V) + K_i(P A, P r1) of the system A e = r1 with
+    r1 = b - A x1 (brute force over explicit bases, independent code)."""
+    inst = tiny(12)
+    A = fdfd.assemble_instance(inst)
+    V = W.random_complex(np.random.default_rng(8), (inst.D, 2))
+    x1b = gmres_aug.augmented_bruteforce(A, inst.b, V, m)
+    x2, info = gmres_aug.gmres_aug(A, inst.b, V, restart=m, tol=0.0, maxit=m + i)
+    assert info["cycles"] == 2 and info["iters"] == m + i
+    x2b = x1b + gmres_aug.augmented_bruteforce(A, inst.b - A @ x1b, V, i)
+    np.testing.assert_allclose(x2, x2b, atol=1e-8 * np.abs(x2b).max())
