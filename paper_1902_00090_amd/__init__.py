@@ -32,6 +32,29 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+DD_MAX_K = 64  # largest number of augmenting vectors the library accepts
+
+
+def _check_lengths(nb, **lists):
+    """Every per-problem list (None allowed) must hold exactly nb entries: the
+    library reads nb pointers from each array it is given."""
+    for name, v in lists.items():
+        if v is not None and len(v) != nb:
+            raise ValueError(f"{name} has {len(v)} entries, expected one per problem ({nb})")
+
+
+def _check_subspace(U, D, what="U"):
+    """U must be a 2-D [k, D] array with 0 <= k <= DD_MAX_K (checked before any
+    pointer reaches the library, which reads k * D elements)."""
+    if U is None:
+        return 0
+    if U.dim() != 2 or U.shape[1] != D:
+        raise ValueError(f"{what} must be [k, D={D}], got {tuple(U.shape)}")
+    if U.shape[0] > DD_MAX_K:
+        raise ValueError(f"{what} has {U.shape[0]} vectors, at most {DD_MAX_K} are supported")
+    return int(U.shape[0])
+
+
 def _dev(t, dtype=None, numel=None, what="tensor"):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -162,14 +185,16 @@ class Solver:
             self.k = [0] * self.nb
             return
         dt = torch.complex64 if self.inner == "c64" else torch.complex128
+        _check_lengths(self.nb, U=U)
         ptrs, ks = [], (C.c_int * self.nb)()
         for p, u in enumerate(U):
             if u is None or u.numel() == 0:
                 ptrs.append(None)
                 ks[p] = 0
                 continue
-            if u.dim() != 2 or u.shape[1] != self.ops[p].D:
-                raise ValueError(f"U[{p}] must be [k, D={self.ops[p].D}]")
+            if _check_subspace(u, self.ops[p].D, f"U[{p}]") > self.kmax:
+                raise ValueError(f"U[{p}] has {u.shape[0]} vectors, the solver's kmax is "
+                                 f"{self.kmax}")
             ptrs.append(_dev(u, dt, what=f"U[{p}]").value)
             ks[p] = u.shape[0]
         check(_lib.lib().dd_solver_set_subspace(self._h, ptr_array(ptrs), ks, _stream()),
@@ -179,6 +204,7 @@ class Solver:
     def solve(self, b, x0=None, tol=1e-6, maxit=20000, x=None):
         """b: list of [D] complex128 tensors.  Returns (x list, list of info dicts, status)."""
         torch = _torch()
+        _check_lengths(self.nb, b=b, x=x, x0=x0)
         if x is None:
             x = [torch.empty_like(bb) for bb in b]
         bp = ptr_array([_dev(bb, torch.complex128, self.ops[p].D, f"b[{p}]").value
@@ -252,7 +278,7 @@ def gmres_solve(op, b, U=None, tol=1e-6, restart=100, maxit=20000, x0=None, inne
         x = torch.empty_like(b)
     o = _opts(restart, 0, inner, cgs_passes)
     info = _lib.dd_info()
-    k = 0 if U is None else U.shape[0]
+    k = _check_subspace(U, op.D)
     dt = torch.complex64 if inner == "c64" else torch.complex128
     st = check(_lib.lib().gmres_solve(
         op.handle, _dev(b, torch.complex128, op.D, "b"),

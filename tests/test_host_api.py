@@ -76,3 +76,24 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_binding_rejects_mismatched_lists_and_subspace_shapes():
+    """Per-problem lists of the wrong length and subspaces of the wrong shape
+    raise in Python before any pointer array reaches the library (which would
+    otherwise read past the end of a short array)."""
+    import torch
+    from paper_1902_00090_amd import _check_lengths, _check_subspace
+    _check_lengths(3, b=[1, 2, 3], x=None, x0=[None, None, None])
+    for kw in (dict(b=[1, 2]), dict(x=[1, 2, 3, 4]), dict(x0=[None])):
+        with pytest.raises(ValueError):
+            _check_lengths(3, **kw)
+    D = 40
+    assert _check_subspace(None, D) == 0
+    assert _check_subspace(torch.zeros((5, D), dtype=torch.complex64), D) == 5
+    for bad in (torch.zeros((5, D + 1), dtype=torch.complex64),
+                torch.zeros((5 * D,), dtype=torch.complex64),
+                torch.zeros((2, 5, D), dtype=torch.complex64),
+                torch.zeros((65, D), dtype=torch.complex64)):
+        with pytest.raises(ValueError):
+            _check_subspace(bad, D)
