@@ -95,15 +95,45 @@ def conv_backward(x, w, dz, stride):
     return dxp[:, :, 1:-1, 1:-1], dw, dz.sum(axis=(0, 2, 3))
 
 
-def forward(params, eps, k: int = 10, eim=None):
+def round_f32(a):
+    """Nearest IEEE single-precision value, as float64."""
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_bf16(a):
+    """Nearest bfloat16 value, as float64.  bfloat16 is the upper half of an
+    IEEE single (sign, 8 exponent bits, 7 fraction bits); the value is first
+    rounded to single precision, then to the nearest bfloat16, ties to the
+    even fraction (adding 0x7FFF plus the lowest kept bit to the 32-bit
+    pattern and truncating the lower 16 bits does exactly that)."""
+    u = np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32)).view(np.uint32)
+    u = u.astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+STORE = {None: (lambda a: a, lambda a: a, lambda a: a),
+         "bf16": (round_f32, round_bf16, round_f32)}
+
+
+def forward(params, eps, k: int = 10, eim=None, store=None):
     """eps: [B, H, W] permittivity; eim: [B, H*W] effective-index fields for a
-    three-channel network.  Returns (out [B, 2k, H, W], cache)."""
-    x = inputs(eps, eim)
+    three-channel network.  Returns (out [B, 2k, H, W], cache).
+
+    store: None keeps every value in float64.  "bf16" rounds the values the
+    method stores between layers to their storage precision (BF16 with FP32
+    accumulation): the input planes to single precision, each hidden layer's
+    activation to bfloat16, the output fields to single precision.  The
+    arithmetic of every layer stays float64."""
+    r_in, r_act, r_out = STORE[store]
+    x = r_in(inputs(eps, eim))
     cache = []
-    for (cin, cout, s, up, relu), (w, b) in zip(layer_list(k, x.shape[1]), params):
+    layers = layer_list(k, x.shape[1])
+    for li, ((cin, cout, s, up, relu), (w, b)) in enumerate(zip(layers, params)):
         xin = upsample2(x) if up else x
         z = conv_forward(xin, w, b, s)
         y = np.maximum(z, 0.0) if relu else z
+        y = r_act(y) if li < len(layers) - 1 else r_out(y)
         cache.append((x, xin, z))
         x = y
     return x, cache
@@ -114,14 +144,23 @@ def mse(out, target):
     return float(np.mean(d * d)), 2.0 * d / d.size
 
 
-def backward(params, cache, dout, k: int = 10):
-    """Gradients [[dw, db], ...] of the loss whose derivative w.r.t. the output is dout."""
+def backward(params, cache, dout, k: int = 10, store=None, dzs=None):
+    """Gradients [[dw, db], ...] of the loss whose derivative w.r.t. the output is dout.
+
+    store: as in forward; "bf16" rounds each layer's gradient with respect
+    to its pre-activation (the value stored between the backward layers) to
+    bfloat16.  dzs: an optional dict that receives, by layer, the pair (gradient
+    with respect to the layer output, gradient with respect to its
+    pre-activation)."""
+    rnd = STORE[store][1]
     grads = [None] * len(params)
     dy = dout
     for li in range(len(params) - 1, -1, -1):
         cin, cout, s, up, relu = layer_list(k)[li]
         x, xin, z = cache[li]
-        dz = dy * (z > 0) if relu else dy
+        dz = rnd(dy * (z > 0) if relu else dy)
+        if dzs is not None:
+            dzs[li] = (dy, dz)
         dxin, dw, db = conv_backward(xin, params[li][0], dz, s)
         grads[li] = [dw, db]
         if up:

@@ -169,3 +169,43 @@ def test_adam_alternating_gradient_closed_form():
         mh = (1 - b1) / (1 + b1) * (1 - (-b1) ** t) / (1 - b1 ** t) * sgn
         ref = ref - lr * mh * g0 / np.abs(g0)
         np.testing.assert_allclose(p[0][0], ref, rtol=1e-12)
+
+
+def test_round_bf16_matches_library_conversion():
+    """The oracle's bfloat16 rounding equals torch's float32 -> bfloat16
+    conversion (round to nearest, ties to even) on random values, exact ties,
+    subnormals and values near the overflow edge."""
+    import torch
+    rng = np.random.default_rng(13)
+    vals = [rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000)]
+    # exact ties: bfloat16 values with the bit just below the kept fraction set
+    base = rng.standard_normal(4000).astype(np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+    vals.append((base | np.uint32(0x8000)).view(np.float32).astype(np.float64))
+    vals.append(np.array([0.0, -0.0, 1e-40, -3e-39, 3.3e38, -3.3e38, 1.0, 1.00390625]))
+    x = np.concatenate(vals)
+    ref = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(cnn.round_bf16(x), ref.astype(np.float64))
+    np.testing.assert_array_equal(cnn.round_f32(x), x.astype(np.float32).astype(np.float64))
+
+
+def test_storage_rounding_only_rounds():
+    """forward/backward with bf16 storage stay within bfloat16 rounding of the
+    float64 network on a small case (the arithmetic is the same), and every
+    stored activation and layer gradient is a bfloat16 value."""
+    rng = np.random.default_rng(14)
+    k = 2
+    params = cnn.init_params(k, seed=2)
+    eps = 2.085 + 10.165 * rng.random((2, 24, 32))
+    o64, c64 = cnn.forward(params, eps, k)
+    o16, c16 = cnn.forward(params, eps, k, store="bf16")
+    assert np.linalg.norm(o16 - o64) / np.linalg.norm(o64) < 3e-2
+    for li in range(1, 8):
+        a = c16[li][0]                      # input of layer li = stored activation of li - 1
+        np.testing.assert_array_equal(a, cnn.round_bf16(a))
+    tgt = rng.standard_normal(o16.shape)
+    _, d16 = cnn.mse(o16, tgt)
+    g16 = cnn.backward(params, c16, d16, k, store="bf16")
+    _, d64 = cnn.mse(o64, tgt)
+    g64 = cnn.backward(params, c64, d64, k)
+    for li in range(8):
+        assert np.linalg.norm(g16[li][0] - g64[li][0]) / np.linalg.norm(g64[li][0]) < 6e-2
