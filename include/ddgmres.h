@@ -286,6 +286,21 @@ dd_status proj_loss_batched(const void* V, const void* f, int nb, int k, int D, 
 dd_status res_loss_batched(const fdfd_op* const* ops, const void* const* b, const void* const* V,
                            int nb, int k, double* out, hipStream_t stream);
 
+/* Residual loss and its gradient with respect to the subspace (Sec. 3,
+ * eq:res_loss), the quantity the residual-loss training feeds into the
+ * network's backward pass.  With c the least-squares coefficients and
+ * r = b - A V c, the conjugate (Wirtinger) gradient is
+ *     G = dl / d conj(V) = -(A^H r) c^H / ||b||^2,
+ * so dl / d Re V = 2 Re G and dl / d Im V = 2 Im G.
+ *   ops, b, V, nb, k, out: as res_loss_batched.
+ *   G[p]: [k][D] c64 output (device, host array of nb pointers); column j is
+ *         -(A^H r) conj(c_j) / ||b||^2.
+ * Matvecs and r in complex64, the Gram matrix FP64, c FP64 on the host.
+ * Scratch is allocated and freed inside the call.  Synchronises the stream. */
+dd_status res_loss_grad_batched(const fdfd_op* const* ops, const void* const* b,
+                                const void* const* V, int nb, int k, double* out,
+                                void* const* G, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Effective-index field (Sec. 3: the CNN's second input)
  * ------------------------------------------------------------------------

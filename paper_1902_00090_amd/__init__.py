@@ -370,4 +370,24 @@ def res_loss_batched(ops, b, V):
     return out
 
 
+def res_loss_grad_batched(ops, b, V):
+    """Residual loss and its conjugate gradient G = -(A^H r) c^H / ||b||^2 with
+    respect to V[p] ([k, D] complex64), for the problems (ops[p], b[p]).
+    Returns (numpy [nb] losses, list of [k, D] complex64 gradients)."""
+    torch = _torch()
+    nb = len(ops)
+    _check_lengths(nb, b=b, V=V)
+    k = V[0].shape[0]
+    out = np.zeros(nb, np.float64)
+    G = [torch.empty((k, op.D), dtype=torch.complex64, device=v.device) for op, v in zip(ops, V)]
+    opp = ptr_array([op._h.value for op in ops])
+    bp = ptr_array([_dev(bb, torch.complex128, ops[p].D, f"b[{p}]").value for p, bb in enumerate(b)])
+    vp = ptr_array([_dev(v, torch.complex64, k * ops[p].D, f"V[{p}]").value for p, v in enumerate(V)])
+    gp = ptr_array([g.data_ptr() for g in G])
+    check(_lib.lib().res_loss_grad_batched(opp, bp, vp, nb, k,
+                                           out.ctypes.data_as(C.POINTER(C.c_double)), gp,
+                                           _stream()), "res_loss_grad_batched")
+    return out, G
+
+
 from .cnn import Cnn  # noqa: E402

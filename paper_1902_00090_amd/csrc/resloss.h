@@ -11,8 +11,11 @@
 // when dz != NULL also dz[(p D + e) coutp + ch] (bf16) = derivative of
 // scale * loss[p] with respect to the real (ch = 2j) and imaginary (ch = 2j+1)
 // part of V[p][j][e], channels >= 2k zero.
+// when Gout != NULL (host array of nb device pointers) also
+// Gout[p][j][e] (complex64) = 2 scale dl / d conj(V[p][j][e]).
 // Wbuf holds k * sum D complex64 values; rbuf and sbuf sum D each (only used
-// when dz != NULL).  Synchronises the stream.
+// when dz or Gout is given).  Synchronises the stream.
 dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const void* const* V,
                         int nb, int k, float2* Wbuf, float2* rbuf, float2* sbuf, double* loss,
-                        __bf16* dz, int coutp, double scale, hipStream_t st);
+                        __bf16* dz, int coutp, double scale, hipStream_t st,
+                        void* const* Gout = nullptr);

@@ -45,6 +45,7 @@ struct RlDesc {
   float2* r;            // [D]
   float2* s;            // [D]
   const double2* c;     // [k] minimiser
+  float2* G;            // [k][D] field gradient (NULL unless requested)
 };
 
 // W_j = A V_j for all k vectors: a thread takes one cell of every vector, so
@@ -143,6 +144,23 @@ __global__ __launch_bounds__(256) void k_rl_dz(const RlDesc* __restrict__ desc, 
       h[q] = (__bf16)g;
     }
     *(rl_u32x4*)(o + c0) = __builtin_bit_cast(rl_u32x4, h);
+  }
+}
+
+// G[j][e] = s_e a_j with a_j = -conj(c_j) / ||b||^2 (coef holds a): the
+// conjugate gradient dl / d conj(V) = -(A^H r) c^H / ||b||^2 in complex64,
+// the field layout of V.
+__global__ __launch_bounds__(256) void k_rl_grad(const RlDesc* __restrict__ desc, int k,
+                                                 const double2* __restrict__ coef) {
+  const int pb = blockIdx.y;
+  const RlDesc d = desc[pb];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= d.D) return;
+  const float2 s = d.s[e];
+  for (int j = 0; j < k; ++j) {
+    const double2 a = coef[(size_t)pb * k + j];
+    d.G[(size_t)j * d.D + e] =
+        make_float2((float)(s.x * a.x - s.y * a.y), (float)(s.x * a.y + s.y * a.x));
   }
 }
 
@@ -293,7 +311,8 @@ bool solve_small(const std::vector<cd>& G, int k, std::vector<cd>& c, double& lo
 
 dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const void* const* V,
                         int nb, int k, float2* Wbuf, float2* rbuf, float2* sbuf, double* loss,
-                        __bf16* dz, int coutp, double scale, hipStream_t st) {
+                        __bf16* dz, int coutp, double scale, hipStream_t st,
+                        void* const* Gout) {
   std::vector<RlDesc> hd(nb);
   int maxD = 0;
   size_t offW = 0, offR = 0;
@@ -307,6 +326,7 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
     d.b = (const double2*)b[p];
     d.r = rbuf ? rbuf + offR : nullptr;
     d.s = sbuf ? sbuf + offR : nullptr;
+    d.G = Gout ? (float2*)Gout[p] : nullptr;
     offW += (size_t)k * op->D;
     offR += (size_t)op->D;
     maxD = std::max(maxD, op->D);
@@ -357,11 +377,14 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
       hc[(size_t)(nb + p) * k + j] = make_double2(a.real(), a.imag());
     }
   }
-  if (dz) {
+  if (dz || Gout) {
     DD_HIP_CHECK(hipMemcpyAsync(dc, hc.data(), sizeof(double2) * hc.size(), hipMemcpyHostToDevice, st));
     k_rl_resid<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k);
     k_rl_adjoint<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd);
-    k_rl_dz<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k, coutp, dc + (size_t)nb * k, dz);
+    if (dz)
+      k_rl_dz<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k, coutp, dc + (size_t)nb * k, dz);
+    if (Gout)
+      k_rl_grad<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k, dc + (size_t)nb * k);
     DD_HIP_CHECK(hipGetLastError());
   }
   DD_HIP_CHECK(hipStreamSynchronize(st));
@@ -386,5 +409,29 @@ extern "C" dd_status res_loss_batched(const fdfd_op* const* ops, const void* con
   DevBuf wb;
   DD_HIP_CHECK(hipMalloc(&wb.p, sizeof(float2) * tot * k));
   return res_loss_core(ops, b, V, nb, k, (float2*)wb.p, nullptr, nullptr, out, nullptr, 0, 0.0,
-                       stream);
+                       stream, nullptr);
+}
+
+extern "C" dd_status res_loss_grad_batched(const fdfd_op* const* ops, const void* const* b,
+                                           const void* const* V, int nb, int k, double* out,
+                                           void* const* G, hipStream_t stream) {
+  if (!ops || !b || !V || !out || !G || nb < 1 || k < 1 || k > 64) {
+    dd_set_error("res_loss_grad_batched: need ops, b, V, out, G, nb >= 1 and 1 <= k <= 64");
+    return DD_EINVAL;
+  }
+  size_t tot = 0;
+  for (int p = 0; p < nb; ++p) {
+    if (!ops[p] || !b[p] || !V[p] || !G[p]) {
+      dd_set_error("res_loss_grad_batched: problem %d has a NULL operator, b, V or G", p);
+      return DD_EINVAL;
+    }
+    tot += (size_t)ops[p]->D;
+  }
+  DevBuf wb, rb, sb;
+  DD_HIP_CHECK(hipMalloc(&wb.p, sizeof(float2) * tot * k));
+  DD_HIP_CHECK(hipMalloc(&rb.p, sizeof(float2) * tot));
+  DD_HIP_CHECK(hipMalloc(&sb.p, sizeof(float2) * tot));
+  // scale 1/2: the coefficient -2 scale conj(c) / ||b||^2 becomes -conj(c) / ||b||^2
+  return res_loss_core(ops, b, V, nb, k, (float2*)wb.p, (float2*)rb.p, (float2*)sb.p, out,
+                       nullptr, 0, 0.5, stream, G);
 }
