@@ -42,30 +42,62 @@ def test_res_loss_batched_matches_oracle(k):
     assert lg[0] < 1e-5 and all(0.0 <= x <= 1.0 for x in lg)
 
 
+@pytest.mark.parametrize("k", [1, 4, 10])
+def test_res_loss_field_gradient_elementwise(k):
+    """The conjugate gradient G = -(A^H r) c^H / ||b||^2 of the residual loss
+    with respect to the subspace (what the residual-loss training feeds into
+    the network), element by element against the oracle's res_loss_grad on
+    three grids of different sizes (ragged slices).  The GPU forms W = A V,
+    r = b - W c and A^H r in complex64 with c from an FP64 Gram matrix, so each
+    element carries a few single-precision roundings of the terms behind it:
+    |dG| <= 2^-16 |a_j| (|A|^T (|b| + sum_i |W_i| |c_i|)) with a_j = c_j/||b||^2."""
+    import torch
+    from paper_1902_00090_amd import res_loss_grad_batched
+    insts = [W.grating(1200, nx=96, ny=48), W.grating(1201, nx=480, ny=240),
+             W.grating(1202, nx=192, ny=96, wavelength=1.55)]
+    rng = np.random.default_rng(16)
+    Vs = [W.random_complex(rng, (k, i.D)).astype(np.complex64) for i in insts]
+    ops, bs = _ops_b(insts)
+    lg, Gg = res_loss_grad_batched(ops, bs, [torch.tensor(v, device="cuda") for v in Vs])
+    for p, inst in enumerate(insts):
+        A = fdfd.assemble_instance(inst)
+        V = Vs[p].T.astype(np.complex128)
+        l, G = losses.res_loss_grad(A, V, inst.b)
+        assert abs(lg[p] - l) <= 1e-5 * max(l, 1e-3), (lg[p], l)
+        AV = A @ V
+        c = np.linalg.lstsq(AV, inst.b, rcond=None)[0]
+        bb = np.vdot(inst.b, inst.b).real
+        absA = abs(A)
+        scale = absA.T @ (np.abs(inst.b) + np.abs(AV) @ np.abs(c))
+        bound = 2.0 ** -16 * np.outer(scale, np.abs(c) / bb)
+        err = np.abs(Gg[p].cpu().numpy().T.astype(np.complex128) - G)
+        ratio = float((err / bound).max())
+        print(f"problem {p} k={k}: max |dG| / bound = {ratio:.3g}")
+        assert ratio <= 1.0, (p, ratio)
+
+
 def test_cnn_residual_gradient_matches_oracle():
     """Forward, residual loss of the predicted fields, A^H back-projection and
-    the network's backward pass, against the float64 oracle at the same
-    (bf16-rounded) weights."""
+    the network's backward pass, element by element against the oracle with
+    the GPU's storage precision (bf16 activations and layer gradients) at the
+    same weights, with the bounds of the MSE case.  The oracle's field
+    gradient comes from its own forward pass."""
     import torch
     from paper_1902_00090_amd import Cnn
     from paper_1902_00090_amd.cnn import flat_to_layers, layers_to_flat
-    from test_gpu_cnn import _bf16
+    from test_gpu_cnn import _quantise, check_forward, check_grads
     nx, ny, B, k = 24, 16, 2, 3
     insts = [W.grating(1100 + i, nx=nx, ny=ny, npml=3) for i in range(B)]
     net = Cnn(nx, ny, B, k, seed=5)
     rng = np.random.default_rng(5)
-    params = flat_to_layers(net.get_params().copy(), net.layers())
-    for w, b in params:
-        b[...] = 0.05 * rng.standard_normal(b.shape)
+    params = _quantise(flat_to_layers(net.get_params().astype(np.float64), net.layers()), rng)
     flat = layers_to_flat(params).astype(np.float32)
     net.set_params(flat)
     op = flat_to_layers(flat.astype(np.float64), net.layers())
-    for li in range(1, 8):
-        op[li][0] = _bf16(op[li][0]).astype(np.float64)
     eps = np.stack([i.eps for i in insts])
     ops, bs = _ops_b(insts)
     loss, g = net.grad_res(torch.tensor(eps, device="cuda"), ops, bs)
-    out, cache = ocnn.forward(op, eps.astype(np.float64), k)
+    out, cache = check_forward(net, op, eps, k, B)
     U = ocnn.channels_to_fields(out)
     ls, Gs = [], []
     for p, inst in enumerate(insts):
@@ -73,33 +105,8 @@ def test_cnn_residual_gradient_matches_oracle():
         ls.append(l)
         Gs.append(G.T)
     dout = ocnn.fields_to_channels(2.0 * np.stack(Gs) / B, ny, nx)
-    go = ocnn.backward(op, cache, dout, k)
-    assert abs(loss - np.mean(ls)) < 2e-2 * np.mean(ls), (loss, np.mean(ls))
-    gg = flat_to_layers(g.astype(np.float64), net.layers())
-    # The bias gradients of this loss are sums over pixels that cancel to 1-30%
-    # of their L1 mass, which multiplies the bf16 rounding of the activations
-    # and of the back-projected gradient: they are compared against that mass,
-    # the weights directly (about 8% in bf16 through eight layers); the whole
-    # gradient must point the same way as the oracle's.
-    dy = dout
-    mass = [None] * 8
-    for li in range(7, -1, -1):
-        x, xin, z = cache[li]
-        dz = dy * (z > 0) if li < 7 else dy
-        mass[li] = np.abs(dz).sum(axis=(0, 2, 3))
-        dxin, _, _ = ocnn.conv_backward(xin, op[li][0], dz, ocnn.layer_list(k)[li][2])
-        if ocnn.layer_list(k)[li][3]:
-            b_, c_, h2, w2 = dxin.shape
-            dxin = dxin.reshape(b_, c_, h2 // 2, 2, w2 // 2, 2).sum(axis=(3, 5))
-        dy = dxin
-    for li in range(8):
-        r = np.linalg.norm(gg[li][0] - go[li][0]) / np.linalg.norm(go[li][0])
-        assert r < 1e-1, ("w", li, r)
-        rb = np.linalg.norm(gg[li][1] - go[li][1]) / np.linalg.norm(mass[li])
-        assert rb < 3e-2, ("b", li, rb)
-    a = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in gg])
-    o = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in go])
-    assert np.dot(a, o) / (np.linalg.norm(a) * np.linalg.norm(o)) > 0.995
+    assert abs(loss - np.mean(ls)) < 1e-4 * np.mean(ls), (loss, np.mean(ls))
+    check_grads(net, op, cache, dout, k, g)
 
 
 def test_residual_loss_training_reduces_the_loss():
