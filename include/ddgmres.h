@@ -324,6 +324,21 @@ dd_status res_loss_grad_batched(const fdfd_op* const* ops, const void* const* b,
 dd_status eim_field(const fdfd_op* const* ops, int nb, const void* const* b, void* const* F,
                     hipStream_t stream);
 
+/* eim_field without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as eim_field; its scratch
+ * is a fixed device array of DD_EIM_NOALLOC_BYTES held by the library on
+ * every GPU it runs on until the process ends (resolved once per device on
+ * the first call there).  A batch needs 16 B per cell plus 120 B per grid
+ * column plus 72 B per problem: 1.86 MB for one 480 x 240 grid, so up to 17
+ * such problems per call.  A larger batch returns DD_EINVAL with a message
+ * and runs nothing.  Every call on one GPU uses the same array: calls that
+ * overlap on one GPU (other threads or streams) race and must be serialised
+ * by the caller.  Synchronises the stream. */
+#define DD_EIM_NOALLOC_BYTES 33554432
+dd_status eim_field_noalloc(const fdfd_op* const* ops, int nb, const void* const* b,
+                            void* const* F, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Convolutional subspace predictor (Sec. 3, CNN paragraph; Methods)
  * ------------------------------------------------------------------------

@@ -355,6 +355,20 @@ def eim_field(ops, b, out=None):
     return F if out is None else out
 
 
+def eim_field_noalloc(ops, b, F):
+    """eim_field into caller-provided outputs F (list of [D] complex64 device
+    tensors) with no device allocation: the library's fixed scratch array
+    holds the work (batches up to DD_EIM_NOALLOC_BYTES of scratch)."""
+    torch = _torch()
+    nb = len(ops)
+    _check_lengths(nb, b=b, F=F)
+    opp = ptr_array([op._h.value for op in ops])
+    bp = ptr_array([_dev(bb, torch.complex128, ops[p].D, f"b[{p}]").value for p, bb in enumerate(b)])
+    fp = ptr_array([_dev(f, torch.complex64, ops[p].D, f"F[{p}]").value for p, f in enumerate(F)])
+    check(_lib.lib().eim_field_noalloc(opp, nb, bp, fp, _stream()), "eim_field_noalloc")
+    return F
+
+
 def res_loss_batched(ops, b, V):
     """Residual loss (eq:res_loss) of V[p] ([k, D] complex64) for the problems
     (ops[p], b[p] [D] complex128), all device tensors.  Returns numpy [nb]."""

@@ -82,6 +82,7 @@ _SIGS = {
     "proj_loss_batched": (I, [P, P, I, I, I, C.POINTER(D), P]),
     "local_pca_targets": (I, [P, I, I, I, I, P, P]),
     "eim_field": (I, [PP, I, PP, PP, P]),
+    "eim_field_noalloc": (I, [PP, I, PP, PP, P]),
     "res_loss_batched": (I, [PP, PP, PP, I, I, C.POINTER(D), P]),
     "res_loss_grad_batched": (I, [PP, PP, PP, I, I, C.POINTER(D), PP, P]),
     "dd_cnn_train_step_res": (I, [P, P, P, PP, PP, I, C.c_float, C.c_float, C.c_float,

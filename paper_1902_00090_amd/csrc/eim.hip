@@ -27,11 +27,15 @@
 //    system is solved by Sherman-Morrison over a tridiagonal elimination with
 //    partial pivoting.  The matrix is indefinite, so pivoting is needed.
 //  * k_eim_assemble: writes F in complex64.
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
 #include "op.h"
+
+#define DD_EIM_MAX_DEVICES 64
 
 namespace {
 
@@ -242,19 +246,33 @@ __global__ __launch_bounds__(256) void k_eim_assemble(const EimDesc* __restrict_
 
 }  // namespace
 
-extern "C" dd_status eim_field(const fdfd_op* const* ops, int nb, const void* const* b,
-                               void* const* F, hipStream_t stream) {
+// Scratch layout of one call: phi and pivots (D doubles each); mu (nx
+// doubles); j, diagonal, two super-diagonals, two right-hand sides, amplitude
+// (nx complex each); then the descriptor table.  Every word is written by the
+// kernels before it is read, so nothing needs clearing between calls.
+static size_t eim_scratch_bytes(size_t s2, size_t s1, int nb) {
+  const size_t s1p = (s1 + 1) & ~(size_t)1;   // keeps the complex arrays 16-byte aligned
+  return sizeof(double) * (2 * s2 + s1p) + sizeof(double2) * 7 * s1 + sizeof(EimDesc) * nb;
+}
+
+// Validates the arguments and fills the descriptor table; returns the
+// scratch bytes the call needs (0 on an invalid argument, message set).
+static size_t eim_prepare(const char* who, const fdfd_op* const* ops, int nb,
+                          const void* const* b, void* const* F, std::vector<EimDesc>& hd,
+                          size_t& s1, int& maxnx, int& maxD) {
   if (!ops || !b || !F || nb < 1) {
-    dd_set_error("eim_field: need nb >= 1 and the ops, b and F arrays");
-    return DD_EINVAL;
+    dd_set_error("%s: need nb >= 1 and the ops, b and F arrays", who);
+    return 0;
   }
-  std::vector<EimDesc> hd(nb);
-  size_t s2 = 0, s1 = 0;
-  int maxnx = 0, maxD = 0;
+  hd.resize(nb);
+  size_t s2 = 0;
+  s1 = 0;
+  maxnx = 0;
+  maxD = 0;
   for (int p = 0; p < nb; ++p) {
     if (!ops[p] || !b[p] || !F[p]) {
-      dd_set_error("eim_field: problem %d has a NULL operator, b or F", p);
-      return DD_EINVAL;
+      dd_set_error("%s: problem %d has a NULL operator, b or F", who, p);
+      return 0;
     }
     const fdfd_op* op = ops[p];
     EimDesc& d = hd[p];
@@ -267,13 +285,17 @@ extern "C" dd_status eim_field(const fdfd_op* const* ops, int nb, const void* co
     maxnx = std::max(maxnx, op->nx);
     maxD = std::max(maxD, op->D);
   }
-  // scratch: phi, pivots (D doubles each); mu (nx doubles); j, diagonal,
-  // two super-diagonals, two right-hand sides, amplitude (nx complex each)
-  const size_t s1p = (s1 + 1) & ~(size_t)1;   // keeps the complex arrays 16-byte aligned
-  const size_t bytes = sizeof(double) * (2 * s2 + s1p) + sizeof(double2) * 7 * s1 +
-                       sizeof(EimDesc) * nb;
-  char* ws = nullptr;
-  DD_HIP_CHECK(hipMalloc((void**)&ws, bytes));
+  return eim_scratch_bytes(s2, s1, nb);
+}
+
+// Enqueues the three kernels on scratch ws (eim_scratch_bytes long) and waits
+// for them.
+static hipError_t eim_run(const std::vector<EimDesc>& hd, size_t s1, int maxnx, int maxD,
+                          char* ws, hipStream_t stream) {
+  const int nb = (int)hd.size();
+  size_t s2 = 0;
+  for (const auto& d : hd) s2 += (size_t)d.nx * d.ny;
+  const size_t s1p = (s1 + 1) & ~(size_t)1;
   double* phi = (double*)ws;
   double* piv = phi + s2;
   double* mu = piv + s2;
@@ -289,9 +311,78 @@ extern "C" dd_status eim_field(const fdfd_op* const* ops, int nb, const void* co
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
+}
+
+extern "C" dd_status eim_field(const fdfd_op* const* ops, int nb, const void* const* b,
+                               void* const* F, hipStream_t stream) {
+  std::vector<EimDesc> hd;
+  size_t s1 = 0;
+  int maxnx = 0, maxD = 0;
+  const size_t bytes = eim_prepare("eim_field", ops, nb, b, F, hd, s1, maxnx, maxD);
+  if (bytes == 0) return DD_EINVAL;
+  char* ws = nullptr;
+  DD_HIP_CHECK(hipMalloc((void**)&ws, bytes));
+  hipError_t e = eim_run(hd, s1, maxnx, maxD, ws, stream);
   (void)hipFree(ws);
   if (e != hipSuccess) {
     dd_set_error("eim_field: %s", hipGetErrorString(e));
+    return DD_EHIP;
+  }
+  return DD_OK;
+}
+
+// ------------------------------------------- allocation-free variant ----
+// The scratch of eim_field_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never uses its name as an
+// address: eim_scratch_ptr() resolves the current device's copy once with
+// hipGetSymbolAddress and every kernel argument and copy goes through that
+// pointer.
+static __device__ __align__(256) char eim_scratch[DD_EIM_NOALLOC_BYTES];
+
+static std::mutex g_eim_scratch_mu;
+static void* g_eim_scratch_ptr[DD_EIM_MAX_DEVICES];
+
+static dd_status eim_scratch_ptr(char** out) {
+  int dev = 0;
+  DD_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= DD_EIM_MAX_DEVICES) {
+    dd_set_error("eim_field_noalloc: device %d beyond the %d supported", dev, DD_EIM_MAX_DEVICES);
+    return DD_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_eim_scratch_mu);
+  if (!g_eim_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(eim_scratch));
+    if (e != hipSuccess || !ptr) {
+      dd_set_error("eim_field_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+      return DD_EHIP;
+    }
+    g_eim_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_eim_scratch_ptr[dev];
+  return DD_OK;
+}
+
+extern "C" dd_status eim_field_noalloc(const fdfd_op* const* ops, int nb, const void* const* b,
+                                       void* const* F, hipStream_t stream) {
+  std::vector<EimDesc> hd;
+  size_t s1 = 0;
+  int maxnx = 0, maxD = 0;
+  const size_t bytes = eim_prepare("eim_field_noalloc", ops, nb, b, F, hd, s1, maxnx, maxD);
+  if (bytes == 0) return DD_EINVAL;
+  if (bytes > (size_t)DD_EIM_NOALLOC_BYTES) {
+    dd_set_error("eim_field_noalloc: the batch needs %zu bytes of scratch, more than the %zu "
+                 "the library holds (split the batch, or call eim_field)",
+                 bytes, (size_t)DD_EIM_NOALLOC_BYTES);
+    return DD_EINVAL;
+  }
+  char* ws = nullptr;
+  dd_status rc = eim_scratch_ptr(&ws);
+  if (rc != DD_OK) return rc;
+  const hipError_t e = eim_run(hd, s1, maxnx, maxD, ws, stream);
+  if (e != hipSuccess) {
+    dd_set_error("eim_field_noalloc: %s", hipGetErrorString(e));
     return DD_EHIP;
   }
   return DD_OK;
