@@ -68,6 +68,7 @@ typedef struct {
 typedef struct fdfd_op fdfd_op;
 typedef struct dd_solver dd_solver;
 typedef struct dd_cnn dd_cnn;
+typedef struct dd_predictor dd_predictor;
 
 /* ------------------------------------------------------------------------
  * FDFD operator (Sec. 2, Eq. 1 and the paragraph after it)
@@ -76,11 +77,14 @@ typedef struct dd_cnn dd_cnn;
 /* Create the operator A = -(Dxb Dxf + Dyb Dyf) - omega^2 diag(eps).
  *   eps   (host) [ny][nx] relative permittivity, copied; may be freed on return.
  *   nx, ny >= 3; omega > 0; dx > 0; 2*npml < n on each axis.
+ *   stream: the copies of eps and of the stencil coefficients (computed in
+ *   FP64 on the host) are enqueued on it; the call synchronises it before
+ *   returning.
  * Errors: DD_EINVAL for bad sizes/parameters, DD_ENONFINITE for non-finite
  * eps, DD_ENOMEM / DD_EHIP on allocation or copy failure (op left NULL).
  * The operator owns its device buffers until fdfd_op_destroy. */
 dd_status fdfd_op_create(const float* eps, int nx, int ny, double omega, double dx,
-                         const dd_pml* pml, fdfd_op** op);
+                         const dd_pml* pml, hipStream_t stream, fdfd_op** op);
 
 /* y = A x for one vector of D elements in precision p (x and y must not
  * alias).  Enqueued on stream. */
@@ -127,6 +131,11 @@ typedef struct {
                         /* preconditioner the Givens estimate, the history and    */
                         /* rel_res_est are those of P_L r / ||P_L b||; convergence */
                         /* is still decided by the FP64 ||b - A x|| / ||b||        */
+  void* workspace;      /* caller-owned device workspace (NULL: the solver         */
+                        /* allocates its own); 256-byte aligned, at least the     */
+                        /* size dd_solver_workspace_bytes reports for the same    */
+                        /* operators and options; borrowed until destroy          */
+  size_t workspace_bytes;
 } dd_solver_opts;
 
 /* Per-problem result (host struct). */
@@ -144,8 +153,21 @@ typedef struct {
 
 void dd_solver_opts_default(dd_solver_opts* o);
 
-/* Allocate the workspace for nb problems.  ops (host array of nb operator
- * handles) are borrowed until destroy or the next dd_solver_bind.
+/* Device bytes of the workspace a solver for these operators and options
+ * needs (*bytes, host out): every vector, the FP64 small state and the
+ * partial-sum rows, carved from one block.  No device memory is touched. */
+dd_status dd_solver_workspace_bytes(const fdfd_op* const* ops, int nb,
+                                    const dd_solver_opts* opts, size_t* bytes);
+
+/* The same for one problem with k augmenting vectors, restart m and inner
+ * precision (other options at their defaults), as gmres_solve uses it;
+ * 0 on invalid arguments. */
+size_t gmres_workspace_bytes(const fdfd_op* op, int k, int restart, dd_prec inner);
+
+/* Allocate the workspace for nb problems, or take it from opts->workspace
+ * (then the solver allocates no device memory; the caller keeps ownership
+ * and must keep it alive until dd_solver_destroy).  ops (host array of nb
+ * operator handles) are borrowed until destroy or the next dd_solver_bind.
  * Errors: DD_EINVAL (nb < 1, restart < 1, kmax outside 0..64, bad
  * elems_per_thread), DD_ENOMEM / DD_EHIP. */
 dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
@@ -221,7 +243,7 @@ dd_status dd_solver_profile(dd_solver* s, int enable);
 /* Host copy of the accumulated statistics. */
 dd_status dd_solver_kernel_stats(const dd_solver* s, dd_kernel_stats* out);
 
-/* Device bytes held by the solver workspace. */
+/* Device bytes of the solver workspace (its own or the caller's). */
 size_t dd_solver_device_bytes(const dd_solver* s);
 
 void dd_solver_destroy(dd_solver* s);
@@ -242,9 +264,11 @@ dd_status gmres_solve_batched(const fdfd_op* const* ops, int nb, const void* con
  * ------------------------------------------------------------------------
  * Leading left singular vectors of the uncentred snapshot matrix S whose M
  * columns are solution fields (an "incomplete SVD").  Computed as the FP64
- * Gram matrix G = S^H S on the device, its eigen-decomposition on the host
- * (FP64 Jacobi), U = S W diag(1/sigma) on the device, then re-orthonormalised
- * by Cholesky QR.
+ * Gram matrix G = S^H S on the device, its leading eigenpairs on the host
+ * (FP64 Lanczos with full reorthogonalisation; the small tridiagonal matrix
+ * is diagonalised by Jacobi rotations every ten steps to test convergence),
+ * U = S W diag(1/sigma) on the device, then re-orthonormalised by Cholesky
+ * QR.
  *   S:  [M][D] c64 snapshots (device), M >= k >= 1.
  *   U:  [k][D] c64 output basis (device).
  *   sigma (host, may be NULL): k singular values, descending.
@@ -380,13 +404,28 @@ dd_status dd_cnn_set_params(dd_cnn* net, const float* host_in, size_t count);
  *        as (eps - 2.085) / (12.25 - 2.085).
  *   U:   [B][k][ny*nx] c64 output fields (device).
  *   B <= max_batch. */
-dd_status predict_subspace(dd_cnn* net, const float* eps, int B, void* U, hipStream_t stream);
+dd_status dd_cnn_predict(dd_cnn* net, const float* eps, int B, void* U, hipStream_t stream);
 
 /* Forward pass of a three-input-channel network.
  *   eim: [B][ny*nx] c64 effective-index fields (device, from eim_field).
- * Otherwise as predict_subspace. */
-dd_status predict_subspace_eim(dd_cnn* net, const float* eps, const void* eim, int B, void* U,
-                               hipStream_t stream);
+ * Otherwise as dd_cnn_predict. */
+dd_status dd_cnn_predict_eim(dd_cnn* net, const float* eps, const void* eim, int B, void* U,
+                             hipStream_t stream);
+
+/* Grid, output fields, input planes and batch capacity of a network (host
+ * out-params, each may be NULL). */
+dd_status dd_cnn_dims(const dd_cnn* net, int* nx, int* ny, int* k, int* in_channels,
+                      int* max_batch);
+
+/* Save a network to a predictor file: its configuration, the FP32 master
+ * parameters and the Adam state (first and second moments, step count), so
+ * that training resumes exactly where it stopped.  Synchronises the device. */
+dd_status dd_cnn_save(const dd_cnn* net, const char* path /* (host) */);
+
+/* Recreate a network saved by dd_cnn_save, for batches of up to max_batch
+ * images.  DD_EINVAL (message set) if the file is missing, malformed,
+ * truncated or holds a PCA basis. */
+dd_status dd_cnn_load(const char* path /* (host) */, int max_batch, dd_cnn** out);
 
 /* One training step on a batch:
  *   1. forward pass;
@@ -425,6 +464,47 @@ dd_status dd_cnn_train_step_res(dd_cnn* net, const float* eps, const void* eim,
 dd_status dd_cnn_grad_res(dd_cnn* net, const float* eps, const void* eim,
                           const fdfd_op* const* ops, const void* const* b, int B, float* loss,
                           float* host_grad, size_t count, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Subspace predictor (Sec. 3: a model that maps the permittivity to the
+ * vectors v_1..v_N augmenting GMRES; the PCA basis is the same for every
+ * permittivity, the CNN specialises it)
+ * ------------------------------------------------------------------------
+ * A predictor file holds either a PCA basis (predictor_save_pca) or a CNN
+ * with its Adam state (dd_cnn_save): a 48-byte header (magic "DDPRED01",
+ * kind 1 = PCA / 2 = CNN, nx, ny, k, input planes, value count, Adam step)
+ * followed by little-endian float32 data. */
+
+/* Write the k basis vectors U [k][ny*nx] c64 (device) as a PCA predictor
+ * file.  Synchronises the stream. */
+dd_status predictor_save_pca(const char* path /* (host) */, const void* U, int k, int nx, int ny,
+                             hipStream_t stream);
+
+/* Load a predictor file for batches of up to max_batch problems (the CNN's
+ * activation buffers are sized by it).  DD_EINVAL (message set) if the file
+ * is missing, malformed or truncated; DD_ENOMEM / DD_EHIP on device errors.
+ * The predictor owns its device memory until predictor_destroy. */
+dd_status predictor_load(const char* path /* (host) */, int max_batch, dd_predictor** out);
+
+/* Kind (1 PCA, 2 CNN), grid, k and input planes (0 for PCA) of a predictor
+ * (host out-params, each may be NULL). */
+dd_status predictor_info(const dd_predictor* p, int* kind, int* nx, int* ny, int* k,
+                         int* in_channels);
+
+/* U [B][k][ny*nx] c64 (device) = the predicted subspace of each of B
+ * problems.
+ *   PCA: the basis for every problem; eps may be NULL.
+ *   CNN with one input plane: eps [B][ny][nx] float32 (device).
+ *   CNN with three input planes: eps, plus ops (host array of B operators)
+ *        and b (host array of B device [D] c128 right-hand sides) from which
+ *        the effective-index field is computed (eim_field).
+ * ops, when given, must be on the predictor's grid.  B <= max_batch for a
+ * CNN.  The predictor's internal buffers are reused, so calls on one
+ * predictor must not overlap.  Synchronises the stream. */
+dd_status predict_subspace(dd_predictor* p, const fdfd_op* const* ops, const void* const* b,
+                           const float* eps, int B, void* U, hipStream_t stream);
+
+void predictor_destroy(dd_predictor* p);
 
 /* Copy the bf16 activations of layer l's output (NHWC, as float32) to host.
  * layer = -1 gives the normalised input planes [B][in_channels][ny][nx].  The

@@ -14,8 +14,10 @@ import numpy as np
 from . import _lib
 from ._lib import DD_C64, DD_C128, DDError, check, ptr_array
 
-__all__ = ["FdfdOp", "Solver", "autotune", "gmres_solve", "gmres_solve_batched", "pca_build",
-           "local_pca_targets", "proj_loss_batched", "Cnn", "DDError", "lib_path"]
+__all__ = ["FdfdOp", "Solver", "autotune", "workspace_bytes", "gmres_solve", "gmres_solve_batched",
+           "pca_build",
+           "local_pca_targets", "proj_loss_batched", "Cnn", "Predictor", "save_pca", "DDError",
+           "lib_path"]
 
 
 def lib_path() -> str:
@@ -30,6 +32,13 @@ def _torch():
 def _stream():
     torch = _torch()
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _stream_if_gpu():
+    """The current stream, or the null stream where no GPU is visible (host-side
+    argument checks of the library run before any device call)."""
+    torch = _torch()
+    return _stream() if torch.cuda.is_available() else None
 
 
 DD_MAX_K = 64  # largest number of augmenting vectors the library accepts
@@ -83,7 +92,7 @@ class FdfdOp:
         h = C.c_void_p()
         check(_lib.lib().fdfd_op_create(eps.ctypes.data_as(C.POINTER(C.c_float)), self.nx,
                                         self.ny, self.omega, self.dx, C.byref(pml),
-                                        C.byref(h)), "fdfd_op_create")
+                                        _stream_if_gpu(), C.byref(h)), "fdfd_op_create")
         self._h = h
 
     @classmethod
@@ -122,7 +131,7 @@ PRECONDS = {None: 0, "none": 0, "jacobi": 1, "pml": 2}
 
 
 def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hist_cap=0,
-          check_every=4, select_reorth=True, use_graph=False, precond=None):
+          check_every=4, select_reorth=True, use_graph=False, precond=None, workspace=None):
     o = _lib.dd_solver_opts()
     _lib.lib().dd_solver_opts_default(C.byref(o))
     o.inner = DD_C64 if inner == "c64" else DD_C128
@@ -135,7 +144,23 @@ def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hi
     o.select_reorth = int(bool(select_reorth))
     o.use_graph = int(bool(use_graph))
     o.precond = PRECONDS[precond]
+    if workspace is not None:
+        o.workspace = C.c_void_p(_dev(workspace, what="workspace").value)
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
     return o
+
+
+def workspace_bytes(ops, restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0,
+                    hist_cap=0, precond=None):
+    """Device bytes a Solver with these operators and options needs (no device
+    memory is touched)."""
+    o = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap, 4, True, False,
+              precond)
+    n = C.c_size_t()
+    check(_lib.lib().dd_solver_workspace_bytes(ptr_array([op.handle for op in ops]), len(ops),
+                                               C.byref(o), C.byref(n)),
+          "dd_solver_workspace_bytes")
+    return n.value
 
 
 def autotune(ops, restart=100, inner="c64", cgs_passes=2, select_reorth=True):
@@ -154,12 +179,16 @@ class Solver:
 
     def __init__(self, ops, restart=100, kmax=0, inner="c64", cgs_passes=2,
                  elems_per_thread=0, hist_cap=0, check_every=4, select_reorth=True,
-                 use_graph=False, precond=None):
-        """precond: None, "jacobi" or "pml" (diagonal preconditioners, see the C header)."""
+                 use_graph=False, precond=None, workspace=None):
+        """precond: None, "jacobi" or "pml" (diagonal preconditioners, see the C header).
+        workspace: an optional device tensor (at least workspace_bytes(...) bytes,
+        256-byte aligned) that holds all of the solver's device arrays; the
+        solver then allocates no device memory and keeps a reference to it."""
         self.ops = list(ops)
         self.nb = len(self.ops)
+        self._workspace = workspace
         self.opts = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap,
-                          check_every, select_reorth, use_graph, precond)
+                          check_every, select_reorth, use_graph, precond, workspace)
         self.inner = inner
         self.restart, self.kmax = int(restart), int(kmax)
         h = C.c_void_p()
@@ -402,6 +431,61 @@ def res_loss_grad_batched(ops, b, V):
                                            out.ctypes.data_as(C.POINTER(C.c_double)), gp,
                                            _stream()), "res_loss_grad_batched")
     return out, G
+
+
+def save_pca(path, U, nx, ny):
+    """Write a PCA basis U ([k, D] complex64, device) as a predictor file."""
+    torch = _torch()
+    k = U.shape[0]
+    _check_subspace(U, int(nx) * int(ny))
+    check(_lib.lib().predictor_save_pca(str(path).encode(), _dev(U, torch.complex64, what="U"), k,
+                                        int(nx), int(ny), _stream()), "predictor_save_pca")
+
+
+class Predictor:
+    """A subspace predictor loaded from a file: a PCA basis or a CNN (the
+    C ABI's predictor_load / predict_subspace / predictor_destroy)."""
+
+    KINDS = {1: "pca", 2: "cnn"}
+
+    def __init__(self, path, max_batch=1):
+        h = C.c_void_p()
+        check(_lib.lib().predictor_load(str(path).encode(), int(max_batch), C.byref(h)),
+              "predictor_load")
+        self._h = h
+        v = [C.c_int() for _ in range(5)]
+        check(_lib.lib().predictor_info(h, *[C.byref(x) for x in v]), "predictor_info")
+        kind, self.nx, self.ny, self.k, self.in_channels = (x.value for x in v)
+        self.kind = self.KINDS[kind]
+        self.D = self.nx * self.ny
+        self.max_batch = int(max_batch)
+
+    def predict(self, B, eps=None, ops=None, b=None, U=None):
+        """U [B, k, D] complex64: the subspaces of B problems.  eps [B, ny, nx]
+        float32 for a CNN; ops and b (lists) for a three-plane CNN."""
+        torch = _torch()
+        if U is None:
+            U = torch.empty((B, self.k, self.D), dtype=torch.complex64, device="cuda")
+        _dev(U, torch.complex64, B * self.k * self.D, "U")
+        _check_lengths(B, ops=ops, b=b)
+        opp = None if ops is None else ptr_array([op._h.value for op in ops])
+        bp = None if b is None else ptr_array(
+            [_dev(bb, torch.complex128, self.D, f"b[{i}]").value for i, bb in enumerate(b)])
+        ep = None if eps is None else _dev(eps, torch.float32, B * self.D, "eps")
+        check(_lib.lib().predict_subspace(self._h, opp, bp, ep, int(B), _dev(U), _stream()),
+              "predict_subspace")
+        return U
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().predictor_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 from .cnn import Cnn  # noqa: E402

@@ -33,7 +33,7 @@ class dd_solver_opts(C.Structure):
     _fields_ = [("inner", C.c_int), ("cgs_passes", C.c_int), ("restart", C.c_int),
                 ("kmax", C.c_int), ("elems_per_thread", C.c_int), ("hist_cap", C.c_int),
                 ("check_every", C.c_int), ("select_reorth", C.c_int), ("use_graph", C.c_int),
-                ("precond", C.c_int)]
+                ("precond", C.c_int), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
 class dd_info(C.Structure):
@@ -58,12 +58,14 @@ D = C.c_double
 
 _SIGS = {
     "dd_last_error": (C.c_char_p, []),
-    "fdfd_op_create": (I, [C.POINTER(C.c_float), I, I, D, D, C.POINTER(dd_pml), PP]),
+    "fdfd_op_create": (I, [C.POINTER(C.c_float), I, I, D, D, C.POINTER(dd_pml), P, PP]),
     "fdfd_op_apply": (I, [P, P, P, I, P]),
     "fdfd_op_dims": (I, [P, C.POINTER(I), C.POINTER(I)]),
     "fdfd_op_destroy": (None, [P]),
     "dd_solver_opts_default": (None, [C.POINTER(dd_solver_opts)]),
     "dd_solver_create": (I, [PP, I, C.POINTER(dd_solver_opts), PP]),
+    "dd_solver_workspace_bytes": (I, [PP, I, C.POINTER(dd_solver_opts), C.POINTER(C.c_size_t)]),
+    "gmres_workspace_bytes": (C.c_size_t, [P, I, I, I]),
     "dd_solver_bind": (I, [P, PP]),
     "dd_solver_set_subspace": (I, [P, PP, C.POINTER(I), P]),
     "dd_solver_solve": (I, [P, PP, PP, D, I, PP, C.POINTER(dd_info), P]),
@@ -96,8 +98,17 @@ _SIGS = {
     "dd_cnn_num_params": (C.c_size_t, [P]),
     "dd_cnn_get_params": (I, [P, C.POINTER(C.c_float), C.c_size_t]),
     "dd_cnn_set_params": (I, [P, C.POINTER(C.c_float), C.c_size_t]),
-    "predict_subspace": (I, [P, P, I, P, P]),
-    "predict_subspace_eim": (I, [P, P, P, I, P, P]),
+    "dd_cnn_predict": (I, [P, P, I, P, P]),
+    "dd_cnn_predict_eim": (I, [P, P, P, I, P, P]),
+    "dd_cnn_dims": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+    "dd_cnn_save": (I, [P, C.c_char_p]),
+    "dd_cnn_load": (I, [C.c_char_p, I, PP]),
+    "predictor_save_pca": (I, [C.c_char_p, P, I, I, I, P]),
+    "predictor_load": (I, [C.c_char_p, I, PP]),
+    "predictor_info": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I),
+                           C.POINTER(I)]),
+    "predict_subspace": (I, [P, PP, PP, P, I, P, P]),
+    "predictor_destroy": (None, [P]),
     "dd_cnn_train_step": (I, [P, P, P, P, I, C.c_float, C.c_float, C.c_float,
                               C.POINTER(C.c_float), P]),
     "dd_cnn_grad": (I, [P, P, P, P, I, C.POINTER(C.c_float), C.POINTER(C.c_float),

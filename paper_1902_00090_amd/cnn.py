@@ -36,15 +36,32 @@ class Cnn:
     """Encoder-decoder CNN mapping permittivity [B, ny, nx] (and, with
     in_channels=3, the effective-index field [B, ny*nx]) to k complex fields."""
 
-    def __init__(self, nx, ny, max_batch, k=10, seed=0, in_channels=1):
+    def __init__(self, nx, ny, max_batch, k=10, seed=0, in_channels=1, _handle=None):
         self.nx, self.ny, self.max_batch, self.k = int(nx), int(ny), int(max_batch), int(k)
         self.in_channels = int(in_channels)
         self.D = self.nx * self.ny
+        if _handle is not None:
+            self._h = _handle
+            return
         h = C.c_void_p()
         check(_lib.lib().dd_cnn_create(self.nx, self.ny, self.max_batch, self.k,
                                        self.in_channels, C.c_ulonglong(seed), C.byref(h)),
               "dd_cnn_create")
         self._h = h
+
+    def save(self, path):
+        """Parameters and Adam state to a predictor file (dd_cnn_save)."""
+        check(_lib.lib().dd_cnn_save(self._h, str(path).encode()), "dd_cnn_save")
+
+    @classmethod
+    def load(cls, path, max_batch):
+        """A network saved by save(), for batches of up to max_batch images."""
+        h = C.c_void_p()
+        check(_lib.lib().dd_cnn_load(str(path).encode(), int(max_batch), C.byref(h)), "dd_cnn_load")
+        v = [C.c_int() for _ in range(5)]
+        check(_lib.lib().dd_cnn_dims(h, *[C.byref(x) for x in v]), "dd_cnn_dims")
+        nx, ny, k, cin, mb = (x.value for x in v)
+        return cls(nx, ny, mb, k, in_channels=cin, _handle=h)
 
     def layers(self):
         out = []
@@ -99,12 +116,12 @@ class Cnn:
             u = U[b0:b0 + nb]
             f = self._eim(eim, nb, b0)
             if f is None:
-                rc = _lib.lib().predict_subspace(self._h, C.c_void_p(e.data_ptr()), nb,
-                                                 C.c_void_p(u.data_ptr()), _stream())
+                rc = _lib.lib().dd_cnn_predict(self._h, C.c_void_p(e.data_ptr()), nb,
+                                               C.c_void_p(u.data_ptr()), _stream())
             else:
-                rc = _lib.lib().predict_subspace_eim(self._h, C.c_void_p(e.data_ptr()), f, nb,
-                                                     C.c_void_p(u.data_ptr()), _stream())
-            check(rc, "predict_subspace")
+                rc = _lib.lib().dd_cnn_predict_eim(self._h, C.c_void_p(e.data_ptr()), f, nb,
+                                                   C.c_void_p(u.data_ptr()), _stream())
+            check(rc, "dd_cnn_predict")
         return U
 
     def train_step(self, eps, target, lr=1e-3, b1=0.9, b2=0.999, eim=None):

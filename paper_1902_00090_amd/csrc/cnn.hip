@@ -31,6 +31,7 @@
 
 #include "common.h"
 #include "op.h"
+#include "predfile.h"
 #include "resloss.h"
 
 typedef __bf16 bf16;
@@ -1839,15 +1840,94 @@ static dd_status predict(dd_cnn* n, const float* eps, const void* eim, int B, vo
   return DD_OK;
 }
 
-extern "C" dd_status predict_subspace(dd_cnn* n, const float* eps, int B, void* U,
-                                      hipStream_t st) {
-  return predict(n, eps, nullptr, B, U, st, "predict_subspace");
+extern "C" dd_status dd_cnn_predict(dd_cnn* n, const float* eps, int B, void* U,
+                                    hipStream_t st) {
+  return predict(n, eps, nullptr, B, U, st, "dd_cnn_predict");
 }
 
-extern "C" dd_status predict_subspace_eim(dd_cnn* n, const float* eps, const void* eim, int B,
-                                          void* U, hipStream_t st) {
-  if (!eim) { dd_set_error("predict_subspace_eim: eim is NULL"); return DD_EINVAL; }
-  return predict(n, eps, eim, B, U, st, "predict_subspace_eim");
+extern "C" dd_status dd_cnn_predict_eim(dd_cnn* n, const float* eps, const void* eim, int B,
+                                        void* U, hipStream_t st) {
+  if (!eim) { dd_set_error("dd_cnn_predict_eim: eim is NULL"); return DD_EINVAL; }
+  return predict(n, eps, eim, B, U, st, "dd_cnn_predict_eim");
+}
+
+extern "C" dd_status dd_cnn_dims(const dd_cnn* n, int* nx, int* ny, int* k, int* in_channels,
+                                 int* max_batch) {
+  if (!n) { dd_set_error("dd_cnn_dims: NULL network"); return DD_EINVAL; }
+  if (nx) *nx = n->nx;
+  if (ny) *ny = n->ny;
+  if (k) *k = n->k;
+  if (in_channels) *in_channels = n->cin0;
+  if (max_batch) *max_batch = n->maxB;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_cnn_save(const dd_cnn* n, const char* path) {
+  if (!n || !path) { dd_set_error("dd_cnn_save: NULL argument"); return DD_EINVAL; }
+  const size_t np = n->nparams;
+  std::vector<float> buf(3 * np);
+  DD_HIP_CHECK(hipDeviceSynchronize());
+  DD_HIP_CHECK(hipMemcpy(buf.data(), n->params, sizeof(float) * np, hipMemcpyDeviceToHost));
+  DD_HIP_CHECK(hipMemcpy(buf.data() + np, n->am, sizeof(float) * np, hipMemcpyDeviceToHost));
+  DD_HIP_CHECK(hipMemcpy(buf.data() + 2 * np, n->av, sizeof(float) * np, hipMemcpyDeviceToHost));
+  PredFileHeader h{};
+  std::memcpy(h.magic, DD_PRED_MAGIC, 8);
+  h.kind = DD_PRED_CNN;
+  h.nx = n->nx; h.ny = n->ny; h.k = n->k; h.in_channels = n->cin0;
+  h.count = (int64_t)np;
+  h.adam_t = n->adam_t;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) { dd_set_error("dd_cnn_save: cannot open '%s' for writing", path); return DD_EINVAL; }
+  const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+                  std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  if (std::fclose(f) != 0 || !ok) {
+    dd_set_error("dd_cnn_save: writing '%s' failed", path);
+    return DD_EINVAL;
+  }
+  return DD_OK;
+}
+
+extern "C" dd_status dd_cnn_load(const char* path, int max_batch, dd_cnn** out) {
+  if (!out) { dd_set_error("dd_cnn_load: out is NULL"); return DD_EINVAL; }
+  *out = nullptr;
+  PredFileHeader h{};
+  char msg[512];
+  FILE* f = pred_open(path, h, msg, sizeof(msg));
+  if (!f) { dd_set_error("dd_cnn_load: %s", msg); return DD_EINVAL; }
+  if (h.kind != DD_PRED_CNN) {
+    std::fclose(f);
+    dd_set_error("dd_cnn_load: '%s' holds a PCA basis, not a network", path);
+    return DD_EINVAL;
+  }
+  std::vector<float> buf(3 * (size_t)h.count);
+  const bool ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  std::fclose(f);
+  if (!ok) { dd_set_error("dd_cnn_load: reading '%s' failed", path); return DD_EINVAL; }
+  dd_cnn* n = nullptr;
+  dd_status rc = dd_cnn_create(h.nx, h.ny, max_batch, h.k, h.in_channels, 0, &n);
+  if (rc != DD_OK) return rc;
+  if ((int64_t)n->nparams != h.count) {
+    dd_cnn_destroy(n);
+    dd_set_error("dd_cnn_load: '%s' holds %lld parameters, the network has %zu", path,
+                 (long long)h.count, n->nparams);
+    return DD_EINVAL;
+  }
+  const size_t np = n->nparams;
+  hipError_t e = hipMemcpy(n->params, buf.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(n->am, buf.data() + np, sizeof(float) * np, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(n->av, buf.data() + 2 * np, sizeof(float) * np, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dd_cnn_destroy(n);
+    dd_set_error("dd_cnn_load: %s", hipGetErrorString(e));
+    return DD_EHIP;
+  }
+  n->adam_t = (int)h.adam_t;
+  rc = pack_all(n, 0);
+  if (rc == DD_OK && hipDeviceSynchronize() != hipSuccess) rc = DD_EHIP;
+  if (rc != DD_OK) { dd_cnn_destroy(n); return rc; }
+  *out = n;
+  return DD_OK;
 }
 
 extern "C" dd_status dd_cnn_grad(dd_cnn* n, const float* eps, const void* eim, const void* target,

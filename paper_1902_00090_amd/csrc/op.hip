@@ -62,7 +62,7 @@ static void axis_coeffs(int n, int npml, double dx, double omega, int grade, dou
 }
 
 extern "C" dd_status fdfd_op_create(const float* eps, int nx, int ny, double omega, double dx,
-                                    const dd_pml* pml, fdfd_op** out) {
+                                    const dd_pml* pml, hipStream_t stream, fdfd_op** out) {
   if (!out) { dd_set_error("fdfd_op_create: out is NULL"); return DD_EINVAL; }
   *out = nullptr;
   dd_pml P = pml ? *pml : dd_pml{0, 0, 3, -16.0};
@@ -134,14 +134,21 @@ extern "C" dd_status fdfd_op_create(const float* eps, int nx, int ny, double ome
     fdfd_op_destroy(op);
     return DD_ENOMEM;
   }
-  hipError_t c1 = hipMemcpy(op->eps32, eps, sizeof(float) * D, hipMemcpyHostToDevice);
-  hipError_t c2_ = hipMemcpy(op->eps64, e64.data(), sizeof(double) * D, hipMemcpyHostToDevice);
-  hipError_t c3 = hipMemcpy(op->cf32, c32.data(), sizeof(float2) * NC, hipMemcpyHostToDevice);
-  hipError_t c4 = hipMemcpy(op->cf64, c64.data(), sizeof(double2) * NC, hipMemcpyHostToDevice);
-  hipError_t c5 = hipMemcpy(op->s64, s64.data(), sizeof(double2) * (nx + ny), hipMemcpyHostToDevice);
-  if (c1 != hipSuccess || c2_ != hipSuccess || c3 != hipSuccess || c4 != hipSuccess ||
-      c5 != hipSuccess) {
-    dd_set_error("fdfd_op_create: hipMemcpy failed");
+  // the host arrays are pageable and some are locals: the copies are
+  // enqueued on the caller's stream and finished before returning
+  hipError_t c = hipMemcpyAsync(op->eps32, eps, sizeof(float) * D, hipMemcpyHostToDevice, stream);
+  if (c == hipSuccess)
+    c = hipMemcpyAsync(op->eps64, e64.data(), sizeof(double) * D, hipMemcpyHostToDevice, stream);
+  if (c == hipSuccess)
+    c = hipMemcpyAsync(op->cf32, c32.data(), sizeof(float2) * NC, hipMemcpyHostToDevice, stream);
+  if (c == hipSuccess)
+    c = hipMemcpyAsync(op->cf64, c64.data(), sizeof(double2) * NC, hipMemcpyHostToDevice, stream);
+  if (c == hipSuccess)
+    c = hipMemcpyAsync(op->s64, s64.data(), sizeof(double2) * (nx + ny), hipMemcpyHostToDevice,
+                       stream);
+  if (c == hipSuccess) c = hipStreamSynchronize(stream);
+  if (c != hipSuccess) {
+    dd_set_error("fdfd_op_create: copy to the device failed: %s", hipGetErrorString(c));
     fdfd_op_destroy(op);
     return DD_EHIP;
   }

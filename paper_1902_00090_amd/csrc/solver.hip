@@ -22,7 +22,8 @@ struct dd_solver {
   const void** dU = nullptr;  // device array of nb pointers for set_subspace
   PlanDev P{};
   std::vector<void*> allocs;
-  size_t bytes = 0;
+  size_t bytes = 0;       // device workspace of the solver (owned or the caller's)
+  bool owns_workspace = true;
   int* pinned = nullptr;     // 2 status snapshots + 1 final
   double* pinnedD = nullptr;
   unsigned long long* pinnedK = nullptr;
@@ -74,19 +75,27 @@ extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
   o->select_reorth = 1;
   o->use_graph = 0;
   o->precond = DD_PRECOND_NONE;
+  o->workspace = nullptr;
+  o->workspace_bytes = 0;
 }
 
 static size_t inner_bytes(dd_prec p) { return p == DD_C128 ? 16 : 8; }
 
-template <typename X>
-static hipError_t dalloc(dd_solver* s, X** ptr, size_t count) {
-  const size_t b = std::max<size_t>(count * sizeof(X), 256);
-  hipError_t e = hipMalloc((void**)ptr, b);
-  if (e != hipSuccess) return e;
-  s->allocs.push_back((void*)*ptr);
-  s->bytes += b;
-  return hipMemset(*ptr, 0, b);
-}
+// Device workspace layout: every array of a solver is carved, 256-byte
+// aligned, from one block in a fixed order.  A first pass with base == NULL
+// only measures the block (gmres_workspace_bytes); the second assigns the
+// pointers into the solver's own allocation or the caller's workspace.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename X>
+  void carve(X** ptr, size_t count) {
+    const size_t b = std::max<size_t>(count * sizeof(X), 256);
+    off = (off + 255) & ~(size_t)255;
+    *ptr = base ? (X*)(base + off) : nullptr;
+    off += b;
+  }
+};
 
 static void fill_desc_op(ProbDesc& d, const fdfd_op* op) {
   d.nx = op->nx;
@@ -119,8 +128,72 @@ extern "C" void dd_solver_destroy(dd_solver* s) {
   delete s;
 }
 
-extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
-                                      dd_solver** out) {
+// The arrays of a solver, in layout order (see Arena).
+static void layout_workspace(dd_solver* s, Arena& A, ProbDesc*& dd, int*& db2p) {
+  const dd_solver_opts& o = s->o;
+  const int nb = s->nb, m = o.restart, K = o.kmax;
+  const size_t ib = inner_bytes(o.inner);
+  PlanDev& P = s->P;
+  s->pcbuf.clear();
+  for (int p = 0; p < nb; ++p) {
+    ProbDesc& d = s->hdesc[p];
+    char* basis = nullptr;
+    char* V = nullptr;
+    A.carve(&basis, (size_t)(K + m + 1) * d.Dp * ib);
+    if (K > 0) A.carve(&V, (size_t)K * d.Dp * ib);
+    double2* r = nullptr;
+    A.carve(&r, (size_t)d.Dp);
+    d.basis = basis;
+    d.V = V;
+    d.r = r;
+    if (o.precond != DD_PRECOND_NONE) {
+      double2 *pl64 = nullptr, *pr64 = nullptr;
+      float2 *pl32 = nullptr, *pr32 = nullptr;
+      A.carve(&pl64, (size_t)d.Dp);
+      A.carve(&pr64, (size_t)d.Dp);
+      A.carve(&pl32, (size_t)d.Dp);
+      A.carve(&pr32, (size_t)d.Dp);
+      d.pl64 = pl64;
+      d.pr64 = (o.precond == DD_PRECOND_PML) ? pr64 : nullptr;
+      d.pl = (o.inner == DD_C64) ? (const void*)pl32 : (const void*)pl64;
+      d.pr = (o.precond == DD_PRECOND_PML)
+                 ? ((o.inner == DD_C64) ? (const void*)pr32 : (const void*)pr64) : nullptr;
+      s->pcbuf.push_back({pl64, pr64, pl32, pr32});
+    }
+  }
+  A.carve(&dd, nb);
+  A.carve(&db2p, s->nchunks);
+  A.carve(&s->dU, nb);
+  A.carve(&P.stI, (size_t)nb * ST_NI);
+  A.carve(&P.stD, (size_t)nb * SD_ND);
+  A.carve(&P.H, (size_t)nb * m * (m + 1));
+  A.carve(&P.Hraw, (size_t)nb * m * (m + 1));
+  A.carve(&P.Bc, (size_t)nb * m * std::max(K, 1));
+  A.carve(&P.g, (size_t)nb * (m + 1));
+  A.carve(&P.cs, (size_t)nb * m);
+  A.carve(&P.sn, (size_t)nb * m);
+  A.carve(&P.c0, (size_t)nb * std::max(K, 1));
+  A.carve(&P.coefA, (size_t)nb * P.NC);
+  A.carve(&P.coefB, (size_t)nb * P.NC);
+  A.carve(&P.hscale, (size_t)nb * (m + 1));
+  A.carve(&P.comb, (size_t)nb * (K + m));
+  A.carve(&P.Rinv, (size_t)nb * std::max(K * K, 1));
+  A.carve(&P.Tm, (size_t)nb * std::max(K * K, 1));
+  A.carve(&P.Gm, (size_t)nb * std::max(K * K, 1));
+  A.carve(&P.keep, (size_t)nb);
+  A.carve(&P.bad, (size_t)nb);
+  double* part = nullptr;
+  A.carve(&part, (size_t)s->nchunks * P.NV);
+  P.partial = part;
+  A.carve(&P.gpart, (size_t)nb * P.GB * std::max(1, gram_tiles(std::max(K, 1))) * 32);
+  A.carve(&P.hist, (size_t)nb * std::max(1, o.hist_cap));
+  A.carve(&s->dctl, 2);
+}
+
+// Validates the options and builds the host-side plan of a solver (problem
+// descriptors, chunk map, workspace parameters); no device memory yet.
+static dd_status solver_plan(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
+                             dd_solver** out) {
   if (!out) { dd_set_error("dd_solver_create: out is NULL"); return DD_EINVAL; }
   *out = nullptr;
   dd_solver_opts o;
@@ -195,38 +268,8 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
         ncu > 0)
       s->ncu = ncu;
   }
-  const size_t ib = inner_bytes(o.inner);
   const int NC = K + m + 1;
   const int NV = ((2 * NC + 31) / 32) * 32 + 32;
-  hipError_t e = hipSuccess;
-  auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-  // vectors
-  for (int p = 0; p < nb && e == hipSuccess; ++p) {
-    ProbDesc& d = s->hdesc[p];
-    char* basis = nullptr;
-    char* V = nullptr;
-    chk(dalloc(s, &basis, (size_t)(K + m + 1) * d.Dp * ib));
-    if (K > 0) chk(dalloc(s, &V, (size_t)K * d.Dp * ib));
-    double2* r = nullptr;
-    chk(dalloc(s, &r, (size_t)d.Dp));
-    d.basis = basis;
-    d.V = V;
-    d.r = r;
-    if (o.precond != DD_PRECOND_NONE) {
-      double2 *pl64 = nullptr, *pr64 = nullptr;
-      float2 *pl32 = nullptr, *pr32 = nullptr;
-      chk(dalloc(s, &pl64, (size_t)d.Dp));
-      chk(dalloc(s, &pr64, (size_t)d.Dp));
-      chk(dalloc(s, &pl32, (size_t)d.Dp));
-      chk(dalloc(s, &pr32, (size_t)d.Dp));
-      d.pl64 = pl64;
-      d.pr64 = (o.precond == DD_PRECOND_PML) ? pr64 : nullptr;
-      d.pl = (o.inner == DD_C64) ? (const void*)pl32 : (const void*)pl64;
-      d.pr = (o.precond == DD_PRECOND_PML)
-                 ? ((o.inner == DD_C64) ? (const void*)pr32 : (const void*)pr64) : nullptr;
-      s->pcbuf.push_back({pl64, pr64, pl32, pr32});
-    }
-  }
   PlanDev& P = s->P;
   P.nb = nb; P.m = m; P.kmax = K; P.NC = NC; P.NV = NV; P.hist_cap = o.hist_cap;
   P.qslots = m + 1;
@@ -237,40 +280,48 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     int GB = (int)std::min<size_t>(32, std::max<size_t>(1, (64ull << 20) / per));
     P.GB = GB;
   }
+  *out = s;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
+                                      dd_solver** out) {
+  if (!out) { dd_set_error("dd_solver_create: out is NULL"); return DD_EINVAL; }
+  *out = nullptr;
+  dd_solver* s = nullptr;
+  dd_status rc = solver_plan(ops, nb, opts, &s);
+  if (rc != DD_OK) return rc;
+  const dd_solver_opts& o = s->o;
+  PlanDev& P = s->P;
+  ProbDesc* dd = nullptr;
+  int* db2p = nullptr;
+  Arena A;
+  layout_workspace(s, A, dd, db2p);
+  const size_t total = A.off;
+  hipError_t e = hipSuccess;
+  if (o.workspace) {
+    if (o.workspace_bytes < total || ((uintptr_t)o.workspace & 255) != 0) {
+      dd_set_error("dd_solver_create: the workspace needs %zu bytes at 256-byte alignment "
+                   "(got %zu bytes at %p)", total, o.workspace_bytes, o.workspace);
+      delete s;
+      return DD_EINVAL;
+    }
+    A.base = (char*)o.workspace;
+    s->owns_workspace = false;
+  } else {
+    e = hipMalloc((void**)&A.base, total);
+    if (e == hipSuccess) s->allocs.push_back(A.base);
+  }
+  if (e == hipSuccess) {
+    s->bytes = total;
+    A.off = 0;
+    layout_workspace(s, A, dd, db2p);
+    e = hipMemset(A.base, 0, total);
+  }
   std::vector<int> b2p(s->nchunks);
   for (int p = 0; p < nb; ++p)
     for (int c = 0; c < s->hdesc[p].nblk; ++c) b2p[s->hdesc[p].blk0 + c] = p;
-  ProbDesc* dd = nullptr;
-  int* db2p = nullptr;
-  if (e == hipSuccess) {
-    chk(dalloc(s, &dd, nb));
-    chk(dalloc(s, &db2p, s->nchunks));
-    chk(dalloc(s, &s->dU, nb));
-    chk(dalloc(s, &P.stI, (size_t)nb * ST_NI));
-    chk(dalloc(s, &P.stD, (size_t)nb * SD_ND));
-    chk(dalloc(s, &P.H, (size_t)nb * m * (m + 1)));
-    chk(dalloc(s, &P.Hraw, (size_t)nb * m * (m + 1)));
-    chk(dalloc(s, &P.Bc, (size_t)nb * m * std::max(K, 1)));
-    chk(dalloc(s, &P.g, (size_t)nb * (m + 1)));
-    chk(dalloc(s, &P.cs, (size_t)nb * m));
-    chk(dalloc(s, &P.sn, (size_t)nb * m));
-    chk(dalloc(s, &P.c0, (size_t)nb * std::max(K, 1)));
-    chk(dalloc(s, &P.coefA, (size_t)nb * NC));
-    chk(dalloc(s, &P.coefB, (size_t)nb * NC));
-    chk(dalloc(s, &P.hscale, (size_t)nb * (m + 1)));
-    chk(dalloc(s, &P.comb, (size_t)nb * (K + m)));
-    chk(dalloc(s, &P.Rinv, (size_t)nb * std::max(K * K, 1)));
-    chk(dalloc(s, &P.Tm, (size_t)nb * std::max(K * K, 1)));
-    chk(dalloc(s, &P.Gm, (size_t)nb * std::max(K * K, 1)));
-    chk(dalloc(s, &P.keep, (size_t)nb));
-    chk(dalloc(s, &P.bad, (size_t)nb));
-    double* part = nullptr;
-    chk(dalloc(s, &part, (size_t)s->nchunks * NV));
-    P.partial = part;
-    chk(dalloc(s, &P.gpart, (size_t)nb * P.GB * std::max(1, gram_tiles(std::max(K, 1))) * 32));
-    chk(dalloc(s, &P.hist, (size_t)nb * std::max(1, o.hist_cap)));
-    chk(dalloc(s, &s->dctl, 2));
-  }
+  auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
   if (e == hipSuccess) {
     chk(hipMemcpy(dd, s->hdesc.data(), sizeof(ProbDesc) * nb, hipMemcpyHostToDevice));
     chk(hipMemcpy(db2p, b2p.data(), sizeof(int) * s->nchunks, hipMemcpyHostToDevice));
@@ -302,6 +353,33 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
 }
 
 extern "C" size_t dd_solver_device_bytes(const dd_solver* s) { return s ? s->bytes : 0; }
+
+extern "C" dd_status dd_solver_workspace_bytes(const fdfd_op* const* ops, int nb,
+                                               const dd_solver_opts* opts, size_t* bytes) {
+  if (!bytes) { dd_set_error("dd_solver_workspace_bytes: bytes is NULL"); return DD_EINVAL; }
+  *bytes = 0;
+  dd_solver* s = nullptr;
+  dd_status rc = solver_plan(ops, nb, opts, &s);
+  if (rc != DD_OK) return rc;
+  Arena A;
+  ProbDesc* dd = nullptr;
+  int* db2p = nullptr;
+  layout_workspace(s, A, dd, db2p);
+  *bytes = A.off;
+  delete s;
+  return DD_OK;
+}
+
+extern "C" size_t gmres_workspace_bytes(const fdfd_op* op, int k, int restart, dd_prec inner) {
+  dd_solver_opts o;
+  dd_solver_opts_default(&o);
+  o.kmax = k;
+  o.restart = restart;
+  o.inner = inner;
+  size_t b = 0;
+  const fdfd_op* ops[1] = {op};
+  return dd_solver_workspace_bytes(ops, 1, &o, &b) == DD_OK ? b : 0;
+}
 
 extern "C" dd_status dd_solver_bind(dd_solver* s, const fdfd_op* const* ops) {
   if (!s || !ops) { dd_set_error("dd_solver_bind: NULL argument"); return DD_EINVAL; }
@@ -623,6 +701,8 @@ extern "C" dd_status dd_solver_autotune(const fdfd_op* const* ops, int nb, const
   if (opts) o = *opts;
   o.hist_cap = 0;
   o.kmax = 0;
+  o.workspace = nullptr;      // candidates differ in size: each allocates its own
+  o.workspace_bytes = 0;
   const int cands[4] = {1, 2, 4, 8};
   std::vector<double2*> bufs;
   std::vector<void*> bp(nb), xp(nb);

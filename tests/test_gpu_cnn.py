@@ -318,6 +318,6 @@ def test_channel_count_is_enforced():
     from paper_1902_00090_amd import _lib
     U = torch.empty((1, 2, 24 * 16), dtype=torch.complex64, device="cuda")
     import ctypes as C
-    rc = _lib.lib().predict_subspace(net3._h, C.c_void_p(e3.data_ptr()), 1,
-                                     C.c_void_p(U.data_ptr()), None)
+    rc = _lib.lib().dd_cnn_predict(net3._h, C.c_void_p(e3.data_ptr()), 1,
+                                   C.c_void_p(U.data_ptr()), None)
     assert rc == _lib.DD_EINVAL

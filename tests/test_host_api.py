@@ -25,8 +25,8 @@ def declared_functions():
 def test_header_declares_the_paper_path():
     names = declared_functions()
     for n in ["fdfd_op_create", "fdfd_op_apply", "gmres_solve", "gmres_solve_batched",
-              "dd_solver_solve", "predict_subspace", "pca_build", "dd_cnn_train_step",
-              "dd_last_error"]:
+              "dd_solver_solve", "predict_subspace", "predictor_load", "predictor_destroy",
+              "gmres_workspace_bytes", "pca_build", "dd_cnn_train_step", "dd_last_error"]:
         assert n in names
 
 
@@ -65,7 +65,8 @@ def test_other_entry_points_reject_bad_arguments_on_host():
     assert lib.dd_cnn_create(32, 16, 0, 10, 1, 0, C.byref(h)) == _lib.DD_EINVAL   # max_batch 0
     assert lib.dd_cnn_create(32, 16, 1, 10, 2, 0, C.byref(h)) == _lib.DD_EINVAL   # 2 channels
     assert lib.eim_field(None, 0, None, None, None) == _lib.DD_EINVAL
-    assert lib.predict_subspace_eim(None, None, None, 1, None, None) == _lib.DD_EINVAL
+    assert lib.dd_cnn_predict_eim(None, None, None, 1, None, None) == _lib.DD_EINVAL
+    assert lib.predict_subspace(None, None, None, None, 1, None, None) == _lib.DD_EINVAL
     assert lib.pca_build(None, 10, 100, 3, None, None, None) == _lib.DD_EINVAL
     assert lib.proj_loss_batched(None, None, 1, 1, 1, None, None) == _lib.DD_EINVAL
     assert lib.dd_solver_kernel_stats(None, None) == _lib.DD_EINVAL
@@ -97,3 +98,40 @@ def test_binding_rejects_mismatched_lists_and_subspace_shapes():
                 torch.zeros((65, D), dtype=torch.complex64)):
         with pytest.raises(ValueError):
             _check_subspace(bad, D)
+
+
+def _pred_file(path, kind, nx, ny, k, cin, count, payload_bytes):
+    import struct
+    with open(path, "wb") as f:
+        f.write(struct.pack("<8siiiiiiqq", b"DDPRED01", kind, nx, ny, k, cin, 0, count, 0))
+        f.write(b"\0" * payload_bytes)
+
+
+def test_predictor_files_are_checked_on_the_host(tmp_path):
+    """predictor_load / dd_cnn_load reject missing, foreign, truncated and
+    mismatched files with DD_EINVAL and a message, before touching a device."""
+    from paper_1902_00090_amd import _lib
+    lib = _lib.lib()
+    h = C.c_void_p()
+    missing = str(tmp_path / "none.ddp").encode()
+    assert lib.predictor_load(missing, 1, C.byref(h)) == _lib.DD_EINVAL
+    assert "cannot open" in lib.dd_last_error().decode()
+    foreign = tmp_path / "foreign.ddp"
+    foreign.write_bytes(b"NOTAPRED" + b"\0" * 100)
+    assert lib.predictor_load(str(foreign).encode(), 1, C.byref(h)) == _lib.DD_EINVAL
+    assert "not a predictor file" in lib.dd_last_error().decode()
+    short = tmp_path / "short.ddp"
+    _pred_file(short, 1, 8, 8, 2, 0, 2 * 64, 2 * 64 * 8 - 16)        # 16 bytes missing
+    assert lib.predictor_load(str(short).encode(), 1, C.byref(h)) == _lib.DD_EINVAL
+    assert "bad header or size" in lib.dd_last_error().decode()
+    wrongk = tmp_path / "wrongk.ddp"
+    _pred_file(wrongk, 1, 8, 8, 3, 0, 2 * 64, 2 * 64 * 8)             # count != k * D
+    assert lib.predictor_load(str(wrongk).encode(), 1, C.byref(h)) == _lib.DD_EINVAL
+    pca = tmp_path / "pca.ddp"
+    _pred_file(pca, 1, 8, 8, 2, 0, 2 * 64, 2 * 64 * 8)
+    assert lib.dd_cnn_load(str(pca).encode(), 1, C.byref(h)) == _lib.DD_EINVAL
+    assert "PCA basis" in lib.dd_last_error().decode()
+    assert lib.predictor_load(str(pca).encode(), 0, C.byref(h)) == _lib.DD_EINVAL
+    n = C.c_size_t(7)
+    assert lib.dd_solver_workspace_bytes(None, 1, None, C.byref(n)) == _lib.DD_EINVAL
+    assert n.value == 0
