@@ -68,16 +68,20 @@ def first_below(h, thr):
     return int(idx[0]) + 1 if len(idx) else None
 
 
-def arnoldi_bytes(D, iters, m, k, passes=1):
+def arnoldi_bytes(D, iters, m, k, passes=1, fused=True):
     """Algorithmic HBM bytes of `iters` complex64 Arnoldi steps with restart m
-    and k augmenting vectors: step j of a cycle reads the stencil input and
-    eps and writes w (20 D), reads the k+j+1 basis vectors and w for the dots
-    and again for the update, and writes q_{j+1}: 16 D (k+j) + 44 D; each
-    further Gram-Schmidt pass adds 16 D (k+j) + 24 D."""
+    and k augmenting vectors.  One sweep per step (fused, one Gram-Schmidt
+    pass): step j reads the k+j+1 basis vectors and A q_j, writes q_{j+1} and
+    A q_{j+1}, and reads eps: 8 D (k+j+1) + 28 D.  Two sweeps: the stencil
+    input, eps and w (20 D), the basis and w for the dots and again for the
+    update, and q_{j+1}: 16 D (k+j) + 44 D; each further Gram-Schmidt pass
+    adds 16 D (k+j) + 24 D."""
     full, rem = divmod(int(iters), m)
     def cyc(n):       # sum over j < n of (k + j)
         return n * k + n * (n - 1) // 2
     sj = full * cyc(m) + cyc(rem)
+    if fused and passes == 1:
+        return 8 * D * sj + 36 * D * iters
     return (16 * D * sj + 44 * D * iters) + (passes - 1) * (16 * D * sj + 24 * D * iters)
 
 
@@ -818,7 +822,7 @@ def main():
     ms_k, launches_k, bytes_k = ks[name]
     achieved = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
     kname = {"matvec_dots": "k_matvec_dot", "second_pass": "k_update_dot",
-             "update_norm": "k_update_norm"}[name]
+             "update_norm": "k_update_norm", "fused_sweep": "k_fused_sweep"}[name]
     traffic = None
     if (kname in MEASURED_TRAFFIC["bytes_per_launch"] and args.batch == MEASURED_TRAFFIC["batch"]
             and args.k == MEASURED_TRAFFIC["k"] and args.cgs == 1

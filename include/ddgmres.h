@@ -136,6 +136,10 @@ typedef struct {
                         /* size dd_solver_workspace_bytes reports for the same    */
                         /* operators and options; borrowed until destroy          */
   size_t workspace_bytes;
+  int fused;            /* 1 (default) = one sweep per Arnoldi step where it      */
+                        /* applies (cgs_passes = 1 and kmax + restart + 1 <= 128):*/
+                        /* the update of step j, the matvec and the dots of step  */
+                        /* j + 1 read each basis vector once; 0 = two sweeps      */
 } dd_solver_opts;
 
 /* Per-problem result (host struct). */
@@ -216,17 +220,20 @@ dd_status dd_solver_history(const dd_solver* s, int p, double* out, int cap, int
 dd_status dd_solver_debug_copy(const dd_solver* s, int p, int what, void* host_out,
                                size_t bytes);
 
-/* Live timing of the three streaming sweeps of an Arnoldi step, recorded
- * with HIP events on the solve stream around every launch while enabled:
- * [0] stencil matvec + first Gram-Schmidt dots, [1] second Gram-Schmidt
- * pass (update + dots), [2] final update + norm.  bytes[] are the
- * algorithmic bytes those launches had to move (inner precision ib bytes per
- * complex, eb per permittivity value, n = basis length of the step):
- * [0] (2 ib + eb) D + ib D n, [1] ib D (2n + 2), [2] ib D (n + 2). */
+/* Live timing of the streaming sweeps of an Arnoldi step, recorded with HIP
+ * events on the solve stream around every launch while enabled:
+ * [0] stencil matvec + first Gram-Schmidt dots (with the fused sweep: the
+ * first matvec of each cycle), [1] second Gram-Schmidt pass (update + dots),
+ * [2] final update + norm, [3] fused sweep.  bytes[] are the algorithmic
+ * bytes those launches had to move (inner precision ib bytes per complex, eb
+ * per permittivity value, n = basis length of the step):
+ * [0] (2 ib + eb) D + ib D n, [1] ib D (2n + 2), [2] ib D (n + 2),
+ * [3] ib D (n + 3) + eb D (read the n basis vectors and A q~_j, write q~_{j+1}
+ * and A q~_{j+1}, read eps). */
 typedef struct {
-  double ms[3];
-  long long launches[3];
-  double bytes[3];
+  double ms[4];
+  long long launches[4];
+  double bytes[4];
 } dd_kernel_stats;
 
 /* Tile-shape autotuner: times one restart cycle of Arnoldi steps on ops for each

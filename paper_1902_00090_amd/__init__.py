@@ -131,7 +131,8 @@ PRECONDS = {None: 0, "none": 0, "jacobi": 1, "pml": 2}
 
 
 def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hist_cap=0,
-          check_every=4, select_reorth=True, use_graph=False, precond=None, workspace=None):
+          check_every=4, select_reorth=True, use_graph=False, precond=None, workspace=None,
+          fused=True):
     o = _lib.dd_solver_opts()
     _lib.lib().dd_solver_opts_default(C.byref(o))
     o.inner = DD_C64 if inner == "c64" else DD_C128
@@ -144,6 +145,7 @@ def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hi
     o.select_reorth = int(bool(select_reorth))
     o.use_graph = int(bool(use_graph))
     o.precond = PRECONDS[precond]
+    o.fused = int(bool(fused))
     if workspace is not None:
         o.workspace = C.c_void_p(_dev(workspace, what="workspace").value)
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -151,11 +153,11 @@ def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hi
 
 
 def workspace_bytes(ops, restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0,
-                    hist_cap=0, precond=None):
+                    hist_cap=0, precond=None, fused=True):
     """Device bytes a Solver with these operators and options needs (no device
     memory is touched)."""
     o = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap, 4, True, False,
-              precond)
+              precond, None, fused)
     n = C.c_size_t()
     check(_lib.lib().dd_solver_workspace_bytes(ptr_array([op.handle for op in ops]), len(ops),
                                                C.byref(o), C.byref(n)),
@@ -179,8 +181,10 @@ class Solver:
 
     def __init__(self, ops, restart=100, kmax=0, inner="c64", cgs_passes=2,
                  elems_per_thread=0, hist_cap=0, check_every=4, select_reorth=True,
-                 use_graph=False, precond=None, workspace=None):
+                 use_graph=False, precond=None, workspace=None, fused=True):
         """precond: None, "jacobi" or "pml" (diagonal preconditioners, see the C header).
+        fused: one sweep per Arnoldi step where it applies (cgs_passes=1,
+        kmax + restart + 1 <= 128).
         workspace: an optional device tensor (at least workspace_bytes(...) bytes,
         256-byte aligned) that holds all of the solver's device arrays; the
         solver then allocates no device memory and keeps a reference to it."""
@@ -188,7 +192,7 @@ class Solver:
         self.nb = len(self.ops)
         self._workspace = workspace
         self.opts = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap,
-                          check_every, select_reorth, use_graph, precond, workspace)
+                          check_every, select_reorth, use_graph, precond, workspace, fused)
         self.inner = inner
         self.restart, self.kmax = int(restart), int(kmax)
         h = C.c_void_p()
@@ -277,10 +281,10 @@ class Solver:
         check(_lib.lib().dd_solver_profile(self._h, int(bool(enable))), "dd_solver_profile")
 
     def kernel_stats(self):
-        """{'matvec_dots'|'second_pass'|'update_norm': (ms, launches, bytes)}."""
+        """{'matvec_dots'|'second_pass'|'update_norm'|'fused_sweep': (ms, launches, bytes)}."""
         ks = _lib.dd_kernel_stats()
         check(_lib.lib().dd_solver_kernel_stats(self._h, C.byref(ks)), "dd_solver_kernel_stats")
-        names = ["matvec_dots", "second_pass", "update_norm"]
+        names = ["matvec_dots", "second_pass", "update_norm", "fused_sweep"]
         return {n: (ks.ms[i], ks.launches[i], ks.bytes[i]) for i, n in enumerate(names)}
 
     @property

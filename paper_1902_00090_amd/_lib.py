@@ -33,7 +33,8 @@ class dd_solver_opts(C.Structure):
     _fields_ = [("inner", C.c_int), ("cgs_passes", C.c_int), ("restart", C.c_int),
                 ("kmax", C.c_int), ("elems_per_thread", C.c_int), ("hist_cap", C.c_int),
                 ("check_every", C.c_int), ("select_reorth", C.c_int), ("use_graph", C.c_int),
-                ("precond", C.c_int), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("precond", C.c_int), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("fused", C.c_int)]
 
 
 class dd_info(C.Structure):
@@ -47,8 +48,8 @@ class dd_info(C.Structure):
 
 
 class dd_kernel_stats(C.Structure):
-    _fields_ = [("ms", C.c_double * 3), ("launches", C.c_longlong * 3),
-                ("bytes", C.c_double * 3)]
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_longlong * 4),
+                ("bytes", C.c_double * 4)]
 
 
 P = C.c_void_p

@@ -35,6 +35,17 @@ struct ProbDesc {
   const void* pr;
   const double2* pl64;
   const double2* pr64;
+  // fused Arnoldi sweep: this problem's tiles [t0, t0 + nt) of the tile list,
+  // and two [Dp] inner-precision buffers for A q~ (the current and the next)
+  int t0, nt;
+  void* Z;
+};
+
+// One tile of the fused sweep: the columns [x0, x0 + 64 CPL) (clipped to nx)
+// of rows [y0, y1) of problem p, walked downwards (dir = 1) or upwards
+// (dir = -1).
+struct FusedTile {
+  int p, x0, y0, y1, dir;
 };
 
 // Integer state per problem
@@ -82,4 +93,6 @@ struct PlanDev {
   int reorth_mode;   // 0 one Gram-Schmidt pass, 1 always two, 2 two where needed
   const double* ctl;  // device [tol, maxit] of the current solve (kernel arguments
                       // stay constant, so captured graphs remain valid)
+  int fused;          // 1: one-sweep Arnoldi steps (k_fused_sweep / k_post_fused)
+  const FusedTile* tiles;
 };

@@ -24,6 +24,11 @@ struct dd_solver {
   std::vector<void*> allocs;
   size_t bytes = 0;       // device workspace of the solver (owned or the caller's)
   bool owns_workspace = true;
+  // fused Arnoldi sweep: on when cgs_passes = 1 and kmax + m + 1 <= 128
+  bool fused = false;
+  int cpl = 1;                   // strip width 64 cpl columns
+  std::vector<FusedTile> htiles;
+  FusedTile* dtiles = nullptr;
   int* pinned = nullptr;     // 2 status snapshots + 1 final
   double* pinnedD = nullptr;
   unsigned long long* pinnedK = nullptr;
@@ -77,6 +82,7 @@ extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
   o->precond = DD_PRECOND_NONE;
   o->workspace = nullptr;
   o->workspace_bytes = 0;
+  o->fused = 1;
 }
 
 static size_t inner_bytes(dd_prec p) { return p == DD_C128 ? 16 : 8; }
@@ -146,6 +152,11 @@ static void layout_workspace(dd_solver* s, Arena& A, ProbDesc*& dd, int*& db2p) 
     d.basis = basis;
     d.V = V;
     d.r = r;
+    if (s->fused) {
+      char* Z = nullptr;
+      A.carve(&Z, (size_t)2 * d.Dp * ib);
+      d.Z = Z;
+    }
     if (o.precond != DD_PRECOND_NONE) {
       double2 *pl64 = nullptr, *pr64 = nullptr;
       float2 *pl32 = nullptr, *pr32 = nullptr;
@@ -163,6 +174,7 @@ static void layout_workspace(dd_solver* s, Arena& A, ProbDesc*& dd, int*& db2p) 
   }
   A.carve(&dd, nb);
   A.carve(&db2p, s->nchunks);
+  if (s->fused) A.carve(&s->dtiles, s->htiles.size());
   A.carve(&s->dU, nb);
   A.carve(&P.stI, (size_t)nb * ST_NI);
   A.carve(&P.stD, (size_t)nb * SD_ND);
@@ -183,7 +195,7 @@ static void layout_workspace(dd_solver* s, Arena& A, ProbDesc*& dd, int*& db2p) 
   A.carve(&P.keep, (size_t)nb);
   A.carve(&P.bad, (size_t)nb);
   double* part = nullptr;
-  A.carve(&part, (size_t)s->nchunks * P.NV);
+  A.carve(&part, (size_t)std::max<size_t>(s->nchunks, s->htiles.size()) * P.NV);
   P.partial = part;
   A.carve(&P.gpart, (size_t)nb * P.GB * std::max(1, gram_tiles(std::max(K, 1))) * 32);
   A.carve(&P.hist, (size_t)nb * std::max(1, o.hist_cap));
@@ -280,6 +292,30 @@ static dd_status solver_plan(const fdfd_op* const* ops, int nb, const dd_solver_
     int GB = (int)std::min<size_t>(32, std::max<size_t>(1, (64ull << 20) / per));
     P.GB = GB;
   }
+  // Fused sweep tiles: bands of whole rows (nx <= 1024: 512 cpl columns per
+  // workgroup), about two tiles per compute unit (bands of 2 to 64 rows),
+  // adjacent bands walking in opposite directions.
+  int maxnx = 0;
+  long long rows = 0;
+  for (int p = 0; p < nb; ++p) {
+    maxnx = std::max(maxnx, ops[p]->nx);
+    rows += ops[p]->ny;
+  }
+  s->fused = o.fused && o.cgs_passes == 1 && (K + m + 1) <= 128 && maxnx <= 1024;
+  if (s->fused) {
+    s->cpl = (maxnx <= 512) ? 1 : 2;
+    const int bh = (int)std::min<long long>(64, std::max<long long>(2, rows / (2LL * s->ncu)));
+    s->htiles.clear();
+    for (int p = 0; p < nb; ++p) {
+      ProbDesc& d = s->hdesc[p];
+      const int nyp = ops[p]->ny;
+      d.t0 = (int)s->htiles.size();
+      int band = 0;
+      for (int y0 = 0; y0 < nyp; y0 += bh, ++band)
+        s->htiles.push_back({p, 0, y0, std::min(nyp, y0 + bh), (band & 1) ? -1 : 1});
+      d.nt = (int)s->htiles.size() - d.t0;
+    }
+  }
   *out = s;
   return DD_OK;
 }
@@ -323,6 +359,9 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
     for (int c = 0; c < s->hdesc[p].nblk; ++c) b2p[s->hdesc[p].blk0 + c] = p;
   auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
   if (e == hipSuccess) {
+    if (s->fused)
+      chk(hipMemcpy(s->dtiles, s->htiles.data(), sizeof(FusedTile) * s->htiles.size(),
+                    hipMemcpyHostToDevice));
     chk(hipMemcpy(dd, s->hdesc.data(), sizeof(ProbDesc) * nb, hipMemcpyHostToDevice));
     chk(hipMemcpy(db2p, b2p.data(), sizeof(int) * s->nchunks, hipMemcpyHostToDevice));
     chk(hipHostMalloc((void**)&s->pinned, sizeof(int) * 3 * nb * ST_NI, hipHostMallocDefault));
@@ -342,6 +381,8 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
   P.desc = dd;
   P.blk2prob = db2p;
   P.ctl = s->dctl;
+  P.fused = s->fused ? 1 : 0;
+  P.tiles = s->dtiles;
   e = precond_init(s);
   if (e != hipSuccess) {
     dd_set_error("dd_solver_create: %s", hipGetErrorString(e));
@@ -505,6 +546,30 @@ static void launch_step(dd_solver* s, int j, hipStream_t st) {
   k_post_norm<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
 }
 
+// One fused Arnoldi step: the sweep (update of step j, matvec and dots of
+// step j + 1) and its FP64 bookkeeping.
+template <typename T>
+static void launch_fused_step(dd_solver* s, int j, hipStream_t st) {
+  const int nt = (int)s->htiles.size();
+  const bool pc = s->o.precond != DD_PRECOND_NONE;
+  prof_mark(s, 3, st);
+  if (s->cpl == 2) {
+    if (pc) k_fused_sweep<T, true, 2><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
+    else k_fused_sweep<T, false, 2><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
+  } else {
+    if (pc) k_fused_sweep<T, true, 1><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
+    else k_fused_sweep<T, false, 1><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
+  }
+  prof_end(s, st);
+  k_post_fused<T><<<s->nb, DD_BLOCK, 0, st>>>(s->P, j, 0);
+}
+
+template <typename T, int R>
+static void launch_any_step(dd_solver* s, int j, hipStream_t st) {
+  if (s->fused) launch_fused_step<T>(s, j, st);
+  else launch_step<T, R>(s, j, st);
+}
+
 // Projected start; it always takes the second pass unless one pass is
 // requested, because a good subspace leaves r~ = r - C C^H r tiny against r.
 template <typename T, int R>
@@ -532,7 +597,7 @@ static dd_status launch_group_graph(dd_solver* s, int grp, int jend, hipStream_t
   if (!s->execs[grp]) {
     if (!s->cap) DD_HIP_CHECK(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
     DD_HIP_CHECK(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
-    for (int j = grp * ce; j < jend; ++j) launch_step<T, R>(s, j, s->cap);
+    for (int j = grp * ce; j < jend; ++j) launch_any_step<T, R>(s, j, s->cap);
     hipGraph_t g = nullptr;
     DD_HIP_CHECK(hipStreamEndCapture(s->cap, &g));
     hipGraphExec_t ex = nullptr;
@@ -562,6 +627,16 @@ static dd_status run_cycles(dd_solver* s, hipStream_t st) {
     for (int p = 0; p < nb; ++p) active += snap[0][p * ST_NI + ST_ACTIVE];
     if (active == 0) break;
     launch_start<T, R>(s, st);
+    if (s->fused) {
+      // z_0 = A q~_0 (unscaled) and its dots; then the coefficients of step 0
+      const int ngrp = (s->o.kmax + 1 + 15) / 16;
+      const dim3 gm(s->nchunks, (s->nchunks < s->ncu) ? std::min(4, ngrp) : 1);
+      prof_mark(s, 0, st);
+      if (s->o.precond != DD_PRECOND_NONE) k_matvec_dot<T, R, true><<<gm, DD_BLOCK, 0, st>>>(s->P, 0);
+      else k_matvec_dot<T, R, false><<<gm, DD_BLOCK, 0, st>>>(s->P, 0);
+      prof_end(s, st);
+      k_post_fused<T><<<nb, DD_BLOCK, 0, st>>>(s->P, 0, 1);
+    }
     int pending = -1, grp = 0;
     const int ce = s->o.check_every;
     const bool graph = s->o.use_graph && !s->prof;
@@ -574,7 +649,7 @@ static dd_status run_cycles(dd_solver* s, hipStream_t st) {
         }
         if ((j + 1) % ce != 0 && j + 1 < m) continue;
       } else {
-        launch_step<T, R>(s, j, st);
+        launch_any_step<T, R>(s, j, st);
       }
       if ((j + 1) % ce == 0 && j + 1 < m) {
         const int slot = (grp++) & 1;
@@ -654,9 +729,17 @@ extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const v
       const int* st = fin + p * ST_NI;
       const double* sd = s->pinnedD + p * SD_ND;
       const double D = s->hdesc[p].D, steps = st[ST_ITERS], st2 = st[ST_NREORTH];
-      s->ks.bytes[0] += (2 * ib + eb) * D * steps + ib * D * sd[SD_NSUM];
-      s->ks.bytes[1] += ib * D * (2 * sd[SD_NSUM2] + 2 * st2);
-      s->ks.bytes[2] += ib * D * (sd[SD_NSUM] + 2 * steps);
+      if (s->fused) {
+        // first matvec of each cycle: (2 ib + eb) D + ib D (k + 1); fused
+        // sweep of a step with n basis vectors: ib D (n + 3) + eb D
+        const double cyc = st[ST_CYCLES], kk = s->hdesc[p].k;
+        s->ks.bytes[0] += ((2 * ib + eb) + ib * (kk + 1)) * D * cyc;
+        s->ks.bytes[3] += ib * D * (sd[SD_NSUM] + 3 * steps) + eb * D * steps;
+      } else {
+        s->ks.bytes[0] += (2 * ib + eb) * D * steps + ib * D * sd[SD_NSUM];
+        s->ks.bytes[1] += ib * D * (2 * sd[SD_NSUM2] + 2 * st2);
+        s->ks.bytes[2] += ib * D * (sd[SD_NSUM] + 2 * steps);
+      }
     }
   }
   for (int p = 0; p < nb; ++p) {

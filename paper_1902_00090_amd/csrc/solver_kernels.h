@@ -168,7 +168,11 @@ __device__ void finish_cycle(const PlanDev& P, int p, int k, int n) {
     for (int b = 0; b < k; ++b) z = dadd(z, dmul(Ri[(size_t)t * P.kmax + b], xa[b]));
     comb[t] = z;
   }
-  for (int i = t; i < n; i += DD_BLOCK) comb[k + i] = yv[i];
+  // fused steps store the Krylov vectors unnormalised: q_i = hscale[i] q~_i
+  for (int i = t; i < n; i += DD_BLOCK)
+    comb[k + i] = P.fused ? make_double2(yv[i].x * P.hscale[(size_t)p * (m + 1) + i],
+                                         yv[i].y * P.hscale[(size_t)p * (m + 1) + i])
+                          : yv[i];
   if (t == 0) {
     int* st = P.stI + p * ST_NI;
     st[ST_NCOMB] = n;
@@ -318,8 +322,9 @@ __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
   c2<T>* B = (c2<T>*)d.basis + (size_t)(P.kmax - d.k) * Dp;
   const int n = d.k + j + 1;
   const c2<T>* q = B + (size_t)(n - 1) * Dp;
-  c2<T>* w = B + (size_t)n * Dp;
-  const double hs = P.hscale[(size_t)p * (P.m + 1) + j];
+  // fused steps keep z = A q~ unscaled, in the problem's own buffer
+  c2<T>* w = P.fused ? (c2<T>*)d.Z : B + (size_t)n * Dp;
+  const double hs = P.fused ? 1.0 : P.hscale[(size_t)p * (P.m + 1) + j];
   c2<T> wv[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -509,6 +514,91 @@ __global__ __launch_bounds__(DD_BLOCK) void k_update_norm(PlanDev P, int j, int 
   if (threadIdx.x == 0) prow[0] = tot;
 }
 
+// Column j of the Arnoldi relation, given the FP64 coefficients col (the k
+// entries of B = C^H A q_j, then the j + 1 entries of H) and the norm of the
+// new vector nrm = h_{j+1,j}: stores B and the raw column, applies the
+// previous Givens rotations and a new one, updates the residual estimate
+// g_{j+1} and the step counters, sets hscale[j + 1] = hs_next, and decides
+// whether the cycle ends here (fin, nfin).  Called by all threads of the
+// problem's workgroup.
+__device__ void arnoldi_column(const PlanDev& P, int p, int j, int k, double2* col, double nrm,
+                               double hs_next, int cgs2, double2 gj, int it0, int nre0,
+                               double nsum0, double nsum20, double bn, double ctl_tol,
+                               double ctl_maxit, int& fin, int& nfin) {
+  const int m = P.m, t = threadIdx.x;
+  const int n = k + j + 1;
+  int* st = P.stI + p * ST_NI;
+  double* sd = P.stD + p * SD_ND;
+  double2* Hraw = P.Hraw + ((size_t)p * m + j) * (m + 1);
+  double2* Hc = P.H + ((size_t)p * m + j) * (m + 1);
+  double2* Bc = P.Bc + ((size_t)p * m + j) * P.kmax;
+  double2* hcol = col + k;
+  // the previous rotations, staged by all threads for thread 0's serial pass
+  __shared__ double cs_l[DD_MAX_M];
+  __shared__ double2 sn_l[DD_MAX_M];
+  for (int i = t; i < j; i += DD_BLOCK) {
+    cs_l[i] = P.cs[(size_t)p * m + i];
+    sn_l[i] = P.sn[(size_t)p * m + i];
+  }
+  for (int v = t; v < k; v += DD_BLOCK) Bc[v] = col[v];
+  for (int i = t; i <= j; i += DD_BLOCK) Hraw[i] = col[k + i];
+  __syncthreads();
+  if (t == 0) {
+    Hraw[j + 1] = make_double2(nrm, 0.0);
+    // apply rotations 0..j-1 to the new column; the entry being rotated into
+    // the next position stays in registers
+    double2 cur = hcol[0];
+    for (int i = 0; i < j; ++i) {
+      const double2 b = hcol[i + 1];
+      const double c = cs_l[i];
+      const double2 s = sn_l[i];
+      hcol[i] = dadd(make_double2(c * cur.x, c * cur.y), dmul(s, b));
+      cur = dsub(make_double2(c * b.x, c * b.y), dmulc(s, cur));
+    }
+    // new rotation zeroing the subdiagonal entry nrm
+    const double2 a = cur;
+    const double aa = sqrt(a.x * a.x + a.y * a.y);
+    double c;
+    double2 s, rr;
+    if (aa == 0.0) {
+      c = 0.0; s = make_double2(1.0, 0.0); rr = make_double2(nrm, 0.0);
+    } else {
+      const double nu = sqrt(aa * aa + nrm * nrm);
+      const double2 al = make_double2(a.x / aa, a.y / aa);
+      c = aa / nu;
+      s = make_double2(al.x * nrm / nu, al.y * nrm / nu);
+      rr = make_double2(al.x * nu, al.y * nu);
+    }
+    hcol[j] = rr;
+    P.cs[(size_t)p * m + j] = c;
+    P.sn[(size_t)p * m + j] = s;
+    Hc[j + 1] = make_double2(0.0, 0.0);
+    double2* g = P.g + (size_t)p * (m + 1);
+    const double2 gn = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    g[j + 1] = gn;
+    g[j] = make_double2(c * gj.x, c * gj.y);
+    P.hscale[(size_t)p * (m + 1) + j + 1] = hs_next;
+    const int it = it0 + 1;
+    st[ST_ITERS] = it;
+    if (cgs2) {
+      st[ST_NREORTH] = nre0 + 1;
+      sd[SD_NSUM2] = nsum20 + (double)n;
+    }
+    sd[SD_NSUM] = nsum0 + (double)n;
+    st[ST_J] = j + 1;
+    const double est = sqrt(gn.x * gn.x + gn.y * gn.y);
+    sd[SD_EST] = est / bn;
+    if (it <= P.hist_cap) P.hist[(size_t)p * P.hist_cap + it - 1] = est / bn;
+    if (est <= ctl_tol * bn || it >= (int)ctl_maxit || !(nrm > 0.0) || !isfinite(nrm) ||
+        j + 1 == m) {
+      fin = 1;
+      nfin = j + 1;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i <= j; i += DD_BLOCK) Hc[i] = hcol[i];   // the rotated column
+}
+
 // One workgroup per problem: the FP64 bookkeeping after the final update
 // sweep.  Start phase: beta, c0 = C^H r.  Arnoldi step: the new Hessenberg
 // column, B column, Givens rotation and residual estimate, and at the
@@ -564,74 +654,8 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
       if (!(nrm > 0.0) || !isfinite(nrm)) { fin = 1; nfin = 0; }
     }
   } else {
-    double2* Hraw = P.Hraw + ((size_t)p * m + j) * (m + 1);
-    double2* Hc = P.H + ((size_t)p * m + j) * (m + 1);
-    double2* Bc = P.Bc + ((size_t)p * m + j) * P.kmax;
-    double2* hcol = col + k;
-    // the previous rotations, staged by all threads for thread 0's serial pass
-    __shared__ double cs_l[DD_MAX_M];
-    __shared__ double2 sn_l[DD_MAX_M];
-    for (int i = t; i < j; i += DD_BLOCK) {
-      cs_l[i] = P.cs[(size_t)p * m + i];
-      sn_l[i] = P.sn[(size_t)p * m + i];
-    }
-    for (int v = t; v < k; v += DD_BLOCK) Bc[v] = col[v];
-    for (int i = t; i <= j; i += DD_BLOCK) Hraw[i] = col[k + i];
-    __syncthreads();
-    if (t == 0) {
-      Hraw[j + 1] = make_double2(nrm, 0.0);
-      // apply rotations 0..j-1 to the new column; the entry being rotated into
-      // the next position stays in registers
-      double2 cur = hcol[0];
-      for (int i = 0; i < j; ++i) {
-        const double2 b = hcol[i + 1];
-        const double c = cs_l[i];
-        const double2 s = sn_l[i];
-        hcol[i] = dadd(make_double2(c * cur.x, c * cur.y), dmul(s, b));
-        cur = dsub(make_double2(c * b.x, c * b.y), dmulc(s, cur));
-      }
-      // new rotation zeroing the subdiagonal entry nrm
-      const double2 a = cur;
-      const double aa = sqrt(a.x * a.x + a.y * a.y);
-      double c;
-      double2 s, rr;
-      if (aa == 0.0) {
-        c = 0.0; s = make_double2(1.0, 0.0); rr = make_double2(nrm, 0.0);
-      } else {
-        const double nu = sqrt(aa * aa + nrm * nrm);
-        const double2 al = make_double2(a.x / aa, a.y / aa);
-        c = aa / nu;
-        s = make_double2(al.x * nrm / nu, al.y * nrm / nu);
-        rr = make_double2(al.x * nu, al.y * nu);
-      }
-      hcol[j] = rr;
-      P.cs[(size_t)p * m + j] = c;
-      P.sn[(size_t)p * m + j] = s;
-      Hc[j + 1] = make_double2(0.0, 0.0);
-      double2* g = P.g + (size_t)p * (m + 1);
-      const double2 gn = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
-      g[j + 1] = gn;
-      g[j] = make_double2(c * gj.x, c * gj.y);
-      P.hscale[(size_t)p * (m + 1) + j + 1] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
-      const int it = it0 + 1;
-      st[ST_ITERS] = it;
-      if (cgs2) {
-        st[ST_NREORTH] = nre0 + 1;
-        sd[SD_NSUM2] = nsum20 + (double)n;
-      }
-      sd[SD_NSUM] = nsum0 + (double)n;
-      st[ST_J] = j + 1;
-      const double est = sqrt(gn.x * gn.x + gn.y * gn.y);
-      sd[SD_EST] = est / bn;
-      if (it <= P.hist_cap) P.hist[(size_t)p * P.hist_cap + it - 1] = est / bn;
-      if (est <= ctl_tol * bn || it >= (int)ctl_maxit || !(nrm > 0.0) || !isfinite(nrm) ||
-          j + 1 == m) {
-        fin = 1;
-        nfin = j + 1;
-      }
-    }
-    __syncthreads();
-    for (int i = t; i <= j; i += DD_BLOCK) Hc[i] = hcol[i];   // the rotated column
+    arnoldi_column(P, p, j, k, col, nrm, (nrm > 0.0) ? 1.0 / nrm : 0.0, cgs2, gj, it0, nre0, nsum0,
+                   nsum20, bn, ctl_tol, ctl_maxit, fin, nfin);
   }
   __syncthreads();
   if (fin) finish_cycle(P, p, k, nfin);
@@ -697,6 +721,285 @@ __global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
     const int e = base + r * DD_BLOCK + threadIdx.x;
     if (e < d.D) d.x[e] = dadd(d.x[e], acc[r]);
   }
+}
+
+// ============================ fused Arnoldi sweep ============================
+// One sweep per Arnoldi step (cgs_passes = 1, k + m + 1 <= 128, nx <= 1024).
+// The Krylov vectors are normalised one step late, q_i = s_i q~_i with FP64
+// scales s_i = hscale[i] (C columns: s = 1), and z_j = A q~_j is kept
+// unscaled in a separate double buffer.  With d_v = b_v^H z_j the raw dots of
+// z_j against the basis b = [C, q~_0 .. q~_j], the next vector is the
+// classical Gram-Schmidt remainder of A q_j = s_j z_j,
+//     q~_{j+1} = s_j z_j - sum_v g_v b_v,   g_v = s_j s_v^2 d_v,
+// with h_{v,j} = s_v s_j d_v, h_{j+1,j} = ||q~_{j+1}|| and s_{j+1} =
+// 1 / ||q~_{j+1}|| (so the stored vectors stay of the size of the entries of
+// H).  The sweep of step j forms q~_{j+1}, then z_{j+1} =
+// A q~_{j+1} and its raw dots against [C, q~_0 .. q~_{j+1}] plus ||q~_{j+1}||^2,
+// so every basis value is fetched from memory once per step where the two
+// classical passes (dots, then update) fetch it twice.
+//
+// The stencil needs q~_{j+1} at the rows above and below, which other tiles
+// form in the same launch.  A workgroup therefore walks a band of whole rows:
+// at walk step t it updates row r_t (and the halo rows before the first and
+// after the last row of the band, recomputed rather than read), applies the
+// stencil to row r_{t-1} from a ring of three updated rows in LDS, and takes
+// the dots of row r_{t-2}, whose basis values it fetched two steps before (the
+// repeat fetch hits the caches).  Adjacent bands walk in opposite
+// directions, so the halo row two bands share is fetched by both at the same
+// time.  Lane l of wave w owns the cells x = l + 64 w + 512 c, c < CPL, of
+// each row; the dots of 16 basis vectors at a time are folded across the wave
+// by the transposed butterfly into per-wave LDS sums, added over the waves at
+// the end.  One partial row per tile, reduced in tile order by k_post_fused.
+#define DD_FUSED_THREADS 512
+#define DD_FUSED_MAXN 128                // basis vectors of one step: n + 1 <= 128
+
+template <typename T>
+__device__ __forceinline__ c2<T> stencil_vals(c2<T> c, c2<T> w, c2<T> ea, c2<T> s, c2<T> n,
+                                              c2<T> cxm, c2<T> cxp, c2<T> cym, c2<T> cyp, T de) {
+  // the arithmetic of stencil_point, on values already at hand
+  c2<T> r = cmul(cxm, csub(c, w));
+  r = csub(r, cmul(cxp, csub(ea, c)));
+  r = cadd(r, cmul(cym, csub(c, s)));
+  r = csub(r, cmul(cyp, csub(n, c)));
+  r.x -= de * c.x;
+  r.y -= de * c.y;
+  return r;
+}
+
+template <typename V> __device__ __forceinline__ V cfma(V acc, V a, V b) {   // acc + a*b
+  return cmk<V>(acc.x + (a.x * b.x - a.y * b.y), acc.y + (a.x * b.y + a.y * b.x));
+}
+template <typename V> __device__ __forceinline__ V cfmac(V acc, V a, V b) {  // acc + conj(a)*b
+  return cmk<V>(acc.x + (a.x * b.x + a.y * b.y), acc.y + (a.x * b.y - a.y * b.x));
+}
+
+template <typename T, bool PC, int CPL>
+__global__ __launch_bounds__(DD_FUSED_THREADS) void k_fused_sweep(PlanDev P, int j) {
+  using V = c2<T>;
+  constexpr int NW = DD_FUSED_THREADS / 64;
+  constexpr int RW = DD_FUSED_THREADS * CPL + 2;    // ring row: cells 1..nx, wrap copies unused
+  const FusedTile tl = P.tiles[blockIdx.x];
+  const int p = tl.p;
+  if (P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int nx = d.nx, ny = d.ny;
+  const size_t Dp = d.Dp;
+  const int k = d.k;
+  const int n = k + j + 1;                                   // basis [C, q~_0 .. q~_j]
+  const V* B = (const V*)d.basis + (size_t)(P.kmax - k) * Dp;
+  V* qn = (V*)d.basis + (size_t)(P.kmax + j + 1) * Dp;       // q~_{j+1}
+  const V* zin = (const V*)d.Z + (size_t)(j & 1) * Dp;       // z_j
+  V* zout = (V*)d.Z + (size_t)((j + 1) & 1) * Dp;            // z_{j+1}
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int dir = tl.dir;
+  const int r0 = (dir > 0) ? tl.y0 : tl.y1 - 1;             // first row of the walk
+  const int nrows = tl.y1 - tl.y0;
+  const T sj = (T)P.hscale[(size_t)p * (P.m + 1) + j];      // s_j
+  __shared__ V coef[DD_FUSED_MAXN];
+  __shared__ V ring[3][RW];           // updated rows, cell x at index x + 1
+  __shared__ T accl[NW][2 * DD_FUSED_MAXN];
+  __shared__ T lds_un[NW];
+  const double2* cB = P.coefB + (size_t)p * P.NC;
+  for (int v = threadIdx.x; v < n; v += DD_FUSED_THREADS) coef[v] = to_c<T>(cB[v]);
+  for (int v = threadIdx.x; v < NW * 2 * DD_FUSED_MAXN; v += DD_FUSED_THREADS)
+    (&accl[0][0])[v] = T(0);
+  __syncthreads();
+  const V* cf = OpP<T>::cf(d);
+  const auto* epsp = OpP<T>::eps(d);
+  const T om2 = (T)d.omega2;
+  const V* pl = PC ? (const V*)d.pl : nullptr;
+  const V* pr = PC ? (const V*)d.pr : nullptr;
+  int xs[CPL];
+  bool ok[CPL];
+  V cxm[CPL], cxp[CPL], zdot[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    xs[c] = lane + 64 * wave + DD_FUSED_THREADS * c;
+    ok[c] = xs[c] < nx;
+    const int ix = ok[c] ? xs[c] : 0;
+    cxm[c] = cf[ix];
+    cxp[c] = cf[nx + ix];
+    zdot[c] = cmk<V>(T(0), T(0));
+  }
+  T un2 = T(0);                // ||q~_{j+1}||^2 over the tile
+  auto wrapy = [&](int y) { return (y < 0) ? y + ny : ((y >= ny) ? y - ny : y); };
+  for (int t = 0; t <= nrows + 2; ++t) {
+    const bool upd = t <= nrows + 1;
+    const bool dot = t >= 3;
+    const size_t ru = (size_t)wrapy(r0 - dir + dir * t) * nx;      // row being updated
+    const size_t rd = (size_t)wrapy(r0 - 3 * dir + dir * t) * nx;  // row whose dots are taken
+    // ---- A: update sums of row ru, dots of row rd, 16 basis vectors at a time
+    V pu[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) pu[c] = cmk<V>(T(0), T(0));
+    for (int g = 0; 16 * g <= n; ++g) {
+      T dv[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) dv[i] = T(0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int v = 16 * g + i;
+        if (v < n) {
+          const V* bv = B + (size_t)v * Dp;
+          const V cv = coef[v];
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            if (!ok[c]) continue;
+            if (upd) pu[c] = cfma(pu[c], cv, bv[ru + xs[c]]);
+            if (dot) {
+              const V b = bv[rd + xs[c]];
+              dv[2 * i] += b.x * zdot[c].x + b.y * zdot[c].y;
+              dv[2 * i + 1] += b.x * zdot[c].y - b.y * zdot[c].x;
+            }
+          }
+        } else if (v == n && dot) {
+          // the new vector q~_{j+1} at row rd, still in the ring
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            if (!ok[c]) continue;
+            const V b = ring[(t - 2) % 3][xs[c] + 1];
+            dv[2 * i] += b.x * zdot[c].x + b.y * zdot[c].y;
+            dv[2 * i + 1] += b.x * zdot[c].y - b.y * zdot[c].x;
+          }
+        }
+      }
+      if (dot) {
+        butterfly_step<T, 32>(dv, lane);
+        const T sum = dv[0] + __shfl_xor(dv[0], 1, DD_WAVE);
+        if ((lane & 1) == 0) accl[wave][32 * g + (lane >> 1)] += sum;
+      }
+    }
+    __syncthreads();
+    // ---- B: q~_{j+1} on row ru (the band's own rows stored)
+    if (upd) {
+      V* rg = ring[t % 3];
+      const bool inner = (t >= 1 && t <= nrows);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        if (!ok[c]) continue;
+        const V u = csub(cscale(zin[ru + xs[c]], sj), pu[c]);
+        rg[xs[c] + 1] = u;
+        if (inner) {
+          qn[ru + xs[c]] = u;
+          un2 += u.x * u.x + u.y * u.y;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- C: z_{j+1} = A q~_{j+1} on the row behind
+    if (t >= 2 && t <= nrows + 1) {
+      const int ys = wrapy(r0 + dir * (t - 2));
+      const V* rc = ring[(t - 1) % 3];
+      const V* rs = (dir > 0) ? ring[(t - 2) % 3] : ring[t % 3];   // row ys - 1
+      const V* rn = (dir > 0) ? ring[t % 3] : ring[(t - 2) % 3];   // row ys + 1
+      const V cym = cf[2 * nx + ys], cyp = cf[2 * nx + ny + ys];
+      const int ysm = (ys == 0) ? ny - 1 : ys - 1, ysp = (ys == ny - 1) ? 0 : ys + 1;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        if (!ok[c]) continue;
+        const int x = xs[c];
+        const int xw = (x == 0) ? nx - 1 : x - 1, xe = (x == nx - 1) ? 0 : x + 1;
+        const int e = ys * nx + x;
+        V uc = rc[x + 1], uw = rc[xw + 1], ue = rc[xe + 1], us = rs[x + 1], un = rn[x + 1];
+        if (PC && pr) {
+          uc = cmul(uc, pr[e]);
+          uw = cmul(uw, pr[ys * nx + xw]);
+          ue = cmul(ue, pr[ys * nx + xe]);
+          us = cmul(us, pr[ysm * nx + x]);
+          un = cmul(un, pr[ysp * nx + x]);
+        }
+        V z = stencil_vals<T>(uc, uw, ue, us, un, cxm[c], cxp[c], cym, cyp, om2 * (T)epsp[e]);
+        if (PC && pl) z = cmul(pl[e], z);
+        zdot[c] = z;
+        zout[e] = z;
+      }
+    }
+  }
+  // ---- partial row: dots d_v (v <= n), then ||q~_{j+1}||^2
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) un2 += __shfl_xor(un2, o, DD_WAVE);
+  if (lane == 0) lds_un[wave] = un2;
+  __syncthreads();
+  T* prow = (T*)P.partial + (size_t)blockIdx.x * P.NV;
+  for (int v = threadIdx.x; v < 2 * (n + 1); v += DD_FUSED_THREADS) {
+    T s = T(0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += accl[w][v];
+    prow[v] = s;
+  }
+  if (threadIdx.x == 0) {
+    T s = T(0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += lds_un[w];
+    prow[2 * (n + 1)] = s;
+  }
+}
+
+// One workgroup per problem after a fused sweep (init = 1: after the first
+// matvec of a cycle, k_matvec_dot writing z_0 = A q~_0 unscaled).  Reduces
+// the tile rows: raw dots d' of z_{j+1} (z_0) and ||q~_{j+1}||^2.  For a
+// step: completes column j of the Arnoldi relation from the previous dots
+// (coefA) and h_{j+1,j} = ||q~_{j+1}||, sets s_{j+1}, runs the Givens update
+// (arnoldi_column) and ends the cycle if due.  Then stores the new raw dots
+// (coefA) and the next update coefficients g_v = s_{j+1} s_v^2 d'_v (coefB;
+// s_0 for init).
+template <typename PT>
+__global__ __launch_bounds__(DD_BLOCK) void k_post_fused(PlanDev P, int j, int init) {
+  const int p = blockIdx.x;
+  int* st = P.stI + p * ST_NI;
+  if (st[ST_ACTIVE] == 0) return;
+  const ProbDesc d = P.desc[p];
+  const int k = d.k, m = P.m, t = threadIdx.x;
+  const int nn = init ? k + 1 : k + j + 2;      // vectors of the new dots
+  const double* hs = P.hscale + (size_t)p * (m + 1);
+  double* sd = P.stD + p * SD_ND;
+  double2 gj = make_double2(0.0, 0.0);
+  int it0 = 0;
+  double nsum0 = 0.0, bn = 0.0, ctl_tol = 0.0, ctl_maxit = 0.0;
+  if (t == 0 && !init) {
+    gj = P.g[(size_t)p * (m + 1) + j];
+    it0 = st[ST_ITERS];
+    nsum0 = sd[SD_NSUM];
+    bn = sd[SD_PBNORM];
+    ctl_tol = P.ctl[0];
+    ctl_maxit = P.ctl[1];
+  }
+  __shared__ double red[DD_NV_MAX];
+  __shared__ double2 col[DD_MAX_K + DD_MAX_M + 2];
+  __shared__ int fin, nfin;
+  if (init) {
+    // k_matvec_dot's rows: dots [C, q~_0]^H z_0 in 16-vector groups, ||z||^2 after
+    reduce_rows<PT>(P, d.blk0, d.nblk, 2 * nn, red);
+  } else {
+    reduce_rows<PT>(P, d.t0, d.nt, 2 * nn + 1, red);
+  }
+  if (t == 0) fin = 0;
+  double2* cA = P.coefA + (size_t)p * P.NC;
+  double2* cB = P.coefB + (size_t)p * P.NC;
+  if (!init) {
+    const double sj = hs[j];
+    const double nrm = sqrt(red[2 * nn]);
+    for (int v = t; v < k + j + 1; v += DD_BLOCK) {
+      const double2 dv = cA[v];
+      const double sv = (v < k) ? 1.0 : hs[v - k];
+      col[v] = make_double2(sv * sj * dv.x, sv * sj * dv.y);
+    }
+    __syncthreads();
+    arnoldi_column(P, p, j, k, col, nrm, (nrm > 0.0) ? 1.0 / nrm : 0.0, 0, gj, it0, 0, nsum0,
+                   0.0, bn, ctl_tol, ctl_maxit, fin, nfin);
+    __syncthreads();
+  }
+  // the new raw dots and update coefficients (hscale[j + 1] is set above)
+  const double snew = hs[init ? 0 : j + 1];
+  for (int v = t; v < nn; v += DD_BLOCK) {
+    const double2 dv = make_double2(red[2 * v], red[2 * v + 1]);
+    const double sv = (v < k) ? 1.0 : hs[v - k];
+    const double gs = snew * sv * sv;
+    cA[v] = dv;
+    cB[v] = make_double2(gs * dv.x, gs * dv.y);
+  }
+  __syncthreads();
+  if (fin) finish_cycle(P, p, k, nfin);
 }
 
 // Diagonal preconditioner of problem p, [Dp] elements, zero in the padding.
