@@ -4,8 +4,10 @@
 Workload (the PCA-augmented configuration, C4):
   * predictor training, outside the timed region: 2000 fresh 480 x 240
     grating instances (dx 25 nm, lambda 1.30 um, 20-cell PML; seeds 10,000+i)
-    are solved by this library's GPU solver; their fields form the snapshot
-    matrix and pca_build returns the top k = 20 principal components;
+    are solved by this library's GPU solver (to a relative residual of 1e-2:
+    the principal components only need the fields' dominant content); their
+    fields form the snapshot matrix and pca_build returns the top k = 20
+    principal components;
   * test set: 500 fresh instances of the same distribution (seeds 20,000+i),
     resident in HBM before timing;
   * one timed step = one batch of B = 25 test instances (the steps walk
@@ -602,7 +604,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--tol-acc", type=float, default=2e-7,
                     help="refined tolerance at which the error bound meets 1e-5")
-    ap.add_argument("--train-tol", type=float, default=1e-3)
+    ap.add_argument("--train-tol", type=float, default=1e-2,
+                    help="relative residual of the training solves (the basis only needs "
+                         "the dominant content of the fields)")
     ap.add_argument("--warmup-tol", type=float, default=1e-2)
     ap.add_argument("--maxit", type=int, default=30000)
     ap.add_argument("--cgs", type=int, default=1, help="Gram-Schmidt passes (1 or 2)")

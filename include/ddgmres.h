@@ -136,10 +136,12 @@ typedef struct {
                         /* size dd_solver_workspace_bytes reports for the same    */
                         /* operators and options; borrowed until destroy          */
   size_t workspace_bytes;
-  int fused;            /* 1 (default) = one sweep per Arnoldi step where it      */
-                        /* applies (cgs_passes = 1 and kmax + restart + 1 <= 128):*/
+  int fused;            /* 1 = one sweep per Arnoldi step where it applies        */
+                        /* (cgs_passes = 1, kmax + restart + 1 <= 128, nx <= 512):*/
                         /* the update of step j, the matvec and the dots of step  */
-                        /* j + 1 read each basis vector once; 0 = two sweeps      */
+                        /* j + 1 read each basis vector from memory once (rows    */
+                        /* walked in bands); 0 (default) = two sweeps per step,   */
+                        /* which measure faster on MI355X                         */
 } dd_solver_opts;
 
 /* Per-problem result (host struct). */

@@ -132,7 +132,7 @@ PRECONDS = {None: 0, "none": 0, "jacobi": 1, "pml": 2}
 
 def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hist_cap=0,
           check_every=4, select_reorth=True, use_graph=False, precond=None, workspace=None,
-          fused=True):
+          fused=False):
     o = _lib.dd_solver_opts()
     _lib.lib().dd_solver_opts_default(C.byref(o))
     o.inner = DD_C64 if inner == "c64" else DD_C128
@@ -153,7 +153,7 @@ def _opts(restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0, hi
 
 
 def workspace_bytes(ops, restart=100, kmax=0, inner="c64", cgs_passes=2, elems_per_thread=0,
-                    hist_cap=0, precond=None, fused=True):
+                    hist_cap=0, precond=None, fused=False):
     """Device bytes a Solver with these operators and options needs (no device
     memory is touched)."""
     o = _opts(restart, kmax, inner, cgs_passes, elems_per_thread, hist_cap, 4, True, False,
@@ -181,10 +181,10 @@ class Solver:
 
     def __init__(self, ops, restart=100, kmax=0, inner="c64", cgs_passes=2,
                  elems_per_thread=0, hist_cap=0, check_every=4, select_reorth=True,
-                 use_graph=False, precond=None, workspace=None, fused=True):
+                 use_graph=False, precond=None, workspace=None, fused=False):
         """precond: None, "jacobi" or "pml" (diagonal preconditioners, see the C header).
         fused: one sweep per Arnoldi step where it applies (cgs_passes=1,
-        kmax + restart + 1 <= 128).
+        kmax + restart + 1 <= 128, nx <= 512); off by default (slower here).
         workspace: an optional device tensor (at least workspace_bytes(...) bytes,
         256-byte aligned) that holds all of the solver's device arrays; the
         solver then allocates no device memory and keeps a reference to it."""

@@ -26,7 +26,6 @@ struct dd_solver {
   bool owns_workspace = true;
   // fused Arnoldi sweep: on when cgs_passes = 1 and kmax + m + 1 <= 128
   bool fused = false;
-  int cpl = 1;                   // strip width 64 cpl columns
   std::vector<FusedTile> htiles;
   FusedTile* dtiles = nullptr;
   int* pinned = nullptr;     // 2 status snapshots + 1 final
@@ -82,7 +81,7 @@ extern "C" void dd_solver_opts_default(dd_solver_opts* o) {
   o->precond = DD_PRECOND_NONE;
   o->workspace = nullptr;
   o->workspace_bytes = 0;
-  o->fused = 1;
+  o->fused = 0;
 }
 
 static size_t inner_bytes(dd_prec p) { return p == DD_C128 ? 16 : 8; }
@@ -292,19 +291,27 @@ static dd_status solver_plan(const fdfd_op* const* ops, int nb, const dd_solver_
     int GB = (int)std::min<size_t>(32, std::max<size_t>(1, (64ull << 20) / per));
     P.GB = GB;
   }
-  // Fused sweep tiles: bands of whole rows (nx <= 1024: 512 cpl columns per
-  // workgroup), about two tiles per compute unit (bands of 2 to 64 rows),
-  // adjacent bands walking in opposite directions.
+  // Fused sweep tiles: bands of whole rows (nx <= 512, one column per
+  // thread), adjacent bands walking in opposite directions.
   int maxnx = 0;
   long long rows = 0;
   for (int p = 0; p < nb; ++p) {
     maxnx = std::max(maxnx, ops[p]->nx);
     rows += ops[p]->ny;
   }
-  s->fused = o.fused && o.cgs_passes == 1 && (K + m + 1) <= 128 && maxnx <= 1024;
+  s->fused = o.fused && o.cgs_passes == 1 && (K + m + 1) <= 128 && maxnx <= 512;
   if (s->fused) {
-    s->cpl = (maxnx <= 512) ? 1 : 2;
-    const int bh = (int)std::min<long long>(64, std::max<long long>(2, rows / (2LL * s->ncu)));
+    // bands of ceil(rows / (w ncu)) rows, w the workgroups of the sweep that
+    // fit on a compute unit: one round of tiles, all resident at once
+    int w = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &w, (o.inner == DD_C64) ? (const void*)k_fused_sweep<float, false>
+                                    : (const void*)k_fused_sweep<double, false>,
+            DD_FUSED_THREADS, 0) != hipSuccess || w < 1)
+      w = 1;
+    const long long slots = (long long)w * s->ncu;
+    const long long per = (rows + slots - 1) / slots;
+    const int bh = (int)std::min<long long>(64, std::max<long long>(2, per));
     s->htiles.clear();
     for (int p = 0; p < nb; ++p) {
       ProbDesc& d = s->hdesc[p];
@@ -553,13 +560,8 @@ static void launch_fused_step(dd_solver* s, int j, hipStream_t st) {
   const int nt = (int)s->htiles.size();
   const bool pc = s->o.precond != DD_PRECOND_NONE;
   prof_mark(s, 3, st);
-  if (s->cpl == 2) {
-    if (pc) k_fused_sweep<T, true, 2><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
-    else k_fused_sweep<T, false, 2><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
-  } else {
-    if (pc) k_fused_sweep<T, true, 1><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
-    else k_fused_sweep<T, false, 1><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
-  }
+  if (pc) k_fused_sweep<T, true><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
+  else k_fused_sweep<T, false><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
   prof_end(s, st);
   k_post_fused<T><<<s->nb, DD_BLOCK, 0, st>>>(s->P, j, 0);
 }

@@ -724,7 +724,7 @@ __global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
 }
 
 // ============================ fused Arnoldi sweep ============================
-// One sweep per Arnoldi step (cgs_passes = 1, k + m + 1 <= 128, nx <= 1024).
+// One sweep per Arnoldi step (cgs_passes = 1, k + m + 1 <= 128, nx <= 512).
 // The Krylov vectors are normalised one step late, q_i = s_i q~_i with FP64
 // scales s_i = hscale[i] (C columns: s = 1), and z_j = A q~_j is kept
 // unscaled in a separate double buffer.  With d_v = b_v^H z_j the raw dots of
@@ -746,10 +746,10 @@ __global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
 // the dots of row r_{t-2}, whose basis values it fetched two steps before (the
 // repeat fetch hits the caches).  Adjacent bands walk in opposite
 // directions, so the halo row two bands share is fetched by both at the same
-// time.  Lane l of wave w owns the cells x = l + 64 w + 512 c, c < CPL, of
-// each row; the dots of 16 basis vectors at a time are folded across the wave
-// by the transposed butterfly into per-wave LDS sums, added over the waves at
-// the end.  One partial row per tile, reduced in tile order by k_post_fused.
+// time.  Thread x owns column x of each row (nx <= 512); the dots of 16 basis
+// vectors at a time are folded across the wave by the transposed butterfly
+// into per-wave LDS sums, added over the waves at the end.  One partial row
+// per tile, reduced in tile order by k_post_fused.
 #define DD_FUSED_THREADS 512
 #define DD_FUSED_MAXN 128                // basis vectors of one step: n + 1 <= 128
 
@@ -773,11 +773,11 @@ template <typename V> __device__ __forceinline__ V cfmac(V acc, V a, V b) {  // 
   return cmk<V>(acc.x + (a.x * b.x + a.y * b.y), acc.y + (a.x * b.y - a.y * b.x));
 }
 
-template <typename T, bool PC, int CPL>
+template <typename T, bool PC>
 __global__ __launch_bounds__(DD_FUSED_THREADS) void k_fused_sweep(PlanDev P, int j) {
   using V = c2<T>;
   constexpr int NW = DD_FUSED_THREADS / 64;
-  constexpr int RW = DD_FUSED_THREADS * CPL + 2;    // ring row: cells 1..nx, wrap copies unused
+  constexpr int RW = DD_FUSED_THREADS + 2;    // ring row: cell x at index x + 1
   const FusedTile tl = P.tiles[blockIdx.x];
   const int p = tl.p;
   if (P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
@@ -796,7 +796,7 @@ __global__ __launch_bounds__(DD_FUSED_THREADS) void k_fused_sweep(PlanDev P, int
   const int nrows = tl.y1 - tl.y0;
   const T sj = (T)P.hscale[(size_t)p * (P.m + 1) + j];      // s_j
   __shared__ V coef[DD_FUSED_MAXN];
-  __shared__ V ring[3][RW];           // updated rows, cell x at index x + 1
+  __shared__ V ring[3][RW];
   __shared__ T accl[NW][2 * DD_FUSED_MAXN];
   __shared__ T lds_un[NW];
   const double2* cB = P.coefB + (size_t)p * P.NC;
@@ -809,110 +809,130 @@ __global__ __launch_bounds__(DD_FUSED_THREADS) void k_fused_sweep(PlanDev P, int
   const T om2 = (T)d.omega2;
   const V* pl = PC ? (const V*)d.pl : nullptr;
   const V* pr = PC ? (const V*)d.pr : nullptr;
-  int xs[CPL];
-  bool ok[CPL];
-  V cxm[CPL], cxp[CPL], zdot[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    xs[c] = lane + 64 * wave + DD_FUSED_THREADS * c;
-    ok[c] = xs[c] < nx;
-    const int ix = ok[c] ? xs[c] : 0;
-    cxm[c] = cf[ix];
-    cxp[c] = cf[nx + ix];
-    zdot[c] = cmk<V>(T(0), T(0));
-  }
-  T un2 = T(0);                // ||q~_{j+1}||^2 over the tile
+  const int x = lane + 64 * wave;                  // this thread's column
+  const bool ok = x < nx;
+  const int xc = ok ? x : 0;                       // a valid column for masked loads
+  const V cxm = cf[xc], cxp = cf[nx + xc];
+  const int xw = (xc == 0) ? nx - 1 : xc - 1, xe = (xc == nx - 1) ? 0 : xc + 1;
+  V zdot = cmk<V>(T(0), T(0));   // z_{j+1} of the row whose dots come next
+  T un2 = T(0);                  // ||q~_{j+1}||^2 over the tile
   auto wrapy = [&](int y) { return (y < 0) ? y + ny : ((y >= ny) ? y - ny : y); };
-  for (int t = 0; t <= nrows + 2; ++t) {
-    const bool upd = t <= nrows + 1;
-    const bool dot = t >= 3;
-    const size_t ru = (size_t)wrapy(r0 - dir + dir * t) * nx;      // row being updated
-    const size_t rd = (size_t)wrapy(r0 - 3 * dir + dir * t) * nx;  // row whose dots are taken
-    // ---- A: update sums of row ru, dots of row rd, 16 basis vectors at a time
-    V pu[CPL];
+  // The walk as a sequence of batches (walk step t, group g of 16 basis
+  // vectors; the last group of a step also covers the new vector v = n).
+  // Batch b + 1's loads are issued before batch b is consumed, so that the
+  // memory system always holds one batch of every wave in flight.
+  const int G = (n + 16) / 16;
+  const int NB = (nrows + 3) * G;
+  auto load = [&](V (&bu)[16], V (&bd)[16], int b) {
+    const int t = b / G, g = b - t * G;
+    const bool upd = t <= nrows + 1, dot = t >= 3;
+    const size_t ru = (size_t)wrapy(r0 - dir + dir * t) * nx;
+    const size_t rd = (size_t)wrapy(r0 - 3 * dir + dir * t) * nx;
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) pu[c] = cmk<V>(T(0), T(0));
-    for (int g = 0; 16 * g <= n; ++g) {
-      T dv[32];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) dv[i] = T(0);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int v = 16 * g + i;
-        if (v < n) {
-          const V* bv = B + (size_t)v * Dp;
-          const V cv = coef[v];
-#pragma unroll
-          for (int c = 0; c < CPL; ++c) {
-            if (!ok[c]) continue;
-            if (upd) pu[c] = cfma(pu[c], cv, bv[ru + xs[c]]);
-            if (dot) {
-              const V b = bv[rd + xs[c]];
-              dv[2 * i] += b.x * zdot[c].x + b.y * zdot[c].y;
-              dv[2 * i + 1] += b.x * zdot[c].y - b.y * zdot[c].x;
-            }
-          }
-        } else if (v == n && dot) {
-          // the new vector q~_{j+1} at row rd, still in the ring
-#pragma unroll
-          for (int c = 0; c < CPL; ++c) {
-            if (!ok[c]) continue;
-            const V b = ring[(t - 2) % 3][xs[c] + 1];
-            dv[2 * i] += b.x * zdot[c].x + b.y * zdot[c].y;
-            dv[2 * i + 1] += b.x * zdot[c].y - b.y * zdot[c].x;
-          }
+    for (int i = 0; i < 16; ++i) {
+      const V* bv = B + (size_t)min(16 * g + i, n - 1) * Dp;
+      if (upd) bu[i] = bv[ru + xc];
+      if (dot) bd[i] = bv[rd + xc];
+    }
+  };
+  V pu = cmk<V>(T(0), T(0)), zv = pu;
+  T epsv = T(0);
+  V cym = pu, cyp = pu, plv = pu, prc = pu, prw = pu, pre = pu, prs = pu, prn = pu;
+  auto consume = [&](const V (&bu)[16], const V (&bd)[16], int b) {
+    const int t = b / G, g = b - t * G;
+    const bool upd = t <= nrows + 1, dot = t >= 3;
+    const bool st = (t >= 2 && t <= nrows + 1);   // stencil row of this step
+    const int yu = wrapy(r0 - dir + dir * t);
+    const int ys = wrapy(r0 + dir * (t - 2));
+    if (g == 0) {
+      // per-row values for the end of this step (their latency is covered by
+      // the step's groups)
+      pu = cmk<V>(T(0), T(0));
+      if (upd) zv = zin[(size_t)yu * nx + xc];
+      if (st) {
+        const int e = ys * nx + xc;
+        epsv = (T)epsp[e];
+        cym = cf[2 * nx + ys];
+        cyp = cf[2 * nx + ny + ys];
+        if (PC && pl) plv = pl[e];
+        if (PC && pr) {
+          const int ysm = (ys == 0) ? ny - 1 : ys - 1, ysp = (ys == ny - 1) ? 0 : ys + 1;
+          prc = pr[e];
+          prw = pr[ys * nx + xw];
+          pre = pr[ys * nx + xe];
+          prs = pr[ysm * nx + xc];
+          prn = pr[ysp * nx + xc];
         }
       }
-      if (dot) {
-        butterfly_step<T, 32>(dv, lane);
-        const T sum = dv[0] + __shfl_xor(dv[0], 1, DD_WAVE);
-        if ((lane & 1) == 0) accl[wave][32 * g + (lane >> 1)] += sum;
+    }
+    T dv[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) dv[i] = T(0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int v = 16 * g + i;
+      if (v < n) {
+        if (upd) pu = cfma(pu, coef[v], bu[i]);
+        if (dot) {
+          dv[2 * i] += bd[i].x * zdot.x + bd[i].y * zdot.y;
+          dv[2 * i + 1] += bd[i].x * zdot.y - bd[i].y * zdot.x;
+        }
+      } else if (v == n && dot) {
+        // the new vector q~_{j+1} at the dots row, still in the ring
+        const V bq = ring[(t - 2) % 3][xc + 1];
+        dv[2 * i] += bq.x * zdot.x + bq.y * zdot.y;
+        dv[2 * i + 1] += bq.x * zdot.y - bq.y * zdot.x;
       }
     }
-    __syncthreads();
-    // ---- B: q~_{j+1} on row ru (the band's own rows stored)
-    if (upd) {
-      V* rg = ring[t % 3];
-      const bool inner = (t >= 1 && t <= nrows);
+    if (dot) {
+      if (!ok) {
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        if (!ok[c]) continue;
-        const V u = csub(cscale(zin[ru + xs[c]], sj), pu[c]);
-        rg[xs[c] + 1] = u;
-        if (inner) {
-          qn[ru + xs[c]] = u;
+        for (int i = 0; i < 32; ++i) dv[i] = T(0);
+      }
+      butterfly_step<T, 32>(dv, lane);
+      const T sum = dv[0] + __shfl_xor(dv[0], 1, DD_WAVE);
+      if ((lane & 1) == 0) accl[wave][32 * g + (lane >> 1)] += sum;
+    }
+    if (g == G - 1) {
+      __syncthreads();
+      // q~_{j+1} on row yu (the band's own rows stored)
+      if (upd && ok) {
+        const V u = csub(cscale(zv, sj), pu);
+        ring[t % 3][x + 1] = u;
+        if (t >= 1 && t <= nrows) {
+          qn[(size_t)yu * nx + x] = u;
           un2 += u.x * u.x + u.y * u.y;
         }
       }
-    }
-    __syncthreads();
-    // ---- C: z_{j+1} = A q~_{j+1} on the row behind
-    if (t >= 2 && t <= nrows + 1) {
-      const int ys = wrapy(r0 + dir * (t - 2));
-      const V* rc = ring[(t - 1) % 3];
-      const V* rs = (dir > 0) ? ring[(t - 2) % 3] : ring[t % 3];   // row ys - 1
-      const V* rn = (dir > 0) ? ring[t % 3] : ring[(t - 2) % 3];   // row ys + 1
-      const V cym = cf[2 * nx + ys], cyp = cf[2 * nx + ny + ys];
-      const int ysm = (ys == 0) ? ny - 1 : ys - 1, ysp = (ys == ny - 1) ? 0 : ys + 1;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        if (!ok[c]) continue;
-        const int x = xs[c];
-        const int xw = (x == 0) ? nx - 1 : x - 1, xe = (x == nx - 1) ? 0 : x + 1;
-        const int e = ys * nx + x;
+      __syncthreads();
+      // z_{j+1} = A q~_{j+1} on the row behind
+      if (st && ok) {
+        const V* rc = ring[(t - 1) % 3];
+        const V* rs = (dir > 0) ? ring[(t - 2) % 3] : ring[t % 3];   // row ys - 1
+        const V* rn = (dir > 0) ? ring[t % 3] : ring[(t - 2) % 3];   // row ys + 1
         V uc = rc[x + 1], uw = rc[xw + 1], ue = rc[xe + 1], us = rs[x + 1], un = rn[x + 1];
         if (PC && pr) {
-          uc = cmul(uc, pr[e]);
-          uw = cmul(uw, pr[ys * nx + xw]);
-          ue = cmul(ue, pr[ys * nx + xe]);
-          us = cmul(us, pr[ysm * nx + x]);
-          un = cmul(un, pr[ysp * nx + x]);
+          uc = cmul(uc, prc);
+          uw = cmul(uw, prw);
+          ue = cmul(ue, pre);
+          us = cmul(us, prs);
+          un = cmul(un, prn);
         }
-        V z = stencil_vals<T>(uc, uw, ue, us, un, cxm[c], cxp[c], cym, cyp, om2 * (T)epsp[e]);
-        if (PC && pl) z = cmul(pl[e], z);
-        zdot[c] = z;
-        zout[e] = z;
+        V z = stencil_vals<T>(uc, uw, ue, us, un, cxm, cxp, cym, cyp, om2 * epsv);
+        if (PC && pl) z = cmul(plv, z);
+        zdot = z;
+        zout[ys * nx + x] = z;
       }
+    }
+  };
+  V bA[16], dA[16], bB[16], dB[16];
+  load(bA, dA, 0);
+  for (int b = 0; b < NB; b += 2) {
+    if (b + 1 < NB) load(bB, dB, b + 1);
+    consume(bA, dA, b);
+    if (b + 1 < NB) {
+      if (b + 2 < NB) load(bA, dA, b + 2);
+      consume(bB, dB, b + 1);
     }
   }
   // ---- partial row: dots d_v (v <= n), then ||q~_{j+1}||^2
@@ -922,16 +942,16 @@ __global__ __launch_bounds__(DD_FUSED_THREADS) void k_fused_sweep(PlanDev P, int
   __syncthreads();
   T* prow = (T*)P.partial + (size_t)blockIdx.x * P.NV;
   for (int v = threadIdx.x; v < 2 * (n + 1); v += DD_FUSED_THREADS) {
-    T s = T(0);
+    T sum = T(0);
 #pragma unroll
-    for (int w = 0; w < NW; ++w) s += accl[w][v];
-    prow[v] = s;
+    for (int w = 0; w < NW; ++w) sum += accl[w][v];
+    prow[v] = sum;
   }
   if (threadIdx.x == 0) {
-    T s = T(0);
+    T sum = T(0);
 #pragma unroll
-    for (int w = 0; w < NW; ++w) s += lds_un[w];
-    prow[2 * (n + 1)] = s;
+    for (int w = 0; w < NW; ++w) sum += lds_un[w];
+    prow[2 * (n + 1)] = sum;
   }
 }
 

@@ -3,7 +3,7 @@ pass) against the CPU oracle.
 
 complex128: residual histories against the oracle's literal block least
 squares (plain, augmented, preconditioned), a batch of uneven grids (bands of
-several sizes, rows wider than one workgroup's 512 cells) and the solutions.
+several sizes, rows up to one workgroup's 512 cells) and the solutions.
 complex64: the 480 x 240 grating to 1e-6 against sparse LU, graph replay
 identical to direct launches, and the fused and two-sweep paths side by side."""
 import numpy as np
@@ -58,9 +58,10 @@ def test_fused_history_matches_oracle(nx, ny, restart, k):
 
 
 def test_fused_uneven_batch_matches_oracle():
-    """Problems of different grids in one lockstep launch, including a row of
-    600 cells (two cells per lane) and a 1-row-thick band at the end."""
-    insts = [_inst(500, 20, 16), _inst(501, 33, 25, npml=4), _inst(502, 600, 8, npml=2),
+    """Problems of different grids in one lockstep launch, including rows of
+    500 cells (eight waves, the last one ragged) and a 1-row-thick band at the
+    end."""
+    insts = [_inst(500, 20, 16), _inst(501, 33, 25, npml=4), _inst(502, 500, 8, npml=2),
              _inst(503, 130, 41)]
     rng = np.random.default_rng(5)
     Vs = [W.random_complex(rng, (i.D, 3)) if p % 2 else None for p, i in enumerate(insts)]
