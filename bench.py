@@ -70,7 +70,7 @@ def first_below(h, thr):
     return int(idx[0]) + 1 if len(idx) else None
 
 
-def arnoldi_bytes(D, iters, m, k, passes=1, fused=True):
+def arnoldi_bytes(D, iters, m, k, passes=1, fused=False):
     """Algorithmic HBM bytes of `iters` complex64 Arnoldi steps with restart m
     and k augmenting vectors.  One sweep per step (fused, one Gram-Schmidt
     pass): step j reads the k+j+1 basis vectors and A q_j, writes q_{j+1} and
@@ -123,8 +123,14 @@ def make_instances(seeds, workers):
         parts = [_grating_parts(s) for s in seeds]
     else:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
+        # close + join lets the workers exit normally (a pool's context exit
+        # terminates them with SIGTERM, which profilers' signal handlers catch)
+        pool = mp.get_context("fork").Pool(workers)
+        try:
             parts = pool.map(_grating_parts, seeds, chunksize=16)
+        finally:
+            pool.close()
+            pool.join()
     out = []
     for eps, col, name in parts:
         ny, nx = eps.shape

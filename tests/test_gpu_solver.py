@@ -228,21 +228,27 @@ def test_edge_cases():
 
 
 def test_grating_c64_refined_to_tol():
-    """480x240 grating, complex64 inner iteration, FP64 residual restarts, tol 1e-6:
-    the true FP64 residual meets tol and the solution matches a sparse LU solve."""
+    """480x240 grating (seed 1000), complex64 inner iteration, FP64 residual
+    restarts: at tol 1e-6 and refined on to tol 2e-7 the true FP64 residual
+    meets tol, and at 2e-7 the solution is within 1e-5 of a sparse LU solve.
+    The error bound ||x - x*|| / ||x*|| <= ||A^-1||_2 ||b|| / ||x*|| * tol is
+    about 39 tol on this instance (||A^-1||_2 from a few inverse power steps
+    on A^H A with the LU factors), so 2e-7 is the tolerance that guarantees
+    1e-5."""
     inst = W.grating(1000)
     A = fdfd.assemble_instance(inst)
-    s = _solver([_op(inst)], restart=100, inner="c64")
-    (x,), (info,), st = s.solve([_b(inst)], tol=1e-6, maxit=60000)
-    x = x.cpu().numpy()
-    rr = np.linalg.norm(inst.b - A @ x) / np.linalg.norm(inst.b)
-    print("grating c64:", info, "true", rr)
-    assert st == 0 and rr <= 1e-6
-    assert abs(rr - info["rel_res_true"]) <= 1e-3 * rr
     xs = direct.sparse_solve(A, inst.b)
-    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
-    print("error vs splu", err)
-    assert err < 1e-3
+    s = _solver([_op(inst)], restart=100, inner="c64")
+    for tol, err_max in ((1e-6, 1e-4), (2e-7, 1e-5)):
+        (x,), (info,), st = s.solve([_b(inst)], tol=tol, maxit=60000)
+        x = x.cpu().numpy()
+        rr = np.linalg.norm(inst.b - A @ x) / np.linalg.norm(inst.b)
+        err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+        print(f"grating c64 tol {tol}: iters {info['iters']}, true rel res {rr:.3e}, "
+              f"error vs splu {err:.3e}")
+        assert st == 0 and rr <= tol
+        assert abs(rr - info["rel_res_true"]) <= 1e-3 * rr
+        assert err <= err_max
 
 
 def test_graph_replay_matches_direct_launches():
