@@ -47,9 +47,21 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the dominant sweep from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE, calibrated on a 1 GiB device copy) over this
-# workload; valid only for the kernel sources and batch they were taken with.
-MEASURED_TRAFFIC = {"bytes_per_launch": {}, "batch": None, "k": None,
-                    "sources_sha256_16": None}
+# workload, as recorded in the profile summary beside the commands that took
+# them; valid only for the kernel sources and batch they were taken with.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_matvec_dot_pca_c4_480x240_b25.md")
+
+
+def measured_traffic():
+    import json
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                if line.startswith("traffic-record:"):
+                    return json.loads(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return None
 
 
 def kernel_sources_hash():
@@ -834,18 +846,24 @@ def main():
     kname = {"matvec_dots": "k_matvec_dot", "second_pass": "k_update_dot",
              "update_norm": "k_update_norm", "fused_sweep": "k_fused_sweep"}[name]
     traffic = None
-    if (kname in MEASURED_TRAFFIC["bytes_per_launch"] and args.batch == MEASURED_TRAFFIC["batch"]
-            and args.k == MEASURED_TRAFFIC["k"] and args.cgs == 1
-            and kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]):
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"][kname]
+    rec = measured_traffic()
+    if (rec is not None and rec["kernel"] == kname and args.batch == rec["batch"]
+            and args.k == rec["k"] and args.cgs == 1
+            and kernel_sources_hash() == rec["sources_sha256_16"]):
+        traffic = rec["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_workload": None if traffic is None else
+                {"run": rec["workload"],
+                 "algorithmic_bytes_per_launch": rec["algorithmic_bytes_per_launch"],
+                 "ratio": round(traffic / rec["algorithmic_bytes_per_launch"], 3)},
                 "kernel": kname,
                 "avg_launch_us": round(1000 * ms_k / max(1, launches_k), 2),
                 "launches": int(launches_k),
                 "algorithmic_bytes_per_launch": round(bytes_k / max(1, launches_k))}
     sweeps = {n: {"ms": round(v[0], 2), "launches": int(v[1]),
-                  "GB_per_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+                  "GB_per_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None,
+                  "algorithmic_bytes_per_launch": round(v[2] / v[1]) if v[1] else None}
               for n, v in ks.items()}
 
     # ---------------- CPU baseline: the oracle's augmented GMRES, bounded sample
