@@ -15,4 +15,5 @@ Modules
   losses    -- projection and residual losses
   cnn       -- float64 convolutional predictor: forward, backward, Adam
   eim       -- effective-index approximation of the field (the CNN's second input)
+  recycle   -- harmonic Ritz vectors of a solve's last cycle carried to the next system
 """
