@@ -417,36 +417,54 @@ def precond_leg(args, torch, ops, bs, U):
     return out
 
 
-def recycle_leg(args, torch, data):
-    """Design steps 0..N-1 of every benchmark trajectory, one lockstep batch per
-    step: augmented by the fields of the previous steps of the same trajectory,
-    against plain GMRES on the same schedule."""
+def recycle_leg(args, torch, W):
+    """Trajectory recycling on the correlated batch (8 trajectories of uneven
+    grids 192x96 / 320x160 / 480x240 and wavelengths 1.30 / 1.55 um, design
+    steps 0..N-1), one lockstep batch per step: plain GMRES, augmentation by
+    the fields of the previous steps, by the harmonic Ritz vectors of the
+    previous step's last cycle, and by both."""
     from paper_1902_00090_amd.recycle import solve_trajectories
     S = args.traj_steps
-    trajs = [data[t * S:t * S + args.recycle] for t in range(args.traj)]
+    flat = W.correlated_batch(args.traj, S)
+    trajs = [flat[t * S:t * S + args.recycle] for t in range(args.traj)]
+    modes = {"plain": dict(recycle=False, ritz=0),
+             "solutions": dict(recycle=True, ritz=0),
+             "harmonic_ritz": dict(recycle=False, ritz=args.recycle_ritz),
+             "solutions+harmonic_ritz": dict(recycle=True, ritz=args.recycle_ritz)}
     out = {}
-    for mode in ("recycled", "plain"):
+    refs = None
+    for mode, kw in modes.items():
         torch.cuda.synchronize()
         t0 = time.time()
-        _, inf, hist = solve_trajectories(trajs, window=args.recycle_window, tol=args.tol,
-                                          restart=args.restart, maxit=args.maxit,
-                                          cgs_passes=args.cgs, recycle=(mode == "recycled"),
-                                          hist_cap=args.maxit)
+        xs, inf, hist, _ = solve_trajectories(trajs, window=args.recycle_window, tol=args.tol,
+                                              restart=args.restart, maxit=args.maxit,
+                                              cgs_passes=args.cgs, hist_cap=args.maxit, **kw)
         torch.cuda.synchronize()
         dt = time.time() - t0
         later = [(t, s) for t in range(len(trajs)) for s in range(1, args.recycle)]
+        allp = [(t, s) for t in range(len(trajs)) for s in range(args.recycle)]
+        if refs is None:
+            # errors against the oracle's sparse LU on the last step of two trajectories
+            refs = {(t, args.recycle - 1): oracle_reference(trajs[t][-1]) for t in (0, 2)}
         out[mode] = {
             "seconds": round(dt, 2),
-            "solves_per_s": round(len(trajs) * args.recycle / dt, 4),
+            "solves_per_s": round(len(allp) / dt, 4),
+            "iters_total": int(sum(inf[t][s]["iters"] for t, s in allp)),
             "iters_mean_steps_ge_1": float(np.mean([inf[t][s]["iters"] for t, s in later])),
+            "iters_to_1e-6_mean_steps_ge_1": float(np.mean(
+                [first_below(hist[t][s], 1e-6) or np.nan for t, s in later])),
             "rel_res_after_1_iter_mean_steps_ge_1": float(np.mean([hist[t][s][0] for t, s in later])),
             "iters_to_0.04_mean_steps_ge_1": float(np.mean(
                 [first_below(hist[t][s], 0.04) or np.nan for t, s in later])),
             "all_converged": all(i["status"] == 0 for row in inf for i in row),
+            "error_vs_sparse_lu": {f"traj{t}_step{s}": rel_err(xs[t][s].cpu().numpy(), r["x"])
+                                   for (t, s), r in refs.items()},
         }
         log(f"trajectory {mode}: {dt:.1f}s, {out[mode]}")
     out["steps"] = args.recycle
+    out["trajectories"] = len(trajs)
     out["window"] = args.recycle_window
+    out["ritz"] = args.recycle_ritz
     return out
 
 
@@ -646,6 +664,8 @@ def main():
     ap.add_argument("--uneven", action="store_true", help="also run the uneven correlated batch")
     ap.add_argument("--recycle", type=int, default=0)
     ap.add_argument("--recycle-window", type=int, default=5)
+    ap.add_argument("--recycle-ritz", type=int, default=10,
+                    help="harmonic Ritz vectors carried from step to step")
     ap.add_argument("--precond", action="store_true")
     ap.add_argument("--cnn-kernels", type=int, default=0)
     ap.add_argument("--calibrate-copy", type=int, default=0)
@@ -815,7 +835,7 @@ def main():
 
     # ---------------- optional legs
     cnn = pre = rec = uneven = None
-    if args.cnn or args.precond or args.recycle > 0:
+    if args.cnn or args.precond:
         data = W.trajectory_dataset(args.traj, args.traj_steps)
         tr_idx, te_idx = W.split_train_test(len(data))
         ctrain = [data[i] for i in tr_idx]
@@ -834,8 +854,8 @@ def main():
             del Smat
         if args.precond:
             pre = precond_leg(args, torch, cops, cbs, U)
-        if args.recycle > 0:
-            rec = recycle_leg(args, torch, data)
+    if args.recycle > 0:
+        rec = recycle_leg(args, torch, W)
     if args.uneven:
         uneven = uneven_leg(args, torch, W)
 

@@ -212,6 +212,49 @@ dd_status dd_solver_solve(dd_solver* s, const void* const* b, const void* const*
  * *n receives the number of entries written. */
 dd_status dd_solver_history(const dd_solver* s, int p, double* out, int cap, int* n);
 
+/* Subspace recycling along a sequence of related systems (Sec. 1: Krylov
+ * information from earlier solves of related systems carried into the next
+ * solve; supplement Sec. 1: GCROT keeps a few correction directions from
+ * one cycle to the next).  After dd_solver_solve, for every problem p: the
+ * search space of its last cycle is S = [U, Q_n] (U = V R^{-1}, the
+ * augmenting directions with A U = C; Q_n the cycle's Arnoldi vectors), and
+ * A S = W G with W = [C, Q_{n+1}] orthonormal and G = [[I, B], [0, H]] (the
+ * matrix of eq:final_lsq).  The harmonic Ritz pairs (theta, y = S u), with
+ * A y - theta y orthogonal to A S, solve G^H G u = theta G^H (W^H S) u; the
+ * kout[p] = min(kr, dim S) of smallest |theta| are written to Y[p] as
+ * [kout[p]][D] row-major complex vectors in the solver's inner precision
+ * (complex64 or complex128), each scaled so that ||A y|| = 1, for
+ * dd_solver_set_subspace of the next system (only their span matters).
+ *   Y:     nb device pointers, caller-owned, room for kr vectors each;
+ *          left untouched where kout[p] = 0 (no cycle ran and no subspace).
+ *   kout:  host [nb], the number of vectors written per problem.
+ *   theta: optional host [nb][kr] complex doubles (re, im interleaved): the
+ *          harmonic Ritz values, infinite for a zero eigenvalue; zero past
+ *          kout[p].
+ * The device forms W^H V over the field and Y = S Z; the small eigenproblem
+ * (Householder least squares, Hessenberg QR to Schur form, reordering) runs
+ * on the host in FP64, one host thread per problem up to 16.  Allocates
+ * device scratch of about 16 (kmax + restart + 1) kmax + 16 kr (kmax +
+ * restart) bytes per problem and frees it; synchronises the stream.
+ * Errors: DD_EINVAL (kr outside 1..64, NULL arguments, the fused one-sweep
+ * path or a preconditioner in use, or no solve since the last set_subspace,
+ * bind or solve error), DD_ENONFINITE (a rank-deficient small problem or
+ * no Schur convergence), DD_ENOMEM / DD_EHIP. */
+dd_status dd_solver_recycle(dd_solver* s, int kr, void* const* Y, int* kout, double* theta,
+                            hipStream_t stream);
+
+/* Host only: the small eigenproblem of dd_solver_recycle on its own.  G and
+ * M = W^H S are nw x ns complex matrices (row-major, re/im interleaved) with
+ * A S = W G, W orthonormal, G of full column rank, ns <= nw.  Writes to Z
+ * (ns x kr, row-major complex) an orthonormal basis of the invariant
+ * subspace of G^+ M for its kr eigenvalues of largest magnitude (the
+ * harmonic Ritz values of smallest magnitude), columns scaled so that
+ * ||G z|| = 1, and to theta (kr complex) those harmonic Ritz values in
+ * increasing magnitude.  Errors: DD_EINVAL (sizes), DD_ENONFINITE (rank
+ * deficiency, no convergence). */
+dd_status dd_harmonic_ritz_host(int ns, int nw, const double* G, const double* M, int kr,
+                                double* Z, double* theta);
+
 /* Test introspection: copy an internal array of problem p to host memory.
  * what: 0 = C [k][D] (inner precision), 1 = Q [m+1][D] (after a full cycle the
  * last slot holds the new Arnoldi vector before normalisation, of norm

@@ -280,6 +280,25 @@ class Solver:
         """Turn on live HIP-event timing of the streaming sweeps (resets stats)."""
         check(_lib.lib().dd_solver_profile(self._h, int(bool(enable))), "dd_solver_profile")
 
+    def recycle(self, kr):
+        """Harmonic Ritz vectors of each problem's last cycle (subspace
+        recycling, Sec. 1; supplement Sec. 1): returns (Y, theta) with Y a
+        list of [kout_p, D] tensors in the inner precision (for set_subspace
+        of the next system) and theta an [nb, kr] complex array of their
+        harmonic Ritz values (zero past kout_p)."""
+        torch = _torch()
+        if not 1 <= int(kr) <= 64:
+            raise ValueError(f"kr = {kr} outside 1..64")
+        kr = int(kr)
+        dt = torch.complex64 if self.inner == "c64" else torch.complex128
+        Y = [torch.empty((kr, op.D), dtype=dt, device="cuda") for op in self.ops]
+        kout = (C.c_int * self.nb)()
+        th = np.zeros((self.nb, kr, 2), np.float64)
+        check(_lib.lib().dd_solver_recycle(self._h, kr, ptr_array([y.data_ptr() for y in Y]), kout,
+                                           th.ctypes.data_as(C.POINTER(C.c_double)), _stream()),
+              "dd_solver_recycle")
+        return [Y[p][:kout[p]] for p in range(self.nb)], th[..., 0] + 1j * th[..., 1]
+
     def kernel_stats(self):
         """{'matvec_dots'|'second_pass'|'update_norm'|'fused_sweep': (ms, launches, bytes)}."""
         ks = _lib.dd_kernel_stats()
@@ -493,3 +512,20 @@ class Predictor:
 
 
 from .cnn import Cnn  # noqa: E402
+
+
+def harmonic_ritz_host(G, M, kr):
+    """The host-side small eigenproblem of Solver.recycle: G, M are nw x ns
+    complex arrays (A S = W G, M = W^H S); returns (Z [ns, kr], theta [kr])."""
+    G = np.ascontiguousarray(G, np.complex128)
+    M = np.ascontiguousarray(M, np.complex128)
+    nw, ns = G.shape
+    if M.shape != G.shape:
+        raise ValueError("G and M must have the same shape")
+    Z = np.zeros((ns, kr), np.complex128)
+    th = np.zeros(kr, np.complex128)
+    dp = C.POINTER(C.c_double)
+    check(_lib.lib().dd_harmonic_ritz_host(ns, nw, G.ctypes.data_as(dp), M.ctypes.data_as(dp),
+                                           int(kr), Z.ctypes.data_as(dp), th.ctypes.data_as(dp)),
+          "dd_harmonic_ritz_host")
+    return Z, th

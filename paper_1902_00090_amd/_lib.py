@@ -71,6 +71,8 @@ _SIGS = {
     "dd_solver_set_subspace": (I, [P, PP, C.POINTER(I), P]),
     "dd_solver_solve": (I, [P, PP, PP, D, I, PP, C.POINTER(dd_info), P]),
     "dd_solver_history": (I, [P, I, C.POINTER(D), I, C.POINTER(I)]),
+    "dd_solver_recycle": (I, [P, I, PP, C.POINTER(I), C.POINTER(D), P]),
+    "dd_harmonic_ritz_host": (I, [I, I, C.POINTER(D), C.POINTER(D), I, C.POINTER(D), C.POINTER(D)]),
     "dd_solver_debug_copy": (I, [P, I, I, P, C.c_size_t]),
     "dd_solver_device_bytes": (C.c_size_t, [P]),
     "dd_solver_profile": (I, [P, I]),

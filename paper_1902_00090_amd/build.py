@@ -16,7 +16,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libddgmres.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["op.hip", "solver.hip", "pca.hip", "cnn.hip", "eim.hip", "resloss.hip", "predictor.hip"]
+SOURCES = ["op.hip", "solver.hip", "pca.hip", "cnn.hip", "eim.hip", "resloss.hip", "predictor.hip",
+           "recycle.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wextra",

@@ -7,51 +7,8 @@
 #include <vector>
 
 #include "solver_kernels.h"
+#include "solver_state.h"
 
-struct dd_solver {
-  int nb = 0;
-  dd_solver_opts o{};
-  int R = 1;          // field elements per thread
-  int nchunks = 0;
-  int ncu = 1;        // compute units of the device
-  std::vector<const fdfd_op*> ops;
-  std::vector<ProbDesc> hdesc;
-  std::vector<int> ksetup;  // augmenting columns given per problem
-  ProbDesc* ddesc = nullptr;
-  int* blk2prob = nullptr;
-  const void** dU = nullptr;  // device array of nb pointers for set_subspace
-  PlanDev P{};
-  std::vector<void*> allocs;
-  size_t bytes = 0;       // device workspace of the solver (owned or the caller's)
-  bool owns_workspace = true;
-  // fused Arnoldi sweep: on when cgs_passes = 1 and kmax + m + 1 <= 128
-  bool fused = false;
-  std::vector<FusedTile> htiles;
-  FusedTile* dtiles = nullptr;
-  int* pinned = nullptr;     // 2 status snapshots + 1 final
-  double* pinnedD = nullptr;
-  unsigned long long* pinnedK = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  bool has_subspace = false;
-  // live kernel timing (dd_solver_profile): event pairs around the three
-  // streaming sweeps of every Arnoldi step, read back at each host sync
-  bool prof = false;
-  std::vector<hipEvent_t> pev;
-  std::vector<int> pkind;
-  int pused = 0;
-  dd_kernel_stats ks{};
-  // solve controls (pinned host staging, device copy)
-  double* hctl = nullptr;
-  double* dctl = nullptr;
-  // HIP graphs of groups of check_every Arnoldi steps, captured on a private
-  // stream on first use and replayed on the caller's stream
-  hipStream_t cap = nullptr;
-  std::vector<hipGraph_t> graphs;
-  std::vector<hipGraphExec_t> execs;
-  // diagonal preconditioner buffers per problem (FP64 and FP32 copies)
-  struct PcBuf { double2 *pl64, *pr64; float2 *pl32, *pr32; };
-  std::vector<PcBuf> pcbuf;
-};
 
 // Fill the preconditioner arrays of every problem from its bound operator.
 static hipError_t precond_init(dd_solver* s) {
@@ -444,6 +401,7 @@ extern "C" dd_status dd_solver_bind(dd_solver* s, const fdfd_op* const* ops) {
     s->ksetup[p] = 0;
   }
   s->has_subspace = false;
+  s->cycle_valid = false;
   DD_HIP_CHECK(hipMemcpy(s->ddesc, s->hdesc.data(), sizeof(ProbDesc) * s->nb, hipMemcpyHostToDevice));
   DD_HIP_CHECK(precond_init(s));
   return DD_OK;
@@ -499,6 +457,7 @@ extern "C" dd_status dd_solver_set_subspace(dd_solver* s, const void* const* U, 
   // the host arrays above are pageable: finish the copies before they go away
   DD_HIP_CHECK(hipStreamSynchronize(stream));
   s->has_subspace = any;
+  s->cycle_valid = false;
   return DD_OK;
 }
 
@@ -714,8 +673,10 @@ extern "C" dd_status dd_solver_solve(dd_solver* s, const void* const* b, const v
   }
   k_init_state<<<(nb + 255) / 256, 256, 0, stream>>>(s->P);
   DD_HIP_CHECK(hipGetLastError());
+  s->cycle_valid = false;
   dd_status rc = (s->o.inner == DD_C64) ? run_cycles_T<float>(s, stream) : run_cycles_T<double>(s, stream);
   if (rc != DD_OK) return rc;
+  s->cycle_valid = true;
   int* fin = s->pinned + 2 * nb * ST_NI;
   DD_HIP_CHECK(hipMemcpyAsync(fin, s->P.stI, sizeof(int) * nb * ST_NI, hipMemcpyDeviceToHost, stream));
   DD_HIP_CHECK(hipMemcpyAsync(s->pinnedD, s->P.stD, sizeof(double) * nb * SD_ND, hipMemcpyDeviceToHost, stream));

@@ -135,3 +135,47 @@ def test_predictor_files_are_checked_on_the_host(tmp_path):
     n = C.c_size_t(7)
     assert lib.dd_solver_workspace_bytes(None, 1, None, C.byref(n)) == _lib.DD_EINVAL
     assert n.value == 0
+
+
+@pytest.mark.parametrize("kr", [1, 4, 9])
+def test_recycling_small_problem_matches_the_oracle(kr):
+    """The host half of subspace recycling (Sec. 1; supplement Sec. 1) on the
+    oracle's record of a restarted augmented solve: G = [[I, B], [0, H]] and
+    M = W^H S from the last cycle give the same harmonic Ritz values and
+    the same span S Z as the oracle's dense generalized eigenproblem, with
+    ||A y|| = 1 for every returned column."""
+    import workloads as W
+    from oracle import fdfd, gmres_aug, recycle
+    from paper_1902_00090_amd import harmonic_ritz_host
+    rng = np.random.default_rng(kr)
+    nx, ny = 10, 8
+    eps = (2.085 + 10.165 * (rng.random((ny, nx)) < 0.5)).astype(np.float32)
+    inst = W.Instance(eps, W.random_complex(rng, nx * ny), nx, ny, 0.04, 1.55, 2)
+    A = fdfd.assemble_instance(inst)
+    V = W.random_complex(rng, (inst.D, 3))
+    _, info = gmres_aug.gmres_aug(A, inst.b, V, restart=12, tol=1e-10, maxit=200, record=True)
+    S = recycle.last_cycle_space(V, info)
+    k, n = 3, info["Q"].shape[1] - 1
+    G = np.zeros((k + n + 1, k + n), np.complex128)
+    G[:k, :k] = np.eye(k)
+    G[:k, k:] = info["B"]
+    G[k:, k:] = info["H"]
+    Wb = np.concatenate([info["C"], info["Q"]], axis=1)
+    M = Wb.conj().T @ S
+    Z, th = harmonic_ritz_host(G, M, kr)
+    to, Yo = recycle.harmonic_ritz(A, S, kr)
+    np.testing.assert_allclose(th, to, rtol=1e-9)
+    Y = S @ Z
+    np.testing.assert_allclose(np.linalg.norm(A @ Y, axis=0), 1.0, rtol=1e-9)
+    Qo, _ = np.linalg.qr(Yo)
+    Ql, _ = np.linalg.qr(Y)
+    assert np.linalg.norm(Ql - Qo @ (Qo.conj().T @ Ql)) <= 1e-8
+
+
+def test_recycling_small_problem_rejects_bad_sizes():
+    from paper_1902_00090_amd import DDError, harmonic_ritz_host
+    G = np.eye(4, 3, dtype=np.complex128)
+    with pytest.raises(DDError):
+        harmonic_ritz_host(G, G, 4)           # kr > ns
+    with pytest.raises(DDError):
+        harmonic_ritz_host(np.zeros((4, 3), np.complex128), G, 2)   # rank-deficient G
