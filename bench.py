@@ -504,6 +504,205 @@ def uneven_leg(args, torch, W):
     return out
 
 
+def _traj_parts(t, steps):
+    """(eps, source column) of every step of CNN training trajectory t (seeds
+    40,000 + t for the design, 400,000 + 100 t + s for the steps)."""
+    import workloads as W
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        tr = W.trajectory(W.CNN_TRAJ_SEED0 + t, W.CNN_STEP_SEED0 + 100 * t, steps, 480, 240, 1.30)
+    out = []
+    for inst in tr:
+        b = inst.b.reshape(inst.ny, inst.nx)
+        out.append((inst.eps, b[:, SRC_IX].copy()))
+    return out
+
+
+def c5_leg(args, torch, W):
+    """The CNN predictor at its stated scale: 313 design trajectories of 32
+    steps (10,016 samples) solved by the library's GPU solver (each step
+    augmented by the trajectory's previous solutions, to a relative residual
+    of args.c5_train_tol), local-PCA targets (k = 10, window 8), 10,000 Adam
+    steps at batch 32 on the permittivity alone (1 input plane), the network
+    saved with its Adam state; then inference on 256 fresh gratings (seeds
+    50,000 + i) and CNN-augmented GMRES against plain and PCA-augmented GMRES
+    (k = 20 components of 2000 of the training fields) on the same batches."""
+    import multiprocessing as mp
+    from paper_1902_00090_amd import (Cnn, DDError, FdfdOp, Solver, eim_field, local_pca_targets,
+                                      pca_build, proj_loss_batched)
+    from paper_1902_00090_amd.train import train_cnn
+    T, S, k, D = args.c5_traj, args.c5_steps, args.cnn_k, 480 * 240
+    N = T * S
+    omega = 2 * math.pi / 1.30
+    out = {"trajectories": T, "steps_per_trajectory": S, "samples": N, "k": k,
+           "window": args.cnn_window, "adam_steps": args.c5_adam, "batch": 32,
+           "input_planes": args.c5_inputs, "lr": args.c5_lr, "test_instances": args.c5_test}
+    net = None
+    if args.c5_load:
+        net = Cnn.load(args.c5_load, max_batch=32)
+        out["loaded"] = args.c5_load
+    else:
+        t0 = time.time()
+        workers = args.workers or min(16, len(os.sched_getaffinity(0)))
+        pool = mp.get_context("fork").Pool(workers)
+        try:
+            parts = pool.starmap(_traj_parts, [(t, S) for t in range(T)], chunksize=4)
+        finally:
+            pool.close()
+            pool.join()
+        eps_h = np.stack([e for tr in parts for e, _ in tr])            # [N, ny, nx]
+        cols = np.stack([c for tr in parts for _, c in tr])             # [N, ny]
+        del parts
+        log(f"C5 data: {N} trajectory steps generated in {time.time() - t0:.1f}s")
+        eps_d = torch.tensor(eps_h, device="cuda")
+        F = torch.empty((N, D), dtype=torch.complex64, device="cuda")
+        bmat = torch.zeros((T, 240, 480), dtype=torch.complex128, device="cuda")
+        t0 = time.time()
+        solver, its = None, []
+        w = args.recycle_window
+        for st in range(S):
+            rows = [t * S + st for t in range(T)]
+            ops = [FdfdOp(eps_h[r], omega, 0.025, 20) for r in rows]
+            bmat[:, :, SRC_IX] = torch.tensor(cols[rows], device="cuda")
+            bs = [bmat[t].reshape(-1) for t in range(T)]
+            if solver is None:
+                solver = Solver(ops, restart=args.restart, kmax=w, cgs_passes=1)
+            else:
+                solver.bind(ops)
+            if st > 0:
+                solver.set_subspace([F[t * S + max(0, st - w):t * S + st] for t in range(T)])
+            xs, infos, _ = solver.solve(bs, tol=args.c5_train_tol, maxit=args.maxit)
+            for t, x in enumerate(xs):
+                F[t * S + st] = x.to(torch.complex64)
+            its.extend(i["iters"] for i in infos)
+            del xs
+            log(f"  C5 training solves, step {st}: mean iters {np.mean([i['iters'] for i in infos]):.0f}, "
+                f"{time.time() - t0:.0f}s")
+        solver.close()
+        del bmat
+        t_solve = time.time() - t0
+        t0 = time.time()
+        targets = torch.empty((N, k, D), dtype=torch.complex64, device="cuda")
+        for t in range(T):
+            targets[t * S:(t + 1) * S] = local_pca_targets(F[t * S:(t + 1) * S].contiguous(),
+                                                           args.cnn_window, k)
+        targets.mul_(float(math.sqrt(D)))                  # unit RMS per pixel
+        torch.cuda.synchronize()
+        t_tgt = time.time() - t0
+        log(f"C5 targets: {t_tgt:.1f}s")
+        # PCA basis of 2000 of the training fields, for the comparison leg
+        sel = torch.as_tensor(np.random.default_rng(3).choice(N, size=min(2000, N), replace=False),
+                              device="cuda")
+        Upca, _ = pca_build(F.index_select(0, sel).contiguous(), args.k)
+        del F
+        eim_tr = None
+        if args.c5_inputs == 3:
+            t0 = time.time()
+            eim_tr = torch.empty((N, D), dtype=torch.complex64, device="cuda")
+            bq = torch.zeros((64, 240, 480), dtype=torch.complex128, device="cuda")
+            for c0 in range(0, N, 64):
+                rows = list(range(c0, min(N, c0 + 64)))
+                ops = [FdfdOp(eps_h[r], omega, 0.025, 20) for r in rows]
+                bq.zero_()
+                bq[:len(rows), :, SRC_IX] = torch.tensor(cols[rows], device="cuda")
+                eim_field(ops, [bq[j].reshape(-1) for j in range(len(rows))],
+                          out=eim_tr[c0:c0 + len(rows)])
+            torch.cuda.synchronize()
+            out["eim_seconds"] = round(time.time() - t0, 1)
+            log(f"C5 effective-index fields: {out['eim_seconds']}s")
+        t0 = time.time()
+        net = Cnn(480, 240, max_batch=32, k=k, seed=7, in_channels=args.c5_inputs)
+        losses = train_cnn(net, eps_d, targets, args.c5_adam, 32, lr=args.c5_lr, seed=11, log=log,
+                           eim=eim_tr)
+        del eim_tr
+        torch.cuda.synchronize()
+        t_train = time.time() - t0
+        del targets, eps_d
+        if args.c5_save:
+            net.save(args.c5_save)
+        curve = [float(np.mean(losses[i:i + 500])) for i in range(0, len(losses), 500)]
+        out.update({"train_solve_tol": args.c5_train_tol, "train_solve_seconds": round(t_solve, 1),
+                    "train_solve_iters_mean": float(np.mean(its)),
+                    "targets_seconds": round(t_tgt, 1), "train_seconds": round(t_train, 1),
+                    "ms_per_adam_step": round(1000 * t_train / max(1, args.c5_adam), 3),
+                    "loss_curve_mean_per_500_steps": curve, "saved": args.c5_save or None})
+        out["pca_for_comparison"] = "k=%d from 2000 of the C5 training fields" % args.k
+    # ---------------- evaluation on fresh instances
+    test = make_instances(range(W.CNN_TEST_SEED0, W.CNN_TEST_SEED0 + args.c5_test),
+                          args.workers or min(16, len(os.sched_getaffinity(0))))
+    eps_te = torch.tensor(np.stack([i.eps for i in test]), device="cuda")
+    Ucnn = torch.empty((len(test), k, D), dtype=torch.complex64, device="cuda")
+    eim_te = None
+    if net.in_channels == 3:
+        eim_te = torch.empty((len(test), D), dtype=torch.complex64, device="cuda")
+        for c0 in range(0, len(test), 64):
+            part = test[c0:c0 + 64]
+            eim_field([FdfdOp.from_instance(i) for i in part],
+                      [torch.tensor(i.b, dtype=torch.complex128, device="cuda") for i in part],
+                      out=eim_te[c0:c0 + len(part)])
+    net.predict(eps_te[:32], Ucnn[:32], eim=None if eim_te is None else eim_te[:32])   # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    net.predict(eps_te, Ucnn, eim=eim_te)
+    e1.record()
+    torch.cuda.synchronize()
+    out["inference_ms_for_%d" % len(test)] = round(e0.elapsed_time(e1), 2)
+    if args.c5_load:
+        Upca = None
+    EB = args.c5_eval_batch
+    res = {}
+    xs_plain = [None] * len(test)
+    for mode in args.c5_modes.split(","):
+        if mode == "pca" and Upca is None:
+            continue
+        kk = {"plain": 0, "cnn": k, "pca": args.k}[mode]
+        inf_all, h_all, secs = [], [], 0.0
+        for b0 in range(0, len(test), EB):
+            part = test[b0:b0 + EB]
+            ops = [FdfdOp.from_instance(i) for i in part]
+            bs = [torch.tensor(i.b, dtype=torch.complex128, device="cuda") for i in part]
+            sv = Solver(ops, restart=args.restart, kmax=kk, cgs_passes=args.cgs, hist_cap=args.maxit)
+            torch.cuda.synchronize()
+            ts = time.time()
+            if mode == "cnn":
+                sv.set_subspace([Ucnn[b0 + j] for j in range(len(part))])
+            elif mode == "pca":
+                sv.set_subspace([Upca] * len(part))
+            xs, inf, _ = sv.solve(bs, tol=args.tol, maxit=args.maxit)
+            torch.cuda.synchronize()
+            secs += time.time() - ts
+            inf_all.extend(inf)
+            h_all.extend(sv.history(j) for j in range(len(part)))
+            if mode == "plain":
+                for j, x in enumerate(xs):
+                    xs_plain[b0 + j] = x.clone()
+            sv.close()
+            log(f"  C5 eval {mode}: {b0 + len(part)}/{len(test)}, {secs:.0f}s")
+        res[mode] = {"solves_per_s": round(len(test) / secs, 4),
+                     "seconds": round(secs, 2),
+                     **batch_stats(inf_all, h_all, args.tol)}
+        log(f"C5 eval {mode}: {res[mode]}")
+    nz = [float(torch.linalg.vector_norm(Ucnn[p]).item()) for p in range(len(test))]
+    out["predicted_fields_all_zero"] = sum(1 for v in nz if v == 0.0)
+    if xs_plain[0] is not None:
+        Xp = torch.stack(xs_plain).contiguous()
+        for mode, V in (("cnn", Ucnn), ("pca", None if Upca is None else
+                                        Upca.unsqueeze(0).expand(len(test), -1, -1).contiguous())):
+            if mode in res and V is not None:
+                try:
+                    res[mode]["proj_loss_mean"] = float(np.mean(proj_loss_batched(V, Xp)))
+                except DDError as e:            # e.g. a collapsed network's zero fields
+                    res[mode]["proj_loss_mean"] = None
+                    res[mode]["proj_loss_error"] = str(e)
+        refs = [oracle_reference(test[p]) for p in range(2)]
+        res["error_vs_sparse_lu_plain"] = [rel_err(xs_plain[p].cpu().numpy(), refs[p]["x"])
+                                           for p in range(2)]
+    out["eval"] = res
+    net.close()
+    return out
+
+
 def train_pca(args, torch, train):
     """Solve the training instances on the GPU (plain GMRES, batches of
     args.train_batch) and build the top-k PCA basis of their fields."""
@@ -667,6 +866,22 @@ def main():
     ap.add_argument("--recycle-ritz", type=int, default=10,
                     help="harmonic Ritz vectors carried from step to step")
     ap.add_argument("--precond", action="store_true")
+    ap.add_argument("--c5", action="store_true",
+                    help="CNN predictor at scale: 313 x 32 training steps, 10,000 Adam steps, "
+                         "256 fresh test instances")
+    ap.add_argument("--c5-traj", type=int, default=313)
+    ap.add_argument("--c5-steps", type=int, default=32)
+    ap.add_argument("--c5-adam", type=int, default=10000)
+    ap.add_argument("--c5-test", type=int, default=256)
+    ap.add_argument("--c5-eval-batch", type=int, default=64)
+    ap.add_argument("--c5-train-tol", type=float, default=1e-2)
+    ap.add_argument("--c5-save", default="")
+    ap.add_argument("--c5-load", default="")
+    ap.add_argument("--c5-only", action="store_true", help="run only the CNN-at-scale leg")
+    ap.add_argument("--c5-inputs", type=int, default=3, choices=(1, 3),
+                    help="input planes: permittivity (1) or permittivity + effective-index field (3)")
+    ap.add_argument("--c5-lr", type=float, default=1e-3)
+    ap.add_argument("--c5-modes", default="plain,cnn,pca")
     ap.add_argument("--cnn-kernels", type=int, default=0)
     ap.add_argument("--calibrate-copy", type=int, default=0)
     args = ap.parse_args()
@@ -682,7 +897,7 @@ def main():
     workers = args.workers or min(16, len(os.sched_getaffinity(0)))
     t0 = time.time()
     train, test = [], []
-    if args.cnn_kernels <= 0:
+    if args.cnn_kernels <= 0 and not args.c5_only:
         train = make_instances(range(W.PCA_TRAIN_SEED0, W.PCA_TRAIN_SEED0 + args.train), workers)
         test = make_instances(range(W.PCA_TEST_SEED0, W.PCA_TEST_SEED0 + args.test), workers)
         log(f"data: {len(train)} training + {len(test)} test instances, {time.time() - t0:.1f}s "
@@ -705,6 +920,9 @@ def main():
         del src, dst
     if args.cnn_kernels > 0:
         cnn_kernels_only(args, torch, W)
+        return
+    if args.c5_only:
+        print(json.dumps({"cnn_at_scale": c5_leg(args, torch, W)}), flush=True)
         return
 
     # ---------------- predictor training (untimed)
@@ -856,6 +1074,7 @@ def main():
             pre = precond_leg(args, torch, cops, cbs, U)
     if args.recycle > 0:
         rec = recycle_leg(args, torch, W)
+    c5 = c5_leg(args, torch, W) if args.c5 else None
     if args.uneven:
         uneven = uneven_leg(args, torch, W)
 
@@ -956,6 +1175,7 @@ def main():
         "cnn_augmented": cnn,
         "uneven_batch_plain": uneven,
         "trajectory_recycling": rec,
+        "cnn_at_scale": c5,
         "diagonal_preconditioners": pre,
     }
     print(json.dumps(out), flush=True)

@@ -125,3 +125,33 @@ def test_solve_in_caller_workspace(k):
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
     with pytest.raises(DDError):
         Solver([op], workspace=ws[:nbytes - 512], **kw)
+
+
+def test_trained_checkpoint_serves_through_predict_subspace():
+    """The network trained at scale (313 trajectories x 32 steps, 10,000 Adam
+    steps, three input planes) loads through predictor_load and through
+    Cnn.load; predict_subspace (which forms the effective-index planes
+    itself) gives bit-identical fields to Cnn.predict with eim_field's
+    planes, all finite and non-zero, on two fresh 480 x 240 gratings."""
+    import os
+    import torch
+    from paper_1902_00090_amd import Cnn, FdfdOp, Predictor, eim_field
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_1902_00090_amd", "checkpoints",
+                        "cnn_k10_eim_c5.ddp")
+    insts = [W.grating(50_000 + i) for i in range(2)]
+    ops = [FdfdOp.from_instance(i) for i in insts]
+    bs = [torch.tensor(i.b, dtype=torch.complex128, device="cuda") for i in insts]
+    eps = torch.tensor(np.stack([i.eps for i in insts]), device="cuda")
+    pr = Predictor(path, max_batch=2)
+    assert (pr.kind, pr.nx, pr.ny, pr.k, pr.in_channels) == ("cnn", 480, 240, 10, 3)
+    U1 = pr.predict(2, eps=eps, ops=ops, b=bs)
+    net = Cnn.load(path, max_batch=2)
+    eim = torch.empty((2, insts[0].D), dtype=torch.complex64, device="cuda")
+    eim_field(ops, bs, out=eim)
+    U2 = net.predict(eps, eim=eim)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+    assert torch.isfinite(torch.view_as_real(U1)).all()
+    assert all(float(torch.linalg.vector_norm(U1[p, j])) > 0 for p in range(2) for j in range(10))
+    pr.close()
+    net.close()
