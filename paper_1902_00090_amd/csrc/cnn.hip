@@ -72,6 +72,8 @@ struct dd_cnn {
   // residual-loss scratch (allocated on first use): V = output fields, W = A V,
   // r = b - W c, s = A^H r
   float2 *rl_W = nullptr, *rl_r = nullptr, *rl_s = nullptr;
+  void* rl_scratch = nullptr;      // residual-loss descriptors, coefficients, Gram partials
+  size_t rl_scratch_bytes = 0;
   bf16* act[NL] = {};        // act[l] = output of layer l (l < NL-1), NHWC bf16
   float* out = nullptr;      // last layer output: complex fields [B][k][D] (FP32 pairs)
   const float* last_fields = nullptr;   // where the last forward pass wrote its fields
@@ -1995,6 +1997,8 @@ static dd_status res_step(dd_cnn* n, const float* eps, const void* eim,
     chk(cnn_alloc(n, &n->rl_W, (size_t)n->maxB * n->k * D));
     chk(cnn_alloc(n, &n->rl_r, (size_t)n->maxB * D));
     chk(cnn_alloc(n, &n->rl_s, (size_t)n->maxB * D));
+    n->rl_scratch_bytes = res_loss_scratch_bytes(n->maxB, n->k);
+    chk(cnn_alloc(n, (float2**)&n->rl_scratch, (n->rl_scratch_bytes + 7) / 8));
     if (e != hipSuccess) {
       dd_set_error("%s: %s", who, hipGetErrorString(e));
       return e == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP;
@@ -2007,7 +2011,8 @@ static dd_status res_step(dd_cnn* n, const float* eps, const void* eim,
   for (int p = 0; p < B; ++p) Vp[p] = (const float2*)n->out + (size_t)p * n->k * D;
   std::vector<double> lv(B);
   rc = res_loss_core(ops, b, Vp.data(), B, n->k, n->rl_W, n->rl_r, n->rl_s, lv.data(),
-                     n->dz[NL - 1], n->L[NL - 1].coutp, 1.0 / B, st);
+                     n->dz[NL - 1], n->L[NL - 1].coutp, 1.0 / B, st, nullptr, n->rl_scratch,
+                     n->rl_scratch_bytes);
   if (rc != DD_OK) return rc;
   rc = backward_from_dz(n, B, st);
   if (rc != DD_OK) return rc;

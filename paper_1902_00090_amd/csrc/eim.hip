@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "common.h"
+#include "eim.h"
 #include "op.h"
 
 #define DD_EIM_MAX_DEVICES 64
@@ -325,6 +326,31 @@ extern "C" dd_status eim_field(const fdfd_op* const* ops, int nb, const void* co
   DD_HIP_CHECK(hipMalloc((void**)&ws, bytes));
   hipError_t e = eim_run(hd, s1, maxnx, maxD, ws, stream);
   (void)hipFree(ws);
+  if (e != hipSuccess) {
+    dd_set_error("eim_field: %s", hipGetErrorString(e));
+    return DD_EHIP;
+  }
+  return DD_OK;
+}
+
+// eim_field on a workspace the caller owns (ws_bytes >= eim_ws_bytes of the
+// batch): used by the predictor, which holds one for its largest batch.
+size_t eim_ws_bytes(int nx, int ny, int nb) {
+  return eim_scratch_bytes((size_t)nx * ny * nb, (size_t)nx * nb, nb);
+}
+
+dd_status eim_field_ws(const fdfd_op* const* ops, int nb, const void* const* b, void* const* F,
+                       void* ws, size_t ws_bytes, hipStream_t stream) {
+  std::vector<EimDesc> hd;
+  size_t s1 = 0;
+  int maxnx = 0, maxD = 0;
+  const size_t bytes = eim_prepare("eim_field", ops, nb, b, F, hd, s1, maxnx, maxD);
+  if (bytes == 0) return DD_EINVAL;
+  if (!ws || bytes > ws_bytes) {
+    dd_set_error("eim_field: the batch needs %zu bytes of workspace, %zu given", bytes, ws_bytes);
+    return DD_EINVAL;
+  }
+  const hipError_t e = eim_run(hd, s1, maxnx, maxD, (char*)ws, stream);
   if (e != hipSuccess) {
     dd_set_error("eim_field: %s", hipGetErrorString(e));
     return DD_EHIP;

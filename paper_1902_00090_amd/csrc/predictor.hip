@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.h"
+#include "eim.h"
 #include "op.h"
 #include "predfile.h"
 
@@ -19,12 +20,15 @@ struct dd_predictor {
   float2* U = nullptr;     // PCA basis [k][D]
   dd_cnn* net = nullptr;   // CNN
   float2* eim = nullptr;   // [max_batch][D] effective-index fields (three-plane CNN)
+  void* eim_ws = nullptr;  // their workspace, sized for max_batch problems
+  size_t eim_ws_bytes = 0;
 };
 
 extern "C" void predictor_destroy(dd_predictor* p) {
   if (!p) return;
   if (p->U) (void)hipFree(p->U);
   if (p->eim) (void)hipFree(p->eim);
+  if (p->eim_ws) (void)hipFree(p->eim_ws);
   if (p->net) dd_cnn_destroy(p->net);
   delete p;
 }
@@ -92,7 +96,9 @@ extern "C" dd_status predictor_load(const char* path, int max_batch, dd_predicto
     dd_status rc = dd_cnn_load(path, max_batch, &p->net);
     if (rc != DD_OK) { delete p; return rc; }
     if (p->in_channels == 3) {
-      const hipError_t e = hipMalloc((void**)&p->eim, sizeof(float2) * D * max_batch);
+      p->eim_ws_bytes = eim_ws_bytes(p->nx, p->ny, max_batch);
+      hipError_t e = hipMalloc((void**)&p->eim, sizeof(float2) * D * max_batch);
+      if (e == hipSuccess) e = hipMalloc(&p->eim_ws, p->eim_ws_bytes);
       if (e != hipSuccess) {
         predictor_destroy(p);
         dd_set_error("predictor_load: %s", hipGetErrorString(e));
@@ -152,7 +158,7 @@ extern "C" dd_status predict_subspace(dd_predictor* p, const fdfd_op* const* ops
   }
   std::vector<void*> F(B);
   for (int i = 0; i < B; ++i) F[i] = p->eim + (size_t)i * D;
-  dd_status rc = eim_field(ops, B, b, F.data(), stream);
+  dd_status rc = eim_field_ws(ops, B, b, F.data(), p->eim_ws, p->eim_ws_bytes, stream);
   if (rc != DD_OK) return rc;
   return dd_cnn_predict_eim(p->net, eps, p->eim, B, U, stream);
 }

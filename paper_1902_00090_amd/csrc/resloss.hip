@@ -309,10 +309,24 @@ bool solve_small(const std::vector<cd>& G, int k, std::vector<cd>& c, double& lo
 
 }  // namespace
 
+static size_t rl_align(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Gram partial slices per problem: enough workgroups to fill the chip, at
+// most 256, each slice at least 8 staging groups long.
+static int rl_slices(int nb, int minD) {
+  return std::max(1, std::min({256, (2048 + nb - 1) / nb, minD / (8 * RL_GE)}));
+}
+
+size_t res_loss_scratch_bytes(int nb, int k) {
+  const size_t K1 = k + 1, np = K1 * (K1 + 1) / 2;
+  return rl_align(sizeof(RlDesc) * nb) + rl_align(sizeof(double2) * 2 * (size_t)nb * k) +
+         rl_align(sizeof(double2) * ((size_t)nb * 256 * np + (size_t)nb * np));
+}
+
 dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const void* const* V,
                         int nb, int k, float2* Wbuf, float2* rbuf, float2* sbuf, double* loss,
                         __bf16* dz, int coutp, double scale, hipStream_t st,
-                        void* const* Gout) {
+                        void* const* Gout, void* scratch, size_t scratch_bytes) {
   std::vector<RlDesc> hd(nb);
   int maxD = 0;
   size_t offW = 0, offR = 0;
@@ -331,11 +345,21 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
     offR += (size_t)op->D;
     maxD = std::max(maxD, op->D);
   }
-  DevBuf bdd, bdc, bgp;
-  DD_HIP_CHECK(hipMalloc(&bdd.p, sizeof(RlDesc) * nb));
-  DD_HIP_CHECK(hipMalloc(&bdc.p, sizeof(double2) * 2 * (size_t)nb * k));
-  RlDesc* dd = (RlDesc*)bdd.p;
-  double2* dc = (double2*)bdc.p;
+  DevBuf own;
+  const size_t need = res_loss_scratch_bytes(nb, k);
+  if (scratch && scratch_bytes < need) {
+    dd_set_error("res_loss: scratch of %zu bytes, %zu needed", scratch_bytes, need);
+    return DD_EINVAL;
+  }
+  if (!scratch) {
+    DD_HIP_CHECK(hipMalloc(&own.p, need));
+    scratch = own.p;
+  }
+  char* sp = (char*)scratch;
+  RlDesc* dd = (RlDesc*)sp;
+  double2* dc = (double2*)(sp + rl_align(sizeof(RlDesc) * nb));
+  double2* gp = (double2*)(sp + rl_align(sizeof(RlDesc) * nb) +
+                           rl_align(sizeof(double2) * 2 * (size_t)nb * k));
   for (int p = 0; p < nb; ++p) hd[p].c = dc + (size_t)p * k;
   DD_HIP_CHECK(hipMemcpyAsync(dd, hd.data(), sizeof(RlDesc) * nb, hipMemcpyHostToDevice, st));
   k_rl_apply<<<dim3((maxD + 255) / 256, nb), 256, 0, st>>>(dd, k);
@@ -345,10 +369,8 @@ dd_status res_loss_core(const fdfd_op* const* ops, const void* const* b, const v
   const int K1 = k + 1, np = K1 * (K1 + 1) / 2;
   int minD = maxD;
   for (const auto& d : hd) minD = std::min(minD, d.D);
-  const int nslices = std::max(1, std::min({256, (2048 + nb - 1) / nb, minD / (8 * RL_GE)}));
+  const int nslices = rl_slices(nb, minD);
   const size_t ngp = (size_t)nb * nslices * np;
-  DD_HIP_CHECK(hipMalloc(&bgp.p, sizeof(double2) * (ngp + (size_t)nb * np)));
-  double2* gp = (double2*)bgp.p;
   double2* gsum = gp + ngp;
   if (K1 * RL_GE <= 2 * 256)
     k_rl_gram<2><<<dim3(nslices, nb), 256, 0, st>>>(dd, k, nslices, gp);
