@@ -468,6 +468,37 @@ def recycle_leg(args, torch, W):
     return out
 
 
+def c4_recycle_leg(args, torch, test, U):
+    """Harmonic Ritz recycling across the C4 test batches: batch s + 1 of the
+    fresh instances is augmented by the harmonic Ritz vectors of batch s's
+    last cycles (problem t of one batch passes its vectors to problem t of the
+    next), with and without the PCA basis, against plain and PCA-only on the
+    same batches (all to args.tol_acc)."""
+    from paper_1902_00090_amd.recycle import solve_trajectories
+    B, S = args.batch, args.c4_recycle
+    trajs = [[test[s * B + t] for s in range(S)] for t in range(B)]
+    modes = {"plain": dict(recycle=False, ritz=0), "pca": dict(recycle=False, ritz=0, base=U),
+             "harmonic_ritz": dict(recycle=False, ritz=args.recycle_ritz),
+             "pca+harmonic_ritz": dict(recycle=False, ritz=args.recycle_ritz, base=U)}
+    out = {"batches": S, "batch": B, "ritz": args.recycle_ritz}
+    for mode, kw in modes.items():
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, inf, hist, _ = solve_trajectories(trajs, tol=args.tol_acc, restart=args.restart,
+                                             maxit=args.maxit, cgs_passes=args.cgs,
+                                             hist_cap=args.maxit, **kw)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        later = [(t, s) for t in range(B) for s in range(1, S)]
+        out[mode] = {"seconds": round(dt, 2), "solves_per_s": round(B * S / dt, 4),
+                     "iters_mean_batches_ge_1": float(np.mean([inf[t][s]["iters"] for t, s in later])),
+                     "iters_to_1e-6_mean_batches_ge_1": float(np.mean(
+                         [first_below(hist[t][s], 1e-6) or np.nan for t, s in later])),
+                     "all_converged": all(i["status"] == 0 for row in inf for i in row)}
+        log(f"C4 recycling {mode}: {out[mode]}")
+    return out
+
+
 def uneven_leg(args, torch, W):
     """8 trajectories x 32 steps of uneven grids (192x96, 320x160, 480x240;
     1.30 / 1.55 um) in one lockstep batch, plain complex64 GMRES, step groups
@@ -863,6 +894,8 @@ def main():
     ap.add_argument("--uneven", action="store_true", help="also run the uneven correlated batch")
     ap.add_argument("--recycle", type=int, default=0)
     ap.add_argument("--recycle-window", type=int, default=5)
+    ap.add_argument("--c4-recycle", type=int, default=0,
+                    help="batches of the C4 test set solved with recycled harmonic Ritz vectors")
     ap.add_argument("--recycle-ritz", type=int, default=10,
                     help="harmonic Ritz vectors carried from step to step")
     ap.add_argument("--precond", action="store_true")
@@ -1044,6 +1077,8 @@ def main():
             errs.append(e)
             log(f"  oracle check {p}: {e}")
 
+    c4rec = c4_recycle_leg(args, torch, test, U) if args.c4_recycle > 0 else None
+
     # ---------------- C1 and C2 beside their oracle figures
     c1 = None if args.no_c1 else c1_leg(args, torch, W)
     c2 = None
@@ -1176,6 +1211,7 @@ def main():
         "uneven_batch_plain": uneven,
         "trajectory_recycling": rec,
         "cnn_at_scale": c5,
+        "c4_recycling": c4rec,
         "diagonal_preconditioners": pre,
     }
     print(json.dumps(out), flush=True)

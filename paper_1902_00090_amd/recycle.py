@@ -26,12 +26,15 @@ from . import FdfdOp, Solver
 
 
 def solve_trajectories(trajs, window=5, tol=1e-6, restart=100, maxit=30000, cgs_passes=1,
-                       recycle=True, ritz=0, hist_cap=0, inner="c64"):
+                       recycle=True, ritz=0, hist_cap=0, inner="c64", base=None):
     """trajs: T trajectories, each a list of S instances (equal S; the grids of
     one trajectory must not change).  Step s of trajectory t is augmented by
     the solutions of its steps max(0, s - window) .. s - 1 (recycle=True) and
     by the `ritz` harmonic Ritz vectors of its step s - 1 (ritz > 0); neither
     at s = 0.  recycle=False and ritz=0 run plain GMRES on the same schedule.
+    base: an optional [k0, D] tensor (a predicted basis, such as the PCA
+    components) that augments every step of every trajectory ahead of the
+    recycled vectors.
 
     Returns (x, infos, hist, theta): x[t][s] complex128 device tensors,
     infos[t][s] info dicts, hist[t][s] residual histories (empty unless
@@ -43,7 +46,8 @@ def solve_trajectories(trajs, window=5, tol=1e-6, restart=100, maxit=30000, cgs_
     if any(len(tr) != S for tr in trajs):
         raise ValueError("all trajectories need the same number of steps")
     dt = torch.complex64 if inner == "c64" else torch.complex128
-    kmax = (window if recycle else 0) + int(ritz)
+    k0 = 0 if base is None else int(base.shape[0])
+    kmax = k0 + (window if recycle else 0) + int(ritz)
     solver = None
     prev = [[] for _ in range(T)]
     Y = [None] * T
@@ -63,7 +67,7 @@ def solve_trajectories(trajs, window=5, tol=1e-6, restart=100, maxit=30000, cgs_
             solver.bind(ops)
         U = []
         for t in range(T):
-            parts = []
+            parts = [] if base is None else [base.to(dt)]
             if recycle and s > 0:
                 parts.append(torch.stack(prev[t][-window:]))
             if ritz > 0 and s > 0 and Y[t] is not None and Y[t].shape[0] > 0:
