@@ -118,8 +118,11 @@ typedef struct {
   int cgs_passes;       /* 1 = classical Gram-Schmidt, 2 = CGS2 (default)          */
   int restart;          /* m >= 1 (default 100)                                     */
   int kmax;             /* largest number of augmenting vectors, 0..64 (default 0) */
-  int elems_per_thread; /* field elements per thread: 1, 2, 4, 8; 0 = 8 for batches */
-                        /* of >= 512 chunks of 2048 elements, else 2 (default)    */
+  int elems_per_thread; /* field elements per thread: 1, 2, 4, 8; 0 (default) = 8 */
+                        /* for batches of >= 512 chunks of 2048 elements, else 2; */
+                        /* -1 = the autotuner's choice (dd_solver_autotune, run   */
+                        /* once per process for each set of grid sizes and        */
+                        /* options, then remembered)                              */
   int hist_cap;         /* residual-history entries kept per problem (default 0)   */
   int check_every;      /* steps between host checks for an early cycle end (4)    */
   int select_reorth;    /* with cgs_passes = 2: run the second pass only in steps  */
@@ -294,6 +297,10 @@ dd_status dd_solver_autotune(const fdfd_op* const* ops, int nb, const dd_solver_
 dd_status dd_solver_profile(dd_solver* s, int enable);
 /* Host copy of the accumulated statistics. */
 dd_status dd_solver_kernel_stats(const dd_solver* s, dd_kernel_stats* out);
+
+/* Field elements per thread the solver runs with (the tile width chosen by
+ * the rule or the autotuner; 0 for a NULL solver). */
+int dd_solver_elems_per_thread(const dd_solver* s);
 
 /* Device bytes of the solver workspace (its own or the caller's). */
 size_t dd_solver_device_bytes(const dd_solver* s);

@@ -307,6 +307,11 @@ class Solver:
         return {n: (ks.ms[i], ks.launches[i], ks.bytes[i]) for i, n in enumerate(names)}
 
     @property
+    def elems_per_thread(self):
+        """The tile width the solver runs with (the rule's or the autotuner's)."""
+        return _lib.lib().dd_solver_elems_per_thread(self._h)
+
+    @property
     def device_bytes(self):
         return _lib.lib().dd_solver_device_bytes(self._h)
 

@@ -75,6 +75,7 @@ _SIGS = {
     "dd_harmonic_ritz_host": (I, [I, I, C.POINTER(D), C.POINTER(D), I, C.POINTER(D), C.POINTER(D)]),
     "dd_solver_debug_copy": (I, [P, I, I, P, C.c_size_t]),
     "dd_solver_device_bytes": (C.c_size_t, [P]),
+    "dd_solver_elems_per_thread": (I, [P]),
     "dd_solver_profile": (I, [P, I]),
     "dd_solver_autotune": (I, [PP, I, C.POINTER(dd_solver_opts), C.POINTER(I), C.POINTER(D)]),
     "dd_solver_kernel_stats": (I, [P, C.POINTER(dd_kernel_stats)]),

@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "solver_kernels.h"
@@ -160,6 +163,35 @@ static void layout_workspace(dd_solver* s, Arena& A, ProbDesc*& dd, int*& db2p) 
 
 // Validates the options and builds the host-side plan of a solver (problem
 // descriptors, chunk map, workspace parameters); no device memory yet.
+extern "C" dd_status dd_solver_autotune(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
+                                        int* best, double* ms_per_step);
+
+// elems_per_thread = -1: the autotuner's choice for this set of grid sizes and
+// options, measured once per process and remembered.
+static dd_status tuned_elems_per_thread(const fdfd_op* const* ops, int nb, const dd_solver_opts& o,
+                                        int* R) {
+  static std::mutex mu;
+  static std::map<std::string, int> cache;
+  std::string key = std::to_string(nb) + "/" + std::to_string(o.restart) + "/" +
+                    std::to_string(o.inner) + "/" + std::to_string(o.cgs_passes) + "/" +
+                    std::to_string(o.precond) + "/" + std::to_string(o.fused) + ":";
+  for (int p = 0; p < nb; ++p) key += std::to_string(ops[p]->nx) + "x" + std::to_string(ops[p]->ny) + ",";
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) { *R = it->second; return DD_OK; }
+  }
+  dd_solver_opts t = o;
+  t.elems_per_thread = 0;
+  int best = 0;
+  dd_status rc = dd_solver_autotune(ops, nb, &t, &best, nullptr);
+  if (rc != DD_OK) return rc;
+  std::lock_guard<std::mutex> lock(mu);
+  cache[key] = best;
+  *R = best;
+  return DD_OK;
+}
+
 static dd_status solver_plan(const fdfd_op* const* ops, int nb, const dd_solver_opts* opts,
                              dd_solver** out) {
   if (!out) { dd_set_error("dd_solver_create: out is NULL"); return DD_EINVAL; }
@@ -194,9 +226,13 @@ static dd_status solver_plan(const fdfd_op* const* ops, int nb, const dd_solver_
     return DD_EINVAL;
   }
   int R = o.elems_per_thread;
-  if (R != 0 && R != 1 && R != 2 && R != 4 && R != 8) {
-    dd_set_error("dd_solver_create: elems_per_thread must be 0, 1, 2, 4 or 8");
+  if (R != -1 && R != 0 && R != 1 && R != 2 && R != 4 && R != 8) {
+    dd_set_error("dd_solver_create: elems_per_thread must be -1, 0, 1, 2, 4 or 8");
     return DD_EINVAL;
+  }
+  if (R == -1) {
+    dd_status rc = tuned_elems_per_thread(ops, nb, o, &R);
+    if (rc != DD_OK) return rc;
   }
   if (R == 0) {
     // Measured by dd_solver_autotune on MI355X over full GMRES(100) cycles of
@@ -358,6 +394,8 @@ extern "C" dd_status dd_solver_create(const fdfd_op* const* ops, int nb, const d
 }
 
 extern "C" size_t dd_solver_device_bytes(const dd_solver* s) { return s ? s->bytes : 0; }
+
+extern "C" int dd_solver_elems_per_thread(const dd_solver* s) { return s ? s->R : 0; }
 
 extern "C" dd_status dd_solver_workspace_bytes(const fdfd_op* const* ops, int nb,
                                                const dd_solver_opts* opts, size_t* bytes) {

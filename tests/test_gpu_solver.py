@@ -284,6 +284,30 @@ def test_autotune_picks_a_candidate():
     assert ms[[1, 2, 4, 8].index(best)] == min(ms)
 
 
+def test_autotuned_tile_width_is_used_and_remembered():
+    """elems_per_thread = -1: the solver runs the autotuner's choice, the same
+    one for a second solver of the same grids (remembered, so the histories
+    are bit-identical), and its history is that of one explicit width."""
+    from paper_1902_00090_amd import Solver
+    insts = [W.grating(1010 + i, nx=96, ny=48, npml=8) for i in range(2)]
+    ops = [_op(i) for i in insts]
+    bs = [_b(i) for i in insts]
+
+    def run(R):
+        s = Solver(ops, restart=20, cgs_passes=1, elems_per_thread=R, hist_cap=60)
+        s.solve(bs, tol=0.0, maxit=60)
+        h, r = s.history(0), s.elems_per_thread
+        s.close()
+        return h, r
+
+    h1, r1 = run(-1)
+    h2, r2 = run(-1)
+    assert r1 == r2 and r1 in (1, 2, 4, 8)
+    assert np.array_equal(h1, h2)
+    h3, r3 = run(r1)
+    assert r3 == r1 and np.array_equal(h1, h3)
+
+
 @pytest.mark.parametrize("R", [1, 2, 4, 8])
 def test_tile_width_matches_oracle(R):
     """Every elements-per-thread choice (chunks of 256 R elements; 96 x 61 = 5856
