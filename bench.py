@@ -561,7 +561,7 @@ def c5_leg(args, torch, W):
     import multiprocessing as mp
     from paper_1902_00090_amd import (Cnn, DDError, FdfdOp, Solver, eim_field, local_pca_targets,
                                       pca_build, proj_loss_batched)
-    from paper_1902_00090_amd.train import train_cnn
+    from paper_1902_00090_amd.train import train_cnn, train_cnn_res
     T, S, k, D = args.c5_traj, args.c5_steps, args.cnn_k, 480 * 240
     N = T * S
     omega = 2 * math.pi / 1.30
@@ -586,46 +586,59 @@ def c5_leg(args, torch, W):
         del parts
         log(f"C5 data: {N} trajectory steps generated in {time.time() - t0:.1f}s")
         eps_d = torch.tensor(eps_h, device="cuda")
-        F = torch.empty((N, D), dtype=torch.complex64, device="cuda")
-        bmat = torch.zeros((T, 240, 480), dtype=torch.complex128, device="cuda")
-        t0 = time.time()
-        solver, its = None, []
-        w = args.recycle_window
-        for st in range(S):
-            rows = [t * S + st for t in range(T)]
-            ops = [FdfdOp(eps_h[r], omega, 0.025, 20) for r in rows]
-            bmat[:, :, SRC_IX] = torch.tensor(cols[rows], device="cuda")
-            bs = [bmat[t].reshape(-1) for t in range(T)]
-            if solver is None:
-                solver = Solver(ops, restart=args.restart, kmax=w, cgs_passes=1)
-            else:
-                solver.bind(ops)
-            if st > 0:
-                solver.set_subspace([F[t * S + max(0, st - w):t * S + st] for t in range(T)])
-            xs, infos, _ = solver.solve(bs, tol=args.c5_train_tol, maxit=args.maxit)
-            for t, x in enumerate(xs):
-                F[t * S + st] = x.to(torch.complex64)
-            its.extend(i["iters"] for i in infos)
-            del xs
-            log(f"  C5 training solves, step {st}: mean iters {np.mean([i['iters'] for i in infos]):.0f}, "
-                f"{time.time() - t0:.0f}s")
-        solver.close()
-        del bmat
-        t_solve = time.time() - t0
-        t0 = time.time()
-        targets = torch.empty((N, k, D), dtype=torch.complex64, device="cuda")
-        for t in range(T):
-            targets[t * S:(t + 1) * S] = local_pca_targets(F[t * S:(t + 1) * S].contiguous(),
-                                                           args.cnn_window, k)
-        targets.mul_(float(math.sqrt(D)))                  # unit RMS per pixel
-        torch.cuda.synchronize()
-        t_tgt = time.time() - t0
-        log(f"C5 targets: {t_tgt:.1f}s")
-        # PCA basis of 2000 of the training fields, for the comparison leg
-        sel = torch.as_tensor(np.random.default_rng(3).choice(N, size=min(2000, N), replace=False),
-                              device="cuda")
-        Upca, _ = pca_build(F.index_select(0, sel).contiguous(), args.k)
-        del F
+        res = args.c5_loss == "res"
+        t_solve = t_tgt = 0.0
+        its = []
+        Upca = None
+        if res:
+            # unsupervised: each sample's own operator and right-hand side, no solved fields
+            t0 = time.time()
+            all_ops = [FdfdOp(eps_h[r], omega, 0.025, 20) for r in range(N)]
+            ball = torch.zeros((N, 240, 480), dtype=torch.complex128, device="cuda")
+            ball[:, :, SRC_IX] = torch.tensor(cols, device="cuda")
+            all_b = [ball[r].reshape(-1) for r in range(N)]
+            log(f"C5 operators: {time.time() - t0:.1f}s")
+        else:
+            F = torch.empty((N, D), dtype=torch.complex64, device="cuda")
+            bmat = torch.zeros((T, 240, 480), dtype=torch.complex128, device="cuda")
+            t0 = time.time()
+            solver, its = None, []
+            w = args.recycle_window
+            for st in range(S):
+                rows = [t * S + st for t in range(T)]
+                ops = [FdfdOp(eps_h[r], omega, 0.025, 20) for r in rows]
+                bmat[:, :, SRC_IX] = torch.tensor(cols[rows], device="cuda")
+                bs = [bmat[t].reshape(-1) for t in range(T)]
+                if solver is None:
+                    solver = Solver(ops, restart=args.restart, kmax=w, cgs_passes=1)
+                else:
+                    solver.bind(ops)
+                if st > 0:
+                    solver.set_subspace([F[t * S + max(0, st - w):t * S + st] for t in range(T)])
+                xs, infos, _ = solver.solve(bs, tol=args.c5_train_tol, maxit=args.maxit)
+                for t, x in enumerate(xs):
+                    F[t * S + st] = x.to(torch.complex64)
+                its.extend(i["iters"] for i in infos)
+                del xs
+                log(f"  C5 training solves, step {st}: mean iters {np.mean([i['iters'] for i in infos]):.0f}, "
+                    f"{time.time() - t0:.0f}s")
+            solver.close()
+            del bmat
+            t_solve = time.time() - t0
+            t0 = time.time()
+            targets = torch.empty((N, k, D), dtype=torch.complex64, device="cuda")
+            for t in range(T):
+                targets[t * S:(t + 1) * S] = local_pca_targets(F[t * S:(t + 1) * S].contiguous(),
+                                                               args.cnn_window, k)
+            targets.mul_(float(math.sqrt(D)))                  # unit RMS per pixel
+            torch.cuda.synchronize()
+            t_tgt = time.time() - t0
+            log(f"C5 targets: {t_tgt:.1f}s")
+            # PCA basis of 2000 of the training fields, for the comparison leg
+            sel = torch.as_tensor(np.random.default_rng(3).choice(N, size=min(2000, N), replace=False),
+                                  device="cuda")
+            Upca, _ = pca_build(F.index_select(0, sel).contiguous(), args.k)
+            del F
         eim_tr = None
         if args.c5_inputs == 3:
             t0 = time.time()
@@ -633,31 +646,44 @@ def c5_leg(args, torch, W):
             bq = torch.zeros((64, 240, 480), dtype=torch.complex128, device="cuda")
             for c0 in range(0, N, 64):
                 rows = list(range(c0, min(N, c0 + 64)))
-                ops = [FdfdOp(eps_h[r], omega, 0.025, 20) for r in rows]
-                bq.zero_()
-                bq[:len(rows), :, SRC_IX] = torch.tensor(cols[rows], device="cuda")
-                eim_field(ops, [bq[j].reshape(-1) for j in range(len(rows))],
-                          out=eim_tr[c0:c0 + len(rows)])
+                if res:
+                    ops, bl = [all_ops[r] for r in rows], [all_b[r] for r in rows]
+                else:
+                    ops = [FdfdOp(eps_h[r], omega, 0.025, 20) for r in rows]
+                    bq.zero_()
+                    bq[:len(rows), :, SRC_IX] = torch.tensor(cols[rows], device="cuda")
+                    bl = [bq[j].reshape(-1) for j in range(len(rows))]
+                eim_field(ops, bl, out=eim_tr[c0:c0 + len(rows)])
             torch.cuda.synchronize()
             out["eim_seconds"] = round(time.time() - t0, 1)
             log(f"C5 effective-index fields: {out['eim_seconds']}s")
         t0 = time.time()
         net = Cnn(480, 240, max_batch=32, k=k, seed=7, in_channels=args.c5_inputs)
-        losses = train_cnn(net, eps_d, targets, args.c5_adam, 32, lr=args.c5_lr, seed=11, log=log,
-                           eim=eim_tr)
+        if res:
+            losses = train_cnn_res(net, eps_d, all_ops, all_b, args.c5_adam, 32, lr=args.c5_lr,
+                                   seed=11, log=log, eim=eim_tr)
+        else:
+            losses = train_cnn(net, eps_d, targets, args.c5_adam, 32, lr=args.c5_lr, seed=11,
+                               log=log, eim=eim_tr)
+            del targets
         del eim_tr
         torch.cuda.synchronize()
         t_train = time.time() - t0
-        del targets, eps_d
+        del eps_d
+        if res:
+            del all_ops, all_b, ball
         if args.c5_save:
             net.save(args.c5_save)
         curve = [float(np.mean(losses[i:i + 500])) for i in range(0, len(losses), 500)]
-        out.update({"train_solve_tol": args.c5_train_tol, "train_solve_seconds": round(t_solve, 1),
-                    "train_solve_iters_mean": float(np.mean(its)),
+        out.update({"training_loss": args.c5_loss,
+                    "train_solve_tol": None if res else args.c5_train_tol,
+                    "train_solve_seconds": round(t_solve, 1),
+                    "train_solve_iters_mean": float(np.mean(its)) if its else None,
                     "targets_seconds": round(t_tgt, 1), "train_seconds": round(t_train, 1),
                     "ms_per_adam_step": round(1000 * t_train / max(1, args.c5_adam), 3),
                     "loss_curve_mean_per_500_steps": curve, "saved": args.c5_save or None})
-        out["pca_for_comparison"] = "k=%d from 2000 of the C5 training fields" % args.k
+        if Upca is not None:
+            out["pca_for_comparison"] = "k=%d from 2000 of the C5 training fields" % args.k
     # ---------------- evaluation on fresh instances
     test = make_instances(range(W.CNN_TEST_SEED0, W.CNN_TEST_SEED0 + args.c5_test),
                           args.workers or min(16, len(os.sched_getaffinity(0))))
@@ -915,6 +941,8 @@ def main():
                     help="input planes: permittivity (1) or permittivity + effective-index field (3)")
     ap.add_argument("--c5-lr", type=float, default=1e-3)
     ap.add_argument("--c5-modes", default="plain,cnn,pca")
+    ap.add_argument("--c5-loss", default="proj", choices=("proj", "res"),
+                    help="projection-type (local-PCA targets) or residual loss (unsupervised)")
     ap.add_argument("--cnn-kernels", type=int, default=0)
     ap.add_argument("--calibrate-copy", type=int, default=0)
     args = ap.parse_args()
