@@ -903,6 +903,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=30000)
     ap.add_argument("--cgs", type=int, default=1, help="Gram-Schmidt passes (1 or 2)")
     ap.add_argument("--plain-batches", type=int, default=2)
+    ap.add_argument("--first-cycle-batches", type=int, default=0,
+                    help="batches also solved with the basis for the first cycle only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=400)
     ap.add_argument("--oracle-check", type=int, default=4)
@@ -1049,6 +1051,29 @@ def main():
         torch.cuda.synchronize()
         t6[bi] = time.time() - ts
         x6[bi] = xb
+    # ---------------- the predicted basis for the first cycle only (optional):
+    # one augmented cycle, then plain GMRES from its iterate
+    first_cycle = None
+    if args.first_cycle_batches > 0:
+        fc_t, fc_it = 0.0, []
+        for bi in range(min(args.first_cycle_batches, nbat)):
+            sl = slice(bi * B, (bi + 1) * B)
+            xb = [torch.empty_like(b) for b in bs[sl]]
+            aug.bind(ops[sl])
+            torch.cuda.synchronize()
+            ts = time.time()
+            aug.set_subspace(Ulist)
+            _, inf1, _ = aug.solve(bs[sl], tol=args.tol_acc, maxit=args.restart, x=xb)
+            aug.set_subspace(None)
+            _, inf2, _ = aug.solve(bs[sl], x0=xb, tol=args.tol_acc, maxit=args.maxit, x=xb)
+            torch.cuda.synchronize()
+            fc_t += time.time() - ts
+            fc_it.extend(a["iters"] + b2["iters"] for a, b2 in zip(inf1, inf2))
+        nfc = min(args.first_cycle_batches, nbat) * B
+        first_cycle = {"problems": nfc, "solves_per_s": round(nfc / fc_t, 4),
+                       "iters_mean": float(np.mean(fc_it)),
+                       "note": "one PCA-augmented cycle, then plain GMRES from its iterate"}
+        log(f"PCA basis for the first cycle only: {first_cycle}")
     tile = aug.elems_per_thread
     aug.close()
 
@@ -1244,6 +1269,7 @@ def main():
         "trajectory_recycling": rec,
         "cnn_at_scale": c5,
         "c4_recycling": c4rec,
+        "pca_first_cycle_only": first_cycle,
         "diagonal_preconditioners": pre,
     }
     print(json.dumps(out), flush=True)
