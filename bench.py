@@ -858,9 +858,12 @@ def c2_leg(args, torch, W, U, ref):
     b = torch.tensor(inst.b, dtype=torch.complex128, device="cuda")
     out = {"instance": "grating seed 1000, 480x240", "err_factor": ref["err_factor"],
            "kappa_1_estimate": ref["kappa_1"], "sparse_lu_seconds": round(ref["lu_seconds"], 2)}
-    for aug in (False, True):
+    # plain and augmented with the two-sweep Arnoldi step, then both with the
+    # one-sweep step (which moves each basis vector once and takes two
+    # launches per step: the faster of the two for one problem alone)
+    for aug, fused in ((False, False), (True, False), (False, True), (True, True)):
         s = Solver([op], restart=args.restart, kmax=args.k if aug else 0, cgs_passes=args.cgs,
-                   use_graph=True)
+                   use_graph=True, fused=fused)
         if aug:
             s.set_subspace([U])
         s.solve([b], tol=args.tol, maxit=args.maxit)       # warm-up (graph capture)
@@ -877,7 +880,7 @@ def c2_leg(args, torch, W, U, ref):
                                    "rel_res_true": inf["rel_res_true"],
                                    "error_vs_sparse_lu": rel_err(x.cpu().numpy(), ref["x"])}
         s.close()
-        out["augmented" if aug else "plain"] = res
+        out[("augmented" if aug else "plain") + ("_one_sweep" if fused else "")] = res
     log(f"C2: {out}")
     return out
 
@@ -902,6 +905,8 @@ def main():
     ap.add_argument("--warmup-tol", type=float, default=1e-2)
     ap.add_argument("--maxit", type=int, default=30000)
     ap.add_argument("--cgs", type=int, default=1, help="Gram-Schmidt passes (1 or 2)")
+    ap.add_argument("--fused", action="store_true",
+                    help="one sweep per Arnoldi step (the slower option, for measurement)")
     ap.add_argument("--plain-batches", type=int, default=2)
     ap.add_argument("--first-cycle-batches", type=int, default=0,
                     help="batches also solved with the basis for the first cycle only")
@@ -1001,7 +1006,7 @@ def main():
     xs = [torch.empty_like(b) for b in bs]
     # tile width from the autotuner (timed once per process, outside the timed region)
     aug = Solver(ops[:B], restart=args.restart, kmax=args.k, cgs_passes=args.cgs,
-                 hist_cap=args.maxit, elems_per_thread=-1)
+                 hist_cap=args.maxit, elems_per_thread=-1, fused=args.fused)
     Ulist = [U] * B
 
     def step(bi, tol):

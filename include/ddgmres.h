@@ -140,11 +140,12 @@ typedef struct {
                         /* operators and options; borrowed until destroy          */
   size_t workspace_bytes;
   int fused;            /* 1 = one sweep per Arnoldi step where it applies        */
-                        /* (cgs_passes = 1, kmax + restart + 1 <= 128, nx <= 512):*/
-                        /* the update of step j, the matvec and the dots of step  */
-                        /* j + 1 read each basis vector from memory once (rows    */
-                        /* walked in bands); 0 (default) = two sweeps per step,   */
-                        /* which measure faster on MI355X                         */
+                        /* (cgs_passes = 1, kmax + restart + 1 <= 128): the       */
+                        /* update of step j, the matvec and the dots of step j+1  */
+                        /* read each basis vector from memory once (30-column     */
+                        /* strips walked down bands of rows); faster for one      */
+                        /* problem alone, slower for batches; 0 (default) = two   */
+                        /* sweeps per step                                        */
 } dd_solver_opts;
 
 /* Per-problem result (host struct). */

@@ -184,7 +184,8 @@ class Solver:
                  use_graph=False, precond=None, workspace=None, fused=False):
         """precond: None, "jacobi" or "pml" (diagonal preconditioners, see the C header).
         fused: one sweep per Arnoldi step where it applies (cgs_passes=1,
-        kmax + restart + 1 <= 128, nx <= 512); off by default (slower here).
+        kmax + restart + 1 <= 128); off by default (faster for one problem
+        alone, slower for batches).
         workspace: an optional device tensor (at least workspace_bytes(...) bytes,
         256-byte aligned) that holds all of the solver's device arrays; the
         solver then allocates no device memory and keeps a reference to it."""

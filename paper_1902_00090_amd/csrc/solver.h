@@ -41,11 +41,12 @@ struct ProbDesc {
   void* Z;
 };
 
-// One tile of the fused sweep: the columns [x0, x0 + 64 CPL) (clipped to nx)
-// of rows [y0, y1) of problem p, walked downwards (dir = 1) or upwards
-// (dir = -1).
+// One tile of the fused sweep: the columns [x0, x0 + DD_FUSED_SW) (clipped to
+// nx) of rows [y0, y1) of problem p, walked downwards (dir = 1); its dots go
+// to partial row `row` (tiles of a problem have consecutive rows).  p < 0 is
+// a padding tile.
 struct FusedTile {
-  int p, x0, y0, y1, dir;
+  int p, x0, y0, y1, dir, row;
 };
 
 // Integer state per problem

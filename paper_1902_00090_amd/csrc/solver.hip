@@ -284,36 +284,42 @@ static dd_status solver_plan(const fdfd_op* const* ops, int nb, const dd_solver_
     int GB = (int)std::min<size_t>(32, std::max<size_t>(1, (64ull << 20) / per));
     P.GB = GB;
   }
-  // Fused sweep tiles: bands of whole rows (nx <= 512, one column per
-  // thread), adjacent bands walking in opposite directions.
-  int maxnx = 0;
-  long long rows = 0;
-  for (int p = 0; p < nb; ++p) {
-    maxnx = std::max(maxnx, ops[p]->nx);
-    rows += ops[p]->ny;
-  }
-  s->fused = o.fused && o.cgs_passes == 1 && (K + m + 1) <= 128 && maxnx <= 512;
+  // Fused sweep tiles: strips of DD_FUSED_SW columns walked down bands of rows
+  s->fused = o.fused && o.cgs_passes == 1 && (K + m + 1) <= DD_FUSED_MAXN;
   if (s->fused) {
-    // bands of ceil(rows / (w ncu)) rows, w the workgroups of the sweep that
-    // fit on a compute unit: one round of tiles, all resident at once
+    // two rounds of tiles over the resident workgroups (w per compute unit),
+    // bands of 8 to 64 rows (each band recomputes one halo row at either end)
     int w = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &w, (o.inner == DD_C64) ? (const void*)k_fused_sweep<float, false>
                                     : (const void*)k_fused_sweep<double, false>,
             DD_FUSED_THREADS, 0) != hipSuccess || w < 1)
       w = 1;
-    const long long slots = (long long)w * s->ncu;
-    const long long per = (rows + slots - 1) / slots;
-    const int bh = (int)std::min<long long>(64, std::max<long long>(2, per));
-    s->htiles.clear();
+    long long strip_rows = 0;
+    for (int p = 0; p < nb; ++p)
+      strip_rows += (long long)((ops[p]->nx + DD_FUSED_SW - 1) / DD_FUSED_SW) * ops[p]->ny;
+    const long long slots = 2LL * w * s->ncu;
+    const long long per = (strip_rows + slots - 1) / slots;
+    const int bh = (int)std::min<long long>(64, std::max<long long>(8, per));
+    std::vector<FusedTile> logical;
     for (int p = 0; p < nb; ++p) {
       ProbDesc& d = s->hdesc[p];
-      const int nyp = ops[p]->ny;
-      d.t0 = (int)s->htiles.size();
-      int band = 0;
-      for (int y0 = 0; y0 < nyp; y0 += bh, ++band)
-        s->htiles.push_back({p, 0, y0, std::min(nyp, y0 + bh), (band & 1) ? -1 : 1});
-      d.nt = (int)s->htiles.size() - d.t0;
+      const int nxp = ops[p]->nx, nyp = ops[p]->ny;
+      d.t0 = (int)logical.size();
+      for (int y0 = 0; y0 < nyp; y0 += bh)
+        for (int x0 = 0; x0 < nxp; x0 += DD_FUSED_SW)
+          logical.push_back({p, x0, y0, std::min(nyp, y0 + bh), 1, (int)logical.size()});
+      d.nt = (int)logical.size() - d.t0;
+    }
+    // XCD-aware launch order: workgroup b runs on XCD b % 8, so XCD x is given
+    // the x-th contiguous eighth of the tiles; neighbouring strips of a band
+    // then share an L2, which serves the cache lines at their common edge
+    const int X = 8;
+    const int perx = (int)((logical.size() + X - 1) / X);
+    s->htiles.assign((size_t)perx * X, FusedTile{-1, 0, 0, 0, 1, 0});
+    for (int b = 0; b < perx * X; ++b) {
+      const int i = (b % X) * perx + b / X;
+      if (i < (int)logical.size()) s->htiles[b] = logical[i];
     }
   }
   *out = s;

@@ -739,19 +739,26 @@ __global__ __launch_bounds__(DD_BLOCK) void k_combine(PlanDev P) {
 // classical passes (dots, then update) fetch it twice.
 //
 // The stencil needs q~_{j+1} at the rows above and below, which other tiles
-// form in the same launch.  A workgroup therefore walks a band of whole rows:
-// at walk step t it updates row r_t (and the halo rows before the first and
-// after the last row of the band, recomputed rather than read), applies the
-// stencil to row r_{t-1} from a ring of three updated rows in LDS, and takes
-// the dots of row r_{t-2}, whose basis values it fetched two steps before (the
-// repeat fetch hits the caches).  Adjacent bands walk in opposite
-// directions, so the halo row two bands share is fetched by both at the same
-// time.  Thread x owns column x of each row (nx <= 512); the dots of 16 basis
-// vectors at a time are folded across the wave by the transposed butterfly
-// into per-wave LDS sums, added over the waves at the end.  One partial row
-// per tile, reduced in tile order by k_post_fused.
+// form in the same launch.  A workgroup therefore walks a strip of
+// DD_FUSED_SW columns down a band of rows.  At walk step t it updates row
+// y0 - 1 + t over the strip and one halo column on each side (the halo
+// columns and the halo rows above and below the band are recomputed rather
+// than read), applies the stencil to the row behind it from a ring of three
+// updated rows in LDS, and takes that row's dots against the basis values it
+// fetched at the step before, still in registers: every basis value is read
+// from memory once.  Thread (vl, c) of the 512 handles column c of the strip
+// (with its halos, 32 lanes) and the basis vectors v = vl, vl + 16, ...;
+// its dots accumulate in registers over the whole band and are folded over
+// the columns once at the end.  One partial row per tile, reduced in tile
+// order by k_post_fused.
 #define DD_FUSED_THREADS 512
 #define DD_FUSED_MAXN 128                // basis vectors of one step: n + 1 <= 128
+#ifndef DD_FUSED_LANES
+#define DD_FUSED_LANES 32                // column lanes of a strip (owned columns + 2 halos)
+#endif
+#define DD_FUSED_SW (DD_FUSED_LANES - 2)
+#define DD_FUSED_VL (DD_FUSED_THREADS / DD_FUSED_LANES)
+#define DD_FUSED_PER (DD_FUSED_MAXN / DD_FUSED_VL)
 
 template <typename T>
 __device__ __forceinline__ c2<T> stencil_vals(c2<T> c, c2<T> w, c2<T> ea, c2<T> s, c2<T> n,
@@ -774,13 +781,12 @@ template <typename V> __device__ __forceinline__ V cfmac(V acc, V a, V b) {  // 
 }
 
 template <typename T, bool PC>
-__global__ __launch_bounds__(DD_FUSED_THREADS) void k_fused_sweep(PlanDev P, int j) {
+__global__ __launch_bounds__(DD_FUSED_THREADS, 4) void k_fused_sweep(PlanDev P, int j) {
   using V = c2<T>;
-  constexpr int NW = DD_FUSED_THREADS / 64;
-  constexpr int RW = DD_FUSED_THREADS + 2;    // ring row: cell x at index x + 1
+  constexpr int NVL = DD_FUSED_VL, PER = DD_FUSED_PER, L = DD_FUSED_LANES;
   const FusedTile tl = P.tiles[blockIdx.x];
   const int p = tl.p;
-  if (P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
+  if (p < 0 || P.stI[p * ST_NI + ST_ACTIVE] == 0) return;
   const ProbDesc d = P.desc[p];
   const int nx = d.nx, ny = d.ny;
   const size_t Dp = d.Dp;
@@ -790,168 +796,141 @@ __global__ __launch_bounds__(DD_FUSED_THREADS) void k_fused_sweep(PlanDev P, int
   V* qn = (V*)d.basis + (size_t)(P.kmax + j + 1) * Dp;       // q~_{j+1}
   const V* zin = (const V*)d.Z + (size_t)(j & 1) * Dp;       // z_j
   V* zout = (V*)d.Z + (size_t)((j + 1) & 1) * Dp;            // z_{j+1}
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int dir = tl.dir;
-  const int r0 = (dir > 0) ? tl.y0 : tl.y1 - 1;             // first row of the walk
-  const int nrows = tl.y1 - tl.y0;
+  const int vl = threadIdx.x / L, cl = threadIdx.x % L;
+  const int w = min(DD_FUSED_SW, nx - tl.x0);                // owned columns of the strip
+  const bool lane_ok = cl <= w + 1;                          // owned or halo column
+  const bool owned = cl >= 1 && cl <= w;
+  int c = tl.x0 - 1 + cl;                                    // this lane's column (wrapped)
+  c = (c < 0) ? c + nx : ((c >= nx) ? c - nx : c);
+  if (!lane_ok) c = 0;                                       // a valid address, value unused
+  const int y0 = tl.y0, nrows = tl.y1 - tl.y0;
   const T sj = (T)P.hscale[(size_t)p * (P.m + 1) + j];      // s_j
   __shared__ V coef[DD_FUSED_MAXN];
-  __shared__ V ring[3][RW];
-  __shared__ T accl[NW][2 * DD_FUSED_MAXN];
-  __shared__ T lds_un[NW];
+  __shared__ V part[NVL][L];
+  __shared__ V ring[3][L];                                   // q~_{j+1} on the last 3 rows
+  __shared__ V ringp[3][L];                                  // P_R q~_{j+1} (stencil input)
+  __shared__ V zrow[L];
   const double2* cB = P.coefB + (size_t)p * P.NC;
   for (int v = threadIdx.x; v < n; v += DD_FUSED_THREADS) coef[v] = to_c<T>(cB[v]);
-  for (int v = threadIdx.x; v < NW * 2 * DD_FUSED_MAXN; v += DD_FUSED_THREADS)
-    (&accl[0][0])[v] = T(0);
-  __syncthreads();
   const V* cf = OpP<T>::cf(d);
   const auto* epsp = OpP<T>::eps(d);
   const T om2 = (T)d.omega2;
   const V* pl = PC ? (const V*)d.pl : nullptr;
   const V* pr = PC ? (const V*)d.pr : nullptr;
-  const int x = lane + 64 * wave;                  // this thread's column
-  const bool ok = x < nx;
-  const int xc = ok ? x : 0;                       // a valid column for masked loads
-  const V cxm = cf[xc], cxp = cf[nx + xc];
-  const int xw = (xc == 0) ? nx - 1 : xc - 1, xe = (xc == nx - 1) ? 0 : xc + 1;
-  V zdot = cmk<V>(T(0), T(0));   // z_{j+1} of the row whose dots come next
-  T un2 = T(0);                  // ||q~_{j+1}||^2 over the tile
+  const V zero = cmk<V>(T(0), T(0));
+  V cxm = zero, cxp = zero;
+  if (vl == 0) {
+    cxm = cf[c];
+    cxp = cf[nx + c];
+  }
+  V bprev[PER], bcur[PER], bnext[PER], acc[PER];
   auto wrapy = [&](int y) { return (y < 0) ? y + ny : ((y >= ny) ? y - ny : y); };
-  // The walk as a sequence of batches (walk step t, group g of 16 basis
-  // vectors; the last group of a step also covers the new vector v = n).
-  // Batch b + 1's loads are issued before batch b is consumed, so that the
-  // memory system always holds one batch of every wave in flight.
-  const int G = (n + 16) / 16;
-  const int NB = (nrows + 3) * G;
-  auto load = [&](V (&bu)[16], V (&bd)[16], int b) {
-    const int t = b / G, g = b - t * G;
-    const bool upd = t <= nrows + 1, dot = t >= 3;
-    const size_t ru = (size_t)wrapy(r0 - dir + dir * t) * nx;
-    const size_t rd = (size_t)wrapy(r0 - 3 * dir + dir * t) * nx;
+  // unconditional loads from valid addresses (vector index clamped, invalid
+  // lanes at column 0), zeroed where they are used: a branch per load would
+  // make the compiler wait for each before issuing the next
+  auto load_row = [&](V (&dst)[PER], int t) {
+    const size_t r = (size_t)wrapy(y0 - 1 + t) * nx + c;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const V* bv = B + (size_t)min(16 * g + i, n - 1) * Dp;
-      if (upd) bu[i] = bv[ru + xc];
-      if (dot) bd[i] = bv[rd + xc];
-    }
+    for (int i = 0; i < PER; ++i) dst[i] = B[(size_t)min(vl + NVL * i, n - 1) * Dp + r];
   };
-  V pu = cmk<V>(T(0), T(0)), zv = pu;
-  T epsv = T(0);
-  V cym = pu, cyp = pu, plv = pu, prc = pu, prw = pu, pre = pu, prs = pu, prn = pu;
-  auto consume = [&](const V (&bu)[16], const V (&bd)[16], int b) {
-    const int t = b / G, g = b - t * G;
-    const bool upd = t <= nrows + 1, dot = t >= 3;
-    const bool st = (t >= 2 && t <= nrows + 1);   // stencil row of this step
-    const int yu = wrapy(r0 - dir + dir * t);
-    const int ys = wrapy(r0 + dir * (t - 2));
-    if (g == 0) {
-      // per-row values for the end of this step (their latency is covered by
-      // the step's groups)
-      pu = cmk<V>(T(0), T(0));
-      if (upd) zv = zin[(size_t)yu * nx + xc];
-      if (st) {
-        const int e = ys * nx + xc;
-        epsv = (T)epsp[e];
-        cym = cf[2 * nx + ys];
-        cyp = cf[2 * nx + ny + ys];
-        if (PC && pl) plv = pl[e];
-        if (PC && pr) {
-          const int ysm = (ys == 0) ? ny - 1 : ys - 1, ysp = (ys == ny - 1) ? 0 : ys + 1;
-          prc = pr[e];
-          prw = pr[ys * nx + xw];
-          pre = pr[ys * nx + xe];
-          prs = pr[ysm * nx + xc];
-          prn = pr[ysp * nx + xc];
-        }
-      }
-    }
-    T dv[32];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) dv[i] = T(0);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int v = 16 * g + i;
-      if (v < n) {
-        if (upd) pu = cfma(pu, coef[v], bu[i]);
-        if (dot) {
-          dv[2 * i] += bd[i].x * zdot.x + bd[i].y * zdot.y;
-          dv[2 * i + 1] += bd[i].x * zdot.y - bd[i].y * zdot.x;
-        }
-      } else if (v == n && dot) {
-        // the new vector q~_{j+1} at the dots row, still in the ring
-        const V bq = ring[(t - 2) % 3][xc + 1];
-        dv[2 * i] += bq.x * zdot.x + bq.y * zdot.y;
-        dv[2 * i + 1] += bq.x * zdot.y - bq.y * zdot.x;
-      }
-    }
-    if (dot) {
-      if (!ok) {
-#pragma unroll
-        for (int i = 0; i < 32; ++i) dv[i] = T(0);
-      }
-      butterfly_step<T, 32>(dv, lane);
-      const T sum = dv[0] + __shfl_xor(dv[0], 1, DD_WAVE);
-      if ((lane & 1) == 0) accl[wave][32 * g + (lane >> 1)] += sum;
-    }
-    if (g == G - 1) {
-      __syncthreads();
-      // q~_{j+1} on row yu (the band's own rows stored)
-      if (upd && ok) {
-        const V u = csub(cscale(zv, sj), pu);
-        ring[t % 3][x + 1] = u;
-        if (t >= 1 && t <= nrows) {
-          qn[(size_t)yu * nx + x] = u;
-          un2 += u.x * u.x + u.y * u.y;
-        }
-      }
-      __syncthreads();
-      // z_{j+1} = A q~_{j+1} on the row behind
-      if (st && ok) {
-        const V* rc = ring[(t - 1) % 3];
-        const V* rs = (dir > 0) ? ring[(t - 2) % 3] : ring[t % 3];   // row ys - 1
-        const V* rn = (dir > 0) ? ring[t % 3] : ring[(t - 2) % 3];   // row ys + 1
-        V uc = rc[x + 1], uw = rc[xw + 1], ue = rc[xe + 1], us = rs[x + 1], un = rn[x + 1];
-        if (PC && pr) {
-          uc = cmul(uc, prc);
-          uw = cmul(uw, prw);
-          ue = cmul(ue, pre);
-          us = cmul(us, prs);
-          un = cmul(un, prn);
-        }
-        V z = stencil_vals<T>(uc, uw, ue, us, un, cxm, cxp, cym, cyp, om2 * epsv);
-        if (PC && pl) z = cmul(plv, z);
-        zdot = z;
-        zout[ys * nx + x] = z;
-      }
-    }
-  };
-  V bA[16], dA[16], bB[16], dB[16];
-  load(bA, dA, 0);
-  for (int b = 0; b < NB; b += 2) {
-    if (b + 1 < NB) load(bB, dB, b + 1);
-    consume(bA, dA, b);
-    if (b + 1 < NB) {
-      if (b + 2 < NB) load(bA, dA, b + 2);
-      consume(bB, dB, b + 1);
-    }
-  }
-  // ---- partial row: dots d_v (v <= n), then ||q~_{j+1}||^2
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) un2 += __shfl_xor(un2, o, DD_WAVE);
-  if (lane == 0) lds_un[wave] = un2;
+  for (int i = 0; i < PER; ++i) { bprev[i] = zero; acc[i] = zero; }
+  V accn = zero;                 // dots of the new vector (vl = 0 lanes)
+  T un2 = T(0);                  // ||q~_{j+1}||^2 over the tile's owned cells
+  load_row(bcur, 0);
   __syncthreads();
-  T* prow = (T*)P.partial + (size_t)blockIdx.x * P.NV;
-  for (int v = threadIdx.x; v < 2 * (n + 1); v += DD_FUSED_THREADS) {
-    T sum = T(0);
+  for (int t = 0; t <= nrows + 1; ++t) {
+    const int yu = wrapy(y0 - 1 + t);
+    const size_t ru = (size_t)yu * nx + c;
+    // the next row's values are in flight during this step
+    if (t <= nrows) load_row(bnext, t + 1);
 #pragma unroll
-    for (int w = 0; w < NW; ++w) sum += accl[w][v];
-    prow[v] = sum;
+    for (int i = 0; i < PER; ++i)
+      if (!(vl + NVL * i < n && lane_ok)) bcur[i] = zero;
+    // (a) the update of row yu: this thread's share of sum_v g_v b_v
+    V pu = zero;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int v = vl + NVL * i;
+      pu = cfma(pu, coef[min(v, n - 1)], bcur[i]);
+    }
+    part[vl][cl] = pu;
+    V zj = zero, prv = zero;
+    if (vl == 0 && lane_ok) {
+      zj = zin[ru];
+      if (PC && pr) prv = pr[ru];
+    }
+    __syncthreads();
+    if (vl == 0) {
+      V sum = zero;
+#pragma unroll
+      for (int q = 0; q < NVL; ++q) sum = cadd(sum, part[q][cl]);
+      const V u = csub(cscale(zj, sj), sum);
+      ring[t % 3][cl] = u;
+      ringp[t % 3][cl] = (PC && pr) ? cmul(u, prv) : u;
+      if (owned && t >= 1 && t <= nrows) {
+        qn[ru] = u;
+        un2 += u.x * u.x + u.y * u.y;
+      }
+    }
+    __syncthreads();
+    // (b) z_{j+1} = A q~_{j+1} on row ys = yu - 1, then its dots against the
+    // basis row fetched at the step before
+    if (t >= 2) {
+      const int ys = y0 + t - 2;
+      if (vl == 0) {
+        V z = zero;
+        if (owned) {
+          const size_t rs = (size_t)ys * nx + c;
+          const V* rc = ringp[(t - 1) % 3];
+          z = stencil_vals<T>(rc[cl], rc[cl - 1], rc[cl + 1], ringp[(t - 2) % 3][cl],
+                              ringp[t % 3][cl], cxm, cxp, cf[2 * nx + ys], cf[2 * nx + ny + ys],
+                              om2 * (T)epsp[rs]);
+          if (PC && pl) z = cmul(pl[rs], z);
+          zout[rs] = z;
+          accn = cfmac(accn, ring[(t - 1) % 3][cl], z);
+        }
+        zrow[cl] = z;
+      }
+      __syncthreads();
+      const V zc = zrow[cl];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) acc[i] = cfmac(acc[i], bprev[i], zc);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      bprev[i] = bcur[i];
+      bcur[i] = bnext[i];
+    }
   }
-  if (threadIdx.x == 0) {
-    T sum = T(0);
+  // ---- partial row: dots d_v (v <= n), then ||q~_{j+1}||^2, folded over the
+  // column lanes of each vector lane in a fixed order
 #pragma unroll
-    for (int w = 0; w < NW; ++w) sum += lds_un[w];
-    prow[2 * (n + 1)] = sum;
+  for (int o = L / 2; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      acc[i].x += __shfl_xor(acc[i].x, o, DD_WAVE);
+      acc[i].y += __shfl_xor(acc[i].y, o, DD_WAVE);
+    }
+    accn.x += __shfl_xor(accn.x, o, DD_WAVE);
+    accn.y += __shfl_xor(accn.y, o, DD_WAVE);
+    un2 += __shfl_xor(un2, o, DD_WAVE);
+  }
+  T* prow = (T*)P.partial + (size_t)tl.row * P.NV;
+  if (cl == 0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int v = vl + NVL * i;
+      if (v < n) {
+        prow[2 * v] = acc[i].x;
+        prow[2 * v + 1] = acc[i].y;
+      }
+    }
+    if (vl == 0) {
+      prow[2 * n] = accn.x;
+      prow[2 * n + 1] = accn.y;
+      prow[2 * (n + 1)] = un2;
+    }
   }
 }
 

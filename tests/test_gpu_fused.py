@@ -2,8 +2,9 @@
 pass) against the CPU oracle.
 
 complex128: residual histories against the oracle's literal block least
-squares (plain, augmented, preconditioned), a batch of uneven grids (bands of
-several sizes, rows up to one workgroup's 512 cells) and the solutions.
+squares (plain, augmented, preconditioned), a batch of uneven grids (strips of
+30 columns with a ragged last strip, bands of several heights, halos across
+the periodic wrap) and the solutions.
 complex64: the 480 x 240 grating to 1e-6 against sparse LU, graph replay
 identical to direct launches, and the fused and two-sweep paths side by side."""
 import numpy as np
@@ -43,8 +44,9 @@ def _solve(insts, Vs, restart, steps, inner="c128", fused=True, **kw):
 @pytest.mark.parametrize("restart", [9, 40])
 @pytest.mark.parametrize("nx,ny", [(20, 16), (70, 24)])
 def test_fused_history_matches_oracle(nx, ny, restart, k):
-    """One problem; bands of a few rows (several tiles, both walk directions,
-    halo rows across the periodic wrap)."""
+    """One problem: a single strip narrower than 30 columns (20 x 16, its halo
+    columns wrapping onto its own cells) and three strips with a ragged last
+    one (70 x 24); halo rows across the periodic wrap."""
     inst = _inst(400 + nx + k, nx, ny)
     A = fdfd.assemble_instance(inst)
     V = W.random_complex(np.random.default_rng(41 + k), (inst.D, k)) if k else None

@@ -158,3 +158,43 @@ def test_recycle_reports_misuse():
     with pytest.raises(DDError):
         f.recycle(4)                                   # one-sweep path keeps no normalised basis
     f.close()
+
+
+def test_recycle_edge_cases():
+    """A problem already solved at the start (x0 exact: no cycle runs) keeps
+    only its augmenting vectors' span; a short last cycle gives fewer vectors
+    than asked for; a duplicated augmenting column is dropped and recycling
+    works on the kept ones."""
+    import torch
+    from paper_1902_00090_amd import FdfdOp, Solver
+    insts = [W.grating(1400 + i, nx=48, ny=32, npml=6) for i in range(2)]
+    ops = [FdfdOp.from_instance(i) for i in insts]
+    bs = [torch.tensor(i.b, dtype=torch.complex128, device="cuda") for i in insts]
+    from oracle import direct, fdfd
+    s = Solver(ops, restart=12, kmax=6, inner="c128", cgs_passes=2)
+    # problem 1 starts from its exact solution (sparse LU): no cycle and no
+    # subspace, so nothing to recycle
+    x1 = torch.tensor(direct.sparse_solve(fdfd.assemble_instance(insts[1]), insts[1].b),
+                      dtype=torch.complex128, device="cuda")
+    _, infos, _ = s.solve(bs, x0=[torch.zeros_like(bs[0]), x1], tol=1e-9, maxit=300)
+    assert infos[1]["iters"] == 0 and infos[0]["iters"] > 12
+    Y, th = s.recycle(3)
+    assert Y[0].shape[0] == 3 and Y[1].shape[0] == 0
+    # a short cycle: 2 steps give at most 2 vectors
+    s.solve(bs, tol=0.0, maxit=2)
+    Y, th = s.recycle(5)
+    assert Y[0].shape[0] == 2 and Y[1].shape[0] == 2
+    assert np.all(np.isfinite(th[:, :2])) and np.all(th[:, 2:] == 0)
+    # a duplicated column is dropped (k_used 3 of 4); recycling uses the kept 3
+    rng = np.random.default_rng(1)
+    v = torch.tensor(W.random_complex(rng, (3, insts[0].D)), device="cuda")
+    U = torch.cat([v, v[:1]]).contiguous()
+    s.set_subspace([U, U])
+    _, infos, _ = s.solve(bs, tol=0.0, maxit=12)
+    assert infos[0]["k_used"] == 3
+    Y, th = s.recycle(6)
+    assert Y[0].shape[0] == 6 and torch.isfinite(torch.view_as_real(Y[0])).all()
+    A = fdfd.assemble_instance(insts[0])
+    y = Y[0].cpu().numpy().T
+    np.testing.assert_allclose(np.linalg.norm(A @ y, axis=0), 1.0, rtol=1e-9)
+    s.close()
