@@ -387,8 +387,9 @@ def single_leg(args, torch, ops, bs, U):
 
 
 def precond_leg(args, torch, ops, bs, U):
-    """The evaluation batch with the supplement's diagonal preconditioners
-    (Jacobi; PML grid-spacing scaling), without and with the PCA basis."""
+    """Two C4 test batches with the supplement's diagonal preconditioners
+    (Jacobi; PML grid-spacing scaling), without and with the PCA basis, to
+    args.tol."""
     from paper_1902_00090_amd import Solver
     B = len(ops)
     out = {}
@@ -1084,8 +1085,9 @@ def main():
 
     # ---------------- plain GMRES on the same batches (tol_acc and 1e-6)
     plain = None
-    if args.plain_batches > 0:
-        pb = list(range(min(args.plain_batches, nbat)))
+    # batches the timed steps covered (their augmented times are known)
+    pb = [bi for bi in range(min(args.plain_batches, nbat)) if bi in t_batch]
+    if pb:
         ps = Solver(ops[:B], restart=args.restart, cgs_passes=args.cgs, hist_cap=args.maxit,
                     elems_per_thread=-1)
         pinf, phist, pt, pt6, xp, xp6 = [], [], 0.0, 0.0, {}, {}
@@ -1139,6 +1141,9 @@ def main():
             log(f"  oracle check {p}: {e}")
 
     c4rec = c4_recycle_leg(args, torch, test, U) if args.c4_recycle > 0 else None
+    # the supplement's diagonal preconditioners on the first two C4 batches
+    pre = (precond_leg(args, torch, ops[:2 * B], bs[:2 * B], U)
+           if args.precond and nbat >= 2 else None)
 
     # ---------------- C1 and C2 beside their oracle figures
     c1 = None if args.no_c1 else c1_leg(args, torch, W)
@@ -1148,8 +1153,8 @@ def main():
         c2 = c2_leg(args, torch, W, U, ref2)
 
     # ---------------- optional legs
-    cnn = pre = rec = uneven = None
-    if args.cnn or args.precond:
+    cnn = rec = uneven = None
+    if args.cnn:
         data = W.trajectory_dataset(args.traj, args.traj_steps)
         tr_idx, te_idx = W.split_train_test(len(data))
         ctrain = [data[i] for i in tr_idx]
@@ -1166,8 +1171,6 @@ def main():
             cnn = {m: cnn_leg(args, torch, W, data, tr_idx, ctrain, ctest, Smat, cops, cbs, cxs,
                               U, None, None, m) for m in modes}
             del Smat
-        if args.precond:
-            pre = precond_leg(args, torch, cops, cbs, U)
     if args.recycle > 0:
         rec = recycle_leg(args, torch, W)
     c5 = c5_leg(args, torch, W) if args.c5 else None
