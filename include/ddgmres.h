@@ -240,10 +240,12 @@ dd_status dd_solver_history(const dd_solver* s, int p, double* out, int cap, int
  * on the host in FP64, one host thread per problem up to 16.  Allocates
  * device scratch of about 16 (kmax + restart + 1) kmax + 16 kr (kmax +
  * restart) bytes per problem and frees it; synchronises the stream.
- * Errors: DD_EINVAL (kr outside 1..64, NULL arguments, the fused one-sweep
- * path or a preconditioner in use, or no solve since the last set_subspace,
- * bind or solve error), DD_ENONFINITE (a rank-deficient small problem or
- * no Schur convergence), DD_ENOMEM / DD_EHIP. */
+ * Works on both Arnoldi paths (two sweeps, or one sweep with every Krylov
+ * vector stored unnormalised, which the dots and the combination rescale).
+ * Errors: DD_EINVAL (kr outside 1..64, NULL arguments, a preconditioner in
+ * use, or no solve since the last set_subspace, bind or solve error),
+ * DD_ENONFINITE (a rank-deficient small problem or no Schur convergence),
+ * DD_ENOMEM / DD_EHIP. */
 dd_status dd_solver_recycle(dd_solver* s, int kr, void* const* Y, int* kout, double* theta,
                             hipStream_t stream);
 

@@ -22,8 +22,8 @@
 
 // X[p][a][i] = W_a^H V_i in FP64, a < k + nq[p], i < k, in 4 x 4 tiles
 // (one workgroup per tile pair and problem, over the whole field).  W_a is
-// the C slot a for a < k and the Krylov vector q_{a-k} otherwise; the last
-// one, q_n, is stored unnormalised and scaled by hscale[n] here.
+// the C slot a for a < k and the Krylov vector q_{a-k} otherwise, scaled here
+// by hscale where it is stored unnormalised.
 template <typename T>
 __global__ __launch_bounds__(DD_BLOCK) void k_recycle_dots(PlanDev P, const int* __restrict__ nq,
                                                            double2* __restrict__ X, int rows) {
@@ -47,7 +47,9 @@ __global__ __launch_bounds__(DD_BLOCK) void k_recycle_dots(PlanDev P, const int*
       wp[q] = basis + (size_t)(P.kmax - k + a) * d.Dp;
     } else if (a < nw) {
       wp[q] = basis + (size_t)(P.kmax + a - k) * d.Dp;
-      if (a - k == nq[p] - 1) ws[q] = P.hscale[(size_t)p * (P.m + 1) + (a - k)];
+      // stored unnormalised: the last vector always, every vector on the
+      // one-sweep path (q_i = s_i q~_i)
+      if (a - k == nq[p] - 1 || P.fused) ws[q] = P.hscale[(size_t)p * (P.m + 1) + (a - k)];
     }
     vp[q] = (i < k) ? Vb + (size_t)i * d.Dp : nullptr;
   }
@@ -134,8 +136,8 @@ struct ProbIn {
 // The small problem of one problem p; fills cf ([kr][ldc] complex, first k
 // entries over the V slots, then n over q_0..q_{n-1}), theta and kout.
 bool small_problem(const ProbIn& in, int K, int m, int rows, int kr, const double2* X,
-                   const double2* Hraw, const double2* Bc, const double2* Ri, int ldc,
-                   double2* cf, double* theta, int& kout) {
+                   const double2* Hraw, const double2* Bc, const double2* Ri, const double* hs,
+                   bool fused, int ldc, double2* cf, double* theta, int& kout) {
   const int kk = (int)in.kept.size(), n = in.n, k = in.k;
   const int ns = kk + n, nw = kk + (n > 0 ? n + 1 : 0);
   kout = std::min(kr, ns);
@@ -180,7 +182,9 @@ bool small_problem(const ProbIn& in, int K, int m, int rows, int kr, const doubl
       co[i] = make_double2(s.real(), s.imag());
     }
     for (int j = 0; j < n; ++j) {
-      const cd z = Z[(size_t)(kk + j) * kout + o];
+      // the combination reads the stored vectors: q~_j = q_j / s_j on the
+      // one-sweep path
+      const cd z = Z[(size_t)(kk + j) * kout + o] * (fused ? hs[j] : 1.0);
       co[k + j] = make_double2(z.real(), z.imag());
     }
     theta[2 * o] = th[o].real();
@@ -213,10 +217,6 @@ extern "C" dd_status dd_solver_recycle(dd_solver* s, int kr, void* const* Y, int
   if (!s || !Y || !kout) { dd_set_error("dd_solver_recycle: NULL argument"); return DD_EINVAL; }
   if (kr < 1 || kr > DD_MAX_K) {
     dd_set_error("dd_solver_recycle: kr = %d outside 1..%d", kr, DD_MAX_K);
-    return DD_EINVAL;
-  }
-  if (s->fused) {
-    dd_set_error("dd_solver_recycle: needs the two-sweep Arnoldi path (opts.fused = 0)");
     return DD_EINVAL;
   }
   if (s->o.precond != DD_PRECOND_NONE) {
@@ -298,7 +298,8 @@ extern "C" dd_status dd_solver_recycle(dd_solver* s, int kr, void* const* Y, int
     for (int p = t0; p < nb; p += nthr)
       ok[p] = small_problem(in[p], K, m, rows, kr, X.data() + (size_t)p * rows * std::max(K, 1),
                             Hraw.data() + (size_t)p * m * (m + 1), Bc.data() + (size_t)p * m * K,
-                            Ri.data() + (size_t)p * K * K, ldc, cf.data() + (size_t)p * kr * ldc,
+                            Ri.data() + (size_t)p * K * K, hs.data() + (size_t)p * (m + 1),
+                            s->fused, ldc, cf.data() + (size_t)p * kr * ldc,
                             th.data() + (size_t)p * kr * 2, ko[p]);
   };
   if (nthr == 1) {

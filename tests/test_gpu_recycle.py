@@ -46,10 +46,11 @@ def _span_gap(Y1, Y2):
     return np.linalg.norm(Q1 - Q2 @ (Q2.conj().T @ Q1))
 
 
-def _run_sequence(trajs, kr, m, tol, maxit):
+def _run_sequence(trajs, kr, m, tol, maxit, fused=False):
     """GPU: the recycled sequence of each trajectory, all trajectories in one
-    complex128 batch (two Gram-Schmidt passes).  Per step: (x, infos,
-    histories) and, for all but the last step, (Y, theta) passed on."""
+    complex128 batch (two Gram-Schmidt passes; one on the one-sweep path).
+    Per step: (x, infos, histories) and, for all but the last step, (Y,
+    theta) passed on."""
     import torch
     from paper_1902_00090_amd import FdfdOp, Solver
     solver, Y, out = None, None, []
@@ -57,7 +58,8 @@ def _run_sequence(trajs, kr, m, tol, maxit):
         ops = [FdfdOp.from_instance(tr[s]) for tr in trajs]
         bs = [torch.tensor(tr[s].b, dtype=torch.complex128, device="cuda") for tr in trajs]
         if solver is None:
-            solver = Solver(ops, restart=m, kmax=kr, inner="c128", cgs_passes=2, hist_cap=maxit)
+            solver = Solver(ops, restart=m, kmax=kr, inner="c128", cgs_passes=1 if fused else 2,
+                            hist_cap=maxit, fused=fused)
         else:
             solver.bind(ops)
         solver.set_subspace(Y)
@@ -75,8 +77,8 @@ def _run_sequence(trajs, kr, m, tol, maxit):
 TRAJS = [(7000, 700000, 24, 16), (7004, 700100, 20, 16)]
 
 
-@pytest.mark.parametrize("kr", [4, 7])
-def test_harmonic_ritz_recycling_matches_the_oracle_c128(kr):
+@pytest.mark.parametrize("kr,fused", [(4, False), (7, False), (4, True)])
+def test_harmonic_ritz_recycling_matches_the_oracle_c128(kr, fused):
     """Element-wise parity over short solves (two full GMRES(15) cycles per
     step, so rounding has not yet reordered the iterations): two trajectories
     of three steps on grids of two sizes in one complex128 batch.  Per step the
@@ -85,7 +87,7 @@ def test_harmonic_ritz_recycling_matches_the_oracle_c128(kr):
     span the oracle's space (gap 1e-8) with ||A y|| = 1."""
     m, maxit = 15, 30
     trajs = [W.trajectory(b, s0, 3, nx, ny, 1.30, npml=3) for b, s0, nx, ny in TRAJS]
-    gpu = _run_sequence(trajs, kr, m, 1e-14, maxit)
+    gpu = _run_sequence(trajs, kr, m, 1e-14, maxit, fused)
     for t, tr in enumerate(trajs):
         As = [fdfd.assemble_instance(i) for i in tr]
         seq = recycle.solve_sequence(As, [i.b for i in tr], kr=kr, restart=m, tol=1e-14,
@@ -153,10 +155,10 @@ def test_recycle_reports_misuse():
     with pytest.raises(ValueError):
         s.recycle(0)
     s.close()
-    f = Solver([op], restart=10, kmax=4, cgs_passes=1, fused=True)
+    f = Solver([op], restart=10, kmax=4, precond="pml")
     f.solve(b, tol=1e-3, maxit=200)
     with pytest.raises(DDError):
-        f.recycle(4)                                   # one-sweep path keeps no normalised basis
+        f.recycle(4)                                   # the preconditioned operator is not A
     f.close()
 
 
