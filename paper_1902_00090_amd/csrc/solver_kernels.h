@@ -873,9 +873,10 @@ __global__ __launch_bounds__(DD_FUSED_THREADS, 4) void k_fused_sweep(PlanDev P, 
         un2 += u.x * u.x + u.y * u.y;
       }
     }
-    __syncthreads();
     // (b) z_{j+1} = A q~_{j+1} on row ys = yu - 1, then its dots against the
-    // basis row fetched at the step before
+    // basis row fetched at the step before.  The ring is written and read
+    // only by the vl = 0 lanes, which are one wave (lanes 0-31 of wave 0), so
+    // it needs no barrier of its own.
     if (t >= 2) {
       const int ys = y0 + t - 2;
       if (vl == 0) {
