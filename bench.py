@@ -64,11 +64,28 @@ def measured_traffic():
     return None
 
 
+def _function_text(src, head):
+    """The text of the function whose definition starts at `head` (its
+    template line included), up to its closing brace at column 0."""
+    a = src.index(head)
+    a = src.rfind("template <", 0, a) if "template <" in src[max(0, a - 80):a] else a
+    return src[a:src.index("\n}\n", a) + 3]
+
+
 def kernel_sources_hash():
+    """First 16 hex digits of the SHA-256 of the dominant sweep's own source:
+    k_matvec_dot and block_dots (csrc/solver_kernels.h) and the headers they
+    build on (csrc/op.h, csrc/common.h)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("solver_kernels.h", "op.h", "common.h"):
-        with open(os.path.join(ROOT, "paper_1902_00090_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_1902_00090_amd", "csrc")
+    with open(os.path.join(csrc, "solver_kernels.h")) as fh:
+        src = fh.read()
+    for head in ("__device__ __forceinline__ void block_dots(",
+                 "__global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot("):
+        h.update(_function_text(src, head).encode())
+    for f in ("op.h", "common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
