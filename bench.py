@@ -519,8 +519,8 @@ def c4_recycle_leg(args, torch, test, U):
 
 def uneven_leg(args, torch, W):
     """8 trajectories x 32 steps of uneven grids (192x96, 320x160, 480x240;
-    1.30 / 1.55 um) in one lockstep batch, plain complex64 GMRES, step groups
-    replayed as HIP graphs."""
+    1.30 / 1.55 um) in one lockstep batch, plain complex64 GMRES to tol_acc,
+    step groups replayed as HIP graphs."""
     from paper_1902_00090_amd import FdfdOp, Solver
     insts = W.correlated_batch(8, 32)
     ops = [FdfdOp.from_instance(i) for i in insts]
@@ -529,13 +529,20 @@ def uneven_leg(args, torch, W):
     s = Solver(ops, restart=args.restart, cgs_passes=args.cgs, use_graph=True)
     torch.cuda.synchronize()
     t0 = time.time()
-    _, inf, st = s.solve(bs, tol=args.tol, maxit=args.maxit, x=xs)
+    # to tol_acc, where the error bound meets 1e-5 (as the headline)
+    _, inf, st = s.solve(bs, tol=args.tol_acc, maxit=args.maxit, x=xs)
     torch.cuda.synchronize()
     dt = time.time() - t0
     s.close()
     it = np.array([i["iters"] for i in inf])
     mv = sum(i["matvecs"] for i in inf)
     cells = sum(i.D for i in insts)
+    # error against the oracle's sparse LU on one problem of each grid size
+    errs = {}
+    for p, inst in enumerate(insts):
+        key = f"{inst.nx}x{inst.ny}"
+        if key not in errs:
+            errs[key] = rel_err(xs[p].cpu().numpy(), oracle_reference(inst)["x"])
     alg = sum(arnoldi_bytes(p.D, i["iters"], args.restart, 0, args.cgs) + 52 * p.D * i["restarts"]
               for i, p in zip(inf, insts))
     out = {
@@ -547,6 +554,7 @@ def uneven_leg(args, torch, W):
         "worst_rel_res_true": max(i["rel_res_true"] for i in inf),
         "algorithmic_GB_per_s_whole_solve": round(alg / dt / 1e9, 1),
         "hbm_frac_whole_solve": round(alg / dt / 1e9 / HBM_PEAK_GBS, 4),
+        "error_vs_sparse_lu": errs,
     }
     log(f"uneven batch: {len(insts)} problems, {cells} cells, {dt:.1f}s, iters "
         f"{out['iters_min_mean_max']}, {out['algorithmic_GB_per_s_whole_solve']} GB/s")
@@ -727,6 +735,7 @@ def c5_leg(args, torch, W):
         Upca = None
     EB = args.c5_eval_batch
     res = {}
+    first_two = {}
     xs_plain = [None] * len(test)
     for mode in args.c5_modes.split(","):
         if mode == "pca" and Upca is None:
@@ -752,6 +761,8 @@ def c5_leg(args, torch, W):
             if mode == "plain":
                 for j, x in enumerate(xs):
                     xs_plain[b0 + j] = x.clone()
+            if b0 == 0:
+                first_two[mode] = [xs[0].cpu().numpy(), xs[1].cpu().numpy()]
             sv.close()
             log(f"  C5 eval {mode}: {b0 + len(part)}/{len(test)}, {secs:.0f}s")
         res[mode] = {"solves_per_s": round(len(test) / secs, 4),
@@ -773,6 +784,9 @@ def c5_leg(args, torch, W):
         refs = [oracle_reference(test[p]) for p in range(2)]
         res["error_vs_sparse_lu_plain"] = [rel_err(xs_plain[p].cpu().numpy(), refs[p]["x"])
                                            for p in range(2)]
+        for mode, xl in first_two.items():
+            res[mode]["error_vs_sparse_lu_first_two"] = [rel_err(xl[p], refs[p]["x"])
+                                                         for p in range(2)]
     out["eval"] = res
     net.close()
     return out
