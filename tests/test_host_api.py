@@ -179,3 +179,45 @@ def test_recycling_small_problem_rejects_bad_sizes():
         harmonic_ritz_host(G, G, 4)           # kr > ns
     with pytest.raises(DDError):
         harmonic_ritz_host(np.zeros((4, 3), np.complex128), G, 2)   # rank-deficient G
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_small_harmonic_ritz_problem_against_generalized_eig(seed):
+    """The host eigen-solver of recycling (Householder least squares,
+    Hessenberg QR, Schur reordering) on random problems of sizes 1 to 40,
+    square and overdetermined: the harmonic Ritz values equal scipy's
+    generalized eigenvalues of (G^H G, G^H M) of smallest magnitude, and the
+    returned columns span the same invariant subspace with ||G z|| = 1."""
+    import scipy.linalg as sla
+    from paper_1902_00090_amd import harmonic_ritz_host
+    rng = np.random.default_rng(100 + seed)
+    ns = int(rng.integers(1, 41))
+    nw = ns + int(rng.integers(0, 2))
+    kr = int(rng.integers(1, ns + 1))
+    G = rng.standard_normal((nw, ns)) + 1j * rng.standard_normal((nw, ns))
+    M = rng.standard_normal((nw, ns)) + 1j * rng.standard_normal((nw, ns))
+    Z, th = harmonic_ritz_host(G, M, kr)
+    w, U = sla.eig(G.conj().T @ G, G.conj().T @ M)
+    order = np.argsort(np.abs(w), kind="stable")
+    np.testing.assert_allclose(np.sort_complex(th), np.sort_complex(w[order[:kr]]), rtol=1e-8)
+    np.testing.assert_allclose(np.linalg.norm(G @ Z, axis=0), 1.0, rtol=1e-10)
+    if kr < ns and abs(abs(w[order[kr - 1]]) - abs(w[order[kr]])) > 1e-6 * abs(w[order[kr]]):
+        Qa, _ = np.linalg.qr(U[:, order[:kr]])
+        Qb, _ = np.linalg.qr(Z)
+        assert np.linalg.norm(Qb - Qa @ (Qa.conj().T @ Qb)) <= 1e-7
+
+
+def test_small_harmonic_ritz_problem_with_repeated_eigenvalues():
+    """G = I (square) and M = diag with repeated entries: T = M, whose
+    eigenvalues of largest magnitude (smallest 1/theta) come out exactly,
+    including a repeated one, and the basis lies in their eigenspace."""
+    from paper_1902_00090_amd import harmonic_ritz_host
+    d = np.array([1.0, 3.0, 3.0, 0.5, 2.0, 3.0], np.complex128)
+    G = np.eye(6, dtype=np.complex128)
+    M = np.diag(d)
+    Z, th = harmonic_ritz_host(G, M, 3)
+    np.testing.assert_allclose(th, 1.0 / 3.0 * np.ones(3), rtol=1e-12)
+    # the span is that of e_1, e_2, e_5 (the entries equal to 3)
+    P = np.zeros((6, 6))
+    P[[1, 2, 5], [1, 2, 5]] = 1.0
+    np.testing.assert_allclose(P @ Z, Z, atol=1e-12)
