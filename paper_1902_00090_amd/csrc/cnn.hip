@@ -688,186 +688,54 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
 }
 
 // --------------------------------------------------- weight gradients ----
-// Weight gradients of a 3x3 layer of any map (stride 1, stride 2, upsampling)
-// as GEMMs over stages of 32 S consecutive output pixels (flattened b, y, x
-// order; the last stage is ragged).  Work items: (pixel slice, channel block
-// of NB = 16 NT input channels, dy), dy fastest.  Per stage the workgroup
-// stages in LDS,
-// transposed to [channel][pixel]:
+// Weight gradients of a 3x3 layer (stride 1, stride 2 or upsampling) as GEMMs
+// dW[tap][r][c] = sum_p dz[p][r] in[src(p, tap)][c] over stages of PX = 32 S
+// pixels of one output row (the last chunk of a row is ragged).  Work items:
+// (pixel slice, channel block of NB = 16 NT input channels, dy), dy fastest,
+// or with ND = 3 (slice, channel block) taking all three dy.  Per stage the
+// workgroup stages in LDS, transposed to [channel][pixel]:
 //  * dz of the stage, all Mr = 16 MT output channels;
-//  * for the three taps (dy, 0..2), the layer input at each pixel's source,
-//    NB channels from channel n0.
+//  * per dy, the input row the stage reads, NB channels from channel n0,
+//    once for the three dx taps:
+//    - stride 1 (MK = MAP_S1): input columns x0 - 8 .. x0 + PX + 7 at columns
+//      0 .. PX + 15; dx reads at shifts -1, 0, +1;
+//    - upsampling (MAP_UP): the same, the source row expanded x2 while
+//      staging;
+//    - stride 2 (MAP_S2): output pixel p reads input columns 2p - 1, 2p and
+//      2p + 1, so the row is split by parity: odd columns 2j + 1 (j = x0 - 1 ..
+//      x0 + PX - 1) at columns j - x0 + 8, even columns 2j (j = x0 ..
+//      x0 + PX - 1) at columns PX + 8 + j - x0.  dx = 2 and dx = 1 read the
+//      odd and even halves aligned, dx = 0 the odd half shifted by one.  The
+//      one odd column left of the chunk (2 x0 - 1) is loaded by a thread of
+//      its own rather than as a block of 8.
 // A staging block is 8 pixels x 8 channels: loaded with 16-byte reads,
-// transposed in registers, stored with 16-byte writes.  The next stage's
-// blocks are loaded while the current stage's MFMAs run.  Partials:
-// weights [slice][tap][r][c], bias [slice][r].
-template <int MT, int NT, int S>
-__global__ __launch_bounds__(256) void k_conv_wgrad_seg(const bf16* __restrict__ dz,
-                                                        const bf16* __restrict__ x, int B,
-                                                        int Hout, int Wout, int Hin, int Win,
-                                                        int Nc, int mode, int stages_per,
-                                                        int nwork, float* __restrict__ part,
-                                                        float* __restrict__ bpart) {
-  constexpr int Mr = 16 * MT, NB = 16 * NT, PX = 32 * S, LD = PX + 8;
-  constexpr int ABLK = (PX / 8) * (Mr / 8);         // dz blocks of a stage
-  constexpr int XBLK = 3 * (PX / 8) * (NB / 8);     // input blocks of a stage (3 taps)
-  constexpr int NBLK = ABLK + XBLK, BPT = (NBLK + 255) / 256;
-  constexpr int NTILE = 3 * MT * NT, PER_WAVE = (NTILE + 3) / 4;
-  __shared__ __attribute__((aligned(16))) bf16 As[Mr][LD];
-  __shared__ __attribute__((aligned(16))) bf16 Xs[3][NB][LD];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // 1D grid, a multiple of 8 long: consecutive work items (the three dy and
-  // the channel blocks of one pixel slice) go to the same XCD, whose L2 then
-  // serves their shared dz and input rows.
-  const int w = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-  if (w >= nwork) return;
-  const int nblk = Nc / NB;
-  const int dy = w % 3, n0 = ((w / 3) % nblk) * NB, slice = w / (3 * nblk);
-  const int HW = Hout * Wout, npix = B * HW, nst = (npix + PX - 1) / PX;
-  const int s0 = slice * stages_per, s1 = min(nst, s0 + stages_per);
-  bf16x8 reg[BPT][8];
-  auto load = [&](int sg) {
-#pragma unroll
-    for (int bi = 0; bi < BPT; ++bi) {
-      const int blk = threadIdx.x + 256 * bi;
-      const bool isA = blk < ABLK;
-      int pg, cg, dx = 0;
-      if (isA) {
-        pg = blk / (Mr / 8); cg = (blk % (Mr / 8)) * 8;
-      } else {
-        const int r = blk - ABLK, r2 = r % ((PX / 8) * (NB / 8));
-        dx = r / ((PX / 8) * (NB / 8)); pg = r2 / (NB / 8); cg = (r2 % (NB / 8)) * 8;
-      }
-      int p = sg * PX + pg * 8;
-      int b = p / HW, rem = p - b * HW, y = rem / Wout, xx = rem - y * Wout;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        // out-of-range reads go to dz[0] and are zeroed after the load, so
-        // every load is issued unconditionally
-        int ys = 0, xs = 0;
-        const bool src_ok = isA || fwd_src(mode, y, xx, dy, dx, Hin, Win, Hout, Wout, ys, xs);
-        const bool ok = blk < NBLK && p < npix && src_ok;
-        const bf16* ptr = !ok ? dz
-                          : isA ? dz + (size_t)p * Mr + cg
-                                : x + ((size_t)(b * Hin + ys) * Win + xs) * Nc + n0 + cg;
-        const bf16x8 v = load8(ptr);
-        reg[bi][i] = ok ? v : zero8();
-        ++p;
-        if (++xx == Wout) { xx = 0; if (++y == Hout) { y = 0; ++b; } }
-      }
-    }
-  };
-  f32x4 acc[PER_WAVE];
-#pragma unroll
-  for (int i = 0; i < PER_WAVE; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // the slice's (dy 0, first channel block) item also sums dz over its pixels
-  // (the bias gradient) as dz^T times a column of ones
-  constexpr int BT = (MT + 3) / 4;
-  const bool bias = (dy == 0 && n0 == 0);
-  f32x4 accb[BT];
-#pragma unroll
-  for (int i = 0; i < BT; ++i) accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bf16x8 ones;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.f;
-  const int kq = 8 * (lane >> 4);
-  if (s0 < s1) load(s0);
-  for (int sg = s0; sg < s1; ++sg) {
-    __syncthreads();
-#pragma unroll
-    for (int bi = 0; bi < BPT; ++bi) {
-      const int blk = threadIdx.x + 256 * bi;
-      if (blk < NBLK) {
-        bf16* dst;
-        if (blk < ABLK) {
-          dst = &As[(blk % (Mr / 8)) * 8][(blk / (Mr / 8)) * 8];
-        } else {
-          const int r = blk - ABLK, r2 = r % ((PX / 8) * (NB / 8));
-          dst = &Xs[r / ((PX / 8) * (NB / 8))][(r2 % (NB / 8)) * 8][(r2 / (NB / 8)) * 8];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          bf16x8 w;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) w[i] = reg[bi][i][q];
-          *(bf16x8*)(dst + q * LD) = w;
-        }
-      }
-    }
-    __syncthreads();
-    if (sg + 1 < s1) load(sg + 1);
-#pragma unroll
-    for (int kk = 0; kk < S; ++kk) {
-#pragma unroll
-      for (int i = 0; i < PER_WAVE; ++i) {
-        const int tt = wave + 4 * i;
-        if (tt < NTILE) {
-          const int tdx = tt / (MT * NT), rr = tt - tdx * MT * NT, ti = rr / NT, tj = rr - ti * NT;
-          const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
-          const bf16x8 bv = *(const bf16x8*)&Xs[tdx][tj * 16 + (lane & 15)][kk * 32 + kq];
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
-        }
-      }
-      if (bias) {
-#pragma unroll
-        for (int i = 0; i < BT; ++i) {
-          const int ti = wave + 4 * i;
-          if (ti < MT) {
-            const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
-            accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb[i], 0, 0, 0);
-          }
-        }
-      }
-    }
-  }
-  if (bias) {
-#pragma unroll
-    for (int i = 0; i < BT; ++i) {
-      const int ti = wave + 4 * i;
-      if (ti < MT && (lane & 15) == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bpart[(size_t)slice * Mr + ti * 16 + 4 * (lane >> 4) + q] = accb[i][q];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < PER_WAVE; ++i) {
-    const int tt = wave + 4 * i;
-    if (tt < NTILE) {
-      const int tdx = tt / (MT * NT), rr = tt - tdx * MT * NT, ti = rr / NT, tj = rr - ti * NT;
-      float* out = part + (((size_t)slice * 9 + dy * 3 + tdx) * Mr) * Nc + n0;
-      const int c = tj * 16 + (lane & 15);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[i][q];
-    }
-  }
-}
-
-// Weight gradients of the stride-1 and upsampling layers over row chunks:
-// the same GEMM as k_conv_wgrad_seg, but a stage is PX = 32 S pixels of one
-// output row (the last chunk of a row is ragged), so the three dx taps read
-// one staged input row at column shifts -1, 0, +1.  The row is staged once
-// (transposed, [channel][column], column = input column - x0 + 8; for the
-// upsampling layers the source row is expanded x2 while staging), and the
-// shifted operands are built from aligned 16-byte LDS reads by funnel shifts.
-// Per stage that moves PX + 16 (stride 1) or PX / 2 + 8 (upsampling) input
-// pixels instead of 3 PX.  A wave owns (row tile, column tile) units and
-// applies all three dx to each.  Work items, grid and partials are
-// k_conv_wgrad_seg's.
-template <int MT, int NT, int S, bool UP, int ND = 1>
+// transposed in registers, stored with 16-byte writes; the next stage's
+// blocks are loaded while the current stage's MFMAs run.  Shifted operands
+// are built from aligned 16-byte LDS reads by funnel shifts.  Per stage that
+// moves PX + 16 (stride 1), PX / 2 + 8 (upsampling) or 2 PX + 1 (stride 2)
+// input pixels per dy instead of 3 PX.  A wave owns (row tile, column tile)
+// units and applies all three dx to each.  The slice's (dy 0, first channel
+// block) item also sums dz over its pixels (the bias gradient) as dz^T times
+// a column of ones.  Partials: weights [slice][tap][r][c], bias [slice][r].
+template <int MT, int NT, int S, int MK, int ND = 1>
 __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__ dz,
                                                         const bf16* __restrict__ x, int B,
                                                         int Hout, int Wout, int Hin, int Win,
                                                         int Nc, int stages_per, int nwork,
                                                         float* __restrict__ part,
                                                         float* __restrict__ bpart) {
+  constexpr bool UP = MK == MAP_UP, S2 = MK == MAP_S2;
   constexpr int Mr = 16 * MT, NB = 16 * NT, PX = 32 * S, LD = PX + 8;
-  constexpr int XC = PX + 16, LDX = XC + 8;          // staged columns x0 - 8 .. x0 + PX + 7
+  // staged columns per channel and row pitch (a pitch of an odd number of
+  // 16-byte units)
+  constexpr int XC = S2 ? 2 * PX + 8 : PX + 16, LDX = S2 ? XC : XC + 8;
   constexpr int ABLK = (PX / 8) * (Mr / 8);
-  constexpr int XG = UP ? (PX / 16 + 1) : (PX / 8 + 2);   // source groups of 8 pixels
+  // source groups of 8 pixels (stride 2: odd groups, then even groups)
+  constexpr int XG = UP ? (PX / 16 + 1) : S2 ? 2 * (PX / 8) : (PX / 8 + 2);
   constexpr int XBLK = XG * (NB / 8);
   constexpr int NBLK = ABLK + ND * XBLK, BPT = (NBLK + 255) / 256;
   constexpr int NU = MT * NT, PER_WAVE = (NU + 3) / 4;
+  static_assert(!S2 || ND * (NB / 8) <= 256, "stride-2 halo loads: one per thread");
   __shared__ __attribute__((aligned(16))) bf16 As[Mr][LD];
   __shared__ __attribute__((aligned(16))) bf16 Xs[ND][NB][LDX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -881,31 +749,80 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
   const int nch = (Wout + PX - 1) / PX, nst = B * Hout * nch;
   const int s0 = slice * stages_per, s1 = min(nst, s0 + stages_per);
   bf16x8 reg[BPT][8];
+  bf16x8 hreg = zero8();
+  unsigned okm[BPT];   // stride 2: bit i, element i of the block is in range
+  bool hok = false;
   auto load = [&](int sg) {
     const int b = sg / (Hout * nch), rem = sg - b * Hout * nch, y = rem / nch;
     const int x0 = (rem - y * nch) * PX;
+    if constexpr (S2) {
+      // Every load is issued unconditionally (reads out of range go to
+      // element 0 of their array) and out-of-range values are zeroed when
+      // the block is stored to LDS: with conditional loads, or zeroing right
+      // after the load, the waves waited for the prefetch before the current
+      // stage's MFMAs.  First the odd column 2 x0 - 1 of row rd.
+      const bool hv = threadIdx.x < ND * (NB / 8);
+      const int rd = hv ? threadIdx.x / (NB / 8) : 0, cg = (threadIdx.x % (NB / 8)) * 8;
+      const int ys = 2 * y + dy0 + rd - 1, c = 2 * x0 - 1;
+      hok = hv && ys >= 0 && ys < Hin && c >= 0 && c < Win;
+      hreg = load8(x + (hok ? (((size_t)b * Hin + ys) * Win + c) * Nc + n0 + cg : 0));
 #pragma unroll
-    for (int bi = 0; bi < BPT; ++bi) {
-      const int blk = threadIdx.x + 256 * bi;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) reg[bi][i] = zero8();
-      if (blk < ABLK) {
-        const int pg = blk / (Mr / 8), cg = (blk % (Mr / 8)) * 8;
-        const bf16* src = dz + (((size_t)b * Hout + y) * Wout + x0) * Mr + cg;
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (x0 + pg * 8 + i < Wout) reg[bi][i] = load8(src + (size_t)(pg * 8 + i) * Mr);
-      } else if (blk < NBLK) {
-        const int rd = (blk - ABLK) / XBLK, r = blk - ABLK - rd * XBLK;   // dy row, item
-        const int uy = y + dy0 + rd - 1;
-        if (uy >= 0 && uy < Hout) {
-          const int ys = UP ? (uy >> 1) : uy;
+      for (int bi = 0; bi < BPT; ++bi) {
+        const int blk = threadIdx.x + 256 * bi;
+        // element i is input column c0 + 2 i of source row ys (dz: pixel
+        // x0 + 8 pg + i), in range for 0 <= column < climit
+        const bf16* src = dz;
+        long off0 = 0;
+        int c0 = 0, cstep = 1, climit = 0, ostep = 0;
+        if (blk < ABLK) {
+          const int pg = blk / (Mr / 8), cg = (blk % (Mr / 8)) * 8;
+          c0 = x0 + pg * 8; climit = Wout; ostep = Mr;
+          off0 = (((long)b * Hout + y) * Wout + c0) * Mr + cg;
+        } else if (blk < NBLK) {
+          const int rd = (blk - ABLK) / XBLK, r = blk - ABLK - rd * XBLK;   // dy row, item
+          const int ys = 2 * y + dy0 + rd - 1;
           const int m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
-          const int c0 = UP ? (x0 / 2 - 4 + 8 * m) : (x0 - 8 + 8 * m);   // first source column
-          const bf16* src = x + ((size_t)b * Hin + ys) * Win * Nc + n0 + cg;
+          c0 = 2 * (x0 + 8 * (m % (PX / 8))) + (m < PX / 8 ? 1 : 0);   // odd, then even groups
+          cstep = 2;
+          climit = (ys >= 0 && ys < Hin) ? Win : 0;
+          src = x; ostep = 2 * Nc;
+          off0 = (((long)b * Hin + ys) * Win + c0) * Nc + n0 + cg;
+        }
+        okm[bi] = 0;
+        if (blk < NBLK) {   // false only in the last round, for its spare threads
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int c = c0 + cstep * i;
+            const bool ok = c >= 0 && c < climit;
+            reg[bi][i] = load8(src + (ok ? off0 + (long)i * ostep : 0));
+            okm[bi] |= (unsigned)ok << i;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int bi = 0; bi < BPT; ++bi) {
+        const int blk = threadIdx.x + 256 * bi;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) reg[bi][i] = zero8();
+        if (blk < ABLK) {
+          const int pg = blk / (Mr / 8), cg = (blk % (Mr / 8)) * 8;
+          const bf16* src = dz + (((size_t)b * Hout + y) * Wout + x0) * Mr + cg;
 #pragma unroll
           for (int i = 0; i < 8; ++i)
-            if (c0 + i >= 0 && c0 + i < Win) reg[bi][i] = load8(src + (size_t)(c0 + i) * Nc);
+            if (x0 + pg * 8 + i < Wout) reg[bi][i] = load8(src + (size_t)(pg * 8 + i) * Mr);
+        } else if (blk < NBLK) {
+          const int rd = (blk - ABLK) / XBLK, r = blk - ABLK - rd * XBLK;   // dy row, item
+          const int uy = y + dy0 + rd - 1;   // row of the stride-1 or upsampled grid
+          if (uy >= 0 && uy < Hout) {
+            const int ys = UP ? (uy >> 1) : uy;
+            const int m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+            const int c0 = UP ? (x0 / 2 - 4 + 8 * m) : (x0 - 8 + 8 * m);   // first source column
+            const bf16* src = x + ((size_t)b * Hin + ys) * Win * Nc + n0 + cg;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+              if (c0 + i >= 0 && c0 + i < Win) reg[bi][i] = load8(src + (size_t)(c0 + i) * Nc);
+          }
         }
       }
     }
@@ -929,6 +846,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
     __syncthreads();
 #pragma unroll
     for (int bi = 0; bi < BPT; ++bi) {
+      if constexpr (S2) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) reg[bi][i] = ((okm[bi] >> i) & 1) ? reg[bi][i] : zero8();
+      }
       const int blk = threadIdx.x + 256 * bi;
       if (blk < ABLK) {
         bf16* dst = &As[(blk % (Mr / 8)) * 8][(blk / (Mr / 8)) * 8];
@@ -954,14 +875,19 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
             }
             *(bf16x8*)&Xr[cg + q][16 * m] = lo;
             *(bf16x8*)&Xr[cg + q][16 * m + 8] = hi;
-          } else {
+          } else {   // stride 2: odd and even groups both land at column 8 m + 8
             bf16x8 t;
 #pragma unroll
             for (int i = 0; i < 8; ++i) t[i] = reg[bi][i][q];
-            *(bf16x8*)&Xr[cg + q][8 * m] = t;
+            *(bf16x8*)&Xr[cg + q][S2 ? 8 * m + 8 : 8 * m] = t;
           }
         }
       }
+    }
+    if (S2 && threadIdx.x < ND * (NB / 8)) {
+      const int rd = threadIdx.x / (NB / 8), cg = (threadIdx.x % (NB / 8)) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Xs[rd][cg + q][7] = hok ? hreg[q] : (bf16)0.f;
     }
     __syncthreads();
     if (sg + 1 < s1) load(sg + 1);
@@ -975,17 +901,20 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
           const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
 #pragma unroll
           for (int rd = 0; rd < ND; ++rd) {
-            const bf16* xr = &Xs[rd][tj * 16 + (lane & 15)][kk * 32 + kq + 8];   // column of dx = 1
+            // stride 1 / upsampling: the column of dx = 1; stride 2: the
+            // odd column of dx = 2
+            const bf16* xr = &Xs[rd][tj * 16 + (lane & 15)][kk * 32 + kq + 8];
             const u32x4 a4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr - 8));
             const u32x4 b4 = __builtin_bit_cast(u32x4, *(const bf16x8*)xr);
-            const u32x4 c4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr + 8));
+            // stride 1: the next 8 columns; stride 2: the even columns (dx = 1)
+            const u32x4 c4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr + (S2 ? PX : 8)));
             // columns shifted by one bf16: word j = high half of word j-1, low half of word j
             const unsigned s0w = (a4[3] >> 16) | (b4[0] << 16), s1w = (b4[0] >> 16) | (b4[1] << 16);
             const unsigned s2w = (b4[1] >> 16) | (b4[2] << 16), s3w = (b4[2] >> 16) | (b4[3] << 16);
             const unsigned s4w = (b4[3] >> 16) | (c4[0] << 16);
             const bf16x8 bl = __builtin_bit_cast(bf16x8, u32x4{s0w, s1w, s2w, s3w});   // dx = 0
-            const bf16x8 bm = __builtin_bit_cast(bf16x8, b4);                          // dx = 1
-            const bf16x8 br = __builtin_bit_cast(bf16x8, u32x4{s1w, s2w, s3w, s4w});   // dx = 2
+            const bf16x8 bm = __builtin_bit_cast(bf16x8, S2 ? c4 : b4);                // dx = 1
+            const bf16x8 br = __builtin_bit_cast(bf16x8, S2 ? b4 : u32x4{s1w, s2w, s3w, s4w});   // dx = 2
             acc[i][3 * rd] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[i][3 * rd], 0, 0, 0);
             acc[i][3 * rd + 1] =
                 __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bm, acc[i][3 * rd + 1], 0, 0, 0);
@@ -1453,8 +1382,9 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_
     }
     if (l < NL - 1) chk(cnn_alloc(n, &n->act[l], pix * L.coutp));
     chk(cnn_alloc(n, &n->dz[l], pix * L.coutp));
-    // gradient partials: k_conv_wgrad_seg runs at most 8 workgroups per CU
-    // (256 threads each) over 3 dy and the 64-channel blocks; layer 1 uses
+    // gradient partials: room for 8 workgroups per CU (256 threads each)
+    // over 3 dy and the 64-channel blocks (k_conv_wgrad_row takes fewer
+    // slices when its occupancy asks for more than fit); layer 1 uses
     // [slice][32][32] (at most 8 slices per CU)
     if (l > 0) {
       const size_t nblk = (size_t)std::max(1, L.cinp / 64);
@@ -1646,7 +1576,7 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
   return DD_OK;
 }
 
-// Work split of a weight-gradient kernel (k_conv_wgrad_seg, k_conv_wgrad_row)
+// Work split of the weight-gradient kernel k_conv_wgrad_row
 // over nst stages: one round of resident workgroups (cap per CU), within the
 // partial buffer (weights, then bias).
 struct WgradSplit {
@@ -1673,35 +1603,21 @@ static int occupancy(K kern) {
   return c;
 }
 
-template <int MT, int NT, int S>
-static int launch_wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
-  static const int cap = occupancy(k_conv_wgrad_seg<MT, NT, S>);
-  const CnnLayer& L = n->L[l];
-  const int Mr = 16 * MT, Nc = L.cinp;
-  const int nst = (B * L.Hout * L.Wout + 32 * S - 1) / (32 * S);
-  const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst);
-  k_conv_wgrad_seg<MT, NT, S><<<w.grid, 256, 0, st>>>(
-      n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, L.Hin, L.Win, Nc, L.mode, w.stages_per,
-      w.nwork, n->wpart, n->wpart + (size_t)w.slices * 9 * Mr * Nc);
-  return w.slices;
-}
-
-template <int MT, int NT, int S, bool UP, int ND = 1>
+template <int MT, int NT, int S, int MK, int ND = 1>
 static int launch_wgrad_row(dd_cnn* n, int l, int B, hipStream_t st) {
-  static const int cap = occupancy(k_conv_wgrad_row<MT, NT, S, UP, ND>);
+  static const int cap = occupancy(k_conv_wgrad_row<MT, NT, S, MK, ND>);
   const CnnLayer& L = n->L[l];
   const int Mr = 16 * MT, Nc = L.cinp;
   const int nst = B * L.Hout * ((L.Wout + 32 * S - 1) / (32 * S));
   const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst, ND == 3 ? 1 : 3);
-  k_conv_wgrad_row<MT, NT, S, UP, ND><<<w.grid, 256, 0, st>>>(
+  k_conv_wgrad_row<MT, NT, S, MK, ND><<<w.grid, 256, 0, st>>>(
       n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, L.Hin, L.Win, Nc, w.stages_per, w.nwork,
       n->wpart, n->wpart + (size_t)w.slices * 9 * Mr * Nc);
   return w.slices;
 }
 
-// Weight- and bias-gradient partials of layer l >= 1: row chunks for the
-// stride-1 and upsampling layers, flattened pixel segments for the stride-2
-// ones.  Returns the number of pixel slices written to n->wpart (weights
+// Weight- and bias-gradient partials of layer l >= 1 (row chunks, every
+// map).  Returns the number of pixel slices written to n->wpart (weights
 // [slice][9][coutp][cinp], then bias [slice][coutp]), 0 (nothing launched)
 // for channel counts without an instance.
 static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
@@ -1709,11 +1625,11 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   const int Mr = L.coutp, Nc = L.cinp, NB = std::min(Nc, 64);
   if (Nc % NB) return 0;
   // S (stage width 32 S pixels, 1, 2 or 4): the largest whose 8 x 8 staging
-  // blocks (dz, then the input pixels a stage needs) fit one per thread.
-  // The row-chunk kernels with 32 output channels take all three dy per work
-  // item (ND = 3: dz staged once for the three input rows).
+  // blocks (dz, then the input pixels of one dy row) fit one per thread.
+  // The kernels with 32 output channels take all three dy per work item
+  // (ND = 3: dz staged once for the three input rows).
   auto blocks = [&](int S) {
-    const int xg = (L.mode == MAP_S1) ? 4 * S + 2 : (L.mode == MAP_UP) ? 2 * S + 1 : 12 * S;
+    const int xg = (L.mode == MAP_S1) ? 4 * S + 2 : (L.mode == MAP_UP) ? 2 * S + 1 : 8 * S;
     return 4 * S * (Mr / 8) + xg * (NB / 8);
   };
   const int S = blocks(4) <= 256 ? 4 : (blocks(2) <= 256 ? 2 : 1);
@@ -1724,20 +1640,22 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
   if (Mr == 64 && NB == 64) return S == 4 ? F(4, 4, 4) : F(4, 4, 2);   \
   if (Mr == 128 && NB == 32) return S == 2 ? F(8, 2, 2) : 0;           \
   if (Mr == 128 && NB == 64) return S == 2 ? F(8, 4, 2) : F(8, 4, 1);
-#define WG_SEG(a, b, c) launch_wgrad_seg<a, b, c>(n, l, B, st)
-#define WG_ROW1(a, b, c) launch_wgrad_row<a, b, c, false>(n, l, B, st)
-#define WG_ROWU(a, b, c) launch_wgrad_row<a, b, c, true>(n, l, B, st)
-#define WG_ROW3(a, b, c) launch_wgrad_row<a, b, c, false, 3>(n, l, B, st)
-#define WG_ROWU3(a, b, c) launch_wgrad_row<a, b, c, true, 3>(n, l, B, st)
-  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_ROW3) }
+#define WG_ROW1(a, b, c) launch_wgrad_row<a, b, c, MAP_S1>(n, l, B, st)
+#define WG_ROWU(a, b, c) launch_wgrad_row<a, b, c, MAP_UP>(n, l, B, st)
+#define WG_ROW2(a, b, c) launch_wgrad_row<a, b, c, MAP_S2>(n, l, B, st)
+#define WG_ROW13(a, b, c) launch_wgrad_row<a, b, c, MAP_S1, 3>(n, l, B, st)
+#define WG_ROWU3(a, b, c) launch_wgrad_row<a, b, c, MAP_UP, 3>(n, l, B, st)
+#define WG_ROW23(a, b, c) launch_wgrad_row<a, b, c, MAP_S2, 3>(n, l, B, st)
+  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_ROW13) }
   else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU, WG_ROWU3) }
-  else { WG_CASES(WG_SEG, WG_SEG) }
+  else { WG_CASES(WG_ROW2, WG_ROW23) }
 #undef WG_CASES
-#undef WG_SEG
 #undef WG_ROW1
 #undef WG_ROWU
-#undef WG_ROW3
+#undef WG_ROW2
+#undef WG_ROW13
 #undef WG_ROWU3
+#undef WG_ROW23
   return 0;
 }
 
