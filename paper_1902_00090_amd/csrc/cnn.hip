@@ -475,42 +475,45 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
   }
 }
 
-// Backward data of the stride-2 layers, LDS-tiled: a workgroup computes a
-// 4 x 64 tile of layer-input pixels (all M = 16 MT channels) from the 3 x 33
-// dz pixels it reads (rows y0/2 .. y0/2 + 2, columns x0/2 .. x0/2 + 32),
-// staged in LDS per 32 dz channels.  Wave w owns input row y = y0 + w and four
-// pixel tiles of 16: even columns x0 + 2 i (tiles 0, 1) and odd columns
-// x0 + 2 i + 1 (tiles 2, 3).  Tap (dy, dx) reaches row y only when
-// y + 1 - dy is even (one dy at even y, two at odd) and a column only when
-// x + 1 - dx is even (dx = 1 for the even tiles, 0 and 2 for the odd ones), so
-// each wave applies 3 or 6 taps to two tiles each.  The weights of all nine
-// taps (backward-data copy [tap][cinp][coutp]) are staged in LDS with the
-// patch; the epilogue masks by the ReLU of the layer input.
-#define BS_TH 4
+// Backward data of the stride-2 layers, LDS-tiled: a workgroup computes an
+// 8 x 64 tile of layer-input pixels (all M = 16 MT channels, y0 a multiple of
+// 8) from the 5 x 33 dz pixels it reads (rows y0/2 .. y0/2 + 4, columns
+// x0/2 .. x0/2 + 32), staged in LDS per 32 dz channels with the weights of
+// all nine taps (backward-data copy [tap][cinp][coutp]).  Tap (dy, dx)
+// reaches input row y only when y + 1 - dy is even (dy = 1 at even y, 0 and 2
+// at odd y) and column x only when x + 1 - dx is even (dx = 1 at even x, 0
+// and 2 at odd x).  Wave w owns the even row y0 + 2w and the odd row
+// y0 + 2w + 1, four pixel tiles of 16 each: even columns x0 + 2i (tiles 0,
+// 1) and odd columns x0 + 2i + 1 (tiles 2, 3), so every wave applies each of
+// the nine taps to two tiles.  Per dz row a wave reads two B operands per
+// tile pair (dz column c for dx = 1 at even x and dx = 2 at odd x, column c + 1
+// for dx = 0 at odd x); dz row w serves dy = 1 of the even row and dy = 2 of
+// the odd row.  The next chunk's patch and weights are loaded while the
+// current chunk's MFMAs run.  The epilogue masks by the ReLU of the layer
+// input.
+#define BS_TH 8
 #define BS_TW 64
-#define BS_PR 3
+#define BS_PR 5
 #define BS_PC 34
 template <int MT>
 __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) bf16 patch[BS_PR * BS_PC * CT_PS];
-  // the chunk's weights of all nine taps, staged with the patch ([tap][row][40])
   __shared__ __attribute__((aligned(16))) bf16 wl[9 * 16 * MT * CT_PS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x0 = blockIdx.x * BS_TW, y0 = blockIdx.y * BS_TH, b = blockIdx.z;
   const int Hq = a.Hq, Wq = a.Wq, py0 = y0 / 2, px0 = x0 / 2;
-  const int y = y0 + wave;
-  f32x4 acc[MT][4];
+  f32x4 acc[2][4][MT];   // [row: even, odd][tile][row tile]
 #pragma unroll
-  for (int i = 0; i < MT; ++i)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < MT; ++i) acc[h][j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int kq = 8 * (lane >> 4);
-  const int dy0 = (y & 1) ? 0 : 1, ntap = (y & 1) ? 6 : 3;   // taps (dy0 + 2 (i / 3), i % 3)
-  constexpr int NSTG = (BS_PR * BS_PC * 4 + 255) / 256;
-  constexpr int NWI = 9 * 16 * MT * 4, NWS = (NWI + 255) / 256;   // weight items
-  for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
-    bf16x8 wcur[MT];
-    u32x4 wv[NWS];
+  constexpr int NPI = BS_PR * BS_PC * 4, NSTG = (NPI + 255) / 256;   // patch items
+  constexpr int NWI = 9 * 16 * MT * 4, NWS = (NWI + 255) / 256;      // weight items
+  u32x4 sv[NSTG], wv[NWS];
+  auto fetch = [&](int c0) {
 #pragma unroll
     for (int it = 0; it < NWS; ++it) {
       const int u = threadIdx.x + 256 * it;   // (tap, row, quarter)
@@ -519,7 +522,6 @@ __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
       if (u < NWI)
         wv[it] = *(const u32x4*)(a.W + ((size_t)tq * a.M + (rem >> 2)) * a.Ksrc + c0 + 8 * (rem & 3));
     }
-    u32x4 sv[NSTG];
 #pragma unroll
     for (int it = 0; it < NSTG; ++it) {
       const int u = threadIdx.x + 256 * it;
@@ -527,13 +529,17 @@ __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
       const int pr = pix / BS_PC, pc = pix - pr * BS_PC;
       const int sy = py0 + pr, sx = px0 + pc;   // dz grid
       sv[it] = u32x4{0u, 0u, 0u, 0u};
-      if (u < BS_PR * BS_PC * 4 && sy < a.Hs && sx < a.Ws)
+      if (u < NPI && sy < a.Hs && sx < a.Ws)
         sv[it] = *(const u32x4*)(a.src + ((size_t)(b * a.Hs + sy) * a.Ws + sx) * a.Ksrc + c0 + 8 * q);
     }
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
+    __syncthreads();   // the previous chunk's readers are done
 #pragma unroll
     for (int it = 0; it < NSTG; ++it) {
       const int u = threadIdx.x + 256 * it;
-      if (u < BS_PR * BS_PC * 4) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
+      if (u < NPI) *(u32x4*)(patch + (u >> 2) * CT_PS + 8 * (u & 3)) = sv[it];
     }
 #pragma unroll
     for (int it = 0; it < NWS; ++it) {
@@ -541,59 +547,73 @@ __global__ __launch_bounds__(256) void k_bwd_s2_tile(GemmArgs a) {
       if (u < NWI) *(u32x4*)(wl + (u >> 2) * CT_PS + 8 * (u & 3)) = wv[it];
     }
     __syncthreads();
-#pragma unroll 1
-    for (int i = 0; i < ntap; ++i) {
-      const int dy = dy0 + 2 * (i / 3), dx = i % 3;
+    if (c0 + 32 < a.Ksrc) fetch(c0 + 32);
+    // dz rows w (r = 0) and w + 1 (r = 1) of the patch
 #pragma unroll
-      for (int r = 0; r < MT; ++r)
-        wcur[r] = *(const bf16x8*)(wl + ((3 * dy + dx) * 16 * MT + r * 16 + (lane & 15)) * CT_PS + kq);
-      const int pr = (y + 1 - dy) / 2 - py0;                 // 0..2
-      const int j0 = (dx == 1) ? 0 : 2;                      // even tiles take dx = 1
-      const int coff = (dx == 0) ? 1 : 0;                    // odd x, dx = 0: one column on
-      bf16x8 bv[2];
+    for (int r = 0; r < 2; ++r) {
+      bf16x8 bc[2], bn[2];   // dz columns c and c + 1 of the two tile pairs
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) {
-        const int c = 16 * jj + (lane & 15) + coff;
-        bv[jj] = *(const bf16x8*)(patch + (pr * BS_PC + c) * CT_PS + kq);
+        const bf16* pp = patch + ((wave + r) * BS_PC + 16 * jj + (lane & 15)) * CT_PS + kq;
+        bc[jj] = *(const bf16x8*)pp;
+        bn[jj] = *(const bf16x8*)(pp + CT_PS);
       }
+      // (input row h, dy): r = 0 serves (even, 1) and (odd, 2); r = 1 serves (odd, 0)
 #pragma unroll
-      for (int r = 0; r < MT; ++r) {
-        if (j0 == 0) {
-          acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[0], acc[r][0], 0, 0, 0);
-          acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[1], acc[r][1], 0, 0, 0);
-        } else {
-          acc[r][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[0], acc[r][2], 0, 0, 0);
-          acc[r][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[r], bv[1], acc[r][3], 0, 0, 0);
+      for (int s2 = 0; s2 < 2 - r; ++s2) {
+        const int h = (r == 0 && s2 == 0) ? 0 : 1;
+        const int dy = (r == 1) ? 0 : (s2 == 0 ? 1 : 2);
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          bf16x8 wcur[MT];
+#pragma unroll
+          for (int i = 0; i < MT; ++i)
+            wcur[i] = *(const bf16x8*)(wl + ((3 * dy + dx) * 16 * MT + i * 16 + (lane & 15)) *
+                                                CT_PS + kq);
+          // dx = 1: even tiles 0, 1 from column c; dx = 2: odd tiles from
+          // column c; dx = 0: odd tiles from column c + 1
+          const int j0 = (dx == 1) ? 0 : 2;
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            const bf16x8 bv = (dx == 0) ? bn[jj] : bc[jj];
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+              acc[h][j0 + jj][i] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], bv, acc[h][j0 + jj][i], 0, 0, 0);
+          }
         }
       }
     }
-    __syncthreads();
   }
-  if (y >= Hq) return;
-  u32x2 mk[MT][4];
 #pragma unroll
-  for (int r = 0; r < MT; ++r)
+  for (int h = 0; h < 2; ++h) {
+    const int y = y0 + 2 * wave + h;
+    if (y >= Hq) break;
+    u32x2 mk[4][MT];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int x = x0 + 2 * (16 * (j & 1) + (lane & 15)) + (j >> 1);
-      mk[r][j] = u32x2{0u, 0u};
-      if (x < Wq)
-        mk[r][j] = *(const u32x2*)(a.mask + (((size_t)b * Hq + y) * Wq + x) * a.M + r * 16 +
-                                   4 * (lane >> 4));
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        mk[j][i] = u32x2{0u, 0u};
+        if (x < Wq)
+          mk[j][i] = *(const u32x2*)(a.mask + (((size_t)b * Hq + y) * Wq + x) * a.M + i * 16 +
+                                     4 * (lane >> 4));
+      }
     }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int x = x0 + 2 * (16 * (j & 1) + (lane & 15)) + (j >> 1);
-    if (x >= Wq) continue;
-    const size_t p = ((size_t)b * Hq + y) * Wq + x;
+    for (int j = 0; j < 4; ++j) {
+      const int x = x0 + 2 * (16 * (j & 1) + (lane & 15)) + (j >> 1);
+      if (x >= Wq) continue;
+      const size_t p = ((size_t)b * Hq + y) * Wq + x;
 #pragma unroll
-    for (int r = 0; r < MT; ++r) {
-      const int r0 = r * 16 + 4 * (lane >> 4);
-      const bf16x4 m4 = __builtin_bit_cast(bf16x4, mk[r][j]);
-      bf16 h[4];
+      for (int i = 0; i < MT; ++i) {
+        const bf16x4 m4 = __builtin_bit_cast(bf16x4, mk[j][i]);
+        bf16 hv[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) h[q] = (bf16)(((float)m4[q] > 0.f) ? acc[r][j][q] : 0.f);
-      *(u32x2*)(a.out + p * a.M + r0) = __builtin_bit_cast(u32x2, h);
+        for (int q = 0; q < 4; ++q) hv[q] = (bf16)(((float)m4[q] > 0.f) ? acc[h][j][i][q] : 0.f);
+        *(u32x2*)(a.out + p * a.M + i * 16 + 4 * (lane >> 4)) = __builtin_bit_cast(u32x2, hv);
+      }
     }
   }
 }
@@ -1523,12 +1543,13 @@ static dd_status gemm_dispatch(const GemmArgs& a, bool bwd, hipStream_t st) {
   }
   if (bwd && a.mode == MAP_S2) {
     const dim3 grid((a.Wq + BS_TW - 1) / BS_TW, (a.Hq + BS_TH - 1) / BS_TH, a.B);
+    // the stride-2 layers have 32- and 64-channel inputs
     switch (MT) {
-      case 2: k_bwd_s2_tile<2><<<grid, 256, 0, st>>>(a); break;
-      case 4: k_bwd_s2_tile<4><<<grid, 256, 0, st>>>(a); break;
-      case 8: k_bwd_s2_tile<8><<<grid, 256, 0, st>>>(a); break;
+      case 2: k_bwd_s2_tile<2><<<grid, 256, 0, st>>>(a); return DD_OK;
+      case 4: k_bwd_s2_tile<4><<<grid, 256, 0, st>>>(a); return DD_OK;
     }
-    return DD_OK;
+    dd_set_error("dd_cnn: no stride-2 backward-data kernel for %d channels", a.M);
+    return DD_EINVAL;
   }
   dd_set_error("dd_cnn: no convolution kernel for this layer map");
   return DD_EINVAL;
