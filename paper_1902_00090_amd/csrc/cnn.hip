@@ -374,12 +374,18 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
       if (u < NWI) *(u32x4*)(wl + (u >> 2) * CT_PS + 8 * (u & 3)) = wv[it];
     }
   };
+  // without WL the 9-tap kernels keep the weights of the next PD taps in
+  // flight in a register ring (a tap's MFMAs are too few to cover an L2 load
+  // one tap ahead); the 16-tap kernels load one tap ahead (a ring cost them
+  // occupancy)
+  constexpr int PD = (WL || KS == 4) ? 1 : (NTAP < 16 / MT ? NTAP : 16 / MT);
   for (int c0 = 0; c0 < a.Ksrc; c0 += 32) {
-    bf16x8 wcur[MT], wnext[MT];
+    bf16x8 wcur[MT], wr[PD][MT];
     if (WL) {
       wfetch(0, c0);
     } else {
-      wload(0, c0, wcur);
+#pragma unroll
+      for (int d = 0; d < PD; ++d) wload(d, c0, wr[d]);
     }
     u32x4 sv[NSTG];
 #pragma unroll
@@ -399,21 +405,8 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
     }
     if (WL) wstore();
     __syncthreads();
-#pragma unroll 1
-    for (int t = 0; t < NTAP; ++t) {
-      if (WL) {
-        if (t > 0 && t % NTW == 0) {   // next tap group (only for NTW < NTAP)
-          __syncthreads();
-          wfetch(t, c0);
-          wstore();
-          __syncthreads();
-        }
-#pragma unroll
-        for (int i = 0; i < MT; ++i)
-          wcur[i] = *(const bf16x8*)(wl + ((t % NTW) * 16 * MT + i * 16 + (lane & 15)) * CT_PS + kq);
-      } else if (t + 1 < NTAP) {
-        wload(t + 1, c0, wnext);
-      }
+    // MFMAs of tap t with weights w
+    auto tap = [&](int t, const bf16x8 (&w)[MT]) {
       const int ty = t / KS, tx = t - KS * (t / KS);
       bf16x8 bv[2];
 #pragma unroll
@@ -424,10 +417,42 @@ __global__ __launch_bounds__(256) void k_conv_tile_s2(GemmArgs a) {
       for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wcur[i], bv[j], acc[i][j], 0, 0, 0);
-      if (!WL && t + 1 < NTAP) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[i], bv[j], acc[i][j], 0, 0, 0);
+    };
+    if constexpr (WL) {
+#pragma unroll 1
+      for (int t = 0; t < NTAP; ++t) {
+        if (t > 0 && t % NTW == 0) {   // next tap group (only for NTW < NTAP)
+          __syncthreads();
+          wfetch(t, c0);
+          wstore();
+          __syncthreads();
+        }
 #pragma unroll
-        for (int i = 0; i < MT; ++i) wcur[i] = wnext[i];
+        for (int i = 0; i < MT; ++i)
+          wcur[i] = *(const bf16x8*)(wl + ((t % NTW) * 16 * MT + i * 16 + (lane & 15)) * CT_PS + kq);
+        tap(t, wcur);
+      }
+    } else if constexpr (PD == 1) {
+#pragma unroll 1
+      for (int t = 0; t < NTAP; ++t) {
+        bf16x8 wnext[MT];
+        if (t + 1 < NTAP) wload(t + 1, c0, wnext);
+        tap(t, wr[0]);
+        if (t + 1 < NTAP) {
+#pragma unroll
+          for (int i = 0; i < MT; ++i) wr[0][i] = wnext[i];
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int tg = 0; tg < NTAP; tg += PD) {
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+          const int t = tg + d;
+          if (t < NTAP) tap(t, wr[d]);
+          if (t + PD < NTAP) wload(t + PD, c0, wr[d]);
+        }
       }
     }
     __syncthreads();
