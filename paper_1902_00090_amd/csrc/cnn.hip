@@ -1694,7 +1694,12 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
 #define WG_ROW23(a, b, c) launch_wgrad_row<a, b, c, MAP_S2, 3>(n, l, B, st)
   if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_ROW13) }
   else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU, WG_ROWU3) }
-  else { WG_CASES(WG_ROW2, WG_ROW23) }
+  else {
+    // 64 output and 32 input channels: three dy per item at half the stage
+    // width (the 18 accumulators per unit fit; 130 -> 101 us at batch 32)
+    if (Mr == 64 && NB == 32) return WG_ROW23(4, 2, 2);
+    WG_CASES(WG_ROW2, WG_ROW23)
+  }
 #undef WG_CASES
 #undef WG_ROW1
 #undef WG_ROWU
