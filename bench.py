@@ -1215,17 +1215,17 @@ def main():
     kname = {"matvec_dots": "k_matvec_dot", "second_pass": "k_update_dot",
              "update_norm": "k_update_norm", "fused_sweep": "k_fused_sweep"}[name]
     traffic = None
-    rec = measured_traffic()
-    if (rec is not None and rec["kernel"] == kname and args.batch == rec["batch"]
-            and args.k == rec["k"] and args.cgs == 1
-            and kernel_sources_hash() == rec["sources_sha256_16"]):
-        traffic = rec["bytes_per_launch"]
+    trec = measured_traffic()
+    if (trec is not None and trec["kernel"] == kname and args.batch == trec["batch"]
+            and args.k == trec["k"] and args.cgs == 1
+            and kernel_sources_hash() == trec["sources_sha256_16"]):
+        traffic = trec["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_workload": None if traffic is None else
-                {"run": rec["workload"],
-                 "algorithmic_bytes_per_launch": rec["algorithmic_bytes_per_launch"],
-                 "ratio": round(traffic / rec["algorithmic_bytes_per_launch"], 3)},
+                {"run": trec["workload"],
+                 "algorithmic_bytes_per_launch": trec["algorithmic_bytes_per_launch"],
+                 "ratio": round(traffic / trec["algorithmic_bytes_per_launch"], 3)},
                 "kernel": kname,
                 "avg_launch_us": round(1000 * ms_k / max(1, launches_k), 2),
                 "launches": int(launches_k),
