@@ -1006,6 +1006,217 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
   }
 }
 
+// Weight gradients of the upsampling layers at the source resolution.  The
+// layer input u is the source x repeated over 2 x 2 blocks, so for output
+// pixel (2i + a, 2j + b) tap t reads x at (i + dy, j + dx) with
+// d = (parity + t - 1) >> 1: per parity only two row and two column shifts
+// occur, d = parity + s - 1 for s = 0, 1.  The sixteen products
+//   G[a][b][sy][sx][r][c] = sum_{i,j} dz[2i + a][2j + b][r] x[i + a + sy - 1][j + b + sx - 1][c]
+// give every tap as a sum of four, dW[ty][tx] = sum_{a,b} G[a][b][sy(a, ty)][sx(b, tx)]
+// with sy(a, t) = ((a + t - 1) >> 1) - a + 1 (k_up_tapmap): 16 products per
+// source pixel instead of the 36 of the upsampled grid.  Work items: (pixel
+// slice, channel block of NB = 16 NT input channels, output-row parity a),
+// a fastest.  A stage is PX = 32 S source pixels of source row i; the
+// workgroup stages in LDS, transposed to [channel][pixel]:
+//  * dz of output row 2i + a, columns 2j and 2j + 1 (b = 0, 1) in two halves;
+//  * source rows i + a - 1 and i + a (sy = 0, 1), columns j0 - 8 ..
+//    j0 + PX + 7, read by the column shifts -1, 0, +1 as in k_conv_wgrad_row.
+// Loads, staging blocks and funnel shifts are those of k_conv_wgrad_row.
+// Partials: [slice][16][r][c] (index ((a 2 + b) 2 + sy) 2 + sx), bias
+// [slice][a][r] (every channel-block-0 item sums its dz row).
+template <int MT, int NT, int S>
+__global__ __launch_bounds__(256) void k_conv_wgrad_up(const bf16* __restrict__ dz,
+                                                       const bf16* __restrict__ x, int B,
+                                                       int Hout, int Wout, int Hin, int Win,
+                                                       int Nc, int stages_per, int nwork,
+                                                       float* __restrict__ part,
+                                                       float* __restrict__ bpart) {
+  constexpr int Mr = 16 * MT, NB = 16 * NT, PX = 32 * S, LD = PX + 8;
+  constexpr int XC = PX + 16, LDX = XC + 8;
+  constexpr int AHALF = (PX / 8) * (Mr / 8), ABLK = 2 * AHALF;   // dz: b = 0, then b = 1
+  constexpr int XBLK = (PX / 8 + 2) * (NB / 8);                  // per source row
+  constexpr int NBLK = ABLK + 2 * XBLK, BPT = (NBLK + 255) / 256;
+  constexpr int NU = MT * NT, PER_WAVE = (NU + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16 As[2][Mr][LD];
+  __shared__ __attribute__((aligned(16))) bf16 Xs[2][NB][LDX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (w >= nwork) return;
+  const int nblk = Nc / NB;
+  const int a = w & 1, n0 = ((w >> 1) % nblk) * NB, slice = w / (2 * nblk);
+  const int nch = (Win + PX - 1) / PX, nst = B * Hin * nch;
+  const int s0 = slice * stages_per, s1 = min(nst, s0 + stages_per);
+  bf16x8 reg[BPT][8];
+  auto load = [&](int sg) {
+    const int b = sg / (Hin * nch), rem = sg - b * Hin * nch, i = rem / nch;
+    const int j0 = (rem - i * nch) * PX;
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) reg[bi][e] = zero8();
+      if (blk < ABLK) {
+        const int par = blk / AHALF, r = blk - par * AHALF;
+        const int pg = r / (Mr / 8), cg = (r % (Mr / 8)) * 8;
+        const int Y = 2 * i + a;
+        const bf16* src = dz + ((size_t)b * Hout + Y) * Wout * Mr + cg;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int X = 2 * (j0 + 8 * pg + e) + par;
+          if (Y < Hout && X < Wout) reg[bi][e] = load8(src + (size_t)X * Mr);
+        }
+      } else if (blk < NBLK) {
+        const int sy = (blk - ABLK) / XBLK, r = blk - ABLK - sy * XBLK;
+        const int ys = i + a + sy - 1;
+        if (ys >= 0 && ys < Hin) {
+          const int m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+          const int c0 = j0 - 8 + 8 * m;
+          const bf16* src = x + ((size_t)b * Hin + ys) * Win * Nc + n0 + cg;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (c0 + e >= 0 && c0 + e < Win) reg[bi][e] = load8(src + (size_t)(c0 + e) * Nc);
+        }
+      }
+    }
+  };
+  f32x4 acc[PER_WAVE][8];   // [unit][(b 2 + sy) 2 + sx]
+#pragma unroll
+  for (int u = 0; u < PER_WAVE; ++u)
+#pragma unroll
+    for (int d = 0; d < 8; ++d) acc[u][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int BT = (MT + 3) / 4;
+  const bool bias = (n0 == 0);
+  f32x4 accb[BT];
+#pragma unroll
+  for (int u = 0; u < BT; ++u) accb[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.f;
+  const int kq = 8 * (lane >> 4);
+  if (s0 < s1) load(s0);
+  for (int sg = s0; sg < s1; ++sg) {
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      bf16* dst = nullptr;
+      if (blk < ABLK) {
+        const int par = blk / AHALF, r = blk - par * AHALF;
+        dst = &As[par][(r % (Mr / 8)) * 8][(r / (Mr / 8)) * 8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          bf16x8 t;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) t[e] = reg[bi][e][q];
+          *(bf16x8*)(dst + q * LD) = t;
+        }
+      } else if (blk < NBLK) {
+        const int sy = (blk - ABLK) / XBLK, r = blk - ABLK - sy * XBLK;
+        const int m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          bf16x8 t;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) t[e] = reg[bi][e][q];
+          *(bf16x8*)&Xs[sy][cg + q][8 * m] = t;
+        }
+      }
+    }
+    __syncthreads();
+    if (sg + 1 < s1) load(sg + 1);
+#pragma unroll
+    for (int kk = 0; kk < S; ++kk) {
+#pragma unroll
+      for (int u = 0; u < PER_WAVE; ++u) {
+        const int uu = wave + 4 * u;
+        if (uu < NU) {
+          const int ti = uu / NT, tj = uu - ti * NT;
+          const bf16x8 av0 = *(const bf16x8*)&As[0][ti * 16 + (lane & 15)][kk * 32 + kq];
+          const bf16x8 av1 = *(const bf16x8*)&As[1][ti * 16 + (lane & 15)][kk * 32 + kq];
+#pragma unroll
+          for (int sy = 0; sy < 2; ++sy) {
+            const bf16* xr = &Xs[sy][tj * 16 + (lane & 15)][kk * 32 + kq + 8];   // shift 0
+            const u32x4 a4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr - 8));
+            const u32x4 b4 = __builtin_bit_cast(u32x4, *(const bf16x8*)xr);
+            const u32x4 c4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr + 8));
+            const unsigned s0w = (a4[3] >> 16) | (b4[0] << 16), s1w = (b4[0] >> 16) | (b4[1] << 16);
+            const unsigned s2w = (b4[1] >> 16) | (b4[2] << 16), s3w = (b4[2] >> 16) | (b4[3] << 16);
+            const unsigned s4w = (b4[3] >> 16) | (c4[0] << 16);
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, u32x4{s0w, s1w, s2w, s3w});   // -1
+            const bf16x8 bm = __builtin_bit_cast(bf16x8, b4);                          // 0
+            const bf16x8 br = __builtin_bit_cast(bf16x8, u32x4{s1w, s2w, s3w, s4w});   // +1
+            // b = 0: column shifts -1 (sx 0), 0 (sx 1); b = 1: 0 (sx 0), +1 (sx 1)
+            acc[u][2 * sy] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bl, acc[u][2 * sy], 0, 0, 0);
+            acc[u][2 * sy + 1] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bm, acc[u][2 * sy + 1], 0, 0, 0);
+            acc[u][4 + 2 * sy] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bm, acc[u][4 + 2 * sy], 0, 0, 0);
+            acc[u][5 + 2 * sy] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, br, acc[u][5 + 2 * sy], 0, 0, 0);
+          }
+        }
+      }
+      if (bias) {
+#pragma unroll
+        for (int u = 0; u < BT; ++u) {
+          const int ti = wave + 4 * u;
+          if (ti < MT) {
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+              const bf16x8 av = *(const bf16x8*)&As[par][ti * 16 + (lane & 15)][kk * 32 + kq];
+              accb[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb[u], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (bias) {
+#pragma unroll
+    for (int u = 0; u < BT; ++u) {
+      const int ti = wave + 4 * u;
+      if (ti < MT && (lane & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          bpart[((size_t)slice * 2 + a) * Mr + ti * 16 + 4 * (lane >> 4) + q] = accb[u][q];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PER_WAVE; ++u) {
+    const int uu = wave + 4 * u;
+    if (uu < NU) {
+      const int ti = uu / NT, tj = uu - ti * NT;
+      const int c = tj * 16 + (lane & 15);
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {   // product index (a 2 + b) 2 + sy) 2 + sx = 8 a + d
+        float* out = part + (((size_t)slice * 16 + 8 * a + d) * Mr) * Nc + n0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[u][d][q];
+      }
+    }
+  }
+}
+
+// The nine tap gradients of an upsampling layer from the sixteen products
+// summed over slices (S [16][Mr][Nc], see k_conv_wgrad_up), in a fixed order.
+__global__ void k_up_tapmap(const float* __restrict__ S, int Mr, int Nc, int cout, int cin,
+                            float* __restrict__ g) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;   // (co, ci, tap)
+  if (id >= cout * cin * 9) return;
+  const int tap = id % 9, ci = (id / 9) % cin, co = id / (9 * cin);
+  const int ty = tap / 3, tx = tap % 3;
+  float v = 0.f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int sy = ((a + ty - 1) >> 1) - a + 1, sx = ((b + tx - 1) >> 1) - b + 1;
+      v += S[((size_t)(((a * 2 + b) * 2 + sy) * 2 + sx) * Mr + co) * Nc + ci];
+    }
+  g[id] = v;
+}
+
 // Layer-1 weight and bias gradients on FP32 matrix cores: dW[co][j] =
 // sum_p dz[p][co] u[p][j], where u[p] is the pixel's 9 C input values
 // (plane-major, tap-minor: the [cout][cin][3][3] order of the weights), then 1
@@ -1144,12 +1355,15 @@ __global__ __launch_bounds__(256) void k_conv1_rows_reduce(const float* __restri
 // order.  A workgroup takes 64 consecutive partial entries ([tap][r][c]
 // order, coalesced reads) and four slice groups (slices g, g + 4, ...), which
 // are then added in group order.
+// NE = 9: the tap gradients, written to g ([cout][cin][9]); NE = 16: the
+// products of an upsampling layer, written to S ([16][Mr][Nc]) for k_up_tapmap.
+template <int NE>
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nslices,
                                                       int Mr, int Nc, int cout, int cin,
                                                       float* __restrict__ g) {
   __shared__ float red[4][64];
   const int j = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int ent = blockIdx.x * 64 + j, nent = 9 * Mr * Nc;
+  const int ent = blockIdx.x * 64 + j, nent = NE * Mr * Nc;
   float s = 0.f;
   if (ent < nent) {
     // slices grp, grp + 4, ... added in order; eight loads in flight at a time
@@ -1166,9 +1380,13 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
   red[grp][j] = s;
   __syncthreads();
   if (grp == 0 && ent < nent) {
-    const int tap = ent / (Mr * Nc), rem = ent - tap * Mr * Nc, co = rem / Nc, ci = rem - co * Nc;
-    if (co < cout && ci < cin)
-      g[((size_t)co * cin + ci) * 9 + tap] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    const float v = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    if (NE == 16) {
+      g[ent] = v;
+    } else {
+      const int tap = ent / (Mr * Nc), rem = ent - tap * Mr * Nc, co = rem / Nc, ci = rem - co * Nc;
+      if (co < cout && ci < cin) g[((size_t)co * cin + ci) * 9 + tap] = v;
+    }
   }
 }
 __global__ __launch_bounds__(256) void k_bgrad_reduce(const float* __restrict__ part, int nslices,
@@ -1434,7 +1652,11 @@ extern "C" dd_status dd_cnn_create(int nx, int ny, int max_batch, int k, int in_
     if (l > 0) {
       const size_t nblk = (size_t)std::max(1, L.cinp / 64);
       const size_t sl = std::max<size_t>(1, (size_t)8 * n->ncu / (3 * nblk));
-      wp = std::max(wp, sl * ((size_t)9 * L.coutp * L.cinp + L.coutp));
+      const size_t wl = (size_t)L.coutp * L.cinp;
+      wp = std::max(wp, sl * (9 * wl + L.coutp));
+      // upsampling (k_conv_wgrad_up, up to 4 workgroups per CU over the two
+      // parities): 16 products and two bias rows per slice, then their sums
+      if (L.up) wp = std::max(wp, (size_t)2 * n->ncu / nblk * (16 * wl + 2 * L.coutp) + 16 * wl);
     } else {
       wp = std::max(wp, (size_t)8 * n->ncu * 32 * 32);
     }
@@ -1628,12 +1850,17 @@ static dd_status forward(dd_cnn* n, const float* eps, const void* eim, int B, hi
 struct WgradSplit {
   int slices, stages_per, nwork, grid;
 };
-// dsplit: work items per (slice, channel block), 3 (one per dy) or 1.
+// dsplit: work items per (slice, channel block), 3 (one per dy), 2 (one per
+// output-row parity, upsampling) or 1.  ne: weight partials per slice (9
+// taps, or the 16 products of an upsampling layer, which also keep their
+// 16 Mr Nc sums after the partials); nbias: bias partials per slice.
 static WgradSplit wgrad_split(const dd_cnn* n, int cap, int Mr, int Nc, int NB, int nst,
-                              int dsplit = 3) {
+                              int dsplit = 3, int ne = 9, int nbias = 1) {
   const int nblk = Nc / NB;
+  const size_t per = (size_t)ne * Mr * Nc + (size_t)nbias * Mr;
+  const size_t reserve = ne == 9 ? 0 : (size_t)ne * Mr * Nc;
   int slices = std::max(1, cap * n->ncu / (dsplit * nblk));
-  slices = (int)std::min<size_t>((size_t)slices, n->wpart_elems / ((size_t)9 * Mr * Nc + Mr));
+  slices = (int)std::min<size_t>((size_t)slices, (n->wpart_elems - reserve) / per);
   slices = std::max(1, std::min(slices, nst));
   const int sp = (nst + slices - 1) / slices;
   slices = (nst + sp - 1) / sp;
@@ -1659,6 +1886,25 @@ static int launch_wgrad_row(dd_cnn* n, int l, int B, hipStream_t st) {
   k_conv_wgrad_row<MT, NT, S, MK, ND><<<w.grid, 256, 0, st>>>(
       n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, L.Hin, L.Win, Nc, w.stages_per, w.nwork,
       n->wpart, n->wpart + (size_t)w.slices * 9 * Mr * Nc);
+  return w.slices;
+}
+
+// whether an upsampling layer's weight gradient runs on k_conv_wgrad_up
+static bool wgrad_up_kernel(const CnnLayer& L) {
+  const int NB = std::min(L.cinp, 64);
+  return L.cinp % NB == 0 && NB == 64 && (L.coutp == 64 || L.coutp == 32);
+}
+
+template <int MT, int NT, int S>
+static int launch_wgrad_up(dd_cnn* n, int l, int B, hipStream_t st) {
+  static const int cap = occupancy(k_conv_wgrad_up<MT, NT, S>);
+  const CnnLayer& L = n->L[l];
+  const int Mr = 16 * MT, Nc = L.cinp;
+  const int nst = B * L.Hin * ((L.Win + 32 * S - 1) / (32 * S));
+  const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst, 2, 16, 2);
+  k_conv_wgrad_up<MT, NT, S><<<w.grid, 256, 0, st>>>(
+      n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, L.Hin, L.Win, Nc, w.stages_per, w.nwork,
+      n->wpart, n->wpart + (size_t)w.slices * 16 * Mr * Nc);
   return w.slices;
 }
 
@@ -1693,7 +1939,14 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
 #define WG_ROWU3(a, b, c) launch_wgrad_row<a, b, c, MAP_UP, 3>(n, l, B, st)
 #define WG_ROW23(a, b, c) launch_wgrad_row<a, b, c, MAP_S2, 3>(n, l, B, st)
   if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_ROW13) }
-  else if (L.mode == MAP_UP) { WG_CASES(WG_ROWU, WG_ROWU3) }
+  else if (L.mode == MAP_UP) {
+    // the two upsampling layers (128 -> 64 and 64 -> 32 channels) at the
+    // source resolution, sixteen products per pixel
+    if (wgrad_up_kernel(L)) {
+      return Mr == 64 ? launch_wgrad_up<4, 4, 1>(n, l, B, st) : launch_wgrad_up<2, 4, 2>(n, l, B, st);
+    }
+    WG_CASES(WG_ROWU, WG_ROWU3)
+  }
   else {
     // 64 output and 32 input channels: three dy per item at half the stage
     // width (the 18 accumulators per unit fit; 130 -> 101 us at batch 32)
@@ -1721,12 +1974,27 @@ static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
       dd_set_error("dd_cnn: no weight-gradient kernel for %d x %d channels", L.coutp, L.cinp);
       return DD_EINVAL;
     }
-    const int nent = 9 * L.coutp * L.cinp;
-    k_wgrad_reduce<<<(nent + 63) / 64, 256, 0, st>>>(n->wpart, wslices, L.coutp, L.cinp, L.cout,
-                                                     L.cin, n->grads + L.woff);
-    k_bgrad_reduce<<<(L.coutp + 15) / 16, 256, 0, st>>>(n->wpart + (size_t)wslices * nent,
-                                                         wslices, L.coutp, L.cout,
-                                                         n->grads + L.boff);
+    if (L.mode == MAP_UP && wgrad_up_kernel(L)) {
+      // sixteen products per slice, then bias [slice][parity][r]; their sums
+      // over slices after both, then mapped onto the nine taps
+      const int nent = 16 * L.coutp * L.cinp;
+      float* S = n->wpart + (size_t)wslices * (nent + 2 * L.coutp);
+      k_wgrad_reduce<16><<<(nent + 63) / 64, 256, 0, st>>>(n->wpart, wslices, L.coutp, L.cinp,
+                                                           L.cout, L.cin, S);
+      const int nmap = 9 * L.cout * L.cin;
+      k_up_tapmap<<<(nmap + 255) / 256, 256, 0, st>>>(S, L.coutp, L.cinp, L.cout, L.cin,
+                                                      n->grads + L.woff);
+      k_bgrad_reduce<<<(L.coutp + 15) / 16, 256, 0, st>>>(n->wpart + (size_t)wslices * nent,
+                                                           2 * wslices, L.coutp, L.cout,
+                                                           n->grads + L.boff);
+    } else {
+      const int nent = 9 * L.coutp * L.cinp;
+      k_wgrad_reduce<9><<<(nent + 63) / 64, 256, 0, st>>>(n->wpart, wslices, L.coutp, L.cinp,
+                                                          L.cout, L.cin, n->grads + L.woff);
+      k_bgrad_reduce<<<(L.coutp + 15) / 16, 256, 0, st>>>(n->wpart + (size_t)wslices * nent,
+                                                           wslices, L.coutp, L.cout,
+                                                           n->grads + L.boff);
+    }
     // data gradient into the previous layer (masked by its ReLU)
     GemmArgs a{};
     a.src = n->dz[l];
