@@ -1891,8 +1891,7 @@ static int launch_wgrad_row(dd_cnn* n, int l, int B, hipStream_t st) {
 
 // whether an upsampling layer's weight gradient runs on k_conv_wgrad_up
 static bool wgrad_up_kernel(const CnnLayer& L) {
-  const int NB = std::min(L.cinp, 64);
-  return L.cinp % NB == 0 && NB == 64 && (L.coutp == 64 || L.coutp == 32);
+  return (L.coutp == 64 && L.cinp % 32 == 0) || (L.coutp == 32 && L.cinp % 64 == 0);
 }
 
 template <int MT, int NT, int S>
@@ -1943,7 +1942,7 @@ static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
     // the two upsampling layers (128 -> 64 and 64 -> 32 channels) at the
     // source resolution, sixteen products per pixel
     if (wgrad_up_kernel(L)) {
-      return Mr == 64 ? launch_wgrad_up<4, 4, 1>(n, l, B, st) : launch_wgrad_up<2, 4, 2>(n, l, B, st);
+      return Mr == 64 ? launch_wgrad_up<4, 2, 2>(n, l, B, st) : launch_wgrad_up<2, 4, 2>(n, l, B, st);
     }
     WG_CASES(WG_ROWU, WG_ROWU3)
   }
