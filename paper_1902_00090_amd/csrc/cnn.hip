@@ -1911,7 +1911,7 @@ static int launch_wgrad_up(dd_cnn* n, int l, int B, hipStream_t st) {
 // map).  Returns the number of pixel slices written to n->wpart (weights
 // [slice][9][coutp][cinp], then bias [slice][coutp]), 0 (nothing launched)
 // for channel counts without an instance.
-static int wgrad_seg(dd_cnn* n, int l, int B, hipStream_t st) {
+static int wgrad_partials(dd_cnn* n, int l, int B, hipStream_t st) {
   const CnnLayer& L = n->L[l];
   const int Mr = L.coutp, Nc = L.cinp, NB = std::min(Nc, 64);
   if (Nc % NB) return 0;
@@ -1968,7 +1968,7 @@ static dd_status backward_from_dz(dd_cnn* n, int B, hipStream_t st) {
   for (int l = NL - 1; l >= 1; --l) {
     const CnnLayer& L = n->L[l];
     // weight and bias gradients of layer l
-    const int wslices = wgrad_seg(n, l, B, st);
+    const int wslices = wgrad_partials(n, l, B, st);
     if (wslices <= 0) {
       dd_set_error("dd_cnn: no weight-gradient kernel for %d x %d channels", L.coutp, L.cinp);
       return DD_EINVAL;

@@ -209,9 +209,10 @@ def test_forward_full_size():
 @pytest.mark.parametrize("nx,ny,k", [(24, 16, 10), (64, 32, 10), (40, 12, 20), (24, 16, 32),
                                      (8, 8, 10)])
 def test_gradients_match_oracle(nx, ny, k):
-    """Weight gradients: row chunks for the stride-1 and upsampling layers
-    (one ragged chunk per row at these widths), flattened pixel stages for the
-    stride-2 layers (crossing rows and images, ragged at the end).  k = 20 / 32
+    """Weight gradients: row chunks for the stride-1 and stride-2 layers (one
+    ragged chunk per row at these widths; stride 2 with the odd and even input
+    columns staged apart), chunks of source rows for the upsampling layers
+    (sixteen parity-shift products mapped onto the nine taps).  k = 20 / 32
     give the last layer 40 / 64 real channels (padded to 64).  8 x 8 shrinks
     the stride-2 layers to 4 x 4 and 2 x 2 outputs (batch 8 there).  Layer 1's
     gradient runs over flattened pixel ranges, crossing rows and images at
