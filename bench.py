@@ -881,9 +881,9 @@ def c1_leg(args, torch, W):
 
 
 def c2_leg(args, torch, W, U, ref):
-    """The single grating solve (seed 1000) alone, plain and PCA-augmented,
-    step groups replayed as HIP graphs, to 1e-6 and to tol_acc; errors
-    against the FP64 sparse LU solution."""
+    """The single grating solve (seed 1000) alone, plain and PCA-augmented
+    (plain only without a basis U), step groups replayed as HIP graphs, to
+    1e-6 and to tol_acc; errors against the FP64 sparse LU solution."""
     from paper_1902_00090_amd import FdfdOp, Solver
     inst = W.grating(1000)
     op = FdfdOp.from_instance(inst)
@@ -894,6 +894,8 @@ def c2_leg(args, torch, W, U, ref):
     # one-sweep step (which moves each basis vector once and takes two
     # launches per step: the faster of the two for one problem alone)
     for aug, fused in ((False, False), (True, False), (False, True), (True, True)):
+        if aug and U is None:
+            continue
         s = Solver([op], restart=args.restart, kmax=args.k if aug else 0, cgs_passes=args.cgs,
                    use_graph=True, fused=fused)
         if aug:
@@ -983,6 +985,9 @@ def main():
     ap.add_argument("--c5-loss", default="proj", choices=("proj", "res"),
                     help="projection-type (local-PCA targets) or residual loss (unsupervised)")
     ap.add_argument("--cnn-kernels", type=int, default=0)
+    ap.add_argument("--c2-only", action="store_true",
+                    help="only the single grating solve (seed 1000), plain GMRES, two-sweep and "
+                         "one-sweep steps")
     ap.add_argument("--calibrate-copy", type=int, default=0)
     args = ap.parse_args()
 
@@ -997,7 +1002,7 @@ def main():
     workers = args.workers or min(16, len(os.sched_getaffinity(0)))
     t0 = time.time()
     train, test = [], []
-    if args.cnn_kernels <= 0 and not args.c5_only:
+    if args.cnn_kernels <= 0 and not args.c5_only and not args.c2_only:
         train = make_instances(range(W.PCA_TRAIN_SEED0, W.PCA_TRAIN_SEED0 + args.train), workers)
         test = make_instances(range(W.PCA_TEST_SEED0, W.PCA_TEST_SEED0 + args.test), workers)
         log(f"data: {len(train)} training + {len(test)} test instances, {time.time() - t0:.1f}s "
@@ -1023,6 +1028,11 @@ def main():
         return
     if args.c5_only:
         print(json.dumps({"cnn_at_scale": c5_leg(args, torch, W)}), flush=True)
+        return
+    if args.c2_only:
+        print(json.dumps({"c2_single_grating": c2_leg(args, torch, W, None,
+                                                      oracle_reference(W.grating(1000)))}),
+              flush=True)
         return
 
     # ---------------- predictor training (untimed)

@@ -80,6 +80,7 @@ struct PlanDev {
   double2* c0;       // [nb][kmax]
   double2* coefA;    // [nb][NC]
   double2* coefB;    // [nb][NC]
+  double2* coefA2;   // [nb][NC] one-sweep steps: raw dots of odd steps (coefA: even)
   double* hscale;    // [nb][m+1]
   double2* comb;     // [nb][kmax + m]
   double2* Rinv;     // [nb][kmax][kmax]

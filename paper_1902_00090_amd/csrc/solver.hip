@@ -146,6 +146,7 @@ static void layout_workspace(dd_solver* s, Arena& A, ProbDesc*& dd, int*& db2p) 
   A.carve(&P.c0, (size_t)nb * std::max(K, 1));
   A.carve(&P.coefA, (size_t)nb * P.NC);
   A.carve(&P.coefB, (size_t)nb * P.NC);
+  A.carve(&P.coefA2, (size_t)nb * P.NC);
   A.carve(&P.hscale, (size_t)nb * (m + 1));
   A.carve(&P.comb, (size_t)nb * (K + m));
   A.carve(&P.Rinv, (size_t)nb * std::max(K * K, 1));
@@ -529,6 +530,14 @@ static void prof_collect(dd_solver* s) {
   s->pused = 0;
 }
 
+// Workgroups per problem for the reduction of a sweep's dot products: up to
+// 32 value slices (about 256 workgroups in all), one where the adaptive
+// second-pass test needs every coefficient of the first pass at once.
+static int post_slices(const dd_solver* s, bool first_pass) {
+  if (first_pass && s->P.reorth_mode == 2) return 1;
+  return std::max(1, std::min(32, 256 / std::max(1, s->nb)));
+}
+
 // One Arnoldi step: matvec + first-pass dots, their reduction (which also
 // decides the second pass), the optional second pass (only flagged problems
 // do work in it), the final update + norm and the FP64 bookkeeping.
@@ -543,12 +552,12 @@ static void launch_step(dd_solver* s, int j, hipStream_t st) {
   if (s->o.precond != DD_PRECOND_NONE) k_matvec_dot<T, R, true><<<gm, DD_BLOCK, 0, st>>>(s->P, j);
   else k_matvec_dot<T, R, false><<<gm, DD_BLOCK, 0, st>>>(s->P, j);
   prof_end(s, st);
-  k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
+  k_post_dots<T><<<dim3(nb, post_slices(s, true)), DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
   if (s->P.reorth_mode != 0) {
     prof_mark(s, 1, st);
     k_update_dot<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI);
     prof_end(s, st);
-    k_post_dots<T><<<nb, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 1);
+    k_post_dots<T><<<dim3(nb, post_slices(s, false)), DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 1);
   }
   prof_mark(s, 2, st);
   k_update_norm<T, R><<<g, DD_BLOCK, 0, st>>>(s->P, j, MODE_ARNOLDI, 0);
@@ -566,7 +575,7 @@ static void launch_fused_step(dd_solver* s, int j, hipStream_t st) {
   if (pc) k_fused_sweep<T, true><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
   else k_fused_sweep<T, false><<<nt, DD_FUSED_THREADS, 0, st>>>(s->P, j);
   prof_end(s, st);
-  k_post_fused<T><<<s->nb, DD_BLOCK, 0, st>>>(s->P, j, 0);
+  k_post_fused<T><<<dim3(s->nb, post_slices(s, false)), DD_BLOCK, 0, st>>>(s->P, j, 0);
 }
 
 template <typename T, int R>
@@ -640,7 +649,7 @@ static dd_status run_cycles(dd_solver* s, hipStream_t st) {
       if (s->o.precond != DD_PRECOND_NONE) k_matvec_dot<T, R, true><<<gm, DD_BLOCK, 0, st>>>(s->P, 0);
       else k_matvec_dot<T, R, false><<<gm, DD_BLOCK, 0, st>>>(s->P, 0);
       prof_end(s, st);
-      k_post_fused<T><<<nb, DD_BLOCK, 0, st>>>(s->P, 0, 1);
+      k_post_fused<T><<<dim3(nb, post_slices(s, false)), DD_BLOCK, 0, st>>>(s->P, 0, 1);
     }
     int pending = -1, grp = 0;
     const int ce = s->o.check_every;

@@ -99,9 +99,12 @@ __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t D
 // [g per, (g+1) per) and the G group sums are added in group order, so the
 // result is the same every run and the serial chain of dependent loads is G
 // times shorter (one problem of 480 x 240 in 512-element chunks has 225 rows).
+// voff: the first value summed (values voff .. voff + nvals - 1 land in
+// red[0 .. nvals - 1]).
 template <typename PT>
-__device__ void reduce_rows(const PlanDev& P, int blk0, int nblk, int nvals, double* red) {
-  const PT* part = (const PT*)P.partial + (size_t)blk0 * P.NV;
+__device__ void reduce_rows(const PlanDev& P, int blk0, int nblk, int nvals, double* red,
+                            int voff = 0) {
+  const PT* part = (const PT*)P.partial + (size_t)blk0 * P.NV + voff;
   __shared__ double grp[DD_BLOCK];
   const int G = (nvals >= DD_BLOCK) ? 1 : min(64, DD_BLOCK / nvals);
   const int per = (nblk + G - 1) / G;
@@ -359,6 +362,10 @@ __global__ __launch_bounds__(DD_BLOCK) void k_matvec_dot(PlanDev P, int j) {
 // coefficients (dst 0 -> coefA, 1 -> coefB).  After the first sweep of an
 // Arnoldi step it also rescales the dot with the deferred-normalisation
 // vector q_j and decides whether this step takes the second pass.
+// grid.y > 1 (only without the adaptive second-pass test, which needs all
+// coefficients at once): workgroup y sums its own slice of the 2n values,
+// so a problem's rows are summed by several workgroups (one problem alone
+// otherwise leaves the reduction to a single workgroup).
 template <typename PT>
 __global__ __launch_bounds__(DD_BLOCK) void k_post_dots(PlanDev P, int j, int mode, int dst) {
   const int p = blockIdx.x;
@@ -372,6 +379,22 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_dots(PlanDev P, int j, int mo
   const bool first_arnoldi = (mode == MODE_ARNOLDI && dst == 0);
   __shared__ double red[DD_NV_MAX];
   __shared__ double cc_l[8];
+  if (gridDim.y > 1) {
+    // complex values [c0, c1) of this slice
+    const int per = (n + gridDim.y - 1) / gridDim.y;
+    const int c0 = blockIdx.y * per, c1 = min(n, c0 + per);
+    // one pass, or two in every step: the second-pass flag is the mode itself
+    if (first_arnoldi && blockIdx.y == 0 && threadIdx.x == 0) st[ST_REORTH] = P.reorth_mode;
+    if (c0 >= c1) return;
+    reduce_rows<PT>(P, d.blk0, d.nblk, 2 * (c1 - c0), red, 2 * c0);
+    const double hs = first_arnoldi ? P.hscale[(size_t)p * (P.m + 1) + j] : 1.0;
+    double2* out = (dst == 0 ? P.coefA : P.coefB) + (size_t)p * P.NC;
+    for (int v = c0 + threadIdx.x; v < c1; v += DD_BLOCK) {
+      const double sc = (first_arnoldi && v == n - 1) ? hs : 1.0;
+      out[v] = make_double2(red[2 * (v - c0)] * sc, red[2 * (v - c0) + 1] * sc);
+    }
+    return;
+  }
   reduce_rows<PT>(P, d.blk0, d.nblk, first_arnoldi ? nvr + 1 : 2 * n, red);
   const double hs = first_arnoldi ? P.hscale[(size_t)p * (P.m + 1) + j] : 1.0;
   double2* out = (dst == 0 ? P.coefA : P.coefB) + (size_t)p * P.NC;
@@ -520,11 +543,15 @@ __global__ __launch_bounds__(DD_BLOCK) void k_update_norm(PlanDev P, int j, int 
 // previous Givens rotations and a new one, updates the residual estimate
 // g_{j+1} and the step counters, sets hscale[j + 1] = hs_next, and decides
 // whether the cycle ends here (fin, nfin).  Called by all threads of the
-// problem's workgroup.
+// problem's workgroup, with thread t < j holding the previous rotation t
+// (cs_t, sn_t: loaded by the caller before its reductions, so that their
+// latency overlaps them).
+static_assert(DD_MAX_M <= DD_BLOCK, "one previous rotation per thread");
+static_assert(DD_MAX_K + DD_MAX_M + 1 <= 2 * DD_BLOCK, "two coefficients per thread");
 __device__ void arnoldi_column(const PlanDev& P, int p, int j, int k, double2* col, double nrm,
                                double hs_next, int cgs2, double2 gj, int it0, int nre0,
                                double nsum0, double nsum20, double bn, double ctl_tol,
-                               double ctl_maxit, int& fin, int& nfin) {
+                               double ctl_maxit, double cs_t, double2 sn_t, int& fin, int& nfin) {
   const int m = P.m, t = threadIdx.x;
   const int n = k + j + 1;
   int* st = P.stI + p * ST_NI;
@@ -536,9 +563,9 @@ __device__ void arnoldi_column(const PlanDev& P, int p, int j, int k, double2* c
   // the previous rotations, staged by all threads for thread 0's serial pass
   __shared__ double cs_l[DD_MAX_M];
   __shared__ double2 sn_l[DD_MAX_M];
-  for (int i = t; i < j; i += DD_BLOCK) {
-    cs_l[i] = P.cs[(size_t)p * m + i];
-    sn_l[i] = P.sn[(size_t)p * m + i];
+  if (t < j) {
+    cs_l[t] = cs_t;
+    sn_l[t] = sn_t;
   }
   for (int v = t; v < k; v += DD_BLOCK) Bc[v] = col[v];
   for (int i = t; i <= j; i += DD_BLOCK) Hraw[i] = col[k + i];
@@ -547,8 +574,27 @@ __device__ void arnoldi_column(const PlanDev& P, int p, int j, int k, double2* c
     Hraw[j + 1] = make_double2(nrm, 0.0);
     // apply rotations 0..j-1 to the new column; the entry being rotated into
     // the next position stays in registers
+    // (eight rotations' operands are read from LDS before their arithmetic:
+    // one rotation at a time waited on each read; entry i + u + 1 is read
+    // before rotation i + u + 1 writes it, as in the one-at-a-time order)
     double2 cur = hcol[0];
-    for (int i = 0; i < j; ++i) {
+    int i = 0;
+    for (; i + 8 <= j; i += 8) {
+      double2 bb[8], ss[8];
+      double cc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        bb[u] = hcol[i + u + 1];
+        cc[u] = cs_l[i + u];
+        ss[u] = sn_l[i + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        hcol[i + u] = dadd(make_double2(cc[u] * cur.x, cc[u] * cur.y), dmul(ss[u], bb[u]));
+        cur = dsub(make_double2(cc[u] * bb[u].x, cc[u] * bb[u].y), dmulc(ss[u], cur));
+      }
+    }
+    for (; i < j; ++i) {
       const double2 b = hcol[i + 1];
       const double c = cs_l[i];
       const double2 s = sn_l[i];
@@ -631,13 +677,36 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
     ctl_tol = P.ctl[0];
     ctl_maxit = P.ctl[1];
   }
+  // the coefficients and the previous rotations are loaded before the
+  // reduction, so that their latency overlaps it (at most two per thread:
+  // n <= DD_MAX_K + DD_MAX_M, j < DD_MAX_M = DD_BLOCK)
+  const double2* cA = P.coefA + (size_t)p * P.NC;
+  const double2* cB = P.coefB + (size_t)p * P.NC;
+  double2 cv[2], cw[2];   // first- and second-pass coefficients
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int v = t + q * DD_BLOCK;
+    cv[q] = cw[q] = make_double2(0.0, 0.0);
+    if (v < n) {
+      cv[q] = cA[v];
+      cw[q] = cB[v];
+    }
+  }
+  double cs_t = 0.0;
+  double2 sn_t = make_double2(0.0, 0.0);
+  if (mode != MODE_START && t < j) {
+    cs_t = P.cs[(size_t)p * m + t];
+    sn_t = P.sn[(size_t)p * m + t];
+  }
   __shared__ double red[1];
   reduce_rows<PT>(P, d.blk0, d.nblk, 1, red);
   __shared__ double2 col[DD_MAX_K + DD_MAX_M + 2];
   __shared__ int fin, nfin;
-  const double2* cA = P.coefA + (size_t)p * P.NC;
-  const double2* cB = P.coefB + (size_t)p * P.NC;
-  for (int v = t; v < n; v += DD_BLOCK) col[v] = cgs2 ? dadd(cA[v], cB[v]) : cA[v];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int v = t + q * DD_BLOCK;
+    if (v < n) col[v] = cgs2 ? dadd(cv[q], cw[q]) : cv[q];
+  }
   if (t == 0) fin = 0;
   __syncthreads();
   const double nrm = sqrt(red[0]);
@@ -655,7 +724,7 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_norm(PlanDev P, int j, int mo
     }
   } else {
     arnoldi_column(P, p, j, k, col, nrm, (nrm > 0.0) ? 1.0 / nrm : 0.0, cgs2, gj, it0, nre0, nsum0,
-                   nsum20, bn, ctl_tol, ctl_maxit, fin, nfin);
+                   nsum20, bn, ctl_tol, ctl_maxit, cs_t, sn_t, fin, nfin);
   }
   __syncthreads();
   if (fin) finish_cycle(P, p, k, nfin);
@@ -935,14 +1004,18 @@ __global__ __launch_bounds__(DD_FUSED_THREADS, 4) void k_fused_sweep(PlanDev P, 
   }
 }
 
-// One workgroup per problem after a fused sweep (init = 1: after the first
-// matvec of a cycle, k_matvec_dot writing z_0 = A q~_0 unscaled).  Reduces
-// the tile rows: raw dots d' of z_{j+1} (z_0) and ||q~_{j+1}||^2.  For a
-// step: completes column j of the Arnoldi relation from the previous dots
-// (coefA) and h_{j+1,j} = ||q~_{j+1}||, sets s_{j+1}, runs the Givens update
-// (arnoldi_column) and ends the cycle if due.  Then stores the new raw dots
-// (coefA) and the next update coefficients g_v = s_{j+1} s_v^2 d'_v (coefB;
-// s_0 for init).
+// After a fused sweep (init = 1: after the first matvec of a cycle,
+// k_matvec_dot writing z_0 = A q~_0 unscaled).  Reduces the tile rows: raw
+// dots d' of z_{j+1} (z_0) and ||q~_{j+1}||^2.  For a step: completes column
+// j of the Arnoldi relation from the previous dots and h_{j+1,j} =
+// ||q~_{j+1}||, sets s_{j+1}, runs the Givens update (arnoldi_column) and ends
+// the cycle if due.  Then stores the new raw dots and the next update
+// coefficients g_v = s_{j+1} s_v^2 d'_v (coefB; s_0 for init).  The raw dots
+// alternate between coefA (written by init and odd j... read back by even
+// steps) and coefA2, so that a step reads the previous dots while the new ones
+// are written: grid.y workgroups per problem each reduce a slice of the new
+// dots (every slice sums the norm in the same order, so s_{j+1} is the same
+// in all), and slice 0 alone does the Givens update.
 template <typename PT>
 __global__ __launch_bounds__(DD_BLOCK) void k_post_fused(PlanDev P, int j, int init) {
   const int p = blockIdx.x;
@@ -953,10 +1026,15 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_fused(PlanDev P, int j, int i
   const int nn = init ? k + 1 : k + j + 2;      // vectors of the new dots
   const double* hs = P.hscale + (size_t)p * (m + 1);
   double* sd = P.stD + p * SD_ND;
+  const bool lead = blockIdx.y == 0;
+  // dots written by the call before (init, or step j - 1), and the new ones
+  double2* cOld = ((j & 1) ? P.coefA2 : P.coefA) + (size_t)p * P.NC;
+  double2* cNew = ((init || (j & 1)) ? P.coefA : P.coefA2) + (size_t)p * P.NC;
+  double2* cB = P.coefB + (size_t)p * P.NC;
   double2 gj = make_double2(0.0, 0.0);
   int it0 = 0;
   double nsum0 = 0.0, bn = 0.0, ctl_tol = 0.0, ctl_maxit = 0.0;
-  if (t == 0 && !init) {
+  if (lead && t == 0 && !init) {
     gj = P.g[(size_t)p * (m + 1) + j];
     it0 = st[ST_ITERS];
     nsum0 = sd[SD_NSUM];
@@ -965,41 +1043,70 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_fused(PlanDev P, int j, int i
     ctl_maxit = P.ctl[1];
   }
   __shared__ double red[DD_NV_MAX];
+  __shared__ double nrm2[1];
   __shared__ double2 col[DD_MAX_K + DD_MAX_M + 2];
   __shared__ int fin, nfin;
-  if (init) {
-    // k_matvec_dot's rows: dots [C, q~_0]^H z_0 in 16-vector groups, ||z||^2 after
-    reduce_rows<PT>(P, d.blk0, d.nblk, 2 * nn, red);
-  } else {
-    reduce_rows<PT>(P, d.t0, d.nt, 2 * nn + 1, red);
-  }
-  if (t == 0) fin = 0;
-  double2* cA = P.coefA + (size_t)p * P.NC;
-  double2* cB = P.coefB + (size_t)p * P.NC;
-  if (!init) {
+  // the lead slice's column of the previous dots and the previous rotations,
+  // loaded before the reductions so that their latency overlaps them (at
+  // most two per thread)
+  double2 cv[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  double cs_t = 0.0;
+  double2 sn_t = make_double2(0.0, 0.0);
+  if (lead && !init) {
     const double sj = hs[j];
-    const double nrm = sqrt(red[2 * nn]);
-    for (int v = t; v < k + j + 1; v += DD_BLOCK) {
-      const double2 dv = cA[v];
-      const double sv = (v < k) ? 1.0 : hs[v - k];
-      col[v] = make_double2(sv * sj * dv.x, sv * sj * dv.y);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int v = t + q * DD_BLOCK;
+      if (v < k + j + 1) {
+        const double2 dv = cOld[v];
+        const double sv = (v < k) ? 1.0 : hs[v - k];
+        cv[q] = make_double2(sv * sj * dv.x, sv * sj * dv.y);
+      }
     }
-    __syncthreads();
-    arnoldi_column(P, p, j, k, col, nrm, (nrm > 0.0) ? 1.0 / nrm : 0.0, 0, gj, it0, 0, nsum0,
-                   0.0, bn, ctl_tol, ctl_maxit, fin, nfin);
-    __syncthreads();
+    if (t < j) {
+      cs_t = P.cs[(size_t)p * m + t];
+      sn_t = P.sn[(size_t)p * m + t];
+    }
   }
-  // the new raw dots and update coefficients (hscale[j + 1] is set above)
-  const double snew = hs[init ? 0 : j + 1];
-  for (int v = t; v < nn; v += DD_BLOCK) {
-    const double2 dv = make_double2(red[2 * v], red[2 * v + 1]);
-    const double sv = (v < k) ? 1.0 : hs[v - k];
+  // complex values [c0, c1) of this slice
+  const int per = (nn + gridDim.y - 1) / gridDim.y;
+  const int c0 = blockIdx.y * per, c1 = min(nn, c0 + per);
+  double snew;
+  if (init) {
+    // k_matvec_dot's rows: dots [C, q~_0]^H z_0 in 16-vector groups
+    if (c0 < c1) reduce_rows<PT>(P, d.blk0, d.nblk, 2 * (c1 - c0), red, 2 * c0);
+    snew = hs[0];
+  } else {
+    reduce_rows<PT>(P, d.t0, d.nt, 1, nrm2, 2 * nn);
+    if (c0 < c1) reduce_rows<PT>(P, d.t0, d.nt, 2 * (c1 - c0), red, 2 * c0);
+    const double nrm = sqrt(nrm2[0]);
+    snew = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+    if (lead) {
+      if (t == 0) fin = 0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int v = t + q * DD_BLOCK;
+        if (v < k + j + 1) col[v] = cv[q];
+      }
+      __syncthreads();
+      arnoldi_column(P, p, j, k, col, nrm, snew, 0, gj, it0, 0, nsum0, 0.0, bn, ctl_tol,
+                     ctl_maxit, cs_t, sn_t, fin, nfin);
+      __syncthreads();
+    }
+  }
+  // the new raw dots and update coefficients (s_v for v <= k + j are those
+  // of earlier steps; s_{j+1} = snew)
+  for (int v = c0 + t; v < c1; v += DD_BLOCK) {
+    const double2 dv = make_double2(red[2 * (v - c0)], red[2 * (v - c0) + 1]);
+    const double sv = (v < k) ? 1.0 : (v - k == (init ? 0 : j + 1) ? snew : hs[v - k]);
     const double gs = snew * sv * sv;
-    cA[v] = dv;
+    cNew[v] = dv;
     cB[v] = make_double2(gs * dv.x, gs * dv.y);
   }
-  __syncthreads();
-  if (fin) finish_cycle(P, p, k, nfin);
+  if (lead && !init) {
+    __syncthreads();
+    if (fin) finish_cycle(P, p, k, nfin);
+  }
 }
 
 // Diagonal preconditioner of problem p, [Dp] elements, zero in the padding.
