@@ -100,27 +100,32 @@ __device__ __forceinline__ void block_dots(const c2<T>* __restrict__ B, size_t D
 // result is the same every run and the serial chain of dependent loads is G
 // times shorter (one problem of 480 x 240 in 512-element chunks has 225 rows).
 // voff: the first value summed (values voff .. voff + nvals - 1 land in
-// red[0 .. nvals - 1]).
+// red[0 .. nvals - 1]); last >= 0: the last of the nvals values is value
+// `last` instead (a value outside the range, summed in the same pass);
+// gfix > 0: that many thread groups (gfix nvals <= DD_BLOCK), so that a value
+// summed by several workgroups with different nvals is added in the same
+// order in all of them.
 template <typename PT>
 __device__ void reduce_rows(const PlanDev& P, int blk0, int nblk, int nvals, double* red,
-                            int voff = 0) {
+                            int voff = 0, int last = -1, int gfix = 0) {
   const PT* part = (const PT*)P.partial + (size_t)blk0 * P.NV + voff;
   __shared__ double grp[DD_BLOCK];
-  const int G = (nvals >= DD_BLOCK) ? 1 : min(64, DD_BLOCK / nvals);
+  const int G = (gfix > 0) ? gfix : (nvals >= DD_BLOCK) ? 1 : min(64, DD_BLOCK / nvals);
   const int per = (nblk + G - 1) / G;
   for (int tv = threadIdx.x; tv < ((G == 1) ? nvals : G * nvals); tv += DD_BLOCK) {
     const int v = (G == 1) ? tv : tv % nvals, g = (G == 1) ? 0 : tv / nvals;
+    const int vc = (last >= 0 && v == nvals - 1) ? last - voff : v;   // column read
     const int c0 = g * per, c1 = min(nblk, c0 + per);
     double s = 0.0;
     int c = c0;
     for (; c + 16 <= c1; c += 16) {
       double a[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) a[q] = (double)part[(size_t)(c + q) * P.NV + v];
+      for (int q = 0; q < 16; ++q) a[q] = (double)part[(size_t)(c + q) * P.NV + vc];
 #pragma unroll
       for (int q = 0; q < 16; ++q) s += a[q];
     }
-    for (; c < c1; ++c) s += (double)part[(size_t)c * P.NV + v];
+    for (; c < c1; ++c) s += (double)part[(size_t)c * P.NV + vc];
     if (G == 1) red[v] = s;
     else grp[tv] = s;
   }
@@ -560,47 +565,53 @@ __device__ void arnoldi_column(const PlanDev& P, int p, int j, int k, double2* c
   double2* Hc = P.H + ((size_t)p * m + j) * (m + 1);
   double2* Bc = P.Bc + ((size_t)p * m + j) * P.kmax;
   double2* hcol = col + k;
-  // the previous rotations, staged by all threads for thread 0's serial pass
-  __shared__ double cs_l[DD_MAX_M];
-  __shared__ double2 sn_l[DD_MAX_M];
-  if (t < j) {
-    cs_l[t] = cs_t;
-    sn_l[t] = sn_t;
-  }
   for (int v = t; v < k; v += DD_BLOCK) Bc[v] = col[v];
   for (int i = t; i <= j; i += DD_BLOCK) Hraw[i] = col[k + i];
+  // Rotations 0..j-1 applied to the new column (entries b_i = hcol[i]):
+  // with cur_0 = b_0 and cur_{i+1} = c_i b_{i+1} - conj(s_i) cur_i, entry i
+  // becomes c_i cur_i + s_i b_{i+1} and cur_j meets the new rotation.  The
+  // recurrence is affine, cur_{i+1} = f_i(cur_i) with f_i(x) = beta_i x +
+  // alpha_i, so thread i forms F_i = f_i o ... o f_0 by a scan over the
+  // workgroup (six shuffle rounds per wave, then the earlier waves' totals)
+  // and has cur_{i+1} = F_i(cur_0) at once, instead of one lane stepping
+  // through j rotations one FP64 operation at a time.
+  const int lane = t & 63, wv = t >> 6;
+  double2 b1 = make_double2(0.0, 0.0);                                       // b_{t+1}
+  double2 MB = make_double2(1.0, 0.0), MA = make_double2(0.0, 0.0);          // identity past j
+  if (t < j) {
+    b1 = hcol[t + 1];
+    MB = make_double2(-sn_t.x, sn_t.y);                                      // -conj(s_t)
+    MA = make_double2(cs_t * b1.x, cs_t * b1.y);                             // c_t b_{t+1}
+  }
+  const double2 cur0 = hcol[0];
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {   // inclusive scan: (B, A) o (pB, pA)
+    const double2 pB = make_double2(__shfl_up(MB.x, off, 64), __shfl_up(MB.y, off, 64));
+    const double2 pA = make_double2(__shfl_up(MA.x, off, 64), __shfl_up(MA.y, off, 64));
+    if (lane >= off) {
+      MA = dadd(dmul(MB, pA), MA);
+      MB = dmul(MB, pB);
+    }
+  }
+  __shared__ double2 tB[DD_BLOCK / 64], tA[DD_BLOCK / 64];
+  __shared__ double2 curs[DD_MAX_M + 1];
+  if (lane == 63) {
+    tB[wv] = MB;
+    tA[wv] = MA;
+  }
+  __syncthreads();   // wave totals visible; every read of hcol above is done
+  double2 PB = make_double2(1.0, 0.0), PA = make_double2(0.0, 0.0);   // earlier waves, in order
+  for (int w = 0; w < wv; ++w) {
+    PA = dadd(dmul(tB[w], PA), tA[w]);
+    PB = dmul(tB[w], PB);
+  }
+  if (t < j) curs[t + 1] = dadd(dmul(dmul(MB, PB), cur0), dadd(dmul(MB, PA), MA));
+  if (t == 0) curs[0] = cur0;
   __syncthreads();
+  if (t < j) hcol[t] = dadd(make_double2(cs_t * curs[t].x, cs_t * curs[t].y), dmul(sn_t, b1));
   if (t == 0) {
     Hraw[j + 1] = make_double2(nrm, 0.0);
-    // apply rotations 0..j-1 to the new column; the entry being rotated into
-    // the next position stays in registers
-    // (eight rotations' operands are read from LDS before their arithmetic:
-    // one rotation at a time waited on each read; entry i + u + 1 is read
-    // before rotation i + u + 1 writes it, as in the one-at-a-time order)
-    double2 cur = hcol[0];
-    int i = 0;
-    for (; i + 8 <= j; i += 8) {
-      double2 bb[8], ss[8];
-      double cc[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        bb[u] = hcol[i + u + 1];
-        cc[u] = cs_l[i + u];
-        ss[u] = sn_l[i + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        hcol[i + u] = dadd(make_double2(cc[u] * cur.x, cc[u] * cur.y), dmul(ss[u], bb[u]));
-        cur = dsub(make_double2(cc[u] * bb[u].x, cc[u] * bb[u].y), dmulc(ss[u], cur));
-      }
-    }
-    for (; i < j; ++i) {
-      const double2 b = hcol[i + 1];
-      const double c = cs_l[i];
-      const double2 s = sn_l[i];
-      hcol[i] = dadd(make_double2(c * cur.x, c * cur.y), dmul(s, b));
-      cur = dsub(make_double2(c * b.x, c * b.y), dmulc(s, cur));
-    }
+    const double2 cur = curs[j];
     // new rotation zeroing the subdiagonal entry nrm
     const double2 a = cur;
     const double aa = sqrt(a.x * a.x + a.y * a.y);
@@ -1077,8 +1088,14 @@ __global__ __launch_bounds__(DD_BLOCK) void k_post_fused(PlanDev P, int j, int i
     if (c0 < c1) reduce_rows<PT>(P, d.blk0, d.nblk, 2 * (c1 - c0), red, 2 * c0);
     snew = hs[0];
   } else {
-    reduce_rows<PT>(P, d.t0, d.nt, 1, nrm2, 2 * nn);
-    if (c0 < c1) reduce_rows<PT>(P, d.t0, d.nt, 2 * (c1 - c0), red, 2 * c0);
+    // the slice's values and ||q~_{j+1}||^2 (value 2 nn) in one pass, with
+    // the thread groups of the largest slice in every slice (the same sum
+    // order for the norm, so every slice has the same s_{j+1})
+    const int nv = (c0 < c1) ? 2 * (c1 - c0) : 0;
+    const int gfix = max(1, min(64, DD_BLOCK / (2 * per + 1)));
+    reduce_rows<PT>(P, d.t0, d.nt, nv + 1, red, (c0 < c1) ? 2 * c0 : 2 * nn, 2 * nn, gfix);
+    if (t == 0) nrm2[0] = red[nv];
+    __syncthreads();
     const double nrm = sqrt(nrm2[0]);
     snew = (nrm > 0.0) ? 1.0 / nrm : 0.0;
     if (lead) {
