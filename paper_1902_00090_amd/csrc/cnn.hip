@@ -1006,6 +1006,200 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
   }
 }
 
+// Weight gradients of a stride-1 layer, all three dy per work item, with the
+// input rows kept in a ring: a slice's stages walk down one column chunk
+// (stage order image, chunk, row), so stage y needs input rows y - 1, y and
+// y + 1 and the next stage only row y + 2, which replaces row y - 1 in the
+// ring of three staged rows.  A stage therefore loads its dz row and one
+// input row (k_conv_wgrad_row with all three dy loads three input rows).  At
+// the first stage of a slice, and where the walk enters a new chunk or image,
+// rows y - 1 and y are loaded as well.  Staging blocks, the column shifts of
+// the three dx taps and the partials are those of k_conv_wgrad_row (dsplit 1).
+template <int MT, int NT, int S>
+__global__ __launch_bounds__(256) void k_conv_wgrad_ring(const bf16* __restrict__ dz,
+                                                         const bf16* __restrict__ x, int B,
+                                                         int H, int W, int Nc, int stages_per,
+                                                         int nwork, float* __restrict__ part,
+                                                         float* __restrict__ bpart) {
+  constexpr int Mr = 16 * MT, NB = 16 * NT, PX = 32 * S, LD = PX + 8;
+  constexpr int XC = PX + 16, LDX = XC + 8;          // staged columns x0 - 8 .. x0 + PX + 7
+  constexpr int ABLK = (PX / 8) * (Mr / 8);
+  constexpr int XBLK = (PX / 8 + 2) * (NB / 8);      // one input row
+  constexpr int NBLK = ABLK + XBLK, BPT = (NBLK + 255) / 256;
+  constexpr int NU = MT * NT, PER_WAVE = (NU + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16 As[Mr][LD];
+  __shared__ __attribute__((aligned(16))) bf16 Xs[3][NB][LDX];   // ring: row r in slot r mod 3
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if (w >= nwork) return;
+  const int nblk = Nc / NB;
+  const int n0 = (w % nblk) * NB, slice = w / nblk;
+  const int nch = (W + PX - 1) / PX, nst = B * nch * H;
+  const int s0 = slice * stages_per, s1 = min(nst, s0 + stages_per);
+  auto slot = [](int r) { return (r + 3) % 3; };   // r >= -1
+  bf16x8 reg[BPT][8];
+  // input row ry (zeros outside the image) of chunk x0 into the X blocks'
+  // registers; with dzrow, dz row y of the chunk into the A blocks' too
+  auto load = [&](int b, int x0, int y, int ry, bool dzrow) {
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) reg[bi][i] = zero8();
+      if (blk < ABLK) {
+        if (dzrow) {
+          const int pg = blk / (Mr / 8), cg = (blk % (Mr / 8)) * 8;
+          const bf16* src = dz + (((size_t)b * H + y) * W + x0) * Mr + cg;
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (x0 + pg * 8 + i < W) reg[bi][i] = load8(src + (size_t)(pg * 8 + i) * Mr);
+        }
+      } else if (blk < NBLK && ry >= 0 && ry < H) {
+        const int r = blk - ABLK, m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+        const int c0 = x0 - 8 + 8 * m;   // first source column
+        const bf16* src = x + ((size_t)b * H + ry) * W * Nc + n0 + cg;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (c0 + i >= 0 && c0 + i < W) reg[bi][i] = load8(src + (size_t)(c0 + i) * Nc);
+      }
+    }
+  };
+  auto store = [&](int xslot, bool dzrow) {
+#pragma unroll
+    for (int bi = 0; bi < BPT; ++bi) {
+      const int blk = threadIdx.x + 256 * bi;
+      if (blk < ABLK) {
+        if (dzrow) {
+          bf16* dst = &As[(blk % (Mr / 8)) * 8][(blk / (Mr / 8)) * 8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            bf16x8 t;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) t[i] = reg[bi][i][q];
+            *(bf16x8*)(dst + q * LD) = t;
+          }
+        }
+      } else if (blk < NBLK) {
+        const int r = blk - ABLK, m = r / (NB / 8), cg = (r % (NB / 8)) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          bf16x8 t;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) t[i] = reg[bi][i][q];
+          *(bf16x8*)&Xs[xslot][cg + q][8 * m] = t;
+        }
+      }
+    }
+  };
+  auto decode = [&](int sg, int& b, int& x0, int& y) {
+    b = sg / (nch * H);
+    const int rem = sg - b * nch * H, ch = rem / H;
+    y = rem - ch * H;
+    x0 = ch * PX;
+  };
+  f32x4 acc[PER_WAVE][9];   // [unit][dy * 3 + dx]
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i)
+#pragma unroll
+    for (int d = 0; d < 9; ++d) acc[i][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int BT = (MT + 3) / 4;
+  const bool bias = (n0 == 0);
+  f32x4 accb[BT];
+#pragma unroll
+  for (int i = 0; i < BT; ++i) accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ones;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ones[q] = (bf16)1.f;
+  const int kq = 8 * (lane >> 4);
+  if (s0 < s1) {
+    int b, x0, y;
+    decode(s0, b, x0, y);
+    load(b, x0, y, y + 1, true);
+  }
+  for (int sg = s0; sg < s1; ++sg) {
+    int b, x0, y;
+    decode(sg, b, x0, y);
+    __syncthreads();   // the previous stage's readers of As and of row y - 2's slot are done
+    store(slot(y + 1), true);
+    if (sg == s0 || y == 0) {   // a new walk: rows y - 1 and y as well
+      for (int r = y - 1; r <= y; ++r) {
+        load(b, x0, y, r, false);
+        store(slot(r), false);
+      }
+    }
+    __syncthreads();
+    if (sg + 1 < s1) {
+      int bn, xn, yn;
+      decode(sg + 1, bn, xn, yn);
+      load(bn, xn, yn, yn + 1, true);
+    }
+    const int sl[3] = {slot(y - 1), slot(y), slot(y + 1)};
+#pragma unroll
+    for (int kk = 0; kk < S; ++kk) {
+#pragma unroll
+      for (int i = 0; i < PER_WAVE; ++i) {
+        const int u = wave + 4 * i;
+        if (u < NU) {
+          const int ti = u / NT, tj = u - ti * NT;
+          const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy) {
+            const bf16* xr = &Xs[sl[dy]][tj * 16 + (lane & 15)][kk * 32 + kq + 8];   // dx = 1
+            const u32x4 a4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr - 8));
+            const u32x4 b4 = __builtin_bit_cast(u32x4, *(const bf16x8*)xr);
+            const u32x4 c4 = __builtin_bit_cast(u32x4, *(const bf16x8*)(xr + 8));
+            const unsigned s0w = (a4[3] >> 16) | (b4[0] << 16), s1w = (b4[0] >> 16) | (b4[1] << 16);
+            const unsigned s2w = (b4[1] >> 16) | (b4[2] << 16), s3w = (b4[2] >> 16) | (b4[3] << 16);
+            const unsigned s4w = (b4[3] >> 16) | (c4[0] << 16);
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, u32x4{s0w, s1w, s2w, s3w});   // dx = 0
+            const bf16x8 bm = __builtin_bit_cast(bf16x8, b4);                          // dx = 1
+            const bf16x8 br = __builtin_bit_cast(bf16x8, u32x4{s1w, s2w, s3w, s4w});   // dx = 2
+            acc[i][3 * dy] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl, acc[i][3 * dy], 0, 0, 0);
+            acc[i][3 * dy + 1] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bm, acc[i][3 * dy + 1], 0, 0, 0);
+            acc[i][3 * dy + 2] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, br, acc[i][3 * dy + 2], 0, 0, 0);
+          }
+        }
+      }
+      if (bias) {
+#pragma unroll
+        for (int i = 0; i < BT; ++i) {
+          const int ti = wave + 4 * i;
+          if (ti < MT) {
+            const bf16x8 av = *(const bf16x8*)&As[ti * 16 + (lane & 15)][kk * 32 + kq];
+            accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb[i], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  if (bias) {
+#pragma unroll
+    for (int i = 0; i < BT; ++i) {
+      const int ti = wave + 4 * i;
+      if (ti < MT && (lane & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bpart[(size_t)slice * Mr + ti * 16 + 4 * (lane >> 4) + q] = accb[i][q];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER_WAVE; ++i) {
+    const int u = wave + 4 * i;
+    if (u < NU) {
+      const int ti = u / NT, tj = u - ti * NT;
+      const int c = tj * 16 + (lane & 15);
+#pragma unroll
+      for (int d = 0; d < 9; ++d) {
+        float* out = part + (((size_t)slice * 9 + d) * Mr) * Nc + n0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[(size_t)(ti * 16 + 4 * (lane >> 4) + q) * Nc + c] = acc[i][d][q];
+      }
+    }
+  }
+}
+
 // Weight gradients of the upsampling layers at the source resolution.  The
 // layer input u is the source x repeated over 2 x 2 blocks, so for output
 // pixel (2i + a, 2j + b) tap t reads x at (i + dy, j + dx) with
@@ -1889,6 +2083,19 @@ static int launch_wgrad_row(dd_cnn* n, int l, int B, hipStream_t st) {
   return w.slices;
 }
 
+template <int MT, int NT, int S>
+static int launch_wgrad_ring(dd_cnn* n, int l, int B, hipStream_t st) {
+  static const int cap = occupancy(k_conv_wgrad_ring<MT, NT, S>);
+  const CnnLayer& L = n->L[l];
+  const int Mr = 16 * MT, Nc = L.cinp;
+  const int nst = B * L.Hout * ((L.Wout + 32 * S - 1) / (32 * S));
+  const WgradSplit w = wgrad_split(n, cap, Mr, Nc, 16 * NT, nst, 1);
+  k_conv_wgrad_ring<MT, NT, S><<<w.grid, 256, 0, st>>>(
+      n->dz[l], n->act[l - 1], B, L.Hout, L.Wout, Nc, w.stages_per, w.nwork, n->wpart,
+      n->wpart + (size_t)w.slices * 9 * Mr * Nc);
+  return w.slices;
+}
+
 // whether an upsampling layer's weight gradient runs on k_conv_wgrad_up
 static bool wgrad_up_kernel(const CnnLayer& L) {
   return (L.coutp == 64 && L.cinp % 32 == 0) || (L.coutp == 32 && L.cinp % 64 == 0);
@@ -1937,7 +2144,11 @@ static int wgrad_partials(dd_cnn* n, int l, int B, hipStream_t st) {
 #define WG_ROW13(a, b, c) launch_wgrad_row<a, b, c, MAP_S1, 3>(n, l, B, st)
 #define WG_ROWU3(a, b, c) launch_wgrad_row<a, b, c, MAP_UP, 3>(n, l, B, st)
 #define WG_ROW23(a, b, c) launch_wgrad_row<a, b, c, MAP_S2, 3>(n, l, B, st)
-  if (L.mode == MAP_S1) { WG_CASES(WG_ROW1, WG_ROW13) }
+  if (L.mode == MAP_S1) {
+    // 32 output and 32 input channels (layers 7, 8): input rows in a ring
+    if (Mr == 32 && NB == 32) return launch_wgrad_ring<2, 2, 4>(n, l, B, st);
+    WG_CASES(WG_ROW1, WG_ROW13)
+  }
   else if (L.mode == MAP_UP) {
     // the two upsampling layers (128 -> 64 and 64 -> 32 channels) at the
     // source resolution, sixteen products per pixel
