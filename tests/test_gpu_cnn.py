@@ -211,7 +211,8 @@ def test_forward_full_size():
 def test_gradients_match_oracle(nx, ny, k):
     """Weight gradients: row chunks for the stride-1 and stride-2 layers (one
     ragged chunk per row at these widths; stride 2 with the odd and even input
-    columns staged apart), chunks of source rows for the upsampling layers
+    columns staged apart; the 32-channel layers walk down column chunks with
+    a ring of input rows), chunks of source rows for the upsampling layers
     (sixteen parity-shift products mapped onto the nine taps).  k = 20 / 32
     give the last layer 40 / 64 real channels (padded to 64).  8 x 8 shrinks
     the stride-2 layers to 4 x 4 and 2 x 2 outputs (batch 8 there).  Layer 1's
@@ -223,6 +224,25 @@ def test_gradients_match_oracle(nx, ny, k):
     rng = np.random.default_rng(11)
     tgt = (rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny))) * 0.1
     tgt = tgt.astype(np.complex64)
+    loss, g = net.grad(eps_d, torch.tensor(tgt, device="cuda"))
+    out, cache = check_forward(net, op, eps, k, B)
+    lo, dout = ocnn.mse(out, ocnn.fields_to_channels(tgt.astype(np.complex128), ny, nx))
+    assert abs(loss - lo) < 1e-4 * lo, (loss, lo)
+    check_grads(net, op, cache, dout, k, g)
+
+
+def test_gradients_long_row_walks():
+    """A tall, narrow grid at batch 16 (32 x 480): the weight-gradient slices
+    of layers 7 and 8 walk eight or more consecutive rows of a column chunk
+    with the input rows in a ring, and the stride-2 and upsampling kernels
+    take several stages per slice.  Every gradient element against the
+    oracle."""
+    import torch
+    nx, ny, B, k = 32, 480, 16, 10
+    net, op, eps, eps_d = _setup(nx, ny, B, k, seed=21)
+    rng = np.random.default_rng(22)
+    tgt = ((rng.standard_normal((B, k, nx * ny)) + 1j * rng.standard_normal((B, k, nx * ny)))
+           * 0.1).astype(np.complex64)
     loss, g = net.grad(eps_d, torch.tensor(tgt, device="cuda"))
     out, cache = check_forward(net, op, eps, k, B)
     lo, dout = ocnn.mse(out, ocnn.fields_to_channels(tgt.astype(np.complex128), ny, nx))
