@@ -762,6 +762,9 @@ __global__ __launch_bounds__(256) void k_conv1_fwd(const float* __restrict__ x0,
 // units and applies all three dx to each.  The slice's (dy 0, first channel
 // block) item also sums dz over its pixels (the bias gradient) as dz^T times
 // a column of ones.  Partials: weights [slice][tap][r][c], bias [slice][r].
+// (The network's upsampling layers use k_conv_wgrad_up and its 32-channel
+// stride-1 layers k_conv_wgrad_ring; the upsampling map here serves other
+// channel counts.)
 template <int MT, int NT, int S, int MK, int ND = 1>
 __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__ dz,
                                                         const bf16* __restrict__ x, int B,
@@ -784,6 +787,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_row(const bf16* __restrict__
   __shared__ __attribute__((aligned(16))) bf16 As[Mr][LD];
   __shared__ __attribute__((aligned(16))) bf16 Xs[ND][NB][LDX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // 1D grid, a multiple of 8 long: consecutive work items (the dy and the
+  // channel blocks of one pixel slice) go to the same XCD, whose L2 then
+  // serves their shared dz and input rows
   const int w = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   if (w >= nwork) return;
   const int nblk = Nc / NB;
