@@ -325,3 +325,33 @@ def test_tile_width_matches_oracle(R):
     _, io = gmres_aug.gmres_aug(A, inst.b, V.T, restart=40, tol=1e-30, maxit=120)
     assert info["iters"] == 120
     np.testing.assert_allclose(s.history(0)[:120], io["history"][:120], rtol=1e-7, atol=1e-14)
+
+
+@pytest.mark.parametrize("cgs,select", [(1, True), (2, True), (2, False)])
+def test_gram_schmidt_modes_match_oracle(cgs, select):
+    """One Gram-Schmidt pass, a second pass when the first removed more than
+    half of ||w||^2, and two passes always: the per-step reductions of the
+    dot products (split over value slices, except where the adaptive test
+    needs every coefficient at once) give the oracle's augmented residual
+    history in complex128, for one problem alone and for a batch of three
+    grids of different sizes."""
+    import torch
+    from gpu_util import to_dev
+    shapes = [(48, 40), (36, 52), (60, 24)]
+    insts = [tiny_instance(70 + i, nx=nx, ny=ny, npml=4) for i, (nx, ny) in enumerate(shapes)]
+    rng = np.random.default_rng(71)
+    Vs = [W.random_complex(rng, (3, i.D)) for i in insts]
+    refs = []
+    for inst, V in zip(insts, Vs):
+        _, io = gmres_aug.gmres_aug(fdfd.assemble_instance(inst), inst.b, V.T, restart=30,
+                                    tol=1e-30, maxit=90)
+        refs.append(io["history"][:90])
+    for group in ([0], [0, 1, 2]):
+        s = _solver([_op(insts[g]) for g in group], restart=30, kmax=3, inner="c128",
+                    hist_cap=200, cgs_passes=cgs, select_reorth=select)
+        s.set_subspace([to_dev(Vs[g], torch.complex128) for g in group])
+        _, infos, _ = s.solve([_b(insts[g]) for g in group], tol=1e-30, maxit=90)
+        for t, g in enumerate(group):
+            assert infos[t]["iters"] == 90
+            np.testing.assert_allclose(s.history(t)[:90], refs[g], rtol=1e-7, atol=1e-14)
+        s.close()
